@@ -1,0 +1,208 @@
+/*
+ * pfmg — IPFASST (PFASST with inexact multigrid node solves) for the heat
+ * equation u_t = nu * Laplace(u) on the unit interval or cube with
+ * homogeneous Dirichlet data, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Minion, Speck, Bolten, Emmett, Ruprecht, "Interweaving PFASST and
+ * Parallel Multigrid", arXiv:1407.6486.
+ *   - collocation problem per time slice: eq. collocation / bigPmatk_2 (Sec. 2.1)
+ *   - SDC sweep with backward-Euler substeps: eq. sdc-be, SDCcompactLIII (Sec. 2.2)
+ *   - collocation residual: eq. resid (Sec. 2.2.2)
+ *   - two-level MLSDC with the FAS correction (Sec. 2.3), IMLSDC (Sec. 2.3.1)
+ *   - PFASST / IPFASST: predictor, iteration, send-forward (Sec. 2.3.2)
+ *   - node solves by geometric multigrid V-cycles: linear interpolation,
+ *     full-weighting restriction, pre/post smoothing (Sec. 4.1.1, 4.2.1)
+ *   - spatial operator: 2nd-order finite differences (3-point in 1D, Sec. 4.1;
+ *     7-point in 3D, Sec. 4.2)
+ *
+ * Conventions for every entry point
+ *   - All functions return a pfmg_status.  No C++ exception crosses the ABI.
+ *     On an error status (< 0) pfmg_last_error() returns a thread-local
+ *     message; the context stays usable except after PFMG_ERR_HIP.
+ *   - Work is enqueued on the HIP stream given to pfmg_create.  Calls that
+ *     return host scalars (residuals, norms) synchronise that stream.
+ *   - Host and device arrays exchanged with the library are dense float64
+ *     arrays of n^dim interior values in C order with x fastest; the halo
+ *     and padding of the internal layout are never visible to callers.
+ *   - Input pointers are borrowed for the duration of the call only.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef PFMG_H
+#define PFMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfmg_ctx pfmg_ctx;
+typedef int32_t pfmg_status;
+
+enum {
+    PFMG_OK = 0,
+    PFMG_NOT_CONVERGED = 1,   /* warning: outputs valid, tolerance not met   */
+    PFMG_STALLED = 2,         /* warning: MG stall criterion stopped a solve */
+    PFMG_ERR_ARG = -1,        /* invalid argument or parameter combination   */
+    PFMG_ERR_WORKSPACE = -2,  /* workspace missing, too small or misaligned  */
+    PFMG_ERR_HIP = -3,        /* a HIP runtime call failed                   */
+    PFMG_ERR_STATE = -4,      /* call out of order (e.g. iterate before set) */
+    PFMG_ERR_NAN = -5         /* a norm evaluated to NaN or Inf              */
+};
+
+enum { PFMG_NODES_LOBATTO = 0 };
+enum { PFMG_SMOOTH_JACOBI = 0, PFMG_SMOOTH_RBGS = 1 };
+enum { PFMG_FP64 = 0, PFMG_MIXED = 1 };
+enum { PFMG_GUESS_PREV = 0, PFMG_GUESS_LEARNED = 1 };
+enum { PFMG_SEND_AFTER_ITER = 0 };
+/* Fields readable / writable with pfmg_get / pfmg_set. */
+enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
+       PFMG_TAU = 4, PFMG_U_COARSE_OLD = 5 };
+
+/*
+ * Problem and method parameters.
+ *   dim              1 or 3.
+ *   n                interior points per dimension of the fine grid; mesh
+ *                    width h = 1/(n+1).  Every multigrid level with n >= 3
+ *                    must be odd: the hierarchy n -> (n+1)/2 - 1 ends at
+ *                    n in {1, 2}, which is solved exactly.
+ *   nu, dt           diffusion coefficient (> 0) and slice length (> 0).
+ *   n_slices         P, the time slices of one PFASST block (>= 1).
+ *   nodes_fine       Gauss-Lobatto nodes per slice on the fine level (2..9).
+ *   nodes_coarse     nodes on the coarse PFASST level (a subset of the fine
+ *                    nodes: 3 with 5 fine nodes), or 0 for a single level
+ *                    (ISDC).  The coarse level uses the grid (n+1)/2 - 1.
+ *   node_family      PFMG_NODES_LOBATTO.
+ *   smoother         PFMG_SMOOTH_JACOBI (weighted, omega) or
+ *                    PFMG_SMOOTH_RBGS (red = (i+j+k) even in 1-based
+ *                    interior indices, red then black, weight omega).
+ *   nu_pre, nu_post  smoothing sweeps before / after the coarse correction.
+ *   vcycles_per_solve  > 0: exactly that many V-cycles per node solve (the
+ *                    inexact solves of IMLSDC/IPFASST); 0: full solve, cycles
+ *                    repeat while |b - H u|_inf > mg_tol |b|_inf and each
+ *                    cycle cuts the residual below mg_stall times the
+ *                    previous one, at most mg_max_cycles (Sec. 4.2.1).
+ *   precision        PFMG_FP64, or PFMG_MIXED: FP32 smoothing, restriction,
+ *                    prolongation and coarsest solve inside FP64 iterative
+ *                    refinement (FP64 residual, FP64 update; one refinement
+ *                    step per V-cycle of the solve policy).
+ *   guess            PFMG_GUESS_PREV (previous iterate at the same node).
+ *   fine_send        PFMG_SEND_AFTER_ITER: slice p takes slice p-1's end
+ *                    value after p-1's previous iteration.
+ *   pfasst_tol       block relative residual tolerance for pfmg_run_block.
+ *   pfasst_max_iter  iteration cap for pfmg_run_block.
+ */
+typedef struct pfmg_params {
+    int32_t dim;
+    int32_t n;
+    double nu;
+    double dt;
+    int32_t n_slices;
+    int32_t nodes_fine;
+    int32_t nodes_coarse;
+    int32_t node_family;
+    int32_t smoother;
+    int32_t nu_pre;
+    int32_t nu_post;
+    double omega;
+    int32_t vcycles_per_solve;
+    double mg_tol;
+    double mg_stall;
+    int32_t mg_max_cycles;
+    int32_t precision;
+    int32_t guess;
+    int32_t fine_send;
+    double pfasst_tol;
+    int32_t pfasst_max_iter;
+} pfmg_params;
+
+/* Fills *p with the defaults: 3D, n = 127, nu = 1, dt = 1e-3, 16 slices,
+ * 5/3 Lobatto nodes, red-black Gauss-Seidel V(2,2), omega 1, one V-cycle per
+ * solve, mg_tol 1e-12, stall 0.75, 50 cycles, FP64, pfasst_tol 1e-10,
+ * 200 iterations. */
+pfmg_status pfmg_default_params(pfmg_params *p);
+
+/* Device bytes the context needs for these parameters (>= 256-byte aligned
+ * workspace).  Errors: PFMG_ERR_ARG for invalid parameters. */
+pfmg_status pfmg_workspace_bytes(const pfmg_params *p, size_t *bytes_out);
+
+/* Create a context.  `workspace` is caller-owned device memory of at least
+ * pfmg_workspace_bytes (256-byte aligned); it must outlive the context and
+ * is not freed by the library.  `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  The library allocates no device memory itself; it keeps
+ * one small pinned host buffer for residual read-back.  Computes the
+ * collocation matrices (Sec. 2.1, eq. Qbe) on the host in long double. */
+pfmg_status pfmg_create(const pfmg_params *p, void *workspace, size_t bytes,
+                        void *hip_stream, pfmg_ctx **out);
+pfmg_status pfmg_destroy(pfmg_ctx *ctx);
+/* Message of the last error on this thread ("" if none). */
+const char *pfmg_last_error(void);
+
+/* Start a block: copy u0 (n^dim float64, host if on_device == 0, device
+ * otherwise) to every node of every slice, evaluate F = nu L u, and — with
+ * two levels — run the PFASST predictor (Sec. 2.3.2: FAS restriction of
+ * the spread state, P pipelined rounds of coarse sweeps in which slice p
+ * sweeps p+1 times, interpolation). */
+pfmg_status pfmg_set_initial(pfmg_ctx *ctx, const double *u0, int32_t on_device);
+
+/* One SDC sweep (eq. sdc-be / SDCcompactLIII) on slices [p_begin, p_end) of
+ * level 0 (fine) or level 1 (coarse, right-hand side corrected by the FAS
+ * term tau[m+1] - tau[m]).  Slices are swept independently (their node-0
+ * values are used as they are).  Each node solve follows the solve policy. */
+pfmg_status pfmg_sdc_sweep(pfmg_ctx *ctx, int32_t level, int32_t p_begin, int32_t p_end);
+
+/* Solve (I - alpha L_h) u = b on the fine grid with V-cycles (Sec. 4.1.1).
+ * b, u: device pointers to n^dim float64; u is the initial guess and is
+ * overwritten.  n_cycles > 0: that many cycles; 0: full solve (mg_tol,
+ * mg_stall, mg_max_cycles).  *relres_out (may be NULL) receives
+ * |b - H u|_inf / |b|_inf; *cycles_out (may be NULL) the cycles run.
+ * Returns PFMG_STALLED / PFMG_NOT_CONVERGED for a full solve that stopped
+ * early. */
+pfmg_status pfmg_vcycle(pfmg_ctx *ctx, double alpha, const double *b, double *u,
+                        int32_t n_cycles, double *relres_out, int32_t *cycles_out);
+
+/* One IPFASST iteration (Sec. 2.3.2): new fine initial values from the
+ * previous slices, fine sweeps on all slices, FAS restriction, coarse sweeps
+ * in slice order, interpolation, collocation residual.  *block_res_out
+ * (may be NULL) receives max over slices of the relative residual. */
+pfmg_status pfmg_pfasst_iter(pfmg_ctx *ctx, double *block_res_out);
+
+/* Collocation residual (eq. resid) of every slice on level 0:
+ * r[m] = U0_p - U[m] + dt sum_i Q[m][i] F[i] (m = 0..M), U0_p the previous
+ * slice's end value (the block's initial value for p = 0);
+ * per_slice_out[p] = max_m |r[m]|_inf / |U0_p|_inf (host array of P).
+ * level must be 0.  PFMG_ERR_NAN if a value is NaN/Inf. */
+pfmg_status pfmg_residual(pfmg_ctx *ctx, int32_t level, double *per_slice_out);
+
+/* Run a whole block: set_initial (u0 as above), then iterations until the
+ * block residual <= pfasst_tol or pfasst_max_iter.  Outputs (each may be
+ * NULL): iterations run, final block residual.  PFMG_NOT_CONVERGED when
+ * the cap was reached. */
+pfmg_status pfmg_run_block(pfmg_ctx *ctx, const double *u0, int32_t on_device,
+                           int32_t *iters_out, double *res_out);
+
+/* Copy a field (PFMG_U_FINE .. PFMG_U_COARSE_OLD) of slice `slice`, node
+ * `node` into / from a dense n^dim (fine) or nc^dim (coarse) float64 array
+ * on the host (on_device == 0) or device. */
+pfmg_status pfmg_get(pfmg_ctx *ctx, int32_t field, int32_t slice, int32_t node,
+                     double *dst, int32_t on_device);
+pfmg_status pfmg_set(pfmg_ctx *ctx, int32_t field, int32_t slice, int32_t node,
+                     const double *src, int32_t on_device);
+
+/* V-cycles run so far by node solves on level 0 / 1 (counted per slice). */
+pfmg_status pfmg_vcycle_count(pfmg_ctx *ctx, int32_t level, int64_t *count_out);
+
+/* Kernel timing for measurement: while enabled, every launch of the named
+ * kernel family is bracketed by HIP events on the context's stream.
+ * pfmg_timing_read returns the launches recorded, their summed duration in
+ * milliseconds and the algorithmic bytes they move (interior points times
+ * the per-point byte count of the kernel). */
+pfmg_status pfmg_timing_enable(pfmg_ctx *ctx, const char *kernel, int32_t enable);
+pfmg_status pfmg_timing_read(pfmg_ctx *ctx, int64_t *launches, double *ms_total,
+                             double *bytes_total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,13 @@
+// Host-side construction of the collocation matrices (Sec. 2.1, eq. Qbe).
+#pragma once
+
+namespace pfmg {
+
+// Gauss-Lobatto nodes on [0, 1] in long double; false if nnodes outside 2..16.
+bool lobatto_nodes_ld(int nnodes, long double *s);
+// Q (nn x nn), S ((nn-1) x nn), d (nn) rounded once to double.
+bool collocation_matrices(int nnodes, const long double *s, double *Q, double *S, double *d);
+// L[mf][mc] = l^c_mc(sf[mf]).
+void lagrange_interp(int nf, const long double *sf, int nc, const long double *sc, double *L);
+
+}  // namespace pfmg

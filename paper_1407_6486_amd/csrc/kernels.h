@@ -1,0 +1,96 @@
+// Host-side launchers of the gfx950 kernels.  Every launcher enqueues one
+// kernel on `s` and returns the launch status.  Views follow layout.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+#include "tile.h"
+
+namespace pfmg {
+namespace k {
+
+// ---------------------------------------------------------------- grid ops
+// r = b - (I - alpha L_h) u
+template <typename T>
+hipError_t resid(const Tiling &t, double alpha, View<T> b, View<T> u, View<T> r, hipStream_t s);
+// FP64 residual rounded once to FP32 (refinement step of the mixed form)
+hipError_t resid_round(const Tiling &t, double alpha, View<double> b, View<double> u,
+                       View<float> r32, hipStream_t s);
+// out = u + omega (b - H u) / diag(H)
+template <typename T>
+hipError_t jacobi(const Tiling &t, double alpha, double omega, View<T> b, View<T> u,
+                  View<T> out, hipStream_t s);
+// First Jacobi sweep from u = 0: out = omega b / diag(H)
+template <typename T>
+hipError_t jacobi_zero(const Tiling &t, double alpha, double omega, View<T> b, View<T> out,
+                       hipStream_t s);
+// Red (colour 0: 1-based i+j+k even) or black points, in place.
+template <typename T>
+hipError_t rbgs(const Tiling &t, double alpha, double omega, int colour, View<T> b, View<T> u,
+                hipStream_t s);
+// Red pass from u = 0: red points omega b / diag(H), black points 0.
+template <typename T>
+hipError_t rbgs_zero_red(const Tiling &t, double alpha, double omega, View<T> b, View<T> u,
+                         hipStream_t s);
+// Full weighting of a fine array (t.n = fine n) onto the coarse grid.
+template <typename T>
+hipError_t restrict_fw(const Tiling &t, View<T> r, View<T> bc, hipStream_t s);
+// Fused: coarse rhs = FW(b - H u) on the fine grid (t.n = fine n).
+template <typename T>
+hipError_t resid_restrict(const Tiling &t, double alpha, View<T> b, View<T> u, View<T> bc,
+                          hipStream_t s);
+// u += P ec, d-linear (t.n = fine n).
+template <typename T>
+hipError_t prolong_add(const Tiling &t, View<T> ec, View<T> u, hipStream_t s);
+// Exact solve for n in {1, 2}.
+template <typename T>
+hipError_t coarsest(const Tiling &t, double alpha, View<T> b, View<T> u, hipStream_t s);
+template <typename T>
+hipError_t zero(const Tiling &t, View<T> u, hipStream_t s);
+template <typename T>
+hipError_t copy(const Tiling &t, View<T> src, View<T> dst, hipStream_t s);
+// u += (double) e
+hipError_t add_f32(const Tiling &t, View<float> e, View<double> u, hipStream_t s);
+// bits[item] = max(bits[item], |v|_inf as ordered bits); bits must be preset
+template <typename T>
+hipError_t norm_inf(const Tiling &t, View<T> v, unsigned long long *bits, hipStream_t s);
+// bits[item] = max |b - H u|
+hipError_t resid_norm(const Tiling &t, double alpha, View<double> b, View<double> u,
+                      unsigned long long *bits, hipStream_t s);
+
+// ------------------------------------------------------------ method ops
+// F = nu L_h u
+hipError_t apply_L(const Tiling &t, double nu, View<double> u, View<double> F, hipStream_t s);
+// I[m] = dt sum_i S[m][i] F[i], m = 0..nn-2, per slice (item = slice).
+hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, View<double> F,
+                         long f_node, View<double> I, long i_node, hipStream_t s);
+// b = U[m] - delta F[m+1] + I[m] (+ tau1 - tau0 when tau1.p != nullptr)
+hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> Fm1,
+                   View<double> Im, View<double> tau1, View<double> tau0, View<double> b,
+                   hipStream_t s);
+// FAS injection (t.n = coarse n): Uc[mc] = Uold[mc] = Uf[cmap[mc]] at 2J,
+// Tau[mc] = dt sum_i Qf[cmap[mc]][i] Ff[i] at 2J.
+hipError_t fas_inject(const Tiling &t, int nf, int nnf, int nnc, const int *cmap, double dt,
+                      const double *Qf, View<double> Uf, View<double> Ff, long f_node,
+                      View<double> Uc, View<double> Uold, View<double> Tau, long c_node,
+                      hipStream_t s);
+// Tau[mc] -= dt sum_j Qc[mc][j] Fc[j]   (t.n = coarse n)
+hipError_t fas_tau(const Tiling &t, int nnc, double dt, const double *Qc, View<double> Fc,
+                   View<double> Tau, long c_node, hipStream_t s);
+// DC[m] = sum_mc Lt[m][mc] (Uc[mc] - Uold[mc]), m = 0..nnf-1 (t.n = coarse n)
+hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, View<double> Uc,
+                         View<double> Uold, long c_node, View<double> DC, long dc_node,
+                         hipStream_t s);
+// Collocation residual (eq. resid) per slice; bits preset to 0.
+hipError_t colloc_resid(const Tiling &t, int nn, double dt, const double *Q, View<double> U,
+                        View<double> F, long node, const double *ublock,
+                        unsigned long long *res_bits, unsigned long long *u0_bits, hipStream_t s);
+// Point-wise injection uc(J) = uf(2J) (t.n = coarse n).
+hipError_t inject(const Tiling &t, int nf, View<double> uf, View<double> uc, hipStream_t s);
+// dense (n^dim, x fastest) <-> field
+hipError_t pack(const Tiling &t, View<double> f, double *dense, hipStream_t s);
+hipError_t unpack(const Tiling &t, const double *dense, View<double> f, hipStream_t s);
+hipError_t fill_u64(unsigned long long *p, unsigned long long v, int count, hipStream_t s);
+
+}  // namespace k
+}  // namespace pfmg

@@ -1,0 +1,93 @@
+// Host-side solver state of one pfmg context.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pfmg.h"
+#include "kernels.h"
+
+namespace pfmg {
+
+// Work arrays of one multigrid level for up to `cap` simultaneous solves.
+struct MGLevel {
+    int n = 0;
+    long fs64 = 0, fs32 = 0;          // slot strides (elements)
+    View<double> e{}, b{}, r{}, t{};  // levels >= 1 use e, b; r/t when needed
+    View<float> e32{}, b32{}, r32{}, t32{};
+};
+
+// One PFASST level: grid, nodes, state of all slices, and its MG hierarchy.
+struct PLevel {
+    int n = 0, nn = 0;
+    long fs = 0;                      // FP64 slot stride
+    double *U = nullptr, *F = nullptr, *I = nullptr, *B = nullptr;
+    double *Tau = nullptr, *Uold = nullptr, *DC = nullptr;   // coarse level only
+    std::vector<MGLevel> mg;          // mg[0].n == n
+    long double s_ld[16];
+    double s[16], Q[256], S[256], d[16];
+    double *dQ = nullptr, *dS = nullptr;
+    double *slot(double *base, int p, int m) const { return base + ((long)p * nn + m) * fs; }
+};
+
+struct Timer {
+    std::string key;                  // kernel family "@" grid n, e.g. "rbgs@127"
+    bool on = false;
+    std::vector<hipEvent_t> ev;       // start/stop pairs
+    size_t used = 0;
+    int depth = 0;                    // current bracket nesting
+    int open = -1;                    // depth of the recording bracket, -1 if none
+    double bytes = 0;
+    long long launches = 0;
+};
+
+struct Solver {
+    pfmg_params p{};
+    hipStream_t s = nullptr;
+    int dim = 3, P = 1, nl = 1;
+    PLevel L[2];
+    double *ublock = nullptr, *ublock_c = nullptr, *fublock_c = nullptr;
+    double *vb = nullptr, *vu = nullptr;      // pfmg_vcycle staging slots (fine)
+    double *dLt = nullptr;
+    int cmap[16] = {0};
+    unsigned long long *bits = nullptr;       // reduction scratch [4 * P]
+    int *mask = nullptr;                      // [P]
+    unsigned long long *hbits = nullptr;      // pinned host mirror [4 * P]
+    int *hmask = nullptr;                     // pinned host mask [P]
+    bool has_state = false;
+    long long vcount[2] = {0, 0};
+    int last_solve_status = 0;
+    Timer timer;
+
+    // --- setup
+    static bool validate(const pfmg_params &p, std::string &why);
+    static size_t carve(const pfmg_params &p, char *base, Solver *sv);   // returns bytes
+    bool init_host(std::string &why);
+    hipError_t upload_constants();
+
+    // --- building blocks (all enqueue on s)
+    hipError_t solve(int lev, View<double> u, View<double> b, int count, double alpha, int cycles,
+                     double *relres_host);
+    hipError_t vcycle64(int lev, int l, View<double> u, View<double> b, int count, const int *mask,
+                        double alpha);
+    hipError_t vcycle32(int lev, int l, View<float> u, View<float> b, int count, const int *mask,
+                        double alpha);
+    template <typename T>
+    hipError_t smooth(int n, int count, const int *mask, double alpha, View<T> u, View<T> b, View<T> tmp,
+                      int sweeps, bool from_zero);
+    hipError_t cycle_step(int lev, View<double> u, View<double> b, int count, const int *mask, double alpha);
+    hipError_t sweep(int lev, int p0, int p1);
+    hipError_t fas_restrict(int p0, int p1);
+    hipError_t interpolate(int p0, int p1);
+    hipError_t predictor();
+    hipError_t spread(const double *u0_dev);
+    hipError_t residual(double *per_slice, double *block);
+    hipError_t iterate(double *block);
+
+    Tiling tl(int n, int count, const int *m = nullptr) const { return Tiling{n, dim, count, m}; }
+    void tstart(const char *fam, int n, double bytes_per_point, long points);
+    void tstop();
+};
+
+}  // namespace pfmg

@@ -1,0 +1,537 @@
+// IPFASST on one GPU: the P time slices of a block are processed together;
+// each "time rank" of the paper is a slice of the batched state.
+//
+// Per iteration (Sec. 2.3.2): new fine initial values from the previous
+// slices (their end values after the previous iteration), one fine SDC
+// sweep on all slices at once, FAS restriction, the coarse sweeps in slice
+// order (the blocking coarse level of PFASST), interpolation of the coarse
+// correction, and the collocation residual (eq. resid).  Every node solve
+// is a fixed number of V-cycles (IMLSDC, Sec. 2.3.1) or a full solve
+// (Sec. 4.2.1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "collocation.h"
+#include "solver.h"
+
+#define HC(x)                                  \
+    do {                                       \
+        hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+
+namespace pfmg {
+
+static inline double bits_to_double(unsigned long long b)
+{
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+bool Solver::validate(const pfmg_params &p, std::string &why)
+{
+    if (p.dim != 1 && p.dim != 3) { why = "dim must be 1 or 3"; return false; }
+    if (p.n < 1) { why = "n must be >= 1"; return false; }
+    for (int n = p.n; n > 2; n = coarser(n))
+        if ((n & 1) == 0) { why = "every multigrid level with n >= 3 must be odd"; return false; }
+    if (!(p.nu > 0) || !(p.dt > 0) || !std::isfinite(p.nu) || !std::isfinite(p.dt)) {
+        why = "nu and dt must be positive and finite"; return false;
+    }
+    if (p.n_slices < 1 || p.n_slices > 4096) { why = "n_slices must be in 1..4096"; return false; }
+    if (p.nodes_fine < 2 || p.nodes_fine > 9) { why = "nodes_fine must be in 2..9"; return false; }
+    if (p.nodes_coarse != 0) {
+        if (p.nodes_coarse < 2 || p.nodes_coarse > p.nodes_fine) { why = "bad nodes_coarse"; return false; }
+        if (p.n < 3) { why = "two levels need n >= 3"; return false; }
+        long double sf[16], sc[16];
+        if (!lobatto_nodes_ld(p.nodes_fine, sf) || !lobatto_nodes_ld(p.nodes_coarse, sc)) {
+            why = "node construction failed"; return false;
+        }
+        for (int mc = 0; mc < p.nodes_coarse; ++mc) {
+            bool found = false;
+            for (int mf = 0; mf < p.nodes_fine; ++mf) found = found || std::fabs((double)(sf[mf] - sc[mc])) < 1e-14;
+            if (!found) { why = "coarse nodes must be a subset of the fine nodes (injection in time)"; return false; }
+        }
+    }
+    if (p.node_family != PFMG_NODES_LOBATTO) { why = "only Lobatto nodes are supported"; return false; }
+    if (p.smoother != PFMG_SMOOTH_JACOBI && p.smoother != PFMG_SMOOTH_RBGS) { why = "bad smoother"; return false; }
+    if (p.nu_pre < 0 || p.nu_post < 0 || p.nu_pre + p.nu_post == 0 || p.nu_pre > 16 || p.nu_post > 16) {
+        why = "smoothing sweeps must be in 0..16 and not both 0"; return false;
+    }
+    if (!(p.omega > 0 && p.omega < 2)) { why = "omega must be in (0, 2)"; return false; }
+    if (p.vcycles_per_solve < 0 || p.vcycles_per_solve > 100) { why = "vcycles_per_solve in 0..100"; return false; }
+    if (p.vcycles_per_solve == 0 && (p.mg_max_cycles < 1 || !(p.mg_tol >= 0) || !(p.mg_stall > 0))) {
+        why = "full solves need mg_max_cycles >= 1, mg_tol >= 0, mg_stall > 0"; return false;
+    }
+    if (p.precision != PFMG_FP64 && p.precision != PFMG_MIXED) { why = "bad precision"; return false; }
+    if (p.guess != PFMG_GUESS_PREV) { why = "this context supports guess = PFMG_GUESS_PREV"; return false; }
+    if (p.fine_send != PFMG_SEND_AFTER_ITER) { why = "fine_send must be PFMG_SEND_AFTER_ITER"; return false; }
+    if (p.pfasst_max_iter < 1) { why = "pfasst_max_iter must be >= 1"; return false; }
+    return true;
+}
+
+// Lay out the workspace.  With base == nullptr only the size is computed.
+size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        off = (off + 255) & ~(size_t)255;
+        char *r = base ? base + off : nullptr;
+        off += bytes;
+        return r;
+    };
+    const int dim = p.dim, P = p.n_slices;
+    const int nl = p.nodes_coarse > 0 ? 2 : 1;
+    const bool mixed = p.precision == PFMG_MIXED;
+    const bool jac = p.smoother == PFMG_SMOOTH_JACOBI;
+    auto f64 = [&](int n, long count) -> double * {
+        const long fs = field_stride(n, dim, 8);
+        char *c = take((size_t)count * fs * 8);
+        return c ? (double *)c + field_lead(8) : nullptr;
+    };
+    auto f32 = [&](int n, long count) -> float * {
+        const long fs = field_stride(n, dim, 4);
+        char *c = take((size_t)count * fs * 4);
+        return c ? (float *)c + field_lead(4) : nullptr;
+    };
+    for (int lev = 0; lev < nl; ++lev) {
+        const int n = lev == 0 ? p.n : coarser(p.n);
+        const int nn = lev == 0 ? p.nodes_fine : p.nodes_coarse;
+        PLevel tmp;
+        PLevel &L = sv ? sv->L[lev] : tmp;
+        L.n = n;
+        L.nn = nn;
+        L.fs = field_stride(n, dim, 8);
+        L.U = f64(n, (long)P * nn);
+        L.F = f64(n, (long)P * nn);
+        L.I = f64(n, (long)P * (nn - 1));
+        L.B = f64(n, P);
+        if (lev == 1) {
+            L.Tau = f64(n, (long)P * nn);
+            L.Uold = f64(n, (long)P * nn);
+            L.DC = f64(n, (long)P * p.nodes_fine);
+        }
+        L.mg.clear();
+        for (int l = 0, nl_ = n;; ++l, nl_ = coarser(nl_)) {
+            MGLevel G;
+            G.n = nl_;
+            G.fs64 = field_stride(nl_, dim, 8);
+            G.fs32 = field_stride(nl_, dim, 4);
+            if (l > 0) {
+                G.e = {f64(nl_, P), G.fs64};
+                G.b = {f64(nl_, P), G.fs64};
+            }
+            if (jac) G.t = {f64(nl_, P), G.fs64};
+            if (mixed) {
+                G.e32 = {f32(nl_, P), G.fs32};
+                G.b32 = {f32(nl_, P), G.fs32};
+                if (jac) G.t32 = {f32(nl_, P), G.fs32};
+            }
+            L.mg.push_back(G);
+            if (nl_ <= 2) break;
+        }
+        double *dQ = (double *)take(256 * 8), *dS = (double *)take(256 * 8);
+        L.dQ = dQ;
+        L.dS = dS;
+    }
+    double *ub = f64(p.n, 1), *vb = f64(p.n, 1), *vu = f64(p.n, 1);
+    double *ubc = nullptr, *fubc = nullptr;
+    if (nl > 1) {
+        ubc = f64(coarser(p.n), 1);
+        fubc = f64(coarser(p.n), 1);
+    }
+    double *lt = (double *)take(256 * 8);
+    auto *bits = (unsigned long long *)take((size_t)4 * P * 8);
+    int *mask = (int *)take((size_t)P * 4);
+    if (sv) {
+        sv->ublock = ub;
+        sv->vb = vb;
+        sv->vu = vu;
+        sv->ublock_c = ubc;
+        sv->fublock_c = fubc;
+        sv->dLt = lt;
+        sv->bits = bits;
+        sv->mask = mask;
+    }
+    return ((off + 255) & ~(size_t)255) + 256;
+}
+
+bool Solver::init_host(std::string &why)
+{
+    dim = p.dim;
+    P = p.n_slices;
+    nl = p.nodes_coarse > 0 ? 2 : 1;
+    for (int lev = 0; lev < nl; ++lev) {
+        PLevel &Lv = L[lev];
+        const int nn = lev == 0 ? p.nodes_fine : p.nodes_coarse;
+        if (!lobatto_nodes_ld(nn, Lv.s_ld)) { why = "node construction failed"; return false; }
+        for (int q = 0; q < nn; ++q) Lv.s[q] = (double)Lv.s_ld[q];
+        if (!collocation_matrices(nn, Lv.s_ld, Lv.Q, Lv.S, Lv.d)) { why = "Q construction failed"; return false; }
+    }
+    if (nl > 1) {
+        for (int mc = 0; mc < p.nodes_coarse; ++mc) {
+            cmap[mc] = -1;
+            for (int mf = 0; mf < p.nodes_fine; ++mf)
+                if (std::fabs((double)(L[0].s_ld[mf] - L[1].s_ld[mc])) < 1e-14) cmap[mc] = mf;
+            if (cmap[mc] < 0) { why = "coarse nodes must be a subset of the fine nodes"; return false; }
+        }
+    }
+    return true;
+}
+
+hipError_t Solver::upload_constants()
+{
+    static thread_local double Lt[256];
+    for (int lev = 0; lev < nl; ++lev) {
+        HC(hipMemcpyAsync(L[lev].dQ, L[lev].Q, sizeof(double) * L[lev].nn * L[lev].nn, hipMemcpyHostToDevice, s));
+        HC(hipMemcpyAsync(L[lev].dS, L[lev].S, sizeof(double) * L[lev].nn * L[lev].nn, hipMemcpyHostToDevice, s));
+    }
+    if (nl > 1) {
+        lagrange_interp(p.nodes_fine, L[0].s_ld, p.nodes_coarse, L[1].s_ld, Lt);
+        HC(hipMemcpyAsync(dLt, Lt, sizeof(double) * p.nodes_fine * p.nodes_coarse, hipMemcpyHostToDevice, s));
+    }
+    return hipStreamSynchronize(s);
+}
+
+// ------------------------------------------------------------------ timing
+// Brackets nest (a whole V-cycle contains its smoother launches); only the
+// bracket whose family matches the enabled key records events, and its stop
+// is the tstop at the same nesting depth.
+void Solver::tstart(const char *fam, int n, double bytes_per_point, long points)
+{
+    const int d = timer.depth++;
+    if (!timer.on || timer.open >= 0) return;
+    if (timer.key != std::string(fam) + "@" + std::to_string(n) || timer.used + 2 > timer.ev.size()) return;
+    (void)hipEventRecord(timer.ev[timer.used], s);
+    timer.bytes += bytes_per_point * (double)points;
+    timer.launches += 1;
+    timer.used += 1;
+    timer.open = d;
+}
+
+void Solver::tstop()
+{
+    const int d = --timer.depth;
+    if (timer.open != d) return;
+    (void)hipEventRecord(timer.ev[timer.used], s);
+    timer.used += 1;
+    timer.open = -1;
+}
+
+// ------------------------------------------------------------- multigrid
+template <typename T>
+hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> u, View<T> b, View<T> tmp,
+                          int sweeps, bool from_zero)
+{
+    const Tiling t = tl(n, count, m);
+    const double om = p.omega;
+    const long pts = interior_points(n, dim) * count;
+    const double w = (double)sizeof(T);
+    if (sweeps == 0) return from_zero ? k::zero(t, u, s) : hipSuccess;
+    if (p.smoother == PFMG_SMOOTH_RBGS) {
+        for (int q = 0; q < sweeps; ++q) {
+            tstart("rbgs", n, 2 * w, pts);
+            if (q == 0 && from_zero) HC(k::rbgs_zero_red(t, alpha, om, b, u, s));
+            else HC(k::rbgs(t, alpha, om, 0, b, u, s));
+            tstop();
+            tstart("rbgs", n, 2 * w, pts);
+            HC(k::rbgs(t, alpha, om, 1, b, u, s));
+            tstop();
+        }
+        return hipSuccess;
+    }
+    View<T> src = u, dst = tmp;
+    for (int q = 0; q < sweeps; ++q) {
+        tstart("jacobi", n, 3 * w, pts);
+        if (q == 0 && from_zero) HC(k::jacobi_zero(t, alpha, om, b, dst, s));
+        else HC(k::jacobi(t, alpha, om, b, src, dst, s));
+        tstop();
+        std::swap(src, dst);
+    }
+    if (src.p != u.p) HC(k::copy(t, src, u, s));
+    return hipSuccess;
+}
+
+hipError_t Solver::vcycle64(int lev, int l, View<double> u, View<double> b, int count, const int *m, double alpha)
+{
+    MGLevel &G = L[lev].mg[l];
+    const Tiling t = tl(G.n, count, m);
+    if (G.n <= 2) return k::coarsest(t, alpha, b, u, s);
+    HC(smooth<double>(G.n, count, m, alpha, u, b, G.t, p.nu_pre, l > 0));
+    MGLevel &C = L[lev].mg[l + 1];
+    const long pts = interior_points(G.n, dim) * count;
+    tstart("resid_restrict", G.n, 16 + 8.0 / (dim == 3 ? 8 : 2), pts);
+    HC(k::resid_restrict(t, alpha, b, u, C.b, s));
+    tstop();
+    HC(vcycle64(lev, l + 1, C.e, C.b, count, m, alpha));
+    tstart("prolong", G.n, 16 + 8.0 / (dim == 3 ? 8 : 2), pts);
+    HC(k::prolong_add(t, C.e, u, s));
+    tstop();
+    return smooth<double>(G.n, count, m, alpha, u, b, G.t, p.nu_post, false);
+}
+
+hipError_t Solver::vcycle32(int lev, int l, View<float> u, View<float> b, int count, const int *m, double alpha)
+{
+    MGLevel &G = L[lev].mg[l];
+    const Tiling t = tl(G.n, count, m);
+    if (G.n <= 2) return k::coarsest(t, alpha, b, u, s);
+    HC(smooth<float>(G.n, count, m, alpha, u, b, G.t32, p.nu_pre, true));
+    MGLevel &C = L[lev].mg[l + 1];
+    HC(k::resid_restrict(t, alpha, b, u, C.b32, s));
+    HC(vcycle32(lev, l + 1, C.e32, C.b32, count, m, alpha));
+    HC(k::prolong_add(t, C.e32, u, s));
+    return smooth<float>(G.n, count, m, alpha, u, b, G.t32, p.nu_post, false);
+}
+
+// One V-cycle, or one refinement step of the mixed form: FP64 residual
+// rounded to FP32, FP32 V-cycle from a zero correction, FP64 update.
+hipError_t Solver::cycle_step(int lev, View<double> u, View<double> b, int count, const int *m, double alpha)
+{
+    if (p.precision != PFMG_MIXED) return vcycle64(lev, 0, u, b, count, m, alpha);
+    MGLevel &G = L[lev].mg[0];
+    const Tiling t = tl(G.n, count, m);
+    HC(k::resid_round(t, alpha, b, u, G.b32, s));
+    HC(vcycle32(lev, 0, G.e32, G.b32, count, m, alpha));
+    return k::add_f32(t, G.e32, u, s);
+}
+
+hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, double alpha, int cycles,
+                         double *relres_host)
+{
+    const int n = L[lev].n;
+    last_solve_status = 0;
+    if (cycles > 0) {
+        for (int c = 0; c < cycles; ++c) {
+            // "vcycle@n" brackets whole cycles; its byte counter holds DOF x cycles
+            tstart("vcycle", n, 1.0, interior_points(n, dim) * count);
+            HC(cycle_step(lev, u, b, count, nullptr, alpha));
+            tstop();
+        }
+        vcount[lev] += (long long)cycles * count;
+        if (relres_host) {
+            HC(k::fill_u64(bits, 0, 2 * count, s));
+            HC(k::norm_inf(tl(n, count), b, bits, s));
+            HC(k::resid_norm(tl(n, count), alpha, b, u, bits + count, s));
+            HC(hipMemcpyAsync(hbits, bits, sizeof(unsigned long long) * 2 * count, hipMemcpyDeviceToHost, s));
+            HC(hipStreamSynchronize(s));
+            for (int q = 0; q < count; ++q) {
+                const double nb = bits_to_double(hbits[q]), r = bits_to_double(hbits[count + q]);
+                relres_host[q] = nb > 0 ? r / nb : r;
+            }
+        }
+        return hipSuccess;
+    }
+    // Full solve, per field: repeat while |r| > tol |b| and each cycle cuts
+    // the residual below stall * the previous one, at most mg_max_cycles.
+    HC(k::fill_u64(bits, 0, 2 * count, s));
+    HC(k::norm_inf(tl(n, count), b, bits, s));
+    HC(k::resid_norm(tl(n, count), alpha, b, u, bits + count, s));
+    HC(hipMemcpyAsync(hbits, bits, sizeof(unsigned long long) * 2 * count, hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    std::vector<double> nb(count), rold(count);
+    int active = 0;
+    for (int q = 0; q < count; ++q) {
+        nb[q] = bits_to_double(hbits[q]);
+        rold[q] = bits_to_double(hbits[count + q]);
+        if (!std::isfinite(nb[q]) || !std::isfinite(rold[q])) { last_solve_status = PFMG_ERR_NAN; return hipSuccess; }
+        hmask[q] = rold[q] > p.mg_tol * nb[q];
+        active += hmask[q];
+    }
+    int c = 0;
+    bool stalled_any = false;
+    while (c < p.mg_max_cycles && active > 0) {
+        HC(hipMemcpyAsync(mask, hmask, sizeof(int) * count, hipMemcpyHostToDevice, s));
+        tstart("vcycle", n, 1.0, interior_points(n, dim) * active);
+        HC(cycle_step(lev, u, b, count, mask, alpha));
+        tstop();
+        ++c;
+        vcount[lev] += active;
+        HC(k::fill_u64(bits + count, 0, count, s));
+        HC(k::resid_norm(tl(n, count, mask), alpha, b, u, bits + count, s));
+        HC(hipMemcpyAsync(hbits + count, bits + count, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, s));
+        HC(hipStreamSynchronize(s));
+        active = 0;
+        for (int q = 0; q < count; ++q) {
+            if (!hmask[q]) continue;
+            const double rn = bits_to_double(hbits[count + q]);
+            if (!std::isfinite(rn)) { last_solve_status = PFMG_ERR_NAN; return hipSuccess; }
+            const bool stalled = !(rn < p.mg_stall * rold[q]);
+            rold[q] = rn;
+            if (rn <= p.mg_tol * nb[q]) hmask[q] = 0;
+            else if (stalled) { hmask[q] = 0; stalled_any = true; }
+            active += hmask[q];
+        }
+    }
+    if (relres_host)
+        for (int q = 0; q < count; ++q) relres_host[q] = nb[q] > 0 ? rold[q] / nb[q] : rold[q];
+    if (stalled_any) last_solve_status = PFMG_STALLED;
+    else if (active > 0) last_solve_status = PFMG_NOT_CONVERGED;
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------- SDC
+hipError_t Solver::sweep(int lev, int p0, int p1)
+{
+    PLevel &Lv = L[lev];
+    const int count = p1 - p0;
+    if (count <= 0) return hipSuccess;
+    const int nn = Lv.nn;
+    const long fs = Lv.fs, sst = (long)nn * fs, ist = (long)(nn - 1) * fs;
+    const Tiling t = tl(Lv.n, count);
+    const long pts = interior_points(Lv.n, dim) * count;
+    tstart("sdc_integrals", Lv.n, 8.0 * (2 * nn - 1), pts);
+    HC(k::sdc_integrals(t, nn, p.dt, Lv.dS, View<double>{Lv.slot(Lv.F, p0, 0), sst}, fs,
+                        View<double>{Lv.I + (long)p0 * ist, ist}, fs, s));
+    tstop();
+    View<double> Bv{Lv.B + (long)p0 * fs, fs};
+    for (int m = 0; m + 1 < nn; ++m) {
+        const double delta = p.dt * Lv.d[m + 1];
+        View<double> Um{Lv.slot(Lv.U, p0, m), sst}, Fm1{Lv.slot(Lv.F, p0, m + 1), sst};
+        View<double> Im{Lv.I + (long)p0 * ist + (long)m * fs, ist};
+        View<double> t1{nullptr, 0}, t0{nullptr, 0};
+        if (lev == 1) {
+            t1 = {Lv.slot(Lv.Tau, p0, m + 1), sst};
+            t0 = {Lv.slot(Lv.Tau, p0, m), sst};
+        }
+        tstart("sdc_rhs", Lv.n, lev == 1 ? 48 : 32, pts);
+        HC(k::sdc_rhs(t, delta, Um, Fm1, Im, t1, t0, Bv, s));
+        tstop();
+        View<double> Uv{Lv.slot(Lv.U, p0, m + 1), sst};
+        HC(solve(lev, Uv, Bv, count, p.nu * delta, p.vcycles_per_solve, nullptr));
+        if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+        tstart("apply_L", Lv.n, 16, pts);
+        HC(k::apply_L(t, p.nu, Uv, Fm1, s));
+        tstop();
+    }
+    return hipSuccess;
+}
+
+hipError_t Solver::fas_restrict(int p0, int p1)
+{
+    PLevel &Fn = L[0], &Cs = L[1];
+    const int count = p1 - p0;
+    const long fst = (long)Fn.nn * Fn.fs, cst = (long)Cs.nn * Cs.fs;
+    HC(k::fas_inject(tl(Cs.n, count), Fn.n, Fn.nn, Cs.nn, cmap, p.dt, Fn.dQ,
+                     View<double>{Fn.slot(Fn.U, p0, 0), fst}, View<double>{Fn.slot(Fn.F, p0, 0), fst}, Fn.fs,
+                     View<double>{Cs.slot(Cs.U, p0, 0), cst}, View<double>{Cs.slot(Cs.Uold, p0, 0), cst},
+                     View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, Cs.fs, s));
+    HC(k::apply_L(tl(Cs.n, count * Cs.nn), p.nu, View<double>{Cs.slot(Cs.U, p0, 0), Cs.fs},
+                  View<double>{Cs.slot(Cs.F, p0, 0), Cs.fs}, s));
+    return k::fas_tau(tl(Cs.n, count), Cs.nn, p.dt, Cs.dQ, View<double>{Cs.slot(Cs.F, p0, 0), cst},
+                      View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, Cs.fs, s);
+}
+
+hipError_t Solver::interpolate(int p0, int p1)
+{
+    PLevel &Fn = L[0], &Cs = L[1];
+    const int count = p1 - p0;
+    const long cst = (long)Cs.nn * Cs.fs, dst = (long)Fn.nn * Cs.fs;
+    double *dc = Cs.DC + (long)p0 * dst;
+    HC(k::interp_coarse(tl(Cs.n, count), Fn.nn, Cs.nn, dLt, View<double>{Cs.slot(Cs.U, p0, 0), cst},
+                        View<double>{Cs.slot(Cs.Uold, p0, 0), cst}, Cs.fs, View<double>{dc, dst}, Cs.fs, s));
+    const long pts = interior_points(Fn.n, dim) * count * Fn.nn;
+    tstart("prolong", Fn.n, 16 + 8.0 / (dim == 3 ? 8 : 2), pts);
+    HC(k::prolong_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs}, s));
+    tstop();
+    tstart("apply_L", Fn.n, 16, pts);
+    HC(k::apply_L(tl(Fn.n, count * Fn.nn), p.nu, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs},
+                  View<double>{Fn.slot(Fn.F, p0, 0), Fn.fs}, s));
+    tstop();
+    return hipSuccess;
+}
+
+hipError_t Solver::spread(const double *u0_dev)
+{
+    PLevel &Fn = L[0];
+    HC(k::unpack(tl(Fn.n, 1), u0_dev, View<double>{ublock, 0}, s));
+    HC(k::copy(tl(Fn.n, P * Fn.nn), View<double>{ublock, 0}, View<double>{Fn.U, Fn.fs}, s));
+    HC(k::apply_L(tl(Fn.n, P * Fn.nn), p.nu, View<double>{ublock, 0}, View<double>{Fn.F, Fn.fs}, s));
+    if (nl > 1) {
+        HC(k::inject(tl(L[1].n, 1), Fn.n, View<double>{ublock, 0}, View<double>{ublock_c, 0}, s));
+        HC(k::apply_L(tl(L[1].n, 1), p.nu, View<double>{ublock_c, 0}, View<double>{fublock_c, 0}, s));
+    }
+    return hipSuccess;
+}
+
+// Predictor (Sec. 2.3.2): round j sweeps every slice p >= j on the coarse
+// level; for j >= 1 those slices first take slice p-1's end value of round
+// j-1 (all copies precede the round's sweeps, so no snapshot is needed).
+hipError_t Solver::predictor()
+{
+    if (nl < 2) return hipSuccess;
+    PLevel &Cs = L[1];
+    const int Mc = Cs.nn - 1;
+    const long cst = (long)Cs.nn * Cs.fs;
+    HC(fas_restrict(0, P));
+    for (int j = 0; j < P; ++j) {
+        if (j >= 1) {
+            const int cnt = P - j;
+            HC(k::copy(tl(Cs.n, cnt), View<double>{Cs.slot(Cs.U, j - 1, Mc), cst}, View<double>{Cs.slot(Cs.U, j, 0), cst}, s));
+            HC(k::copy(tl(Cs.n, cnt), View<double>{Cs.slot(Cs.F, j - 1, Mc), cst}, View<double>{Cs.slot(Cs.F, j, 0), cst}, s));
+        }
+        HC(sweep(1, j, P));
+        if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+    }
+    return interpolate(0, P);
+}
+
+hipError_t Solver::residual(double *per_slice, double *block)
+{
+    PLevel &Fn = L[0];
+    const long fst = (long)Fn.nn * Fn.fs;
+    HC(k::fill_u64(bits, 0, 2 * P, s));
+    tstart("colloc_resid", Fn.n, 8.0 * (2 * Fn.nn + 1), interior_points(Fn.n, dim) * P);
+    HC(k::colloc_resid(tl(Fn.n, P), Fn.nn, p.dt, Fn.dQ, View<double>{Fn.U, fst}, View<double>{Fn.F, fst}, Fn.fs,
+                       ublock, bits, bits + P, s));
+    tstop();
+    HC(hipMemcpyAsync(hbits, bits, sizeof(unsigned long long) * 2 * P, hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    double blk = 0;
+    bool bad = false;
+    for (int q = 0; q < P; ++q) {
+        const double r = bits_to_double(hbits[q]), u0 = bits_to_double(hbits[P + q]);
+        const double v = u0 > 0 ? r / u0 : r;
+        if (!std::isfinite(v)) bad = true;
+        if (per_slice) per_slice[q] = v;
+        if (v > blk || v != v) blk = v;
+    }
+    if (block) *block = blk;
+    last_solve_status = bad ? PFMG_ERR_NAN : 0;
+    return hipSuccess;
+}
+
+hipError_t Solver::iterate(double *block)
+{
+    PLevel &Fn = L[0];
+    const int M = Fn.nn - 1;
+    const long fst = (long)Fn.nn * Fn.fs;
+    if (P > 1) {
+        HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.U, 0, M), fst}, View<double>{Fn.slot(Fn.U, 1, 0), fst}, s));
+        HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.F, 0, M), fst}, View<double>{Fn.slot(Fn.F, 1, 0), fst}, s));
+    }
+    HC(sweep(0, 0, P));
+    if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+    if (nl > 1) {
+        PLevel &Cs = L[1];
+        const int Mc = Cs.nn - 1;
+        HC(fas_restrict(0, P));
+        for (int q = 0; q < P; ++q) {
+            const double *us = q == 0 ? ublock_c : Cs.slot(Cs.U, q - 1, Mc);
+            const double *fsrc = q == 0 ? fublock_c : Cs.slot(Cs.F, q - 1, Mc);
+            HC(k::copy(tl(Cs.n, 1), View<double>{const_cast<double *>(us), 0}, View<double>{Cs.slot(Cs.U, q, 0), 0}, s));
+            HC(k::copy(tl(Cs.n, 1), View<double>{const_cast<double *>(fsrc), 0}, View<double>{Cs.slot(Cs.F, q, 0), 0}, s));
+            HC(sweep(1, q, q + 1));
+            if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+        }
+        HC(interpolate(0, P));
+    }
+    return residual(nullptr, block);
+}
+
+template hipError_t Solver::smooth<double>(int, int, const int *, double, View<double>, View<double>, View<double>, int, bool);
+template hipError_t Solver::smooth<float>(int, int, const int *, double, View<float>, View<float>, View<float>, int, bool);
+
+}  // namespace pfmg

@@ -1,0 +1,260 @@
+"""Python binding of libpfmg (include/pfmg.h): argument marshalling only.
+
+Every numerical step runs in the HIP library; PyTorch provides the device
+workspace and the stream.  The module-level functions carry the C names;
+``Context`` bundles a context with its workspace tensor.
+
+Importing this module without the built library raises ImportError: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfmg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+
+_lib = C.CDLL(LIB_PATH)
+
+# statuses and enums (include/pfmg.h)
+OK, NOT_CONVERGED, STALLED = 0, 1, 2
+ERR_ARG, ERR_WORKSPACE, ERR_HIP, ERR_STATE, ERR_NAN = -1, -2, -3, -4, -5
+NODES_LOBATTO = 0
+SMOOTH_JACOBI, SMOOTH_RBGS = 0, 1
+FP64, MIXED = 0, 1
+GUESS_PREV, GUESS_LEARNED = 0, 1
+SEND_AFTER_ITER = 0
+U_FINE, F_FINE, U_COARSE, F_COARSE, TAU, U_COARSE_OLD = range(6)
+
+
+class PfmgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pfmg status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("nu", C.c_double), ("dt", C.c_double),
+                ("n_slices", C.c_int32), ("nodes_fine", C.c_int32), ("nodes_coarse", C.c_int32),
+                ("node_family", C.c_int32), ("smoother", C.c_int32), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("omega", C.c_double), ("vcycles_per_solve", C.c_int32),
+                ("mg_tol", C.c_double), ("mg_stall", C.c_double), ("mg_max_cycles", C.c_int32),
+                ("precision", C.c_int32), ("guess", C.c_int32), ("fine_send", C.c_int32),
+                ("pfasst_tol", C.c_double), ("pfasst_max_iter", C.c_int32)]
+
+
+_vp, _dp = C.c_void_p, C.POINTER(C.c_double)
+_sigs = {
+    "pfmg_last_error": ([], C.c_char_p),
+    "pfmg_default_params": ([C.POINTER(Params)], C.c_int32),
+    "pfmg_workspace_bytes": ([C.POINTER(Params), C.POINTER(C.c_size_t)], C.c_int32),
+    "pfmg_create": ([C.POINTER(Params), _vp, C.c_size_t, _vp, C.POINTER(_vp)], C.c_int32),
+    "pfmg_destroy": ([_vp], C.c_int32),
+    "pfmg_set_initial": ([_vp, _vp, C.c_int32], C.c_int32),
+    "pfmg_sdc_sweep": ([_vp, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
+    "pfmg_vcycle": ([_vp, C.c_double, _vp, _vp, C.c_int32, _dp, C.POINTER(C.c_int32)], C.c_int32),
+    "pfmg_pfasst_iter": ([_vp, _dp], C.c_int32),
+    "pfmg_residual": ([_vp, C.c_int32, _dp], C.c_int32),
+    "pfmg_run_block": ([_vp, _vp, C.c_int32, C.POINTER(C.c_int32), _dp], C.c_int32),
+    "pfmg_get": ([_vp, C.c_int32, C.c_int32, C.c_int32, _vp, C.c_int32], C.c_int32),
+    "pfmg_set": ([_vp, C.c_int32, C.c_int32, C.c_int32, _vp, C.c_int32], C.c_int32),
+    "pfmg_vcycle_count": ([_vp, C.c_int32, C.POINTER(C.c_int64)], C.c_int32),
+    "pfmg_timing_enable": ([_vp, C.c_char_p, C.c_int32], C.c_int32),
+    "pfmg_timing_read": ([_vp, C.POINTER(C.c_int64), _dp, _dp], C.c_int32),
+}
+for _name, (_args, _res) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_sigs)
+
+
+def _check(st: int) -> int:
+    if st < 0:
+        raise PfmgError(st, pfmg_last_error())
+    return st
+
+
+# ------------------------------------------------------------ C-named calls
+def pfmg_last_error() -> str:
+    return _lib.pfmg_last_error().decode()
+
+
+def pfmg_default_params(**overrides) -> Params:
+    p = Params()
+    _check(_lib.pfmg_default_params(C.byref(p)))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def pfmg_workspace_bytes(p: Params) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.pfmg_workspace_bytes(C.byref(p), C.byref(out)))
+    return out.value
+
+
+def pfmg_create(p: Params, workspace_ptr: int, nbytes: int, stream_ptr: int | None):
+    h = _vp()
+    _check(_lib.pfmg_create(C.byref(p), _vp(workspace_ptr), nbytes, _vp(stream_ptr or 0), C.byref(h)))
+    return h
+
+
+def pfmg_destroy(h) -> None:
+    _check(_lib.pfmg_destroy(h))
+
+
+def pfmg_set_initial(h, u0_ptr: int, on_device: bool) -> int:
+    return _check(_lib.pfmg_set_initial(h, _vp(u0_ptr), int(on_device)))
+
+
+def pfmg_sdc_sweep(h, level: int, p_begin: int, p_end: int) -> int:
+    return _check(_lib.pfmg_sdc_sweep(h, level, p_begin, p_end))
+
+
+def pfmg_vcycle(h, alpha: float, b_ptr: int, u_ptr: int, n_cycles: int):
+    rr = C.c_double(0.0)
+    nc = C.c_int32(0)
+    st = _check(_lib.pfmg_vcycle(h, alpha, _vp(b_ptr), _vp(u_ptr), n_cycles, C.byref(rr), C.byref(nc)))
+    return st, rr.value, nc.value
+
+
+def pfmg_pfasst_iter(h):
+    r = C.c_double(0.0)
+    st = _check(_lib.pfmg_pfasst_iter(h, C.byref(r)))
+    return st, r.value
+
+
+def pfmg_residual(h, level: int, P: int) -> np.ndarray:
+    out = np.zeros(P)
+    _check(_lib.pfmg_residual(h, level, out.ctypes.data_as(_dp)))
+    return out
+
+
+def pfmg_run_block(h, u0_ptr: int, on_device: bool):
+    it = C.c_int32(0)
+    r = C.c_double(0.0)
+    st = _check(_lib.pfmg_run_block(h, _vp(u0_ptr), int(on_device), C.byref(it), C.byref(r)))
+    return st, it.value, r.value
+
+
+def pfmg_get(h, field: int, slice_: int, node: int, dst_ptr: int, on_device: bool) -> None:
+    _check(_lib.pfmg_get(h, field, slice_, node, _vp(dst_ptr), int(on_device)))
+
+
+def pfmg_set(h, field: int, slice_: int, node: int, src_ptr: int, on_device: bool) -> None:
+    _check(_lib.pfmg_set(h, field, slice_, node, _vp(src_ptr), int(on_device)))
+
+
+def pfmg_vcycle_count(h, level: int) -> int:
+    c = C.c_int64(0)
+    _check(_lib.pfmg_vcycle_count(h, level, C.byref(c)))
+    return c.value
+
+
+def pfmg_timing_enable(h, kernel: str | None, enable: bool) -> None:
+    _check(_lib.pfmg_timing_enable(h, kernel.encode() if kernel else None, int(enable)))
+
+
+def pfmg_timing_read(h):
+    n = C.c_int64(0)
+    ms = C.c_double(0.0)
+    by = C.c_double(0.0)
+    _check(_lib.pfmg_timing_read(h, C.byref(n), C.byref(ms), C.byref(by)))
+    return n.value, ms.value, by.value
+
+
+# --------------------------------------------------------------- Context
+class Context:
+    """A pfmg context on one GPU with a torch-owned workspace and stream."""
+
+    def __init__(self, params: Params, device: str = "cuda", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("pfmg needs a ROCm GPU (gfx950); no device is visible")
+        self.torch = torch
+        self.p = params
+        self.device = torch.device(device)
+        self.dim, self.n, self.P = params.dim, params.n, params.n_slices
+        self.nc = (params.n + 1) // 2 - 1
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nbytes = pfmg_workspace_bytes(params)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.h = pfmg_create(params, aligned, self.nbytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            pfmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # arrays are float64 torch tensors on the device (or numpy on the host)
+    def _shape(self, coarse=False):
+        n = self.nc if coarse else self.n
+        return (n,) * self.dim
+
+    def _dev(self, a):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        return a.to(device=self.device, dtype=t.float64).contiguous()
+
+    def set_initial(self, u0):
+        u = self._dev(u0)
+        return pfmg_set_initial(self.h, u.data_ptr(), True)
+
+    def pfasst_iter(self) -> float:
+        return pfmg_pfasst_iter(self.h)[1]
+
+    def residual(self) -> np.ndarray:
+        return pfmg_residual(self.h, 0, self.P)
+
+    def sdc_sweep(self, level: int, p_begin: int = 0, p_end: int | None = None):
+        return pfmg_sdc_sweep(self.h, level, p_begin, self.P if p_end is None else p_end)
+
+    def vcycle(self, alpha: float, b, u, n_cycles: int):
+        """Returns (u_new tensor, status, relres, cycles)."""
+        bb = self._dev(b)
+        uu = self._dev(u).clone()
+        st, rr, nc = pfmg_vcycle(self.h, alpha, bb.data_ptr(), uu.data_ptr(), n_cycles)
+        return uu, st, rr, nc
+
+    def run_block(self, u0):
+        u = self._dev(u0)
+        return pfmg_run_block(self.h, u.data_ptr(), True)
+
+    def get(self, field: int, slice_: int, node: int, host: bool = True):
+        coarse = field >= U_COARSE
+        out = self.torch.empty(self._shape(coarse), dtype=self.torch.float64, device=self.device)
+        pfmg_get(self.h, field, slice_, node, out.data_ptr(), True)
+        return out.cpu().numpy() if host else out
+
+    def set(self, field: int, slice_: int, node: int, value):
+        v = self._dev(value)
+        pfmg_set(self.h, field, slice_, node, v.data_ptr(), True)
+
+    def vcycle_count(self, level: int = 0) -> int:
+        return pfmg_vcycle_count(self.h, level)
+
+    def timing_enable(self, kernel: str | None, enable: bool = True):
+        pfmg_timing_enable(self.h, kernel, enable)
+
+    def timing_read(self):
+        return pfmg_timing_read(self.h)

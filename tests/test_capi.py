@@ -1,0 +1,76 @@
+"""The C-ABI library loads, exports every entry point include/pfmg.h
+declares, and validates parameters on the host (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfmg.h")
+LIB = os.path.join(ROOT, "paper_1407_6486_amd", "libpfmg.so")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfmg_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def pf():
+    if not os.path.exists(LIB):
+        pytest.fail("libpfmg.so is not built (run __graft_entry__.build())")
+    from paper_1407_6486_amd import pfmg
+    return pfmg
+
+
+def test_library_exports_every_declared_symbol(pf):
+    lib = C.CDLL(LIB)
+    names = declared_symbols()
+    assert len(names) >= 16
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(pf.EXPORTED)
+
+
+def test_params_struct_matches_header_layout(pf):
+    # field order in the header
+    src = open(HEADER).read()
+    body = src[src.index("typedef struct pfmg_params {"):src.index("} pfmg_params;")]
+    fields = re.findall(r"\b(?:int32_t|double)\s+(\w+);", body)
+    assert fields == [f for f, _ in pf.Params._fields_]
+
+
+def test_default_params_and_workspace_size(pf):
+    p = pf.pfmg_default_params()
+    assert (p.dim, p.n, p.n_slices, p.nodes_fine, p.nodes_coarse) == (3, 127, 16, 5, 3)
+    nb = pf.pfmg_workspace_bytes(p)
+    # fine U and F stacks alone: 2 * 16 * 5 slots of (128*129*129+1) doubles
+    assert nb > 2 * 16 * 5 * 128 * 129 * 129 * 8
+    assert nb < 8e9
+
+
+@pytest.mark.parametrize("field,value", [("n", 64), ("n", 9), ("dim", 2), ("nu", -1.0), ("dt", 0.0),
+                                         ("n_slices", 0), ("nodes_fine", 1), ("nodes_coarse", 4),
+                                         ("omega", 2.5), ("smoother", 7), ("precision", 3),
+                                         ("vcycles_per_solve", -1), ("fine_send", 1)])
+def test_invalid_parameters_rejected(pf, field, value):
+    p = pf.pfmg_default_params(**{field: value})
+    with pytest.raises(pf.PfmgError) as ei:
+        pf.pfmg_workspace_bytes(p)
+    assert ei.value.status == pf.ERR_ARG
+    assert pf.pfmg_last_error()
+
+
+def test_small_workspace_rejected_without_touching_the_gpu(pf):
+    p = pf.pfmg_default_params(n=15, n_slices=2)
+    with pytest.raises(pf.PfmgError) as ei:
+        pf.pfmg_create(p, 0, 0, None)
+    assert ei.value.status == pf.ERR_WORKSPACE
+
+
+def test_valid_degenerate_sizes_accepted(pf):
+    for n, nc in ((1, 0), (3, 3), (5, 0), (95, 3)):
+        p = pf.pfmg_default_params(n=n, nodes_coarse=nc, n_slices=1)
+        assert pf.pfmg_workspace_bytes(p) > 0

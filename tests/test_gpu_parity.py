@@ -1,0 +1,273 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Bar: FP64 results within 1e-12 relative (max-norm of the difference over
+the max-norm of the oracle's array) of the oracle on the same seeded
+inputs.  Sizes span several 64x4 tiles and ragged tails (n = 31, 63, 95,
+127), the degenerate grids (n = 1, 3, 5: coarsest solves with n in {1, 2}),
+one and several slices, both smoothers, fixed and full solves.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle as O
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible ROCm device"
+    from paper_1407_6486_amd import pfmg
+    return pfmg
+
+
+def make(pf, **kw):
+    return pf.Context(pf.pfmg_default_params(**kw))
+
+
+def smoother_args(pf, sm):
+    return (pf.SMOOTH_JACOBI, O.JACOBI, 2.0 / 3.0) if sm == "jac" else (pf.SMOOTH_RBGS, O.RBGS, 1.0)
+
+
+# ---------------------------------------------------------------- V-cycles
+@pytest.mark.parametrize("dim,n,sm,cycles", [
+    (1, 127, "jac", 1), (1, 95, "jac", 2), (1, 5, "rb", 1), (1, 1, "jac", 1),
+    (3, 1, "rb", 1), (3, 3, "rb", 1), (3, 5, "jac", 2), (3, 15, "rb", 1), (3, 31, "rb", 2),
+    (3, 63, "jac", 1), (3, 95, "rb", 1), (3, 127, "rb", 1), (3, 127, "jac", 1)])
+def test_vcycle_matches_oracle(pf, dim, n, sm, cycles):
+    say(f"vcycle dim={dim} n={n} smoother={sm} cycles={cycles}")
+    psm, osm, om = smoother_args(pf, sm)
+    c = make(pf, dim=dim, n=n, n_slices=1, nodes_coarse=0, smoother=psm, omega=om)
+    alpha = 3.0 / (n + 1) ** 2
+    b = inputs.random_field((n,) * dim, 100 + n)
+    u0 = inputs.random_field((n,) * dim, 200 + n)
+    u_gpu, st, rr, nc = c.vcycle(alpha, b, u0, cycles)
+    assert st == pf.OK and nc == cycles
+    u_or = u0.copy()
+    for _ in range(cycles):
+        u_or = O.vcycle(dim, alpha, b, u_or, osm, om)
+    assert pins.rel_err(u_gpu.cpu().numpy(), u_or) <= TOL
+    r_or = np.max(np.abs(O.resid(dim, alpha, b, u_or))) / np.max(np.abs(b))
+    assert abs(rr - r_or) <= 1e-10 * r_or + 1e-15
+
+
+@pytest.mark.parametrize("dim,n,sm", [(3, 31, "rb"), (1, 63, "jac")])
+def test_full_solve_matches_oracle(pf, dim, n, sm):
+    say(f"full solve dim={dim} n={n} smoother={sm}")
+    psm, osm, om = smoother_args(pf, sm)
+    c = make(pf, dim=dim, n=n, n_slices=1, nodes_coarse=0, smoother=psm, omega=om,
+             mg_tol=1e-12, mg_stall=0.75, mg_max_cycles=50)
+    alpha = 5.0 / (n + 1) ** 2
+    b = inputs.random_field((n,) * dim, 300 + n)
+    u0 = np.zeros_like(b)
+    u_gpu, st, rr, nc = c.vcycle(alpha, b, u0, 0)
+    u_or, nc_or, rr_or = O.mg_solve(dim, alpha, b, u0, O.policy(smoother=osm, omega=om, cycles=0))
+    assert nc == nc_or and st in (pf.OK, pf.STALLED)
+    assert pins.rel_err(u_gpu.cpu().numpy(), u_or) <= TOL
+    assert rr <= 1e-12 or st == pf.STALLED
+
+
+def test_mixed_precision_refinement_converges(pf):
+    """FP32 V-cycles inside FP64 refinement reach the FP64 solution; one
+    refinement step agrees with the oracle's FP32 step to FP32 rounding."""
+    dim, n = 3, 31
+    say("mixed vcycle n=31")
+    c = make(pf, dim=dim, n=n, n_slices=1, nodes_coarse=0, precision=pf.MIXED)
+    alpha = 3.0 / (n + 1) ** 2
+    b = inputs.random_field((n,) * dim, 7)
+    u0 = np.zeros_like(b)
+    u1, _, _, _ = c.vcycle(alpha, b, u0, 1)
+    o1, _, _ = O.mg_solve(dim, alpha, b, u0, O.policy(cycles=1, mixed=1))
+    assert pins.rel_err(u1.cpu().numpy(), o1) <= 2e-6
+    u8, _, rr, _ = c.vcycle(alpha, b, u0, 10)
+    exact, _, _ = O.mg_solve(dim, alpha, b, u0, O.policy(cycles=0, tol=1e-14, stall=0.999, max_cycles=80))
+    assert rr <= 1e-13
+    assert pins.rel_err(u8.cpu().numpy(), exact) <= 1e-12
+
+
+# -------------------------------------------------------------- SDC sweep
+def random_state(c, orc, dim, n, nc, P, nnf, nnc, seed):
+    rng = np.random.default_rng(seed)
+    for p in range(P):
+        for m in range(nnf):
+            for f_or, f_pf in ((O.UF, 0), (O.FF, 1)):
+                v = rng.standard_normal((n,) * dim)
+                c.set(f_pf, p, m, v)
+                orc.set_field(f_or, p, m, v)
+        for m in range(nnc):
+            for f_or, f_pf in ((O.UC, 2), (O.FC, 3), (O.TAU, 4)):
+                v = rng.standard_normal((nc,) * dim) * (1e-3 if f_or == O.TAU else 1.0)
+                c.set(f_pf, p, m, v)
+                orc.set_field(f_or, p, m, v)
+
+
+@pytest.mark.parametrize("dim,n,P,level,sm", [(3, 31, 3, 0, "rb"), (3, 31, 3, 1, "rb"),
+                                              (1, 63, 4, 0, "jac"), (3, 63, 2, 0, "jac")])
+def test_sdc_sweep_matches_oracle(pf, dim, n, P, level, sm):
+    say(f"sweep dim={dim} n={n} P={P} level={level}")
+    psm, osm, om = smoother_args(pf, sm)
+    nu, dt = 1.0, 2e-3
+    c = make(pf, dim=dim, n=n, n_slices=P, smoother=psm, omega=om, nu=nu, dt=dt, vcycles_per_solve=1)
+    orc = O.Pfasst(dim, n, nu, dt, P, 5, 3, O.policy(smoother=osm, omega=om, cycles=1))
+    nc = (n + 1) // 2 - 1
+    random_state(c, orc, dim, n, nc, P, 5, 3, 11)
+    c.sdc_sweep(level, 0, P)
+    for p in range(P):
+        orc.sweep(level, p)
+    fu, ff, nn = (O.UF, O.FF, 5) if level == 0 else (O.UC, O.FC, 3)
+    for p in range(P):
+        for m in range(nn):
+            u_or, f_or = orc.field(fu, p, m), orc.field(ff, p, m)
+            ng = n if level == 0 else nc
+            assert pins.rel_err(c.get(fu, p, m), u_or) <= TOL, (p, m)
+            assert pins.rel_err(c.get(ff, p, m), f_or) <= f_tol(u_or, f_or, ng, dim, nu), (p, m)
+
+
+# ----------------------------------------------------------------- PFASST
+def f_tol(u, f, n, dim, nu=1.0, tol=TOL):
+    """F = nu L_h U is recomputed from U on both sides, so a difference dU
+    of U (bounded by tol |U|) reaches F amplified by |nu L_h|_inf =
+    4 dim nu (n+1)^2: the bar for F is tol * max(1, |nu L_h| |U| / |F|)."""
+    amp = 4 * dim * nu * (n + 1) ** 2 * np.max(np.abs(u)) / max(np.max(np.abs(f)), 1e-300)
+    return tol * max(1.0, amp)
+
+
+def compare_state(c, orc, P, two_levels=True, tol=TOL):
+    for p in range(P):
+        for m in range(5):
+            u_or, f_or = orc.field(O.UF, p, m), orc.field(O.FF, p, m)
+            assert pins.rel_err(c.get(O.UF, p, m), u_or) <= tol, ("U_f", p, m)
+            assert pins.rel_err(c.get(O.FF, p, m), f_or) <= f_tol(u_or, f_or, orc.n, orc.dim, tol=tol), ("F_f", p, m)
+        if two_levels:
+            for m in range(3):
+                assert pins.rel_err(c.get(O.UC, p, m), orc.field(O.UC, p, m)) <= tol, ("U_c", p, m)
+                t_or = orc.field(O.TAU, p, m)
+                if np.max(np.abs(t_or)) > 0:
+                    assert pins.rel_err(c.get(O.TAU, p, m), t_or) <= 1e-10, ("tau", p, m)
+
+
+def test_c1_predictor_and_five_iterations_match_oracle(pf):
+    """1D heat, N=127, P=4, dt=0.01, 5/3 Lobatto, coarse N=63, weighted
+    Jacobi 2/3 V(2,2), one V-cycle per solve, predictor + 5 iterations."""
+    say("C1 parity")
+    n, P, nu, dt = 127, 4, 1.0, 0.01
+    c = make(pf, dim=1, n=n, n_slices=P, nu=nu, dt=dt, smoother=pf.SMOOTH_JACOBI, omega=2 / 3)
+    orc = O.Pfasst(1, n, nu, dt, P, 5, 3, O.policy(smoother=O.JACOBI, omega=2 / 3, cycles=1))
+    u0, _ = inputs.heat_1d(n)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    compare_state(c, orc, P)
+    for k in range(5):
+        r_gpu = c.pfasst_iter()
+        r_or = orc.iterate()
+        assert abs(r_gpu - r_or) <= 1e-10 * r_or, (k, r_gpu, r_or)
+        np.testing.assert_allclose(c.residual(), orc.residual()[1], rtol=1e-10)
+        compare_state(c, orc, P)
+
+
+@pytest.mark.parametrize("n,P,sm,cycles", [(31, 4, "rb", 1), (15, 16, "rb", 2), (63, 2, "jac", 1), (3, 2, "rb", 1),
+                                           (15, 3, "rb", 0)])
+def test_pfasst_3d_matches_oracle(pf, n, P, sm, cycles):
+    say(f"PFASST 3D n={n} P={P} smoother={sm} cycles={cycles}")
+    psm, osm, om = smoother_args(pf, sm)
+    nu, dt = 1.0, 1e-3
+    c = make(pf, dim=3, n=n, n_slices=P, nu=nu, dt=dt, smoother=psm, omega=om, vcycles_per_solve=cycles)
+    orc = O.Pfasst(3, n, nu, dt, P, 5, 3, O.policy(smoother=osm, omega=om, cycles=cycles))
+    u0, _ = inputs.random_fourier(n, 1407) if n >= 7 else (inputs.random_field((n,) * 3, 5), None)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    compare_state(c, orc, P)
+    for k in range(3):
+        r_gpu = c.pfasst_iter()
+        r_or = orc.iterate()
+        assert abs(r_gpu - r_or) <= 1e-9 * r_or, (k, r_gpu, r_or)
+        compare_state(c, orc, P)
+    assert c.vcycle_count(0) == orc.vcycles(0) and c.vcycle_count(1) == orc.vcycles(1)
+
+
+def test_single_level_isdc_matches_oracle(pf):
+    say("ISDC single level")
+    n, P = 31, 1
+    c = make(pf, dim=3, n=n, n_slices=P, nodes_coarse=0, dt=2e-3)
+    orc = O.Pfasst(3, n, 1.0, 2e-3, P, 5, 0, O.policy(cycles=1))
+    u0, _ = inputs.random_fourier(n, 3)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    for _ in range(4):
+        assert abs(c.pfasst_iter() - orc.iterate()) <= 1e-9 * orc.residual()[0]
+    compare_state(c, orc, P, two_levels=False)
+
+
+def test_c1_converges_to_pade_closed_form(pf):
+    say("C1 to convergence")
+    g = pins.golden("lobatto_iiia.json")
+    n, P, nu, dt = 127, 4, 1.0, 0.01
+    c = make(pf, dim=1, n=n, n_slices=P, nu=nu, dt=dt, smoother=pf.SMOOTH_JACOBI, omega=2 / 3,
+             pfasst_tol=1e-12, pfasst_max_iter=300)
+    u0, modes = inputs.heat_1d(n)
+    st, iters, res = c.run_block(u0)
+    assert st == pf.OK and res <= 1e-12
+    for p in range(P):
+        want = sum(a * pins.pade(dt * nu * pins.mu(n, k), g["pade44_num"]) ** (p + 1)
+                   * inputs.sine_mode(n, k, 1) for a, k in zip(modes.amp, modes.k))
+        assert pins.rel_err(c.get(O.UF, p, 4), want) <= 1e-11
+
+
+def test_c2_full_size_first_iteration_matches_oracle(pf):
+    """127^3, 16 slices, dt = 1e-3, RB-GS V(2,2), one V-cycle per solve:
+    predictor + one iteration, compared element by element (the launch
+    configuration the benchmark times)."""
+    say("C2 full size parity: predictor + 1 iteration")
+    n, P = 127, 16
+    c = make(pf, dim=3, n=n, n_slices=P)
+    orc = O.Pfasst(3, n, 1.0, 1e-3, P, 5, 3, O.policy(cycles=1))
+    u0, _ = inputs.random_fourier(n, 1407)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    r_gpu, r_or = c.pfasst_iter(), orc.iterate()
+    assert abs(r_gpu - r_or) <= 1e-9 * r_or
+    for p in (0, 5, 15):
+        for m in (0, 2, 4):
+            assert pins.rel_err(c.get(O.UF, p, m), orc.field(O.UF, p, m)) <= TOL, (p, m)
+        assert pins.rel_err(c.get(O.UC, p, 2), orc.field(O.UC, p, 2)) <= TOL
+
+
+def test_c2_full_size_converges_to_collocation_closed_form(pf):
+    """At convergence every slice's end value is sum_j a_j R44(z_j)^(p+1) phi_j
+    (Lobatto IIIA), a property that holds at any size."""
+    say("C2 full size to 1e-10")
+    g = pins.golden("lobatto_iiia.json")
+    n, P, nu, dt = 127, 16, 1.0, 1e-3
+    c = make(pf, dim=3, n=n, n_slices=P)
+    u0, modes = inputs.random_fourier(n, 1407)
+    st, iters, res = c.run_block(u0)
+    say(f"  iterations {iters} residual {res:.3e}")
+    assert st == pf.OK and res <= 1e-10
+    for p in (0, 7, 15):
+        want = np.zeros((n,) * 3)
+        for a, k in zip(modes.amp, modes.k):
+            want += a * pins.pade(dt * nu * pins.mu(n, k), g["pade44_num"]) ** (p + 1) * inputs.sine_mode(n, k, 3)
+        assert pins.rel_err(c.get(O.UF, p, 4), want) <= 1e-9, p
+
+
+def test_nan_input_reports_err_nan(pf):
+    say("NaN input")
+    n = 15
+    c = make(pf, dim=3, n=n, n_slices=2)
+    u0 = inputs.random_field((n,) * 3, 1)
+    u0[3, 4, 5] = np.nan
+    with pytest.raises(pf.PfmgError) as ei:
+        c.set_initial(u0)
+        c.pfasst_iter()
+    assert ei.value.status == pf.ERR_NAN

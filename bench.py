@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
+    ap.add_argument("--max-iter", type=int, default=400,
+                    help="iteration cap per block (profiling runs cap it to keep traces small)")
     return ap.parse_args()
 
 
@@ -79,7 +81,7 @@ def main():
         dim=3, n=n, n_slices=P, nu=1.0, dt=1e-3, vcycles_per_solve=a.vcycles,
         smoother=pfmg.SMOOTH_RBGS if a.smoother == "rbgs" else pfmg.SMOOTH_JACOBI,
         omega=1.0 if a.smoother == "rbgs" else 2.0 / 3.0,
-        precision=pfmg.FP64 if a.precision == "fp64" else pfmg.MIXED, pfasst_tol=1e-10, pfasst_max_iter=400)
+        precision=pfmg.FP64 if a.precision == "fp64" else pfmg.MIXED, pfasst_tol=1e-10, pfasst_max_iter=a.max_iter)
     ctx = pfmg.Context(p)
     u0_host, _ = inputs.random_fourier(n, 1407)
     u0 = torch.from_numpy(u0_host).to("cuda")

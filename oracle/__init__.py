@@ -37,7 +37,7 @@ class MGPolicy(C.Structure):
 class Params(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int), ("nu", C.c_double), ("dt", C.c_double),
                 ("n_slices", C.c_int), ("nodes_fine", C.c_int), ("nodes_coarse", C.c_int),
-                ("mg", MGPolicy)]
+                ("mg", MGPolicy), ("interp_order", C.c_int)]
 
 
 def lib():
@@ -58,6 +58,7 @@ def lib():
         L.or_smooth.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, _dp, _dp]
         L.or_restrict_fw.argtypes = [C.c_int, C.c_int, _dp, _dp]
         L.or_prolong_add.argtypes = [C.c_int, C.c_int, _dp, _dp]
+        L.or_prolong4_add.argtypes = [C.c_int, C.c_int, _dp, _dp]
         L.or_coarsest.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _dp]
         L.or_vcycle.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double,
                                 C.c_int, C.c_int, _dp, _dp]
@@ -193,9 +194,9 @@ class Pfasst:
     ``nodes_coarse == 0``)."""
 
     def __init__(self, dim, n, nu, dt, n_slices, nodes_fine=5, nodes_coarse=3,
-                 mg: MGPolicy | None = None):
+                 mg: MGPolicy | None = None, interp_order: int = 2):
         self.prm = Params(dim, n, nu, dt, n_slices, nodes_fine, nodes_coarse,
-                          mg if mg is not None else policy())
+                          mg if mg is not None else policy(), interp_order)
         self.dim, self.n, self.P = dim, n, n_slices
         self.nn = [nodes_fine, nodes_coarse]
         self.nc = (n + 1) // 2 - 1
@@ -260,3 +261,8 @@ class Pfasst:
         s = np.zeros(nn); Q = np.zeros((nn, nn))
         lib().or_pfasst_matrices(self._h, level, _p(s), _p(Q))
         return s, Q
+
+
+def prolong4_add(dim, ec, u):
+    ec = np.ascontiguousarray(ec, dtype=np.float64); u = np.array(u, dtype=np.float64, order="C")
+    lib().or_prolong4_add(dim, ec.shape[0], _p(ec), _p(u)); return u

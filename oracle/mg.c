@@ -124,3 +124,51 @@ int or_mg_solve(int dim, int n, double alpha, const or_mg_policy *pol,
     if (relres) *relres = nb > 0 ? r / nb : r;
     return done;
 }
+
+/* Cubic Lagrange weights of fine 1-based index i on coarse 1-based indices;
+ * coarse indices 0 and nc+1 are the zero boundary values. */
+static int cubic_weights(int i, int nc, int *idx, double *w)
+{
+    if ((i & 1) == 0) {
+        idx[0] = i / 2;
+        w[0] = 1.0;
+        return 1;
+    }
+    const int J = (i - 1) / 2;            /* between coarse J and J+1 */
+    int lo = J - 1;
+    if (lo < 0) lo = 0;
+    if (lo + 3 > nc + 1) lo = nc + 1 - 3;
+    const double x = J + 0.5;
+    for (int q = 0; q < 4; ++q) {
+        double v = 1.0;
+        for (int r = 0; r < 4; ++r)
+            if (r != q) v *= (x - (lo + r)) / (double)((lo + q) - (lo + r));
+        idx[q] = lo + q;
+        w[q] = v;
+    }
+    return 4;
+}
+
+void or_prolong4_add(int dim, int nc, const double *ec, double *u)
+{
+    const int n = 2 * (nc + 1) - 1;
+    const int ny = dim >= 2 ? n : 1, nz = dim >= 3 ? n : 1;
+#pragma omp parallel for schedule(static) if (nz > 8)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < n; ++i) {
+                int ix[4], iy[4] = {1}, iz[4] = {1};
+                double wx[4], wy[4] = {1.0}, wz[4] = {1.0};
+                const int cx = cubic_weights(i + 1, nc, ix, wx);
+                const int cy = dim >= 2 ? cubic_weights(j + 1, nc, iy, wy) : 1;
+                const int cz = dim >= 3 ? cubic_weights(k + 1, nc, iz, wz) : 1;
+                double acc = 0.0;
+                for (int c = 0; c < cz; ++c)
+                    for (int b = 0; b < cy; ++b)
+                        for (int a = 0; a < cx; ++a) {
+                            const double v = or_at(ec, nc, ix[a] - 1, dim >= 2 ? iy[b] - 1 : 0, dim >= 3 ? iz[c] - 1 : 0);
+                            acc += wz[c] * wy[b] * wx[a] * v;
+                        }
+                u[(size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k)] += acc;
+            }
+}

@@ -66,6 +66,12 @@ void or_smooth(int dim, int n, double alpha, int smoother, double omega,
 void or_restrict_fw(int dim, int n, const double *r, double *bc);
 /* u += P ec, d-linear interpolation with zero boundary values. */
 void or_prolong_add(int dim, int nc, const double *ec, double *u);
+/* u += P4 ec: tensor-product cubic (fourth-order) Lagrange interpolation.
+ * A fine point on a coarse point takes that value; a fine point between
+ * coarse points J and J+1 interpolates the cubic through J-1..J+2, shifted
+ * inwards next to the boundary (the boundary value 0 is one of the four
+ * points).  Needs nc >= 3. */
+void or_prolong4_add(int dim, int nc, const double *ec, double *u);
 /* Exact solve of (I - alpha L_h) u = b for n in {1,2}. */
 void or_coarsest(int dim, int n, double alpha, const double *b, double *u);
 /* One V(nu1,nu2)-cycle on (I - alpha L_h) u = b, in place on u. */
@@ -111,6 +117,7 @@ typedef struct or_params {
     int nodes_fine;          /* M_f + 1 */
     int nodes_coarse;        /* M_c + 1, 0 = single level (ISDC) */
     or_mg_policy mg;         /* policy for every node solve (both levels) */
+    int interp_order;        /* PFASST spatial interpolation: 2 d-linear, 4 cubic */
 } or_params;
 
 typedef struct or_pfasst or_pfasst;

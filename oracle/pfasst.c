@@ -235,7 +235,8 @@ void or_interpolate(or_pfasst *c, int p)
             dc[x] = acc;
         }
         double *uf = fld(c, c->U[0], 0, p, m);
-        or_prolong_add(dim, nc, dc, uf);
+        if (c->p.interp_order == 4 && nc >= 3) or_prolong4_add(dim, nc, dc, uf);
+        else or_prolong_add(dim, nc, dc, uf);
         feval(c, 0, uf, fld(c, c->F[0], 0, p, m));
     }
     free(dc);

@@ -101,7 +101,7 @@ pfmg_status pfmg_create(const pfmg_params *p, void *workspace, size_t bytes, voi
     sv.s = (hipStream_t)hip_stream;
     if (!sv.init_host(why)) { delete c; return fail(PFMG_ERR_ARG, why); }
     pfmg::Solver::carve(*p, (char *)workspace, &sv);
-    hipError_t e = hipHostMalloc((void **)&sv.hbits, sizeof(unsigned long long) * 4 * sv.P, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&sv.hbits, sizeof(unsigned long long) * 4 * sv.P * pfmg::k::RSLOTS, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv.hmask, sizeof(int) * sv.P, hipHostMallocDefault);
     // Zero the whole workspace once: halos carry the Dirichlet data.
     if (e == hipSuccess) e = hipMemsetAsync(workspace, 0, need, sv.s);
@@ -121,6 +121,7 @@ pfmg_status pfmg_destroy(pfmg_ctx *ctx)
     if (!ctx) return PFMG_OK;
     pfmg::Solver &sv = ctx->sv;
     (void)hipStreamSynchronize(sv.s);
+    sv.release_graphs();
     for (hipEvent_t ev : sv.timer.ev) (void)hipEventDestroy(ev);
     if (sv.hbits) (void)hipHostFree(sv.hbits);
     if (sv.hmask) (void)hipHostFree(sv.hmask);
@@ -138,8 +139,7 @@ pfmg_status pfmg_set_initial(pfmg_ctx *ctx, const double *u0, int32_t on_device)
         HIPCALL(hipMemcpyAsync(sv.vb, u0, sizeof(double) * pts, hipMemcpyHostToDevice, sv.s), "copy u0");
         src = sv.vb;
     }
-    HIPCALL(sv.spread(src), "spread");
-    HIPCALL(sv.predictor(), "predictor");
+    HIPCALL(sv.spread(src), "spread and predictor");
     HIPCALL(hipStreamSynchronize(sv.s), "set_initial");
     sv.has_state = true;
     return solve_status(sv);

@@ -28,10 +28,29 @@ hipError_t jacobi_zero(const Tiling &t, double alpha, double omega, View<T> b, V
 template <typename T>
 hipError_t rbgs(const Tiling &t, double alpha, double omega, int colour, View<T> b, View<T> u,
                 hipStream_t s);
+// Launch shape of the fused sweep: rows per workgroup, planes per z-chunk.
+struct FusedShape {
+    int ty, zchunk;
+    long blocks;
+    size_t lds;
+};
+FusedShape rbgs_fused_shape(int n, int count, size_t elem);
+// One whole red-black sweep out of place (3D, 31 <= n <= 255): uout =
+// RBGS(uin); zero_in treats uin as 0 (first sweep of a coarse correction).
+template <typename T>
+hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in, View<T> b, View<T> uin,
+                      View<T> uout, hipStream_t s);
 // Red pass from u = 0: red points omega b / diag(H), black points 0.
 template <typename T>
 hipError_t rbgs_zero_red(const Tiling &t, double alpha, double omega, View<T> b, View<T> u,
                          hipStream_t s);
+// Whole V(nu1, nu2)-cycle from grid t.n down in LDS, one workgroup per field
+// (small grids).  zero_init starts from u = 0 instead of reading u.
+constexpr size_t BOTTOM_LDS_MAX = 64 * 1024;
+size_t vcycle_bottom_lds(int n0, int dim, int smoother, size_t elem);
+template <typename T>
+hipError_t vcycle_bottom(const Tiling &t, double alpha, int smoother, double omega, int nu1, int nu2, bool zero_init,
+                         View<T> b, View<T> u, hipStream_t s);
 // Full weighting of a fine array (t.n = fine n) onto the coarse grid.
 template <typename T>
 hipError_t restrict_fw(const Tiling &t, View<T> r, View<T> bc, hipStream_t s);
@@ -81,7 +100,9 @@ hipError_t fas_tau(const Tiling &t, int nnc, double dt, const double *Qc, View<d
 hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, View<double> Uc,
                          View<double> Uold, long c_node, View<double> DC, long dc_node,
                          hipStream_t s);
-// Collocation residual (eq. resid) per slice; bits preset to 0.
+// Collocation residual (eq. resid) per slice; each slice's maxima go to
+// RSLOTS partial slots (res_bits[p * RSLOTS + w]); bits preset to 0.
+constexpr int RSLOTS = 64;
 hipError_t colloc_resid(const Tiling &t, int nn, double dt, const double *Q, View<double> U,
                         View<double> F, long node, const double *ublock,
                         unsigned long long *res_bits, unsigned long long *u0_bits, hipStream_t s);

@@ -11,6 +11,8 @@
 // instances serve the plain and the mixed-precision forms.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace pfmg {
@@ -221,6 +223,161 @@ __global__ void coarsest_kernel(int n, int count, const int *mask, T ah, View<T>
     }
 }
 
+// ------------------------------------------- column-blocked 3D variants
+// Same arithmetic as the point kernels above; a thread owns KZ planes of one
+// (i, j) column (tile_col) and issues every load before its stores.
+constexpr int KZ = 4;
+
+// col[q] = u at plane k0-1+q, q = 0 .. nk+1 (planes 0 and n+1 are halo zeros)
+template <typename T>
+__device__ inline void load_col(const T *__restrict__ u, long o, long sz, int nk, T (&col)[KZ + 2])
+{
+#pragma unroll
+    for (int q = 0; q < KZ + 2; ++q) col[q] = q <= nk + 1 ? u[o + (long)(q - 1) * sz] : (T)0;
+}
+
+template <typename T>
+__device__ inline void load_xy(const T *__restrict__ u, long o, long sy, long sz, int nk, T (&xs)[KZ], T (&ys)[KZ])
+{
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        if (q < nk) {
+            const long c = o + (long)q * sz;
+            xs[q] = u[c - 1] + u[c + 1];
+            ys[q] = u[c - sy] + u[c + sy];
+        }
+    }
+}
+
+template <typename T>
+__device__ inline T d2_of(const T (&col)[KZ + 2], const T (&xs)[KZ], const T (&ys)[KZ], int q)
+{
+    T s = xs[q];
+    s += ys[q] + (col[q] + col[q + 2]);
+    return s - (T)6 * col[q + 1];
+}
+
+template <typename T, typename TO>
+__global__ __launch_bounds__(BLOCK) void resid_kz_kernel(Tiling t, T ah, View<T> b, View<T> u, View<TO> r)
+{
+    int item, i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
+    const long sy = row_stride(t.n), sz = plane_stride(t.n);
+    const T *__restrict__ uu = fp(u, item);
+    const T *__restrict__ bb = fp(b, item);
+    TO *__restrict__ rr = fp(r, item);
+    T col[KZ + 2], xs[KZ], ys[KZ], bv[KZ];
+    load_col(uu, o, sz, nk, col);
+    load_xy(uu, o, sy, sz, nk, xs, ys);
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) if (q < nk) bv[q] = bb[o + (long)q * sz];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q)
+        if (q < nk) rr[o + (long)q * sz] = (TO)(bv[q] - (col[q + 1] - ah * d2_of(col, xs, ys, q)));
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void jacobi_kz_kernel(Tiling t, T ah, T winv, View<T> b, View<T> u, View<T> out)
+{
+    int item, i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
+    const long sy = row_stride(t.n), sz = plane_stride(t.n);
+    const T *__restrict__ uu = fp(u, item);
+    const T *__restrict__ bb = fp(b, item);
+    T *__restrict__ oo = fp(out, item);
+    T col[KZ + 2], xs[KZ], ys[KZ], bv[KZ];
+    load_col(uu, o, sz, nk, col);
+    load_xy(uu, o, sy, sz, nk, xs, ys);
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) if (q < nk) bv[q] = bb[o + (long)q * sz];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        if (q < nk) {
+            const T res = bv[q] - (col[q + 1] - ah * d2_of(col, xs, ys, q));
+            oo[o + (long)q * sz] = col[q + 1] + winv * res;
+        }
+    }
+}
+
+// u += P ec: the d-linear value at fine (i, j, k) is the z-average of the
+// bilinear values of coarse planes k>>1 and (k+1)>>1 (one plane when k even).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void prolong_kz_kernel(Tiling t, View<T> ec, View<T> u)
+{
+    int item, i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
+    const int nc = coarser(t.n);
+    const T *__restrict__ e = fp(ec, item);
+    T *__restrict__ uu = fp(u, item);
+    const long csy = row_stride(nc), csz = plane_stride(nc), sz = plane_stride(t.n);
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1;
+    const int c0 = k0 >> 1;                       // first coarse plane touched
+    constexpr int NCP = KZ / 2 + 2;               // coarse planes touched by KZ fine planes
+    T pv[NCP], uv[KZ];
+#pragma unroll
+    for (int cq = 0; cq < NCP; ++cq) {
+        const int kk = c0 + cq;
+        T v = (T)0;
+        if (kk <= nc + 1) {
+            const long ob = (long)kk * csz;
+            auto rowv = [&](int jj) -> T {
+                const long orow = ob + (long)jj * csy;
+                return (i & 1) ? (T)0.5 * (e[orow + i0] + e[orow + i1]) : e[orow + i0];
+            };
+            v = (j & 1) ? (T)0.5 * (rowv(j0) + rowv(j1)) : rowv(j0);
+        }
+        pv[cq] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) if (q < nk) uv[q] = uu[o + (long)q * sz];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        if (q < nk) {
+            const int k = k0 + q;
+            const int a = (k >> 1) - c0, bq = ((k + 1) >> 1) - c0;
+            const T v = (k & 1) ? (T)0.5 * (pv[a] + pv[bq]) : pv[a];
+            uu[o + (long)q * sz] = uv[q] + v;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void copy_kz_kernel(Tiling t, View<T> src, View<T> dst)
+{
+    int item, i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
+    const long sz = plane_stride(t.n);
+    const T *__restrict__ a = fp(src, item);
+    T *__restrict__ d = fp(dst, item);
+    T v[KZ];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) if (q < nk) v[q] = a[o + (long)q * sz];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) if (q < nk) d[o + (long)q * sz] = v[q];
+}
+
+__global__ __launch_bounds__(BLOCK) void add_f32_kz_kernel(Tiling t, View<float> e, View<double> u)
+{
+    int item, i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
+    const float *__restrict__ ee = fp(e, item);
+    double *__restrict__ uu = fp(u, item);
+    const long sz = plane_stride(t.n), ez = plane_stride(t.n);
+    double uv[KZ];
+    float ev[KZ];
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        if (q < nk) {
+            uv[q] = uu[o + (long)q * sz];
+            ev[q] = ee[o + (long)q * ez];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) if (q < nk) uu[o + (long)q * sz] = uv[q] + (double)ev[q];
+}
+
+inline dim3 col_grid(const Tiling &t) { return dim3((unsigned)(col_tiles_per_field(t.n, KZ) * t.count)); }
+
 // ------------------------------------------------------------------- misc
 template <int DIM, typename T>
 __global__ __launch_bounds__(BLOCK) void zero_kernel(Tiling t, View<T> u)
@@ -331,7 +488,7 @@ hipError_t resid(const Tiling &t, double alpha, View<T> b, View<T> u, View<T> r,
 {
     const T ah = (T)ah_of(alpha, t.n);
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) resid_kernel<3, T, T><<<grid_of(t), BLOCK, 0, s>>>(t, ah, b, u, r);
+    if (t.dim == 3) resid_kz_kernel<T, T><<<col_grid(t), BLOCK, 0, s>>>(t, ah, b, u, r);
     else resid_kernel<1, T, T><<<grid_of(t), BLOCK, 0, s>>>(t, ah, b, u, r);
     return hipGetLastError();
 }
@@ -341,7 +498,7 @@ hipError_t resid_round(const Tiling &t, double alpha, View<double> b, View<doubl
 {
     const double ah = ah_of(alpha, t.n);
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) resid_kernel<3, double, float><<<grid_of(t), BLOCK, 0, s>>>(t, ah, b, u, r32);
+    if (t.dim == 3) resid_kz_kernel<double, float><<<col_grid(t), BLOCK, 0, s>>>(t, ah, b, u, r32);
     else resid_kernel<1, double, float><<<grid_of(t), BLOCK, 0, s>>>(t, ah, b, u, r32);
     return hipGetLastError();
 }
@@ -352,7 +509,7 @@ hipError_t jacobi(const Tiling &t, double alpha, double omega, View<T> b, View<T
 {
     const T ah = (T)ah_of(alpha, t.n), wi = (T)winv_of(alpha, omega, t.n, t.dim);
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) jacobi_kernel<3, T><<<grid_of(t), BLOCK, 0, s>>>(t, ah, wi, b, u, out);
+    if (t.dim == 3) jacobi_kz_kernel<T><<<col_grid(t), BLOCK, 0, s>>>(t, ah, wi, b, u, out);
     else jacobi_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, ah, wi, b, u, out);
     return hipGetLastError();
 }
@@ -414,7 +571,7 @@ template <typename T>
 hipError_t prolong_add(const Tiling &t, View<T> ec, View<T> u, hipStream_t s)
 {
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) prolong_kernel<3, T><<<grid_of(t), BLOCK, 0, s>>>(t, ec, u);
+    if (t.dim == 3) prolong_kz_kernel<T><<<col_grid(t), BLOCK, 0, s>>>(t, ec, u);
     else prolong_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, ec, u);
     return hipGetLastError();
 }
@@ -443,13 +600,17 @@ template <typename T>
 hipError_t copy(const Tiling &t, View<T> src, View<T> dst, hipStream_t s)
 {
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) copy_kernel<3, T><<<grid_of(t), BLOCK, 0, s>>>(t, src, dst);
+    if (t.dim == 3) copy_kz_kernel<T><<<col_grid(t), BLOCK, 0, s>>>(t, src, dst);
     else copy_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, src, dst);
     return hipGetLastError();
 }
 
 hipError_t add_f32(const Tiling &t, View<float> e, View<double> u, hipStream_t s)
 {
+    if (t.dim == 3 && grid_blocks(t) > 0) {
+        add_f32_kz_kernel<<<col_grid(t), BLOCK, 0, s>>>(t, e, u);
+        return hipGetLastError();
+    }
     PFMG_DISPATCH(t, add_f32_kernel, t, e, u);
 }
 

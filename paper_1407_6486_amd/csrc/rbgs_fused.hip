@@ -1,0 +1,214 @@
+// One whole red-black Gauss-Seidel sweep in one pass over HBM (3D).
+//
+// uout = RBGS(uin, b): red points (1-based i+j+k even) first, each from the
+// old black neighbours, then black points from the new red ones (the
+// smoother of Sec. 4.2.1; weight omega, omega = 1 is plain Gauss-Seidel).
+// Out of place, so uin and b are read once and uout written once:
+// 24 bytes per point in FP64 instead of 2 x 24 for two in-place colour
+// passes whose interleaved colours waste half of every cache line.
+//
+// A workgroup owns full x-rows (the x boundary is the only x halo), `ty`
+// output rows and a chunk of z planes, and marches upwards in z.  At step k
+//   A: red update of plane k on rows j0-1 .. j0+ty (one halo row each side
+//      is recomputed, so workgroups never exchange data);
+//   B: black update of plane k-1 on rows j0 .. j0+ty-1, written out with the
+//      red values of that plane.
+// Each thread owns the same rows in both phases and keeps its column's
+// values of the neighbouring planes in registers: uin at k-1, k, k+1, the
+// red-updated field at k-2, k-1, k and b at k-1, k.  Only the current plane
+// of uin and of the red-updated field pass through LDS, for the x and y
+// neighbours.  Every global load of a step is issued before its barrier.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+
+#include "kernels.h"
+
+namespace pfmg {
+namespace {
+
+constexpr int QMAX = 6;   // owned rows per thread
+
+template <typename T>
+__device__ inline T *fp(View<T> v, int item) { return v.p + (long)item * v.stride; }
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(int n, int count, const int *mask, int ty, int zchunk,
+                                                           int zero_in, T ah, T winv, View<T> b, View<T> uin,
+                                                           View<T> uout)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int rowlanes = (n + 63) & ~63;
+    const int RL = rowlanes + 2;
+    const int rows = ty + 2;                 // rows of the red update (owned rows)
+    T *up = reinterpret_cast<T *>(smem_raw);             // uin plane k: rows j0-2 .. j0+ty+1
+    T *wp = up + (size_t)(ty + 4) * RL;                  // 2 planes of the red-updated field
+    const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int ytiles = (n + ty - 1) / ty, zch = (n + zchunk - 1) / zchunk;
+    const int item = (int)(bid / (unsigned)(ytiles * zch));
+    const int rem = (int)(bid - (unsigned)item * (unsigned)(ytiles * zch));
+    const int jt = rem / zch, zc = rem - jt * zch;
+    if (item >= count || (mask && !mask[item])) return;
+    const int j0 = jt * ty + 1, k0 = zc * zchunk + 1;
+    const int k1 = min(k0 + zchunk, n + 1);
+    const int rpp = BLOCK / rowlanes;
+    const int i = (int)(threadIdx.x % rowlanes) + 1;
+    const int rsub = (int)(threadIdx.x / rowlanes);
+    const long sy = row_stride(n), sz = plane_stride(n);
+    const T *__restrict__ U = fp(uin, item);
+    const T *__restrict__ Bv = fp(b, item);
+    T *__restrict__ O = fp(uout, item);
+    const bool xin = i <= n;
+
+    // x index 0 is the boundary: zero once in every LDS row
+    for (int r = threadIdx.x; r < (ty + 4) + 2 * rows; r += BLOCK) up[(size_t)r * RL] = (T)0;
+
+    auto inside = [&](int j, int k) { return xin && j >= 1 && j <= n && k >= 1 && k <= n; };
+    auto ld = [&](const T *__restrict__ a, int j, int k) -> T {
+        return inside(j, k) ? a[(long)i + (long)j * sy + (long)k * sz] : (T)0;
+    };
+
+    T um[QMAX], uc[QMAX], wm2[QMAX], wm1[QMAX], bm1[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+        const int r = rsub + q * rpp;
+        const int j = j0 - 1 + r;
+        const bool own = r < rows;
+        um[q] = (own && !zero_in) ? ld(U, j, k0 - 2) : (T)0;
+        uc[q] = (own && !zero_in) ? ld(U, j, k0 - 1) : (T)0;
+        wm2[q] = wm1[q] = bm1[q] = (T)0;
+    }
+
+    for (int k = k0 - 1; k <= k1; ++k) {
+        // ---- loads of this step: uin plane k+1, b plane k, extra uin rows of plane k
+        T un[QMAX], bn[QMAX];
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+            const int r = rsub + q * rpp;
+            const int j = j0 - 1 + r;
+            const bool own = r < rows;
+            un[q] = (own && !zero_in) ? ld(U, j, k + 1) : (T)0;
+            bn[q] = own ? ld(Bv, j, k) : (T)0;
+        }
+        T ex[2] = {(T)0, (T)0};
+        if (!zero_in)
+            for (int e = rsub, q = 0; e < 2; e += rpp, ++q) ex[q] = ld(U, e == 0 ? j0 - 2 : j0 + ty + 1, k);
+        // ---- uin plane k -> LDS (rows e = 0 .. ty+3 <-> j = j0-2+e)
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+            const int r = rsub + q * rpp;
+            if (r < rows) up[(size_t)(r + 1) * RL + i] = uc[q];
+        }
+        for (int e = rsub, q = 0; e < 2; e += rpp, ++q) up[(size_t)(e == 0 ? 0 : ty + 3) * RL + i] = ex[q];
+        __syncthreads();
+        // ---- phase A: red update of plane k on the owned rows
+        T *wk = wp + (size_t)(k & 1) * rows * RL;
+        T wn[QMAX];
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+            const int r = rsub + q * rpp;
+            const int j = j0 - 1 + r;
+            T val = (T)0;
+            if (r < rows && inside(j, k)) {
+                const bool red = ((i + j + k) & 1) == 0;
+                if (zero_in) {
+                    val = red ? winv * bn[q] : (T)0;
+                } else if (red) {
+                    const T *row = up + (size_t)(r + 1) * RL;
+                    T s = row[i - 1] + row[i + 1];
+                    s += (up[(size_t)r * RL + i] + up[(size_t)(r + 2) * RL + i]) + (um[q] + un[q]);
+                    s -= (T)6 * uc[q];
+                    val = uc[q] + winv * (bn[q] - (uc[q] - ah * s));
+                } else {
+                    val = uc[q];
+                }
+            }
+            wn[q] = val;
+            if (r < rows) wk[(size_t)r * RL + i] = val;
+        }
+        __syncthreads();
+        // ---- phase B: black update of plane k-1 on rows 1..ty
+        const int kb = k - 1;
+        if (kb >= k0 && kb < k1) {
+            const T *wb = wp + (size_t)(kb & 1) * rows * RL;
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) {
+                const int r = rsub + q * rpp;
+                const int j = j0 - 1 + r;
+                if (r >= 1 && r <= ty && j <= n && xin) {
+                    const T wc = wm1[q];
+                    T out = wc;
+                    if (((i + j + kb) & 1) == 1) {
+                        const T *row = wb + (size_t)r * RL;
+                        T s = row[i - 1] + row[i + 1];
+                        s += (wb[(size_t)(r - 1) * RL + i] + wb[(size_t)(r + 1) * RL + i]) + (wm2[q] + wn[q]);
+                        s -= (T)6 * wc;
+                        out = wc + winv * (bm1[q] - (wc - ah * s));
+                    }
+                    O[(long)i + (long)j * sy + (long)kb * sz] = out;
+                }
+            }
+        }
+        // ---- rotate the register windows
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+            um[q] = uc[q];
+            uc[q] = un[q];
+            wm2[q] = wm1[q];
+            wm1[q] = wn[q];
+            bm1[q] = bn[q];
+        }
+    }
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+}  // namespace
+
+namespace k {
+
+FusedShape rbgs_fused_shape(int n, int count, size_t elem)
+{
+    const int rowlanes = (n + 63) & ~63;
+    const int rpp = BLOCK / rowlanes;
+    const int RL = rowlanes + 2;
+    FusedShape f;
+    f.ty = env_int("PFMG_RB_TY", rowlanes >= 256 ? 4 : 8);
+    while (f.ty > 1 && (f.ty + 2 + rpp - 1) / rpp > QMAX) f.ty /= 2;
+    const int ytiles = (n + f.ty - 1) / f.ty;
+    const long per_z = (long)count * ytiles;
+    const int target = env_int("PFMG_RB_BLOCKS", 2048);
+    int zch = (int)std::min<long>(std::max<long>(1, (target + per_z - 1) / per_z), std::max(1, n / 4));
+    f.zchunk = env_int("PFMG_RB_ZCH", (n + zch - 1) / zch);
+    zch = (n + f.zchunk - 1) / f.zchunk;
+    f.blocks = per_z * zch;
+    f.lds = (size_t)((f.ty + 4) + 2 * (f.ty + 2)) * RL * elem;
+    return f;
+}
+
+template <typename T>
+hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in, View<T> b, View<T> uin,
+                      View<T> uout, hipStream_t s)
+{
+    if (t.dim != 3 || t.n < 31 || t.n > 255) return hipErrorInvalidValue;
+    if (t.count == 0) return hipSuccess;
+    const double ah = alpha * (double)(t.n + 1) * (double)(t.n + 1);
+    const T ahT = (T)ah, wi = (T)(omega / (1.0 + 6.0 * ah));
+    const FusedShape f = rbgs_fused_shape(t.n, t.count, sizeof(T));
+    rbgs_fused_kernel<T><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t.n, t.count, t.mask, f.ty, f.zchunk,
+                                                                   zero_in ? 1 : 0, ahT, wi, b, uin, uout);
+    return hipGetLastError();
+}
+
+template hipError_t rbgs_fused<double>(const Tiling &, double, double, bool, View<double>, View<double>,
+                                       View<double>, hipStream_t);
+template hipError_t rbgs_fused<float>(const Tiling &, double, double, bool, View<float>, View<float>, View<float>,
+                                      hipStream_t);
+
+}  // namespace k
+}  // namespace pfmg

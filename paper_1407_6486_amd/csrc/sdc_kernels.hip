@@ -14,6 +14,8 @@
 //  colloc_resid  eq. resid, max-norm per slice.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "kernels.h"
 
 namespace pfmg {
@@ -34,10 +36,45 @@ __global__ __launch_bounds__(BLOCK) void apply_L_kernel(Tiling t, double c, View
     fp(F, item)[o] = c * (ih2 * d2sum<DIM>(uu, o, row_stride(t.n), plane_stride(t.n)));
 }
 
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void sdc_integrals_kernel(Tiling t, int nn, double dt, const double *__restrict__ S,
+// Column-blocked 3D variant (KZ planes per thread, loads before stores).
+constexpr int KZ = 4;
+__global__ __launch_bounds__(BLOCK) void apply_L_kz_kernel(Tiling t, double c, View<double> u, View<double> F)
+{
+    int item, i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
+    const long sy = row_stride(t.n), sz = plane_stride(t.n);
+    const double *__restrict__ uu = fp(u, item);
+    double *__restrict__ ff = fp(F, item);
+    const double ih2 = (double)(t.n + 1) * (double)(t.n + 1);
+    double col[KZ + 2], xs[KZ], ys[KZ];
+#pragma unroll
+    for (int q = 0; q < KZ + 2; ++q) col[q] = q <= nk + 1 ? uu[o + (long)(q - 1) * sz] : 0.0;
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        if (q < nk) {
+            const long cc = o + (long)q * sz;
+            xs[q] = uu[cc - 1] + uu[cc + 1];
+            ys[q] = uu[cc - sy] + uu[cc + sy];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        if (q < nk) {
+            double s = xs[q];
+            s += ys[q] + (col[q] + col[q + 2]);
+            s -= 6.0 * col[q + 1];
+            ff[o + (long)q * sz] = c * (ih2 * s);
+        }
+    }
+}
+
+// NN > 0 fixes the node count at compile time (node values stay in
+// registers); NN == 0 is the generic path for any count up to MAXN.
+template <int DIM, int NN>
+__global__ __launch_bounds__(BLOCK) void sdc_integrals_kernel(Tiling t, int nn_rt, double dt, const double *__restrict__ S,
                                                               View<double> F, long f_node, View<double> I, long i_node)
 {
+    const int nn = NN > 0 ? NN : nn_rt;
     int item, i, j, k; long o;
     if (!tile_point<DIM>(t, item, i, j, k, o)) return;
     const double *f = fp(F, item) + o;
@@ -67,12 +104,13 @@ struct IntMap {
 };
 
 // t.n = coarse n.
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nf, int nnf, int nnc, IntMap cmap, double dt,
+template <int DIM, int NNF, int NNC>
+__global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nf, int nnf_rt, int nnc_rt, IntMap cmap, double dt,
                                                            const double *__restrict__ Qf, View<double> Uf,
                                                            View<double> Ff, long f_node, View<double> Uc,
                                                            View<double> Uold, View<double> Tau, long c_node)
 {
+    const int nnf = NNF > 0 ? NNF : nnf_rt, nnc = NNC > 0 ? NNC : nnc_rt;
     int item, I, J, K; long o;
     if (!tile_point<DIM>(t, item, I, J, K, o)) return;
     const long fo = DIM == 3 ? 2L * I + 2L * J * row_stride(nf) + 2L * K * plane_stride(nf) : 2L * I;
@@ -92,10 +130,11 @@ __global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nf, int
     }
 }
 
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void fas_tau_kernel(Tiling t, int nnc, double dt, const double *__restrict__ Qc,
+template <int DIM, int NNC>
+__global__ __launch_bounds__(BLOCK) void fas_tau_kernel(Tiling t, int nnc_rt, double dt, const double *__restrict__ Qc,
                                                         View<double> Fc, View<double> Tau, long c_node)
 {
+    const int nnc = NNC > 0 ? NNC : nnc_rt;
     int item, I, J, K; long o;
     if (!tile_point<DIM>(t, item, I, J, K, o)) return;
     const double *fc = fp(Fc, item) + o;
@@ -109,11 +148,12 @@ __global__ __launch_bounds__(BLOCK) void fas_tau_kernel(Tiling t, int nnc, doubl
     }
 }
 
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void interp_coarse_kernel(Tiling t, int nnf, int nnc, const double *__restrict__ Lt,
+template <int DIM, int NNF, int NNC>
+__global__ __launch_bounds__(BLOCK) void interp_coarse_kernel(Tiling t, int nnf_rt, int nnc_rt, const double *__restrict__ Lt,
                                                               View<double> Uc, View<double> Uold, long c_node,
                                                               View<double> DC, long dc_node)
 {
+    const int nnf = NNF > 0 ? NNF : nnf_rt, nnc = NNC > 0 ? NNC : nnc_rt;
     int item, I, J, K; long o;
     if (!tile_point<DIM>(t, item, I, J, K, o)) return;
     const double *uc = fp(Uc, item) + o, *uo = fp(Uold, item) + o;
@@ -142,13 +182,14 @@ __device__ inline unsigned long long wave_max(unsigned long long v)
 }
 
 // item = slice p; U0 = ublock for p = 0, else U[p-1][nn-1].
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn, double dt, const double *__restrict__ Q,
+template <int DIM, int NN>
+__global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt, double dt, const double *__restrict__ Q,
                                                              View<double> U, View<double> F, long node,
                                                              const double *__restrict__ ublock,
                                                              unsigned long long *res_bits,
                                                              unsigned long long *u0_bits)
 {
+    const int nn = NN > 0 ? NN : nn_rt;
     int item, i, j, k; long o;
     const bool ok = tile_point<DIM>(t, item, i, j, k, o);
     unsigned long long rm = 0, um = 0;
@@ -180,8 +221,9 @@ __global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn, d
             a = part[0][q] > a ? part[0][q] : a;
             b = part[1][q] > b ? part[1][q] : b;
         }
-        if (a) atomicMax(res_bits + blk_item, a);
-        if (b) atomicMax(u0_bits + blk_item, b);
+        const int slot = (int)(bid % (unsigned)k::RSLOTS);
+        if (a) atomicMax(res_bits + (long)blk_item * k::RSLOTS + slot, a);
+        if (b) atomicMax(u0_bits + (long)blk_item * k::RSLOTS + slot, b);
     }
 }
 
@@ -224,12 +266,32 @@ inline dim3 grid_of(const Tiling &t) { return dim3((unsigned)grid_blocks(t)); }
         return hipGetLastError();                                                           \
     } while (0)
 
+#define PFMG_DISPATCH_N(t, KER, NN, ...)                                                    \
+    do {                                                                                    \
+        if (grid_blocks(t) == 0) return hipSuccess;                                         \
+        if ((t).dim == 3) KER<3, NN><<<grid_of(t), BLOCK, 0, s>>>(__VA_ARGS__);             \
+        else KER<1, NN><<<grid_of(t), BLOCK, 0, s>>>(__VA_ARGS__);                          \
+        return hipGetLastError();                                                           \
+    } while (0)
+
+#define PFMG_DISPATCH_N2(t, KER, NA, NB, ...)                                               \
+    do {                                                                                    \
+        if (grid_blocks(t) == 0) return hipSuccess;                                         \
+        if ((t).dim == 3) KER<3, NA, NB><<<grid_of(t), BLOCK, 0, s>>>(__VA_ARGS__);         \
+        else KER<1, NA, NB><<<grid_of(t), BLOCK, 0, s>>>(__VA_ARGS__);                      \
+        return hipGetLastError();                                                           \
+    } while (0)
+
 }  // namespace
 
 namespace k {
 
 hipError_t apply_L(const Tiling &t, double nu, View<double> u, View<double> F, hipStream_t s)
 {
+    if (t.dim == 3 && grid_blocks(t) > 0) {
+        apply_L_kz_kernel<<<(unsigned)(col_tiles_per_field(t.n, KZ) * t.count), BLOCK, 0, s>>>(t, nu, u, F);
+        return hipGetLastError();
+    }
     PFMG_DISPATCH(t, apply_L_kernel, t, nu, u, F);
 }
 
@@ -237,7 +299,9 @@ hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, Vi
                          View<double> I, long i_node, hipStream_t s)
 {
     if (nn > MAXN) return hipErrorInvalidValue;
-    PFMG_DISPATCH(t, sdc_integrals_kernel, t, nn, dt, S, F, f_node, I, i_node);
+    if (nn == 5) PFMG_DISPATCH_N(t, sdc_integrals_kernel, 5, t, nn, dt, S, F, f_node, I, i_node);
+    if (nn == 3) PFMG_DISPATCH_N(t, sdc_integrals_kernel, 3, t, nn, dt, S, F, f_node, I, i_node);
+    PFMG_DISPATCH_N(t, sdc_integrals_kernel, 0, t, nn, dt, S, F, f_node, I, i_node);
 }
 
 hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> Fm1, View<double> Im,
@@ -253,26 +317,35 @@ hipError_t fas_inject(const Tiling &t, int nf, int nnf, int nnc, const int *cmap
     if (nnf > MAXN || nnc > MAXN) return hipErrorInvalidValue;
     IntMap m{};
     for (int q = 0; q < nnc; ++q) m.v[q] = cmap[q];
-    PFMG_DISPATCH(t, fas_inject_kernel, t, nf, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
+    if (nnf == 5 && nnc == 3)
+        PFMG_DISPATCH_N2(t, fas_inject_kernel, 5, 3, t, nf, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
+    PFMG_DISPATCH_N2(t, fas_inject_kernel, 0, 0, t, nf, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
 }
 
 hipError_t fas_tau(const Tiling &t, int nnc, double dt, const double *Qc, View<double> Fc, View<double> Tau,
                    long c_node, hipStream_t s)
 {
-    PFMG_DISPATCH(t, fas_tau_kernel, t, nnc, dt, Qc, Fc, Tau, c_node);
+    if (nnc > MAXN) return hipErrorInvalidValue;
+    if (nnc == 3) PFMG_DISPATCH_N(t, fas_tau_kernel, 3, t, nnc, dt, Qc, Fc, Tau, c_node);
+    PFMG_DISPATCH_N(t, fas_tau_kernel, 0, t, nnc, dt, Qc, Fc, Tau, c_node);
 }
 
 hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, View<double> Uc,
                          View<double> Uold, long c_node, View<double> DC, long dc_node, hipStream_t s)
 {
-    PFMG_DISPATCH(t, interp_coarse_kernel, t, nnf, nnc, Lt, Uc, Uold, c_node, DC, dc_node);
+    if (nnf > MAXN || nnc > MAXN) return hipErrorInvalidValue;
+    if (nnf == 5 && nnc == 3)
+        PFMG_DISPATCH_N2(t, interp_coarse_kernel, 5, 3, t, nnf, nnc, Lt, Uc, Uold, c_node, DC, dc_node);
+    PFMG_DISPATCH_N2(t, interp_coarse_kernel, 0, 0, t, nnf, nnc, Lt, Uc, Uold, c_node, DC, dc_node);
 }
 
 hipError_t colloc_resid(const Tiling &t, int nn, double dt, const double *Q, View<double> U, View<double> F,
                         long node, const double *ublock, unsigned long long *res_bits,
                         unsigned long long *u0_bits, hipStream_t s)
 {
-    PFMG_DISPATCH(t, colloc_resid_kernel, t, nn, dt, Q, U, F, node, ublock, res_bits, u0_bits);
+    if (nn > MAXN) return hipErrorInvalidValue;
+    if (nn == 5) PFMG_DISPATCH_N(t, colloc_resid_kernel, 5, t, nn, dt, Q, U, F, node, ublock, res_bits, u0_bits);
+    PFMG_DISPATCH_N(t, colloc_resid_kernel, 0, t, nn, dt, Q, U, F, node, ublock, res_bits, u0_bits);
 }
 
 hipError_t inject(const Tiling &t, int nf, View<double> uf, View<double> uc, hipStream_t s)

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -85,7 +86,20 @@ struct Solver {
     hipError_t residual(double *per_slice, double *block);
     hipError_t iterate(double *block);
 
-    Tiling tl(int n, int count, const int *m = nullptr) const { return Tiling{n, dim, count, m}; }
+    int noremap = 0;
+    bool use_bottom = true;           // small grids: whole V-cycle in one LDS kernel
+    bool graphs = true;               // replay captured graphs of block start / iteration
+    hipStream_t cap = nullptr;        // private capture stream
+    hipGraphExec_t g_iter = nullptr, g_start = nullptr;
+    bool use_graph() const { return graphs && p.vcycles_per_solve > 0 && !timer.on; }
+    long long vc_iter[2] = {0, 0}, vc_start[2] = {0, 0};   // V-cycles of one replay
+    hipError_t capture(const std::function<hipError_t()> &fn, hipGraphExec_t *out, long long *vc);
+    void release_graphs();
+    hipError_t spread_body();
+    hipError_t iterate_body();
+    hipError_t residual_enqueue();
+    hipError_t residual_read(double *per_slice, double *block);
+    Tiling tl(int n, int count, const int *m = nullptr) const { return Tiling{n, dim, count, m, noremap}; }
     void tstart(const char *fam, int n, double bytes_per_point, long points);
     void tstop();
 };

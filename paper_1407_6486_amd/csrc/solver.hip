@@ -124,11 +124,13 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
                 G.e = {f64(nl_, P), G.fs64};
                 G.b = {f64(nl_, P), G.fs64};
             }
-            if (jac) G.t = {f64(nl_, P), G.fs64};
+            // second buffer for out-of-place sweeps (Jacobi, fused red-black)
+            const bool pingpong = jac || (dim == 3 && nl_ >= 31);
+            if (pingpong) G.t = {f64(nl_, P), G.fs64};
             if (mixed) {
                 G.e32 = {f32(nl_, P), G.fs32};
                 G.b32 = {f32(nl_, P), G.fs32};
-                if (jac) G.t32 = {f32(nl_, P), G.fs32};
+                if (pingpong) G.t32 = {f32(nl_, P), G.fs32};
             }
             L.mg.push_back(G);
             if (nl_ <= 2) break;
@@ -144,7 +146,7 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
         fubc = f64(coarser(p.n), 1);
     }
     double *lt = (double *)take(256 * 8);
-    auto *bits = (unsigned long long *)take((size_t)4 * P * 8);
+    auto *bits = (unsigned long long *)take((size_t)4 * P * k::RSLOTS * 8);
     int *mask = (int *)take((size_t)P * 4);
     if (sv) {
         sv->ublock = ub;
@@ -161,6 +163,12 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
 
 bool Solver::init_host(std::string &why)
 {
+    const char *e = getenv("PFMG_NO_XCD_REMAP");
+    noremap = (e && atoi(e)) ? 1 : 0;
+    e = getenv("PFMG_NO_BOTTOM");
+    use_bottom = !(e && atoi(e));
+    e = getenv("PFMG_NO_GRAPH");
+    graphs = !(e && atoi(e));
     dim = p.dim;
     P = p.n_slices;
     nl = p.nodes_coarse > 0 ? 2 : 1;
@@ -231,6 +239,18 @@ hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> 
     const long pts = interior_points(n, dim) * count;
     const double w = (double)sizeof(T);
     if (sweeps == 0) return from_zero ? k::zero(t, u, s) : hipSuccess;
+    if (p.smoother == PFMG_SMOOTH_RBGS && dim == 3 && n >= 31 && n <= 255 && tmp.p) {
+        // whole sweeps in one pass each, ping-pong between u and tmp
+        View<T> src = u, dst = tmp;
+        for (int q = 0; q < sweeps; ++q) {
+            tstart("rbgs", n, 3 * w, pts);
+            HC(k::rbgs_fused(t, alpha, om, q == 0 && from_zero, b, src, dst, s));
+            tstop();
+            std::swap(src, dst);
+        }
+        if (src.p != u.p) HC(k::copy(t, src, u, s));
+        return hipSuccess;
+    }
     if (p.smoother == PFMG_SMOOTH_RBGS) {
         for (int q = 0; q < sweeps; ++q) {
             tstart("rbgs", n, 2 * w, pts);
@@ -259,6 +279,8 @@ hipError_t Solver::vcycle64(int lev, int l, View<double> u, View<double> b, int 
 {
     MGLevel &G = L[lev].mg[l];
     const Tiling t = tl(G.n, count, m);
+    if (use_bottom && k::vcycle_bottom_lds(G.n, dim, p.smoother, sizeof(double)) <= k::BOTTOM_LDS_MAX)
+        return k::vcycle_bottom(t, alpha, p.smoother, p.omega, p.nu_pre, p.nu_post, l > 0, b, u, s);
     if (G.n <= 2) return k::coarsest(t, alpha, b, u, s);
     HC(smooth<double>(G.n, count, m, alpha, u, b, G.t, p.nu_pre, l > 0));
     MGLevel &C = L[lev].mg[l + 1];
@@ -277,6 +299,8 @@ hipError_t Solver::vcycle32(int lev, int l, View<float> u, View<float> b, int co
 {
     MGLevel &G = L[lev].mg[l];
     const Tiling t = tl(G.n, count, m);
+    if (use_bottom && k::vcycle_bottom_lds(G.n, dim, p.smoother, sizeof(float)) <= k::BOTTOM_LDS_MAX)
+        return k::vcycle_bottom(t, alpha, p.smoother, p.omega, p.nu_pre, p.nu_post, true, b, u, s);
     if (G.n <= 2) return k::coarsest(t, alpha, b, u, s);
     HC(smooth<float>(G.n, count, m, alpha, u, b, G.t32, p.nu_pre, true));
     MGLevel &C = L[lev].mg[l + 1];
@@ -447,13 +471,27 @@ hipError_t Solver::spread(const double *u0_dev)
 {
     PLevel &Fn = L[0];
     HC(k::unpack(tl(Fn.n, 1), u0_dev, View<double>{ublock, 0}, s));
+    if (use_graph()) {
+        if (!g_start) HC(capture([this] { return spread_body(); }, &g_start, vc_start));
+        vcount[0] += vc_start[0];
+        vcount[1] += vc_start[1];
+        return hipGraphLaunch(g_start, s);
+    }
+    return spread_body();
+}
+
+// Everything of a block start after u_block is in place: spread to all nodes
+// and slices, F, the injected coarse initial value and the predictor.
+hipError_t Solver::spread_body()
+{
+    PLevel &Fn = L[0];
     HC(k::copy(tl(Fn.n, P * Fn.nn), View<double>{ublock, 0}, View<double>{Fn.U, Fn.fs}, s));
     HC(k::apply_L(tl(Fn.n, P * Fn.nn), p.nu, View<double>{ublock, 0}, View<double>{Fn.F, Fn.fs}, s));
     if (nl > 1) {
         HC(k::inject(tl(L[1].n, 1), Fn.n, View<double>{ublock, 0}, View<double>{ublock_c, 0}, s));
         HC(k::apply_L(tl(L[1].n, 1), p.nu, View<double>{ublock_c, 0}, View<double>{fublock_c, 0}, s));
     }
-    return hipSuccess;
+    return predictor();
 }
 
 // Predictor (Sec. 2.3.2): round j sweeps every slice p >= j on the coarse
@@ -478,21 +516,34 @@ hipError_t Solver::predictor()
     return interpolate(0, P);
 }
 
-hipError_t Solver::residual(double *per_slice, double *block)
+// Per-slice maxima land in RSLOTS partial slots per slice (spreading the
+// atomics); the host takes the maximum over the slots.
+hipError_t Solver::residual_enqueue()
 {
     PLevel &Fn = L[0];
     const long fst = (long)Fn.nn * Fn.fs;
-    HC(k::fill_u64(bits, 0, 2 * P, s));
+    HC(k::fill_u64(bits, 0, 2 * P * k::RSLOTS, s));
     tstart("colloc_resid", Fn.n, 8.0 * (2 * Fn.nn + 1), interior_points(Fn.n, dim) * P);
     HC(k::colloc_resid(tl(Fn.n, P), Fn.nn, p.dt, Fn.dQ, View<double>{Fn.U, fst}, View<double>{Fn.F, fst}, Fn.fs,
-                       ublock, bits, bits + P, s));
+                       ublock, bits, bits + (long)P * k::RSLOTS, s));
     tstop();
-    HC(hipMemcpyAsync(hbits, bits, sizeof(unsigned long long) * 2 * P, hipMemcpyDeviceToHost, s));
+    return hipSuccess;
+}
+
+hipError_t Solver::residual_read(double *per_slice, double *block)
+{
+    const int ns = 2 * P * k::RSLOTS;
+    HC(hipMemcpyAsync(hbits, bits, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost, s));
     HC(hipStreamSynchronize(s));
     double blk = 0;
     bool bad = false;
     for (int q = 0; q < P; ++q) {
-        const double r = bits_to_double(hbits[q]), u0 = bits_to_double(hbits[P + q]);
+        unsigned long long rb = 0, ub = 0;
+        for (int w = 0; w < k::RSLOTS; ++w) {
+            rb = std::max(rb, hbits[(long)q * k::RSLOTS + w]);
+            ub = std::max(ub, hbits[(long)(P + q) * k::RSLOTS + w]);
+        }
+        const double r = bits_to_double(rb), u0 = bits_to_double(ub);
         const double v = u0 > 0 ? r / u0 : r;
         if (!std::isfinite(v)) bad = true;
         if (per_slice) per_slice[q] = v;
@@ -503,7 +554,13 @@ hipError_t Solver::residual(double *per_slice, double *block)
     return hipSuccess;
 }
 
-hipError_t Solver::iterate(double *block)
+hipError_t Solver::residual(double *per_slice, double *block)
+{
+    HC(residual_enqueue());
+    return residual_read(per_slice, block);
+}
+
+hipError_t Solver::iterate_body()
 {
     PLevel &Fn = L[0];
     const int M = Fn.nn - 1;
@@ -528,7 +585,59 @@ hipError_t Solver::iterate(double *block)
         }
         HC(interpolate(0, P));
     }
-    return residual(nullptr, block);
+    return residual_enqueue();
+}
+
+hipError_t Solver::iterate(double *block)
+{
+    if (use_graph()) {
+        if (!g_iter) HC(capture([this] { return iterate_body(); }, &g_iter, vc_iter));
+        vcount[0] += vc_iter[0];
+        vcount[1] += vc_iter[1];
+        HC(hipGraphLaunch(g_iter, s));
+    } else {
+        HC(iterate_body());
+        if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+    }
+    return residual_read(nullptr, block);
+}
+
+// Record the launches of fn into an executable graph.  Capture runs on a
+// private stream (the caller's stream may be the null stream, which cannot
+// be captured); the graph is then launched on the caller's stream.
+hipError_t Solver::capture(const std::function<hipError_t()> &fn, hipGraphExec_t *out, long long *vc)
+{
+    if (!cap) HC(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    // V-cycles are counted on the host as they are enqueued: keep the count
+    // of one replay and restore the counters (nothing ran during capture)
+    const long long v0 = vcount[0], v1 = vcount[1];
+    hipStream_t saved = s;
+    s = cap;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    hipError_t e1 = e == hipSuccess ? fn() : e;
+    hipGraph_t g = nullptr;
+    hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(cap, &g) : e;
+    s = saved;
+    vc[0] = vcount[0] - v0;
+    vc[1] = vcount[1] - v1;
+    vcount[0] = v0;
+    vcount[1] = v1;
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return e1 != hipSuccess ? e1 : e2;
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+void Solver::release_graphs()
+{
+    if (g_iter) (void)hipGraphExecDestroy(g_iter);
+    if (g_start) (void)hipGraphExecDestroy(g_start);
+    if (cap) (void)hipStreamDestroy(cap);
+    g_iter = g_start = nullptr;
+    cap = nullptr;
 }
 
 template hipError_t Solver::smooth<double>(int, int, const int *, double, View<double>, View<double>, View<double>, int, bool);

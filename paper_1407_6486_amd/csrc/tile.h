@@ -23,6 +23,7 @@ constexpr int BLOCK = 256;
 struct Tiling {
     int n, dim, count;
     const int *mask;  // optional: fields whose mask is 0 are skipped
+    int noremap = 0;  // 1: keep the hardware workgroup order (no XCD grouping)
 };
 
 __host__ __device__ inline long tiles_per_field(int n, int dim)
@@ -47,7 +48,7 @@ __device__ inline unsigned xcd_remap(unsigned bid, unsigned nb)
 template <int DIM>
 __device__ inline bool tile_point(const Tiling &t, int &item, int &i, int &j, int &k, long &off)
 {
-    const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    const unsigned bid = t.noremap ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
     const int n = t.n;
     if (DIM == 3) {
         const unsigned gx = (n + TILE_X - 1) / TILE_X, gy = (n + TILE_Y - 1) / TILE_Y;
@@ -72,6 +73,38 @@ __device__ inline bool tile_point(const Tiling &t, int &item, int &i, int &j, in
     if (item >= t.count) return false;
     if (t.mask && !t.mask[item]) return false;
     return i <= n && j <= n && k <= n;
+}
+
+// Column tiling for 3D streaming stencils: a thread owns one (i, j) column
+// and KZ consecutive planes k0 .. k0+nk-1 (nk = KZ except at the top).  All
+// loads of the KZ points are issued before any store, so each wavefront keeps
+// several KB in flight; one point per thread leaves the HBM pipe latency-bound.
+__host__ __device__ inline long col_tiles_per_field(int n, int kz)
+{
+    return (long)((n + TILE_X - 1) / TILE_X) * ((n + TILE_Y - 1) / TILE_Y) * ((n + kz - 1) / kz);
+}
+
+template <int KZ>
+__device__ inline bool tile_col(const Tiling &t, int &item, int &i, int &j, int &k0, int &nk, long &off)
+{
+    const unsigned bid = t.noremap ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+    const int n = t.n;
+    const unsigned gx = (n + TILE_X - 1) / TILE_X, gy = (n + TILE_Y - 1) / TILE_Y, gz = (n + KZ - 1) / KZ;
+    const unsigned per_plane = gx * gy;
+    const unsigned per_field = per_plane * gz;
+    item = (int)(bid / per_field);
+    unsigned rem = bid - (unsigned)item * per_field;
+    const int kc = (int)(rem / per_plane);
+    rem -= (unsigned)kc * per_plane;
+    const unsigned jt = rem / gx, it = rem - jt * gx;
+    i = (int)(it * TILE_X + (threadIdx.x & (TILE_X - 1))) + 1;
+    j = (int)(jt * TILE_Y + (threadIdx.x >> 6)) + 1;
+    k0 = kc * KZ + 1;
+    nk = n - k0 + 1 < KZ ? n - k0 + 1 : KZ;
+    off = (long)i + (long)j * row_stride(n) + (long)k0 * plane_stride(n);
+    if (item >= t.count) return false;
+    if (t.mask && !t.mask[item]) return false;
+    return i <= n && j <= n;
 }
 
 // Sum over dimensions of the 3-point second differences (not divided by h^2).

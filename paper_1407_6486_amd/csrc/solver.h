@@ -89,6 +89,7 @@ struct Solver {
     int noremap = 0;
     bool use_bottom = true;           // small grids: whole V-cycle in one LDS kernel
     bool graphs = true;               // replay captured graphs of block start / iteration
+    long fused_min_points = 2000000;  // one-pass red-black sweep from this batch size up
     hipStream_t cap = nullptr;        // private capture stream
     hipGraphExec_t g_iter = nullptr, g_start = nullptr;
     bool use_graph() const { return graphs && p.vcycles_per_solve > 0 && !timer.on; }

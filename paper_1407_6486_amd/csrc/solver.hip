@@ -169,6 +169,8 @@ bool Solver::init_host(std::string &why)
     use_bottom = !(e && atoi(e));
     e = getenv("PFMG_NO_GRAPH");
     graphs = !(e && atoi(e));
+    e = getenv("PFMG_FUSED_MIN");
+    fused_min_points = e ? atol(e) : 2000000;
     dim = p.dim;
     P = p.n_slices;
     nl = p.nodes_coarse > 0 ? 2 : 1;
@@ -239,7 +241,11 @@ hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> 
     const long pts = interior_points(n, dim) * count;
     const double w = (double)sizeof(T);
     if (sweeps == 0) return from_zero ? k::zero(t, u, s) : hipSuccess;
-    if (p.smoother == PFMG_SMOOTH_RBGS && dim == 3 && n >= 31 && n <= 255 && tmp.p) {
+    // The one-pass sweep marches in z; on small batches (the coarse chain
+    // sweeps one slice at a time) its serial steps cost more than the second
+    // pass of the colour-by-colour kernels, so it is used on big batches only.
+    if (p.smoother == PFMG_SMOOTH_RBGS && dim == 3 && n >= 31 && n <= 255 && tmp.p &&
+        (long)count * interior_points(n, dim) >= fused_min_points) {
         // whole sweeps in one pass each, ping-pong between u and tmp
         View<T> src = u, dst = tmp;
         for (int q = 0; q < sweeps; ++q) {

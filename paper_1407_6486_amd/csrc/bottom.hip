@@ -12,6 +12,8 @@
 // Dirichlet data.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "../../include/pfmg.h"
 #include "kernels.h"
 
@@ -34,9 +36,6 @@ __device__ inline void for_points(int n, F f)
         for (int i = threadIdx.x; i < n; i += BT) f(i, i, 0, 0);
     }
 }
-
-template <typename T>
-__device__ inline T *fp(View<T> v, int item) { return v.p + (long)item * v.stride; }
 
 __host__ __device__ inline int ipow(int n, int dim) { return dim == 3 ? n * n * n : n; }
 
@@ -194,13 +193,19 @@ __device__ void coarsest(Grid<DIM, T> &g, T ah)
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(1024) void vcycle_bottom_kernel(int n0, int count, const int *mask, double alpha,
-                                                           int smoother, double omega, int nu1, int nu2,
-                                                           int zero_init, View<T> bg, View<T> ug)
+__global__ __launch_bounds__(1024) void vcycle_bottom_kernel(Tiling t, double alpha_s, int smoother, double omega,
+                                                             int nu1, int nu2, int zero_init, View<T> bg,
+                                                             View<T> ug)
 {
     extern __shared__ unsigned char smem_raw[];
-    const int item = blockIdx.x;
-    if (item >= count || (mask && !mask[item])) return;
+    unsigned bid = blockIdx.x;
+    Pt qs;
+    const int *mask;
+    if (!find_seg(t, bid, qs, mask, [](int) { return 1L; })) return;
+    qs.item = (int)bid;
+    if (mask && !mask[qs.item]) return;
+    const int n0 = qs.n;
+    const double alpha = qs.par(alpha_s);
     // level table in LDS (a runtime-indexed private array would live in scratch)
     __shared__ int sn[MAXL], snl;
     __shared__ unsigned soff[MAXL];
@@ -233,8 +238,8 @@ __global__ __launch_bounds__(1024) void vcycle_bottom_kernel(int n0, int count, 
         return g;
     };
     const int nl = snl;
-    const T *bsrc = fp(bg, item);
-    T *udst = fp(ug, item);
+    const T *bsrc = fp(bg, qs);
+    T *udst = fp(ug, qs);
     const long sy = row_stride(n0), sz = plane_stride(n0);
     {
         const Grid<DIM, T> top = grid(0);
@@ -291,15 +296,20 @@ template <typename T>
 hipError_t vcycle_bottom(const Tiling &t, double alpha, int smoother, double omega, int nu1, int nu2, bool zero_init,
                          View<T> b, View<T> u, hipStream_t s)
 {
-    if (t.count == 0) return hipSuccess;
-    const size_t lds = vcycle_bottom_lds(t.n, t.dim, smoother, sizeof(T));
+    long items = 0;
+    size_t lds = 0;
+    for (int sg = 0; sg < t.nseg; ++sg) {
+        items += t.seg_count(sg);
+        lds = std::max(lds, vcycle_bottom_lds(t.seg_n(sg), t.dim, smoother, sizeof(T)));
+    }
+    if (items == 0) return hipSuccess;
     if (lds > BOTTOM_LDS_MAX) return hipErrorInvalidValue;
     if (t.dim == 3)
-        vcycle_bottom_kernel<3, T><<<t.count, dim3(16, 16, 4), lds, s>>>(t.n, t.count, t.mask, alpha, smoother, omega, nu1, nu2,
-                                                            zero_init ? 1 : 0, b, u);
+        vcycle_bottom_kernel<3, T><<<(unsigned)items, dim3(16, 16, 4), lds, s>>>(t, alpha, smoother, omega, nu1, nu2,
+                                                                                 zero_init ? 1 : 0, b, u);
     else
-        vcycle_bottom_kernel<1, T><<<t.count, dim3(BT, 1, 1), lds, s>>>(t.n, t.count, t.mask, alpha, smoother, omega, nu1, nu2,
-                                                            zero_init ? 1 : 0, b, u);
+        vcycle_bottom_kernel<1, T><<<(unsigned)items, dim3(BT, 1, 1), lds, s>>>(t, alpha, smoother, omega, nu1, nu2,
+                                                                                zero_init ? 1 : 0, b, u);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ struct FusedShape {
     long blocks;
     size_t lds;
 };
-FusedShape rbgs_fused_shape(int n, int count, size_t elem);
+FusedShape rbgs_fused_shape(const Tiling &t, size_t elem);
 // One whole red-black sweep out of place (3D, 31 <= n <= 255): uout =
 // RBGS(uin); zero_in treats uin as 0 (first sweep of a coarse correction).
 template <typename T>
@@ -87,9 +87,9 @@ hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, Vi
 hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> Fm1,
                    View<double> Im, View<double> tau1, View<double> tau0, View<double> b,
                    hipStream_t s);
-// FAS injection (t.n = coarse n): Uc[mc] = Uold[mc] = Uf[cmap[mc]] at 2J,
-// Tau[mc] = dt sum_i Qf[cmap[mc]][i] Ff[i] at 2J.
-hipError_t fas_inject(const Tiling &t, int nf, int nnf, int nnc, const int *cmap, double dt,
+// FAS injection (t on the coarse grids): Uc[mc] = Uold[mc] = Uf[cmap[mc]] at
+// 2J, Tau[mc] = dt sum_i Qf[cmap[mc]][i] Ff[i] at 2J.
+hipError_t fas_inject(const Tiling &t, int nnf, int nnc, const int *cmap, double dt,
                       const double *Qf, View<double> Uf, View<double> Ff, long f_node,
                       View<double> Uc, View<double> Uold, View<double> Tau, long c_node,
                       hipStream_t s);
@@ -103,11 +103,13 @@ hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, Vi
 // Collocation residual (eq. resid) per slice; each slice's maxima go to
 // RSLOTS partial slots (res_bits[p * RSLOTS + w]); bits preset to 0.
 constexpr int RSLOTS = 64;
-hipError_t colloc_resid(const Tiling &t, int nn, double dt, const double *Q, View<double> U,
-                        View<double> F, long node, const double *ublock,
+// Fields are (problem, slice) pairs with P slices per problem; ublock holds
+// one block initial value per problem.
+hipError_t colloc_resid(const Tiling &t, int nn, int P, double dt, const double *Q, View<double> U,
+                        View<double> F, long node, View<double> ublock,
                         unsigned long long *res_bits, unsigned long long *u0_bits, hipStream_t s);
-// Point-wise injection uc(J) = uf(2J) (t.n = coarse n).
-hipError_t inject(const Tiling &t, int nf, View<double> uf, View<double> uc, hipStream_t s);
+// Point-wise injection uc(J) = uf(2J) (t on the coarse grids).
+hipError_t inject(const Tiling &t, View<double> uf, View<double> uc, hipStream_t s);
 // dense (n^dim, x fastest) <-> field
 hipError_t pack(const Tiling &t, View<double> f, double *dense, hipStream_t s);
 hipError_t unpack(const Tiling &t, const double *dense, View<double> f, hipStream_t s);

@@ -55,10 +55,13 @@ PFMG_HD inline int coarser(int n) { return (n + 1) / 2 - 1; }
 
 // A batch of `count` fields of one grid, field q at p + q * stride
 // (p already points at element 0 of field 0).
+// Segments 1..3 of a multi-segment launch keep their bases in px / sx.
 template <typename T>
 struct View {
     T *p;
     long stride;
+    T *px[3] = {nullptr, nullptr, nullptr};
+    long sx[3] = {0, 0, 0};
 };
 
 }  // namespace pfmg

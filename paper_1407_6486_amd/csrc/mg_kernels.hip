@@ -6,9 +6,10 @@
 // operators are re-discretised on h_{l+1} = 2 h_l with the same alpha;
 // grids with n in {1, 2} are solved exactly.
 //
-// All kernels are memory-bound stencils: one thread per point, whole
-// 64-point row segments per wavefront, no matrix cores.  FP64 and FP32
-// instances serve the plain and the mixed-precision forms.
+// All kernels are memory-bound stencils, no matrix cores.  FP64 and FP32
+// instances serve the plain and the mixed-precision forms.  Every launch may
+// span several segments (fields of different grids, per-field alpha), so the
+// uneven problems of a batch share one launch per multigrid level.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,74 +19,89 @@
 namespace pfmg {
 namespace {
 
-template <typename T>
-__device__ inline T *fp(View<T> v, int item) { return v.p + (long)item * v.stride; }
+// Coefficients of (I - alpha L_h) on grid n: ah = alpha / h^2 and the
+// smoother weight omega / diag(H), formed in double.
+__host__ __device__ inline double ah_d(double alpha, int n) { return alpha * (double)(n + 1) * (double)(n + 1); }
+__host__ __device__ inline double winv_d(double alpha, double omega, int n, int dim)
+{
+    return omega / (1.0 + 2.0 * dim * ah_d(alpha, n));
+}
 
-// ---------------------------------------------------------------- residual
+// ------------------------------------------------------ point kernels
+// One thread per point (used in 1D and for small 3D grids).
 template <int DIM, typename T, typename TO>
-__global__ __launch_bounds__(BLOCK) void resid_kernel(Tiling t, T ah, View<T> b, View<T> u, View<TO> r)
+__global__ __launch_bounds__(BLOCK) void resid_kernel(Tiling t, double alpha, View<T> b, View<T> u, View<TO> r)
 {
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
-    const T *uu = fp(u, item);
-    const long sy = row_stride(t.n), sz = plane_stride(t.n);
-    const T lap = d2sum<DIM>(uu, c, sy, sz);
-    fp(r, item)[c] = (TO)(fp(b, item)[c] - (uu[c] - ah * lap));
-}
-
-// ------------------------------------------------------------------ Jacobi
-template <int DIM, typename T>
-__global__ __launch_bounds__(BLOCK) void jacobi_kernel(Tiling t, T ah, T winv, View<T> b, View<T> u, View<T> out)
-{
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
-    const T *uu = fp(u, item);
-    const long sy = row_stride(t.n), sz = plane_stride(t.n);
-    const T lap = d2sum<DIM>(uu, c, sy, sz);
-    const T res = fp(b, item)[c] - (uu[c] - ah * lap);
-    fp(out, item)[c] = uu[c] + winv * res;
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
+    const T ah = (T)ah_d(q.par(alpha), q.n);
+    const T *uu = fp(u, q);
+    const T lap = d2sum<DIM>(uu, c, row_stride(q.n), plane_stride(q.n));
+    fp(r, q)[c] = (TO)(fp(b, q)[c] - (uu[c] - ah * lap));
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(BLOCK) void jacobi_zero_kernel(Tiling t, T winv, View<T> b, View<T> out)
+__global__ __launch_bounds__(BLOCK) void jacobi_kernel(Tiling t, double alpha, double omega, View<T> b, View<T> u,
+                                                       View<T> out)
 {
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
-    fp(out, item)[c] = winv * fp(b, item)[c];
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
+    const double a = q.par(alpha);
+    const T ah = (T)ah_d(a, q.n), winv = (T)winv_d(a, omega, q.n, DIM);
+    const T *uu = fp(u, q);
+    const T lap = d2sum<DIM>(uu, c, row_stride(q.n), plane_stride(q.n));
+    const T res = fp(b, q)[c] - (uu[c] - ah * lap);
+    fp(out, q)[c] = uu[c] + winv * res;
 }
 
-// --------------------------------------------------------------- red-black
 template <int DIM, typename T>
-__global__ __launch_bounds__(BLOCK) void rbgs_kernel(Tiling t, T ah, T winv, int colour, View<T> b, View<T> u)
+__global__ __launch_bounds__(BLOCK) void jacobi_zero_kernel(Tiling t, double alpha, double omega, View<T> b,
+                                                            View<T> out)
 {
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
+    const T winv = (T)winv_d(q.par(alpha), omega, q.n, DIM);
+    fp(out, q)[c] = winv * fp(b, q)[c];
+}
+
+// Red (colour 0: 1-based i+j+k even) or black points, in place.
+template <int DIM, typename T>
+__global__ __launch_bounds__(BLOCK) void rbgs_kernel(Tiling t, double alpha, double omega, int colour, View<T> b,
+                                                     View<T> u)
+{
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
     const int par = (DIM == 3 ? (i + j + k) : i) & 1;
     if (par != colour) return;
-    T *uu = fp(u, item);
-    const long sy = row_stride(t.n), sz = plane_stride(t.n);
-    const T lap = d2sum<DIM>(uu, c, sy, sz);
-    const T res = fp(b, item)[c] - (uu[c] - ah * lap);
+    const double a = q.par(alpha);
+    const T ah = (T)ah_d(a, q.n), winv = (T)winv_d(a, omega, q.n, DIM);
+    T *uu = fp(u, q);
+    const T lap = d2sum<DIM>(uu, c, row_stride(q.n), plane_stride(q.n));
+    const T res = fp(b, q)[c] - (uu[c] - ah * lap);
     uu[c] = uu[c] + winv * res;
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(BLOCK) void rbgs_zero_red_kernel(Tiling t, T winv, View<T> b, View<T> u)
+__global__ __launch_bounds__(BLOCK) void rbgs_zero_red_kernel(Tiling t, double alpha, double omega, View<T> b,
+                                                              View<T> u)
 {
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
+    const T winv = (T)winv_d(q.par(alpha), omega, q.n, DIM);
     const int par = (DIM == 3 ? (i + j + k) : i) & 1;
-    fp(u, item)[c] = par == 0 ? winv * fp(b, item)[c] : (T)0;
+    fp(u, q)[c] = par == 0 ? winv * fp(b, q)[c] : (T)0;
 }
 
-// -------------------------------------------------------------- restriction
-// t.n is the coarse n here; nf the fine n.
+// ---------------------------------------------------------- restriction
+// Launched on the coarse grids (q.n = coarse n); the fine grid is
+// 2 (nc + 1) - 1.  Coarse point J (1-based) sits on fine point 2J.
 template <int DIM, typename T>
-__global__ __launch_bounds__(BLOCK) void restrict_kernel(Tiling t, int nf, View<T> r, View<T> bc)
+__global__ __launch_bounds__(BLOCK) void restrict_kernel(Tiling t, View<T> r, View<T> bc)
 {
-    int item, I, J, K; long cc;
-    if (!tile_point<DIM>(t, item, I, J, K, cc)) return;
-    const T *rr = fp(r, item);
+    Pt q; int I, J, K; long cc;
+    if (!tile_point<DIM>(t, q, I, J, K, cc)) return;
+    const int nf = 2 * (q.n + 1) - 1;
+    const T *rr = fp(r, q);
     const long sy = row_stride(nf), sz = plane_stride(nf);
     const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
     T acc = 0;
@@ -101,16 +117,19 @@ __global__ __launch_bounds__(BLOCK) void restrict_kernel(Tiling t, int nf, View<
         const long f = 2L * I;
         acc = w[0] * rr[f - 1] + w[1] * rr[f] + w[2] * rr[f + 1];
     }
-    fp(bc, item)[cc] = acc;
+    fp(bc, q)[cc] = acc;
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(BLOCK) void resid_restrict_kernel(Tiling t, int nf, T ah, View<T> b, View<T> u, View<T> bc)
+__global__ __launch_bounds__(BLOCK) void resid_restrict_kernel(Tiling t, double alpha, View<T> b, View<T> u,
+                                                               View<T> bc)
 {
-    int item, I, J, K; long cc;
-    if (!tile_point<DIM>(t, item, I, J, K, cc)) return;
-    const T *uu = fp(u, item);
-    const T *bb = fp(b, item);
+    Pt q; int I, J, K; long cc;
+    if (!tile_point<DIM>(t, q, I, J, K, cc)) return;
+    const int nf = 2 * (q.n + 1) - 1;
+    const T ah = (T)ah_d(q.par(alpha), nf);
+    const T *uu = fp(u, q);
+    const T *bb = fp(b, q);
     const long sy = row_stride(nf), sz = plane_stride(nf);
     const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
     T acc = 0;
@@ -135,19 +154,19 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_kernel(Tiling t, int nf,
             acc += w[a + 1] * res;
         }
     }
-    fp(bc, item)[cc] = acc;
+    fp(bc, q)[cc] = acc;
 }
 
-// ------------------------------------------------------------ prolongation
-// t.n = fine n; coarse n = coarser(t.n).  Coarse halo entries are zero, so
+// -------------------------------------------------------- prolongation
+// q.n = fine n; coarse n = coarser(q.n).  Coarse halo entries are zero, so
 // the boundary needs no special case.
 template <int DIM, typename T>
 __global__ __launch_bounds__(BLOCK) void prolong_kernel(Tiling t, View<T> ec, View<T> u)
 {
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
-    const int nc = coarser(t.n);
-    const T *e = fp(ec, item);
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
+    const int nc = coarser(q.n);
+    const T *e = fp(ec, q);
     const long sy = row_stride(nc), sz = plane_stride(nc);
     const int i0 = i >> 1, i1 = (i + 1) >> 1;
     T v;
@@ -164,137 +183,137 @@ __global__ __launch_bounds__(BLOCK) void prolong_kernel(Tiling t, View<T> ec, Vi
     } else {
         v = (i & 1) ? (T)0.5 * (e[i0] + e[i1]) : e[i0];
     }
-    fp(u, item)[c] += v;
+    fp(u, q)[c] += v;
 }
 
-// --------------------------------------------------------------- coarsest
+// ------------------------------------------------------------ coarsest
 // n = 1: one unknown.  n = 2: the eigenvectors of the 2-point Dirichlet
 // Laplacian are (1,1) and (1,-1) with eigenvalues -1/h^2 and -3/h^2; in 3D
 // their tensor products diagonalise H, so u = sum_s (v_s . b) v_s / (8 lambda_s).
+// One thread per field.
 template <int DIM, typename T>
-__global__ void coarsest_kernel(int n, int count, const int *mask, T ah, View<T> b, View<T> u)
+__global__ void coarsest_kernel(Tiling t, double alpha, View<T> b, View<T> u)
 {
-    const int item = blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= count || (mask && !mask[item])) return;
-    const T *bb = fp(b, item);
-    T *uu = fp(u, item);
+    unsigned gid = blockIdx.x * blockDim.x + threadIdx.x;
+    Pt q;
+    const int *mask;
+    if (!find_seg(t, gid, q, mask, [](int) { return 1L; })) return;
+    q.item = (int)gid;
+    if (mask && !mask[q.item]) return;
+    const int n = q.n;
+    const T ah = (T)ah_d(q.par(alpha), n);
+    const T *bb = fp(b, q);
+    T *uu = fp(u, q);
     if (n == 1) {
         const long c = DIM == 3 ? 1 + row_stride(1) + plane_stride(1) : 1;
         uu[c] = bb[c] / ((T)1 + (T)(2 * DIM) * ah);
         return;
     }
-    // n == 2
     if (DIM == 1) {
         const T b1 = bb[1], b2 = bb[2];
-        const T p = (b1 + b2) / ((T)1 + ah), q = (b1 - b2) / ((T)1 + (T)3 * ah);
-        uu[1] = (T)0.5 * (p + q);
-        uu[2] = (T)0.5 * (p - q);
+        const T p = (b1 + b2) / ((T)1 + ah), m = (b1 - b2) / ((T)1 + (T)3 * ah);
+        uu[1] = (T)0.5 * (p + m);
+        uu[2] = (T)0.5 * (p - m);
         return;
     }
     const long sy = row_stride(2), sz = plane_stride(2);
     T bv[8];
-    for (int q = 0; q < 8; ++q) {
-        const int ii = (q & 1) + 1, jj = ((q >> 1) & 1) + 1, kk = (q >> 2) + 1;
-        bv[q] = bb[ii + jj * sy + kk * sz];
-    }
+#pragma unroll
+    for (int w = 0; w < 8; ++w) bv[w] = bb[(w & 1) + 1 + (((w >> 1) & 1) + 1) * sy + ((w >> 2) + 1) * sz];
     T coef[8];
-    for (int s = 0; s < 8; ++s) {
+#pragma unroll
+    for (int sgn = 0; sgn < 8; ++sgn) {
         T dot = 0;
-        for (int q = 0; q < 8; ++q) {
-            int sign = 1;
-            for (int d = 0; d < 3; ++d)
-                if (((s >> d) & 1) && ((q >> d) & 1)) sign = -sign;
-            dot += sign > 0 ? bv[q] : -bv[q];
-        }
-        const int nneg = (s & 1) + ((s >> 1) & 1) + ((s >> 2) & 1);
-        const T lam = (T)1 + ah * (T)(3 + 2 * nneg);   // sum_d (1 or 3)
-        coef[s] = dot / ((T)8 * lam);
+#pragma unroll
+        for (int w = 0; w < 8; ++w) dot += (__builtin_popcount(sgn & w) & 1) ? -bv[w] : bv[w];
+        coef[sgn] = dot / ((T)8 * ((T)1 + ah * (T)(3 + 2 * __builtin_popcount(sgn))));
     }
-    for (int q = 0; q < 8; ++q) {
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
         T acc = 0;
-        for (int s = 0; s < 8; ++s) {
-            int sign = 1;
-            for (int d = 0; d < 3; ++d)
-                if (((s >> d) & 1) && ((q >> d) & 1)) sign = -sign;
-            acc += sign > 0 ? coef[s] : -coef[s];
-        }
-        const int ii = (q & 1) + 1, jj = ((q >> 1) & 1) + 1, kk = (q >> 2) + 1;
-        uu[ii + jj * sy + kk * sz] = acc;
+#pragma unroll
+        for (int sgn = 0; sgn < 8; ++sgn) acc += (__builtin_popcount(sgn & w) & 1) ? -coef[sgn] : coef[sgn];
+        uu[(w & 1) + 1 + (((w >> 1) & 1) + 1) * sy + ((w >> 2) + 1) * sz] = acc;
     }
 }
 
 // ------------------------------------------- column-blocked 3D variants
-// Same arithmetic as the point kernels above; a thread owns KZ planes of one
-// (i, j) column (tile_col) and issues every load before its stores.
+// Same arithmetic as the point kernels; a thread owns KZ planes of one
+// (i, j) column and issues every load before its stores (several KB in
+// flight per wavefront; one point per thread leaves HBM latency-bound).
 constexpr int KZ = 4;
 
-// col[q] = u at plane k0-1+q, q = 0 .. nk+1 (planes 0 and n+1 are halo zeros)
+// col[w] = u at plane k0-1+w, w = 0 .. nk+1 (planes 0 and n+1 are halo zeros)
 template <typename T>
 __device__ inline void load_col(const T *__restrict__ u, long o, long sz, int nk, T (&col)[KZ + 2])
 {
 #pragma unroll
-    for (int q = 0; q < KZ + 2; ++q) col[q] = q <= nk + 1 ? u[o + (long)(q - 1) * sz] : (T)0;
+    for (int w = 0; w < KZ + 2; ++w) col[w] = w <= nk + 1 ? u[o + (long)(w - 1) * sz] : (T)0;
 }
 
 template <typename T>
 __device__ inline void load_xy(const T *__restrict__ u, long o, long sy, long sz, int nk, T (&xs)[KZ], T (&ys)[KZ])
 {
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        if (q < nk) {
-            const long c = o + (long)q * sz;
-            xs[q] = u[c - 1] + u[c + 1];
-            ys[q] = u[c - sy] + u[c + sy];
+    for (int w = 0; w < KZ; ++w) {
+        if (w < nk) {
+            const long c = o + (long)w * sz;
+            xs[w] = u[c - 1] + u[c + 1];
+            ys[w] = u[c - sy] + u[c + sy];
         }
     }
 }
 
 template <typename T>
-__device__ inline T d2_of(const T (&col)[KZ + 2], const T (&xs)[KZ], const T (&ys)[KZ], int q)
+__device__ inline T d2_of(const T (&col)[KZ + 2], const T (&xs)[KZ], const T (&ys)[KZ], int w)
 {
-    T s = xs[q];
-    s += ys[q] + (col[q] + col[q + 2]);
-    return s - (T)6 * col[q + 1];
+    T s = xs[w];
+    s += ys[w] + (col[w] + col[w + 2]);
+    return s - (T)6 * col[w + 1];
 }
 
 template <typename T, typename TO>
-__global__ __launch_bounds__(BLOCK) void resid_kz_kernel(Tiling t, T ah, View<T> b, View<T> u, View<TO> r)
+__global__ __launch_bounds__(BLOCK) void resid_kz_kernel(Tiling t, double alpha, View<T> b, View<T> u, View<TO> r)
 {
-    int item, i, j, k0, nk; long o;
-    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
-    const long sy = row_stride(t.n), sz = plane_stride(t.n);
-    const T *__restrict__ uu = fp(u, item);
-    const T *__restrict__ bb = fp(b, item);
-    TO *__restrict__ rr = fp(r, item);
+    Pt q; int i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, q, i, j, k0, nk, o)) return;
+    const T ah = (T)ah_d(q.par(alpha), q.n);
+    const long sy = row_stride(q.n), sz = plane_stride(q.n);
+    const T *__restrict__ uu = fp(u, q);
+    const T *__restrict__ bb = fp(b, q);
+    TO *__restrict__ rr = fp(r, q);
     T col[KZ + 2], xs[KZ], ys[KZ], bv[KZ];
     load_col(uu, o, sz, nk, col);
     load_xy(uu, o, sy, sz, nk, xs, ys);
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) if (q < nk) bv[q] = bb[o + (long)q * sz];
+    for (int w = 0; w < KZ; ++w) if (w < nk) bv[w] = bb[o + (long)w * sz];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q)
-        if (q < nk) rr[o + (long)q * sz] = (TO)(bv[q] - (col[q + 1] - ah * d2_of(col, xs, ys, q)));
+    for (int w = 0; w < KZ; ++w)
+        if (w < nk) rr[o + (long)w * sz] = (TO)(bv[w] - (col[w + 1] - ah * d2_of(col, xs, ys, w)));
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void jacobi_kz_kernel(Tiling t, T ah, T winv, View<T> b, View<T> u, View<T> out)
+__global__ __launch_bounds__(BLOCK) void jacobi_kz_kernel(Tiling t, double alpha, double omega, View<T> b, View<T> u,
+                                                          View<T> out)
 {
-    int item, i, j, k0, nk; long o;
-    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
-    const long sy = row_stride(t.n), sz = plane_stride(t.n);
-    const T *__restrict__ uu = fp(u, item);
-    const T *__restrict__ bb = fp(b, item);
-    T *__restrict__ oo = fp(out, item);
+    Pt q; int i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, q, i, j, k0, nk, o)) return;
+    const double a = q.par(alpha);
+    const T ah = (T)ah_d(a, q.n), winv = (T)winv_d(a, omega, q.n, 3);
+    const long sy = row_stride(q.n), sz = plane_stride(q.n);
+    const T *__restrict__ uu = fp(u, q);
+    const T *__restrict__ bb = fp(b, q);
+    T *__restrict__ oo = fp(out, q);
     T col[KZ + 2], xs[KZ], ys[KZ], bv[KZ];
     load_col(uu, o, sz, nk, col);
     load_xy(uu, o, sy, sz, nk, xs, ys);
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) if (q < nk) bv[q] = bb[o + (long)q * sz];
+    for (int w = 0; w < KZ; ++w) if (w < nk) bv[w] = bb[o + (long)w * sz];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        if (q < nk) {
-            const T res = bv[q] - (col[q + 1] - ah * d2_of(col, xs, ys, q));
-            oo[o + (long)q * sz] = col[q + 1] + winv * res;
+    for (int w = 0; w < KZ; ++w) {
+        if (w < nk) {
+            const T res = bv[w] - (col[w + 1] - ah * d2_of(col, xs, ys, w));
+            oo[o + (long)w * sz] = col[w + 1] + winv * res;
         }
     }
 }
@@ -304,12 +323,12 @@ __global__ __launch_bounds__(BLOCK) void jacobi_kz_kernel(Tiling t, T ah, T winv
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void prolong_kz_kernel(Tiling t, View<T> ec, View<T> u)
 {
-    int item, i, j, k0, nk; long o;
-    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
-    const int nc = coarser(t.n);
-    const T *__restrict__ e = fp(ec, item);
-    T *__restrict__ uu = fp(u, item);
-    const long csy = row_stride(nc), csz = plane_stride(nc), sz = plane_stride(t.n);
+    Pt q; int i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, q, i, j, k0, nk, o)) return;
+    const int nc = coarser(q.n);
+    const T *__restrict__ e = fp(ec, q);
+    T *__restrict__ uu = fp(u, q);
+    const long csy = row_stride(nc), csz = plane_stride(nc), sz = plane_stride(q.n);
     const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1;
     const int c0 = k0 >> 1;                       // first coarse plane touched
     constexpr int NCP = KZ / 2 + 2;               // coarse planes touched by KZ fine planes
@@ -329,14 +348,14 @@ __global__ __launch_bounds__(BLOCK) void prolong_kz_kernel(Tiling t, View<T> ec,
         pv[cq] = v;
     }
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) if (q < nk) uv[q] = uu[o + (long)q * sz];
+    for (int w = 0; w < KZ; ++w) if (w < nk) uv[w] = uu[o + (long)w * sz];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        if (q < nk) {
-            const int k = k0 + q;
+    for (int w = 0; w < KZ; ++w) {
+        if (w < nk) {
+            const int k = k0 + w;
             const int a = (k >> 1) - c0, bq = ((k + 1) >> 1) - c0;
             const T v = (k & 1) ? (T)0.5 * (pv[a] + pv[bq]) : pv[a];
-            uu[o + (long)q * sz] = uv[q] + v;
+            uu[o + (long)w * sz] = uv[w] + v;
         }
     }
 }
@@ -344,64 +363,62 @@ __global__ __launch_bounds__(BLOCK) void prolong_kz_kernel(Tiling t, View<T> ec,
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void copy_kz_kernel(Tiling t, View<T> src, View<T> dst)
 {
-    int item, i, j, k0, nk; long o;
-    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
-    const long sz = plane_stride(t.n);
-    const T *__restrict__ a = fp(src, item);
-    T *__restrict__ d = fp(dst, item);
+    Pt q; int i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, q, i, j, k0, nk, o)) return;
+    const long sz = plane_stride(q.n);
+    const T *__restrict__ a = fp(src, q);
+    T *__restrict__ d = fp(dst, q);
     T v[KZ];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) if (q < nk) v[q] = a[o + (long)q * sz];
+    for (int w = 0; w < KZ; ++w) if (w < nk) v[w] = a[o + (long)w * sz];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) if (q < nk) d[o + (long)q * sz] = v[q];
+    for (int w = 0; w < KZ; ++w) if (w < nk) d[o + (long)w * sz] = v[w];
 }
 
 __global__ __launch_bounds__(BLOCK) void add_f32_kz_kernel(Tiling t, View<float> e, View<double> u)
 {
-    int item, i, j, k0, nk; long o;
-    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
-    const float *__restrict__ ee = fp(e, item);
-    double *__restrict__ uu = fp(u, item);
-    const long sz = plane_stride(t.n), ez = plane_stride(t.n);
+    Pt q; int i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, q, i, j, k0, nk, o)) return;
+    const float *__restrict__ ee = fp(e, q);
+    double *__restrict__ uu = fp(u, q);
+    const long sz = plane_stride(q.n);
     double uv[KZ];
     float ev[KZ];
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        if (q < nk) {
-            uv[q] = uu[o + (long)q * sz];
-            ev[q] = ee[o + (long)q * ez];
+    for (int w = 0; w < KZ; ++w) {
+        if (w < nk) {
+            uv[w] = uu[o + (long)w * sz];
+            ev[w] = ee[o + (long)w * sz];
         }
     }
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) if (q < nk) uu[o + (long)q * sz] = uv[q] + (double)ev[q];
+    for (int w = 0; w < KZ; ++w) if (w < nk) uu[o + (long)w * sz] = uv[w] + (double)ev[w];
 }
 
-inline dim3 col_grid(const Tiling &t) { return dim3((unsigned)(col_tiles_per_field(t.n, KZ) * t.count)); }
-
-// ------------------------------------------------------------------- misc
+// -------------------------------------------------------------- misc
 template <int DIM, typename T>
 __global__ __launch_bounds__(BLOCK) void zero_kernel(Tiling t, View<T> u)
 {
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
-    fp(u, item)[c] = (T)0;
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
+    fp(u, q)[c] = (T)0;
 }
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(BLOCK) void copy_kernel(Tiling t, View<T> src, View<T> dst)
 {
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
-    fp(dst, item)[c] = fp(src, item)[c];
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
+    fp(dst, q)[c] = fp(src, q)[c];
 }
 
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void add_f32_kernel(Tiling t, View<float> e, View<double> u)
 {
-    int item, i, j, k; long c;
-    if (!tile_point<DIM>(t, item, i, j, k, c)) return;
-    double *uu = fp(u, item);
-    uu[c] = uu[c] + (double)fp(e, item)[c];
+    Pt q; int i, j, k; long c;
+    if (!tile_point<DIM>(t, q, i, j, k, c)) return;
+    double *uu = fp(u, q);
+    uu[c] = uu[c] + (double)fp(e, q)[c];
 }
 
 // Max-reduce non-negative doubles through their bit patterns: for x >= 0
@@ -419,63 +436,81 @@ __device__ inline void block_max_bits(unsigned long long v, unsigned long long *
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = part[0];
-        for (int q = 1; q < BLOCK / 64; ++q) m = part[q] > m ? part[q] : m;
+        for (int w = 1; w < BLOCK / 64; ++w) m = part[w] > m ? part[w] : m;
         if (m) atomicMax(dst, m);
     }
 }
 
 __device__ inline unsigned long long abs_bits(double x) { return (unsigned long long)__double_as_longlong(fabs(x)); }
 
+// Index of field q.item of segment q.sg among all fields of the launch.
+__device__ inline int flat_item(const Tiling &t, const Pt &q)
+{
+    int base = 0;
+    for (int s = 0; s < q.sg; ++s) base += t.seg_count(s);
+    return base + q.item;
+}
+
 template <int DIM, typename T>
 __global__ __launch_bounds__(BLOCK) void norm_kernel(Tiling t, View<T> v, unsigned long long *bits)
 {
-    int item, i, j, k; long c;
-    const bool ok = tile_point<DIM>(t, item, i, j, k, c);
-    unsigned long long m = ok ? abs_bits((double)fp(v, item)[c]) : 0ull;
-    // every thread of a block belongs to the same item
-    const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int blk_item = (int)(bid / tiles_per_field(t.n, DIM));
-    if (blk_item >= t.count) return;
-    block_max_bits(m, bits + blk_item);
+    Pt q; int i, j, k; long c;
+    const bool ok = tile_point<DIM>(t, q, i, j, k, c);
+    const unsigned long long m = ok ? abs_bits((double)fp(v, q)[c]) : 0ull;
+    Pt qb;   // every thread of a workgroup belongs to the same field
+    if (!tile_block_item<DIM>(t, qb)) return;
+    block_max_bits(m, bits + flat_item(t, qb));
 }
 
 template <int DIM>
-__global__ __launch_bounds__(BLOCK) void resid_norm_kernel(Tiling t, double ah, View<double> b, View<double> u,
+__global__ __launch_bounds__(BLOCK) void resid_norm_kernel(Tiling t, double alpha, View<double> b, View<double> u,
                                                            unsigned long long *bits)
 {
-    int item, i, j, k; long c;
-    const bool ok = tile_point<DIM>(t, item, i, j, k, c);
+    Pt q; int i, j, k; long c;
+    const bool ok = tile_point<DIM>(t, q, i, j, k, c);
     unsigned long long m = 0ull;
     if (ok) {
-        const double *uu = fp(u, item);
-        const double lap = d2sum<DIM>(uu, c, row_stride(t.n), plane_stride(t.n));
-        m = abs_bits(fp(b, item)[c] - (uu[c] - ah * lap));
+        const double ah = ah_d(q.par(alpha), q.n);
+        const double *uu = fp(u, q);
+        const double lap = d2sum<DIM>(uu, c, row_stride(q.n), plane_stride(q.n));
+        m = abs_bits(fp(b, q)[c] - (uu[c] - ah * lap));
     }
-    const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int blk_item = (int)(bid / tiles_per_field(t.n, DIM));
-    if (blk_item >= t.count) return;
-    block_max_bits(m, bits + blk_item);
+    Pt qb;
+    if (!tile_block_item<DIM>(t, qb)) return;
+    block_max_bits(m, bits + flat_item(t, qb));
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int count)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < count) p[q] = v;
-}
-
-inline double ah_of(double alpha, int n) { return alpha * (double)(n + 1) * (double)(n + 1); }
-inline double winv_of(double alpha, double omega, int n, int dim)
-{
-    return omega / (1.0 + 2.0 * dim * ah_of(alpha, n));
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < count) p[w] = v;
 }
 
 inline dim3 grid_of(const Tiling &t) { return dim3((unsigned)grid_blocks(t)); }
+inline dim3 col_grid(const Tiling &t) { return dim3((unsigned)col_blocks<KZ>(t)); }
+
+// Same launch on the next-coarser grid of every segment.
+inline Tiling coarsen(const Tiling &t)
+{
+    Tiling c = t;
+    c.n = coarser(t.n);
+    for (int s = 1; s < t.nseg; ++s) c.x[s - 1].n = coarser(t.x[s - 1].n);
+    return c;
+}
 
 #define PFMG_DISPATCH(t, KER, ...)                                                          \
     do {                                                                                    \
         if (grid_blocks(t) == 0) return hipSuccess;                                         \
         if ((t).dim == 3) KER<3><<<grid_of(t), BLOCK, 0, s>>>(__VA_ARGS__);                 \
         else KER<1><<<grid_of(t), BLOCK, 0, s>>>(__VA_ARGS__);                              \
+        return hipGetLastError();                                                           \
+    } while (0)
+
+#define PFMG_DISPATCH_T(t, KER, T, ...)                                                     \
+    do {                                                                                    \
+        if (grid_blocks(t) == 0) return hipSuccess;                                         \
+        if ((t).dim == 3) KER<3, T><<<grid_of(t), BLOCK, 0, s>>>(__VA_ARGS__);              \
+        else KER<1, T><<<grid_of(t), BLOCK, 0, s>>>(__VA_ARGS__);                           \
         return hipGetLastError();                                                           \
     } while (0)
 
@@ -486,85 +521,60 @@ namespace k {
 template <typename T>
 hipError_t resid(const Tiling &t, double alpha, View<T> b, View<T> u, View<T> r, hipStream_t s)
 {
-    const T ah = (T)ah_of(alpha, t.n);
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) resid_kz_kernel<T, T><<<col_grid(t), BLOCK, 0, s>>>(t, ah, b, u, r);
-    else resid_kernel<1, T, T><<<grid_of(t), BLOCK, 0, s>>>(t, ah, b, u, r);
+    if (t.dim == 3) resid_kz_kernel<T, T><<<col_grid(t), BLOCK, 0, s>>>(t, alpha, b, u, r);
+    else resid_kernel<1, T, T><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, b, u, r);
     return hipGetLastError();
 }
 
 hipError_t resid_round(const Tiling &t, double alpha, View<double> b, View<double> u, View<float> r32,
                        hipStream_t s)
 {
-    const double ah = ah_of(alpha, t.n);
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) resid_kz_kernel<double, float><<<col_grid(t), BLOCK, 0, s>>>(t, ah, b, u, r32);
-    else resid_kernel<1, double, float><<<grid_of(t), BLOCK, 0, s>>>(t, ah, b, u, r32);
+    if (t.dim == 3) resid_kz_kernel<double, float><<<col_grid(t), BLOCK, 0, s>>>(t, alpha, b, u, r32);
+    else resid_kernel<1, double, float><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, b, u, r32);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t jacobi(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, View<T> out,
-                  hipStream_t s)
+hipError_t jacobi(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, View<T> out, hipStream_t s)
 {
-    const T ah = (T)ah_of(alpha, t.n), wi = (T)winv_of(alpha, omega, t.n, t.dim);
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) jacobi_kz_kernel<T><<<col_grid(t), BLOCK, 0, s>>>(t, ah, wi, b, u, out);
-    else jacobi_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, ah, wi, b, u, out);
+    if (t.dim == 3) jacobi_kz_kernel<T><<<col_grid(t), BLOCK, 0, s>>>(t, alpha, omega, b, u, out);
+    else jacobi_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, omega, b, u, out);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t jacobi_zero(const Tiling &t, double alpha, double omega, View<T> b, View<T> out, hipStream_t s)
 {
-    const T wi = (T)winv_of(alpha, omega, t.n, t.dim);
-    if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) jacobi_zero_kernel<3, T><<<grid_of(t), BLOCK, 0, s>>>(t, wi, b, out);
-    else jacobi_zero_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, wi, b, out);
-    return hipGetLastError();
+    PFMG_DISPATCH_T(t, jacobi_zero_kernel, T, t, alpha, omega, b, out);
 }
 
 template <typename T>
 hipError_t rbgs(const Tiling &t, double alpha, double omega, int colour, View<T> b, View<T> u, hipStream_t s)
 {
-    const T ah = (T)ah_of(alpha, t.n), wi = (T)winv_of(alpha, omega, t.n, t.dim);
-    if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) rbgs_kernel<3, T><<<grid_of(t), BLOCK, 0, s>>>(t, ah, wi, colour, b, u);
-    else rbgs_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, ah, wi, colour, b, u);
-    return hipGetLastError();
+    PFMG_DISPATCH_T(t, rbgs_kernel, T, t, alpha, omega, colour, b, u);
 }
 
 template <typename T>
 hipError_t rbgs_zero_red(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, hipStream_t s)
 {
-    const T wi = (T)winv_of(alpha, omega, t.n, t.dim);
-    if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) rbgs_zero_red_kernel<3, T><<<grid_of(t), BLOCK, 0, s>>>(t, wi, b, u);
-    else rbgs_zero_red_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, wi, b, u);
-    return hipGetLastError();
+    PFMG_DISPATCH_T(t, rbgs_zero_red_kernel, T, t, alpha, omega, b, u);
 }
 
 template <typename T>
 hipError_t restrict_fw(const Tiling &t, View<T> r, View<T> bc, hipStream_t s)
 {
-    Tiling tc = t;
-    tc.n = coarser(t.n);
-    if (grid_blocks(tc) == 0) return hipSuccess;
-    if (t.dim == 3) restrict_kernel<3, T><<<grid_of(tc), BLOCK, 0, s>>>(tc, t.n, r, bc);
-    else restrict_kernel<1, T><<<grid_of(tc), BLOCK, 0, s>>>(tc, t.n, r, bc);
-    return hipGetLastError();
+    const Tiling tc = coarsen(t);
+    PFMG_DISPATCH_T(tc, restrict_kernel, T, tc, r, bc);
 }
 
 template <typename T>
 hipError_t resid_restrict(const Tiling &t, double alpha, View<T> b, View<T> u, View<T> bc, hipStream_t s)
 {
-    Tiling tc = t;
-    tc.n = coarser(t.n);
-    const T ah = (T)ah_of(alpha, t.n);
-    if (grid_blocks(tc) == 0) return hipSuccess;
-    if (t.dim == 3) resid_restrict_kernel<3, T><<<grid_of(tc), BLOCK, 0, s>>>(tc, t.n, ah, b, u, bc);
-    else resid_restrict_kernel<1, T><<<grid_of(tc), BLOCK, 0, s>>>(tc, t.n, ah, b, u, bc);
-    return hipGetLastError();
+    const Tiling tc = coarsen(t);
+    PFMG_DISPATCH_T(tc, resid_restrict_kernel, T, tc, alpha, b, u, bc);
 }
 
 template <typename T>
@@ -579,21 +589,19 @@ hipError_t prolong_add(const Tiling &t, View<T> ec, View<T> u, hipStream_t s)
 template <typename T>
 hipError_t coarsest(const Tiling &t, double alpha, View<T> b, View<T> u, hipStream_t s)
 {
-    const T ah = (T)ah_of(alpha, t.n);
-    if (t.count == 0) return hipSuccess;
-    const unsigned nb = (t.count + 63) / 64;
-    if (t.dim == 3) coarsest_kernel<3, T><<<nb, 64, 0, s>>>(t.n, t.count, t.mask, ah, b, u);
-    else coarsest_kernel<1, T><<<nb, 64, 0, s>>>(t.n, t.count, t.mask, ah, b, u);
+    long items = 0;
+    for (int sg = 0; sg < t.nseg; ++sg) items += t.seg_count(sg);
+    if (items == 0) return hipSuccess;
+    const unsigned nb = (unsigned)((items + 63) / 64);
+    if (t.dim == 3) coarsest_kernel<3, T><<<nb, 64, 0, s>>>(t, alpha, b, u);
+    else coarsest_kernel<1, T><<<nb, 64, 0, s>>>(t, alpha, b, u);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t zero(const Tiling &t, View<T> u, hipStream_t s)
 {
-    if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) zero_kernel<3, T><<<grid_of(t), BLOCK, 0, s>>>(t, u);
-    else zero_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, u);
-    return hipGetLastError();
+    PFMG_DISPATCH_T(t, zero_kernel, T, t, u);
 }
 
 template <typename T>
@@ -617,17 +625,13 @@ hipError_t add_f32(const Tiling &t, View<float> e, View<double> u, hipStream_t s
 template <typename T>
 hipError_t norm_inf(const Tiling &t, View<T> v, unsigned long long *bits, hipStream_t s)
 {
-    if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) norm_kernel<3, T><<<grid_of(t), BLOCK, 0, s>>>(t, v, bits);
-    else norm_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, v, bits);
-    return hipGetLastError();
+    PFMG_DISPATCH_T(t, norm_kernel, T, t, v, bits);
 }
 
-hipError_t resid_norm(const Tiling &t, double alpha, View<double> b, View<double> u,
-                      unsigned long long *bits, hipStream_t s)
+hipError_t resid_norm(const Tiling &t, double alpha, View<double> b, View<double> u, unsigned long long *bits,
+                      hipStream_t s)
 {
-    const double ah = ah_of(alpha, t.n);
-    PFMG_DISPATCH(t, resid_norm_kernel, t, ah, b, u, bits);
+    PFMG_DISPATCH(t, resid_norm_kernel, t, alpha, b, u, bits);
 }
 
 hipError_t fill_u64(unsigned long long *p, unsigned long long v, int count, hipStream_t s)

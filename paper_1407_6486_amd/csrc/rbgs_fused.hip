@@ -31,34 +31,40 @@ namespace {
 constexpr int QMAX = 6;   // owned rows per thread
 
 template <typename T>
-__device__ inline T *fp(View<T> v, int item) { return v.p + (long)item * v.stride; }
-
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(int n, int count, const int *mask, int ty, int zchunk,
-                                                           int zero_in, T ah, T winv, View<T> b, View<T> uin,
-                                                           View<T> uout)
+__global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
+                                                           double omega, View<T> b, View<T> uin, View<T> uout)
 {
     extern __shared__ unsigned char smem_raw[];
+    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    Pt qs;
+    const int *mask;
+    if (!find_seg(t, bid, qs, mask, [ty, zchunk](int nn) {
+            return (long)((nn + ty - 1) / ty) * ((nn + zchunk - 1) / zchunk);
+        }))
+        return;
+    const int n = qs.n;
     const int rowlanes = (n + 63) & ~63;
     const int RL = rowlanes + 2;
     const int rows = ty + 2;                 // rows of the red update (owned rows)
     T *up = reinterpret_cast<T *>(smem_raw);             // uin plane k: rows j0-2 .. j0+ty+1
     T *wp = up + (size_t)(ty + 4) * RL;                  // 2 planes of the red-updated field
-    const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
     const int ytiles = (n + ty - 1) / ty, zch = (n + zchunk - 1) / zchunk;
     const int item = (int)(bid / (unsigned)(ytiles * zch));
     const int rem = (int)(bid - (unsigned)item * (unsigned)(ytiles * zch));
     const int jt = rem / zch, zc = rem - jt * zch;
-    if (item >= count || (mask && !mask[item])) return;
+    if (mask && !mask[item]) return;
+    qs.item = item;
+    const double ahd = qs.par(alpha) * (double)(n + 1) * (double)(n + 1);
+    const T ah = (T)ahd, winv = (T)(omega / (1.0 + 2.0 * 3 * ahd));
     const int j0 = jt * ty + 1, k0 = zc * zchunk + 1;
     const int k1 = min(k0 + zchunk, n + 1);
     const int rpp = BLOCK / rowlanes;
     const int i = (int)(threadIdx.x % rowlanes) + 1;
     const int rsub = (int)(threadIdx.x / rowlanes);
     const long sy = row_stride(n), sz = plane_stride(n);
-    const T *__restrict__ U = fp(uin, item);
-    const T *__restrict__ Bv = fp(b, item);
-    T *__restrict__ O = fp(uout, item);
+    const T *__restrict__ U = fp(uin, qs);
+    const T *__restrict__ Bv = fp(b, qs);
+    T *__restrict__ O = fp(uout, qs);
     const bool xin = i <= n;
 
     // x index 0 is the boundary: zero once in every LDS row
@@ -172,22 +178,31 @@ int env_int(const char *name, int dflt)
 
 namespace k {
 
-FusedShape rbgs_fused_shape(int n, int count, size_t elem)
+// Rows per workgroup and planes per z-chunk for a launch over the grids of
+// `t` (the same shape for every segment; LDS sized for the widest rows).
+FusedShape rbgs_fused_shape(const Tiling &t, size_t elem)
 {
-    const int rowlanes = (n + 63) & ~63;
-    const int rpp = BLOCK / rowlanes;
-    const int RL = rowlanes + 2;
+    int nmax = 0;
+    long rows_total = 0;
+    for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
+    const int rowlanes = (nmax + 63) & ~63;
     FusedShape f;
     f.ty = env_int("PFMG_RB_TY", rowlanes >= 256 ? 4 : 8);
-    while (f.ty > 1 && (f.ty + 2 + rpp - 1) / rpp > QMAX) f.ty /= 2;
-    const int ytiles = (n + f.ty - 1) / f.ty;
-    const long per_z = (long)count * ytiles;
-    const int target = env_int("PFMG_RB_BLOCKS", 2048);
-    int zch = (int)std::min<long>(std::max<long>(1, (target + per_z - 1) / per_z), std::max(1, n / 4));
-    f.zchunk = env_int("PFMG_RB_ZCH", (n + zch - 1) / zch);
-    zch = (n + f.zchunk - 1) / f.zchunk;
-    f.blocks = per_z * zch;
-    f.lds = (size_t)((f.ty + 4) + 2 * (f.ty + 2)) * RL * elem;
+    for (int sg = 0; sg < t.nseg; ++sg) {
+        const int rpp = BLOCK / ((t.seg_n(sg) + 63) & ~63);
+        while (f.ty > 1 && (f.ty + 2 + rpp - 1) / rpp > QMAX) f.ty /= 2;
+    }
+    for (int sg = 0; sg < t.nseg; ++sg) rows_total += (long)t.seg_count(sg) * ((t.seg_n(sg) + f.ty - 1) / f.ty);
+    const int target = env_int("PFMG_RB_BLOCKS", 1024);
+    int zch = (int)std::min<long>(std::max<long>(1, (target + rows_total - 1) / std::max(1L, rows_total)),
+                                  std::max(1, nmax / 4));
+    f.zchunk = env_int("PFMG_RB_ZCH", (nmax + zch - 1) / zch);
+    f.blocks = 0;
+    for (int sg = 0; sg < t.nseg; ++sg) {
+        const int n = t.seg_n(sg);
+        f.blocks += (long)t.seg_count(sg) * ((n + f.ty - 1) / f.ty) * ((n + f.zchunk - 1) / f.zchunk);
+    }
+    f.lds = (size_t)((f.ty + 4) + 2 * (f.ty + 2)) * (rowlanes + 2) * elem;
     return f;
 }
 
@@ -195,13 +210,13 @@ template <typename T>
 hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in, View<T> b, View<T> uin,
                       View<T> uout, hipStream_t s)
 {
-    if (t.dim != 3 || t.n < 31 || t.n > 255) return hipErrorInvalidValue;
-    if (t.count == 0) return hipSuccess;
-    const double ah = alpha * (double)(t.n + 1) * (double)(t.n + 1);
-    const T ahT = (T)ah, wi = (T)(omega / (1.0 + 6.0 * ah));
-    const FusedShape f = rbgs_fused_shape(t.n, t.count, sizeof(T));
-    rbgs_fused_kernel<T><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t.n, t.count, t.mask, f.ty, f.zchunk,
-                                                                   zero_in ? 1 : 0, ahT, wi, b, uin, uout);
+    if (t.dim != 3) return hipErrorInvalidValue;
+    for (int sg = 0; sg < t.nseg; ++sg)
+        if (t.seg_n(sg) < 31 || t.seg_n(sg) > 255) return hipErrorInvalidValue;
+    const FusedShape f = rbgs_fused_shape(t, sizeof(T));
+    if (f.blocks == 0) return hipSuccess;
+    rbgs_fused_kernel<T><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zero_in ? 1 : 0, alpha, omega, b,
+                                                                   uin, uout);
     return hipGetLastError();
 }
 

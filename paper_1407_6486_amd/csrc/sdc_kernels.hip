@@ -23,68 +23,69 @@ namespace {
 
 constexpr int MAXN = 16;   // nodes per slice upper bound
 
-template <typename T>
-__device__ inline T *fp(View<T> v, int item) { return v.p + (long)item * v.stride; }
 
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void apply_L_kernel(Tiling t, double c, View<double> u, View<double> F)
 {
-    int item, i, j, k; long o;
-    if (!tile_point<DIM>(t, item, i, j, k, o)) return;
-    const double *uu = fp(u, item);
-    const double ih2 = (double)(t.n + 1) * (double)(t.n + 1);
-    fp(F, item)[o] = c * (ih2 * d2sum<DIM>(uu, o, row_stride(t.n), plane_stride(t.n)));
+    Pt q; int i, j, k; long o;
+    if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    const double *uu = fp(u, q);
+    const double ih2 = (double)(q.n + 1) * (double)(q.n + 1);
+    fp(F, q)[o] = q.par(c) * (ih2 * d2sum<DIM>(uu, o, row_stride(q.n), plane_stride(q.n)));
 }
 
 // Column-blocked 3D variant (KZ planes per thread, loads before stores).
 constexpr int KZ = 4;
 __global__ __launch_bounds__(BLOCK) void apply_L_kz_kernel(Tiling t, double c, View<double> u, View<double> F)
 {
-    int item, i, j, k0, nk; long o;
-    if (!tile_col<KZ>(t, item, i, j, k0, nk, o)) return;
-    const long sy = row_stride(t.n), sz = plane_stride(t.n);
-    const double *__restrict__ uu = fp(u, item);
-    double *__restrict__ ff = fp(F, item);
-    const double ih2 = (double)(t.n + 1) * (double)(t.n + 1);
+    Pt q; int i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, q, i, j, k0, nk, o)) return;
+    const long sy = row_stride(q.n), sz = plane_stride(q.n);
+    const double *__restrict__ uu = fp(u, q);
+    double *__restrict__ ff = fp(F, q);
+    const double ih2 = (double)(q.n + 1) * (double)(q.n + 1);
+    const double cc = q.par(c);
     double col[KZ + 2], xs[KZ], ys[KZ];
 #pragma unroll
-    for (int q = 0; q < KZ + 2; ++q) col[q] = q <= nk + 1 ? uu[o + (long)(q - 1) * sz] : 0.0;
+    for (int w = 0; w < KZ + 2; ++w) col[w] = w <= nk + 1 ? uu[o + (long)(w - 1) * sz] : 0.0;
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        if (q < nk) {
-            const long cc = o + (long)q * sz;
-            xs[q] = uu[cc - 1] + uu[cc + 1];
-            ys[q] = uu[cc - sy] + uu[cc + sy];
+    for (int w = 0; w < KZ; ++w) {
+        if (w < nk) {
+            const long ow = o + (long)w * sz;
+            xs[w] = uu[ow - 1] + uu[ow + 1];
+            ys[w] = uu[ow - sy] + uu[ow + sy];
         }
     }
 #pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        if (q < nk) {
-            double s = xs[q];
-            s += ys[q] + (col[q] + col[q + 2]);
-            s -= 6.0 * col[q + 1];
-            ff[o + (long)q * sz] = c * (ih2 * s);
+    for (int w = 0; w < KZ; ++w) {
+        if (w < nk) {
+            double s = xs[w];
+            s += ys[w] + (col[w] + col[w + 2]);
+            s -= 6.0 * col[w + 1];
+            ff[o + (long)w * sz] = cc * (ih2 * s);
         }
     }
 }
 
 // NN > 0 fixes the node count at compile time (node values stay in
 // registers); NN == 0 is the generic path for any count up to MAXN.
+// Per-field scalars (dt, delta) come from the segment when it has them.
 template <int DIM, int NN>
 __global__ __launch_bounds__(BLOCK) void sdc_integrals_kernel(Tiling t, int nn_rt, double dt, const double *__restrict__ S,
                                                               View<double> F, long f_node, View<double> I, long i_node)
 {
     const int nn = NN > 0 ? NN : nn_rt;
-    int item, i, j, k; long o;
-    if (!tile_point<DIM>(t, item, i, j, k, o)) return;
-    const double *f = fp(F, item) + o;
+    Pt q; int i, j, k; long o;
+    if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    const double h = q.par(dt);
+    const double *f = fp(F, q) + o;
     double fv[MAXN];
-    for (int q = 0; q < nn; ++q) fv[q] = f[q * f_node];
-    double *out = fp(I, item) + o;
+    for (int w = 0; w < nn; ++w) fv[w] = f[w * f_node];
+    double *out = fp(I, q) + o;
     for (int m = 0; m + 1 < nn; ++m) {
         double acc = 0.0;
-        for (int q = 0; q < nn; ++q) acc += S[m * nn + q] * fv[q];
-        out[m * i_node] = dt * acc;
+        for (int w = 0; w < nn; ++w) acc += S[m * nn + w] * fv[w];
+        out[m * i_node] = h * acc;
     }
 }
 
@@ -92,41 +93,43 @@ template <int DIM>
 __global__ __launch_bounds__(BLOCK) void sdc_rhs_kernel(Tiling t, double delta, View<double> Um, View<double> Fm1,
                                                         View<double> Im, View<double> t1, View<double> t0, View<double> b)
 {
-    int item, i, j, k; long o;
-    if (!tile_point<DIM>(t, item, i, j, k, o)) return;
-    double v = fp(Um, item)[o] - delta * fp(Fm1, item)[o] + fp(Im, item)[o];
-    if (t1.p) v = v + (fp(t1, item)[o] - fp(t0, item)[o]);
-    fp(b, item)[o] = v;
+    Pt q; int i, j, k; long o;
+    if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    double v = fp(Um, q)[o] - q.par(delta) * fp(Fm1, q)[o] + fp(Im, q)[o];
+    if (t1.p) v = v + (fp(t1, q)[o] - fp(t0, q)[o]);
+    fp(b, q)[o] = v;
 }
 
 struct IntMap {
     int v[MAXN];
 };
 
-// t.n = coarse n.
+// Launched on the coarse grids (q.n = coarse n, fine n = 2 (nc + 1) - 1).
 template <int DIM, int NNF, int NNC>
-__global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nf, int nnf_rt, int nnc_rt, IntMap cmap, double dt,
+__global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nnf_rt, int nnc_rt, IntMap cmap, double dt,
                                                            const double *__restrict__ Qf, View<double> Uf,
                                                            View<double> Ff, long f_node, View<double> Uc,
                                                            View<double> Uold, View<double> Tau, long c_node)
 {
     const int nnf = NNF > 0 ? NNF : nnf_rt, nnc = NNC > 0 ? NNC : nnc_rt;
-    int item, I, J, K; long o;
-    if (!tile_point<DIM>(t, item, I, J, K, o)) return;
+    Pt q; int I, J, K; long o;
+    if (!tile_point<DIM>(t, q, I, J, K, o)) return;
+    const int nf = 2 * (q.n + 1) - 1;
+    const double h = q.par(dt);
     const long fo = DIM == 3 ? 2L * I + 2L * J * row_stride(nf) + 2L * K * plane_stride(nf) : 2L * I;
-    const double *uf = fp(Uf, item) + fo;
-    const double *ff = fp(Ff, item) + fo;
+    const double *uf = fp(Uf, q) + fo;
+    const double *ff = fp(Ff, q) + fo;
     double fv[MAXN];
-    for (int q = 0; q < nnf; ++q) fv[q] = ff[q * f_node];
-    double *uc = fp(Uc, item) + o, *uo = fp(Uold, item) + o, *ta = fp(Tau, item) + o;
+    for (int w = 0; w < nnf; ++w) fv[w] = ff[w * f_node];
+    double *uc = fp(Uc, q) + o, *uo = fp(Uold, q) + o, *ta = fp(Tau, q) + o;
     for (int mc = 0; mc < nnc; ++mc) {
         const int mf = cmap.v[mc];
         const double v = uf[mf * f_node];
         uc[mc * c_node] = v;
         uo[mc * c_node] = v;
         double acc = 0.0;
-        for (int q = 0; q < nnf; ++q) acc += Qf[mf * nnf + q] * fv[q];
-        ta[mc * c_node] = dt * acc;
+        for (int w = 0; w < nnf; ++w) acc += Qf[mf * nnf + w] * fv[w];
+        ta[mc * c_node] = h * acc;
     }
 }
 
@@ -135,16 +138,17 @@ __global__ __launch_bounds__(BLOCK) void fas_tau_kernel(Tiling t, int nnc_rt, do
                                                         View<double> Fc, View<double> Tau, long c_node)
 {
     const int nnc = NNC > 0 ? NNC : nnc_rt;
-    int item, I, J, K; long o;
-    if (!tile_point<DIM>(t, item, I, J, K, o)) return;
-    const double *fc = fp(Fc, item) + o;
+    Pt q; int I, J, K; long o;
+    if (!tile_point<DIM>(t, q, I, J, K, o)) return;
+    const double h = q.par(dt);
+    const double *fc = fp(Fc, q) + o;
     double fv[MAXN];
-    for (int q = 0; q < nnc; ++q) fv[q] = fc[q * c_node];
-    double *ta = fp(Tau, item) + o;
+    for (int w = 0; w < nnc; ++w) fv[w] = fc[w * c_node];
+    double *ta = fp(Tau, q) + o;
     for (int mc = 0; mc < nnc; ++mc) {
         double acc = 0.0;
-        for (int q = 0; q < nnc; ++q) acc += Qc[mc * nnc + q] * fv[q];
-        ta[mc * c_node] = ta[mc * c_node] - dt * acc;
+        for (int w = 0; w < nnc; ++w) acc += Qc[mc * nnc + w] * fv[w];
+        ta[mc * c_node] = ta[mc * c_node] - h * acc;
     }
 }
 
@@ -154,12 +158,12 @@ __global__ __launch_bounds__(BLOCK) void interp_coarse_kernel(Tiling t, int nnf_
                                                               View<double> DC, long dc_node)
 {
     const int nnf = NNF > 0 ? NNF : nnf_rt, nnc = NNC > 0 ? NNC : nnc_rt;
-    int item, I, J, K; long o;
-    if (!tile_point<DIM>(t, item, I, J, K, o)) return;
-    const double *uc = fp(Uc, item) + o, *uo = fp(Uold, item) + o;
+    Pt q; int I, J, K; long o;
+    if (!tile_point<DIM>(t, q, I, J, K, o)) return;
+    const double *uc = fp(Uc, q) + o, *uo = fp(Uold, q) + o;
     double d[MAXN];
     for (int mc = 0; mc < nnc; ++mc) d[mc] = uc[mc * c_node] - uo[mc * c_node];
-    double *dc = fp(DC, item) + o;
+    double *dc = fp(DC, q) + o;
     for (int m = 0; m < nnf; ++m) {
         double acc = 0.0;
         for (int mc = 0; mc < nnc; ++mc) acc += Lt[m * nnc + mc] * d[mc];
@@ -181,34 +185,46 @@ __device__ inline unsigned long long wave_max(unsigned long long v)
     return v;
 }
 
-// item = slice p; U0 = ublock for p = 0, else U[p-1][nn-1].
+// Fields are (problem, slice) pairs, P slices per problem, slice fastest.
+// U0 = the problem's block initial value for slice 0, else U[item-1][nn-1].
 template <int DIM, int NN>
-__global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt, double dt, const double *__restrict__ Q,
-                                                             View<double> U, View<double> F, long node,
-                                                             const double *__restrict__ ublock,
+__global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt, int P, double dt,
+                                                             const double *__restrict__ Q, View<double> U,
+                                                             View<double> F, long node, View<double> ublock,
                                                              unsigned long long *res_bits,
                                                              unsigned long long *u0_bits)
 {
     const int nn = NN > 0 ? NN : nn_rt;
-    int item, i, j, k; long o;
-    const bool ok = tile_point<DIM>(t, item, i, j, k, o);
+    Pt q; int i, j, k; long o;
+    const bool ok = tile_point<DIM>(t, q, i, j, k, o);
     unsigned long long rm = 0, um = 0;
     if (ok) {
-        const double u0 = item == 0 ? ublock[o] : fp(U, item - 1)[o + (nn - 1) * node];
-        const double *uu = fp(U, item) + o, *ff = fp(F, item) + o;
+        const double h = q.par(dt);
+        double u0;
+        if (q.item % P == 0) {
+            Pt qp = q;
+            qp.item = q.item / P;
+            u0 = fp(ublock, qp)[o];
+        } else {
+            Pt qm = q;
+            qm.item = q.item - 1;
+            u0 = fp(U, qm)[o + (nn - 1) * node];
+        }
+        const double *uu = fp(U, q) + o, *ff = fp(F, q) + o;
         double fv[MAXN];
-        for (int q = 0; q < nn; ++q) fv[q] = ff[q * node];
+        for (int w = 0; w < nn; ++w) fv[w] = ff[w * node];
         for (int m = 0; m < nn; ++m) {
             double acc = 0.0;
-            for (int q = 0; q < nn; ++q) acc += Q[m * nn + q] * fv[q];
-            const unsigned long long r = abs_bits(u0 - uu[m * node] + dt * acc);
+            for (int w = 0; w < nn; ++w) acc += Q[m * nn + w] * fv[w];
+            const unsigned long long r = abs_bits(u0 - uu[m * node] + h * acc);
             rm = r > rm ? r : rm;
         }
         um = abs_bits(u0);
     }
-    const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int blk_item = (int)(bid / tiles_per_field(t.n, DIM));
-    if (blk_item >= t.count) return;
+    Pt qb;
+    if (!tile_block_item<DIM>(t, qb)) return;
+    int flat = qb.item;
+    for (int s = 0; s < qb.sg; ++s) flat += t.seg_count(s);
     rm = wave_max(rm);
     um = wave_max(um);
     __shared__ unsigned long long part[2][BLOCK / 64];
@@ -217,43 +233,46 @@ __global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long a = part[0][0], b = part[1][0];
-        for (int q = 1; q < BLOCK / 64; ++q) {
-            a = part[0][q] > a ? part[0][q] : a;
-            b = part[1][q] > b ? part[1][q] : b;
+        for (int w = 1; w < BLOCK / 64; ++w) {
+            a = part[0][w] > a ? part[0][w] : a;
+            b = part[1][w] > b ? part[1][w] : b;
         }
-        const int slot = (int)(bid % (unsigned)k::RSLOTS);
-        if (a) atomicMax(res_bits + (long)blk_item * k::RSLOTS + slot, a);
-        if (b) atomicMax(u0_bits + (long)blk_item * k::RSLOTS + slot, b);
+        const int slot = (int)(blockIdx.x % (unsigned)k::RSLOTS);
+        if (a) atomicMax(res_bits + (long)flat * k::RSLOTS + slot, a);
+        if (b) atomicMax(u0_bits + (long)flat * k::RSLOTS + slot, b);
     }
 }
 
+// Launched on the coarse grids.
 template <int DIM>
-__global__ __launch_bounds__(BLOCK) void inject_kernel(Tiling t, int nf, View<double> uf, View<double> uc)
+__global__ __launch_bounds__(BLOCK) void inject_kernel(Tiling t, View<double> uf, View<double> uc)
 {
-    int item, I, J, K; long o;
-    if (!tile_point<DIM>(t, item, I, J, K, o)) return;
+    Pt q; int I, J, K; long o;
+    if (!tile_point<DIM>(t, q, I, J, K, o)) return;
+    const int nf = 2 * (q.n + 1) - 1;
     const long fo = DIM == 3 ? 2L * I + 2L * J * row_stride(nf) + 2L * K * plane_stride(nf) : 2L * I;
-    fp(uc, item)[o] = fp(uf, item)[fo];
+    fp(uc, q)[o] = fp(uf, q)[fo];
 }
 
+// dense[item][z][y][x] <-> field; single-segment launches.
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void pack_kernel(Tiling t, View<double> f, double *dense)
 {
-    int item, i, j, k; long o;
-    if (!tile_point<DIM>(t, item, i, j, k, o)) return;
-    const long n = t.n;
+    Pt q; int i, j, k; long o;
+    if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    const long n = q.n;
     const long d = DIM == 3 ? (i - 1) + n * ((j - 1) + n * (long)(k - 1)) : i - 1;
-    dense[(long)item * interior_points(t.n, DIM) + d] = fp(f, item)[o];
+    dense[(long)q.item * interior_points(q.n, DIM) + d] = fp(f, q)[o];
 }
 
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void unpack_kernel(Tiling t, const double *dense, View<double> f)
 {
-    int item, i, j, k; long o;
-    if (!tile_point<DIM>(t, item, i, j, k, o)) return;
-    const long n = t.n;
+    Pt q; int i, j, k; long o;
+    if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    const long n = q.n;
     const long d = DIM == 3 ? (i - 1) + n * ((j - 1) + n * (long)(k - 1)) : i - 1;
-    fp(f, item)[o] = dense[(long)item * interior_points(t.n, DIM) + d];
+    fp(f, q)[o] = dense[(long)q.item * interior_points(q.n, DIM) + d];
 }
 
 inline dim3 grid_of(const Tiling &t) { return dim3((unsigned)grid_blocks(t)); }
@@ -289,7 +308,7 @@ namespace k {
 hipError_t apply_L(const Tiling &t, double nu, View<double> u, View<double> F, hipStream_t s)
 {
     if (t.dim == 3 && grid_blocks(t) > 0) {
-        apply_L_kz_kernel<<<(unsigned)(col_tiles_per_field(t.n, KZ) * t.count), BLOCK, 0, s>>>(t, nu, u, F);
+        apply_L_kz_kernel<<<(unsigned)col_blocks<KZ>(t), BLOCK, 0, s>>>(t, nu, u, F);
         return hipGetLastError();
     }
     PFMG_DISPATCH(t, apply_L_kernel, t, nu, u, F);
@@ -310,16 +329,16 @@ hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> 
     PFMG_DISPATCH(t, sdc_rhs_kernel, t, delta, Um, Fm1, Im, tau1, tau0, b);
 }
 
-hipError_t fas_inject(const Tiling &t, int nf, int nnf, int nnc, const int *cmap, double dt, const double *Qf,
+hipError_t fas_inject(const Tiling &t, int nnf, int nnc, const int *cmap, double dt, const double *Qf,
                       View<double> Uf, View<double> Ff, long f_node, View<double> Uc, View<double> Uold,
                       View<double> Tau, long c_node, hipStream_t s)
 {
     if (nnf > MAXN || nnc > MAXN) return hipErrorInvalidValue;
     IntMap m{};
-    for (int q = 0; q < nnc; ++q) m.v[q] = cmap[q];
+    for (int w = 0; w < nnc; ++w) m.v[w] = cmap[w];
     if (nnf == 5 && nnc == 3)
-        PFMG_DISPATCH_N2(t, fas_inject_kernel, 5, 3, t, nf, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
-    PFMG_DISPATCH_N2(t, fas_inject_kernel, 0, 0, t, nf, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
+        PFMG_DISPATCH_N2(t, fas_inject_kernel, 5, 3, t, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
+    PFMG_DISPATCH_N2(t, fas_inject_kernel, 0, 0, t, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
 }
 
 hipError_t fas_tau(const Tiling &t, int nnc, double dt, const double *Qc, View<double> Fc, View<double> Tau,
@@ -339,18 +358,19 @@ hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, Vi
     PFMG_DISPATCH_N2(t, interp_coarse_kernel, 0, 0, t, nnf, nnc, Lt, Uc, Uold, c_node, DC, dc_node);
 }
 
-hipError_t colloc_resid(const Tiling &t, int nn, double dt, const double *Q, View<double> U, View<double> F,
-                        long node, const double *ublock, unsigned long long *res_bits,
+hipError_t colloc_resid(const Tiling &t, int nn, int P, double dt, const double *Q, View<double> U,
+                        View<double> F, long node, View<double> ublock, unsigned long long *res_bits,
                         unsigned long long *u0_bits, hipStream_t s)
 {
-    if (nn > MAXN) return hipErrorInvalidValue;
-    if (nn == 5) PFMG_DISPATCH_N(t, colloc_resid_kernel, 5, t, nn, dt, Q, U, F, node, ublock, res_bits, u0_bits);
-    PFMG_DISPATCH_N(t, colloc_resid_kernel, 0, t, nn, dt, Q, U, F, node, ublock, res_bits, u0_bits);
+    if (nn > MAXN || P < 1) return hipErrorInvalidValue;
+    if (nn == 5)
+        PFMG_DISPATCH_N(t, colloc_resid_kernel, 5, t, nn, P, dt, Q, U, F, node, ublock, res_bits, u0_bits);
+    PFMG_DISPATCH_N(t, colloc_resid_kernel, 0, t, nn, P, dt, Q, U, F, node, ublock, res_bits, u0_bits);
 }
 
-hipError_t inject(const Tiling &t, int nf, View<double> uf, View<double> uc, hipStream_t s)
+hipError_t inject(const Tiling &t, View<double> uf, View<double> uc, hipStream_t s)
 {
-    PFMG_DISPATCH(t, inject_kernel, t, nf, uf, uc);
+    PFMG_DISPATCH(t, inject_kernel, t, uf, uc);
 }
 
 hipError_t pack(const Tiling &t, View<double> f, double *dense, hipStream_t s)

@@ -444,7 +444,7 @@ hipError_t Solver::fas_restrict(int p0, int p1)
     PLevel &Fn = L[0], &Cs = L[1];
     const int count = p1 - p0;
     const long fst = (long)Fn.nn * Fn.fs, cst = (long)Cs.nn * Cs.fs;
-    HC(k::fas_inject(tl(Cs.n, count), Fn.n, Fn.nn, Cs.nn, cmap, p.dt, Fn.dQ,
+    HC(k::fas_inject(tl(Cs.n, count), Fn.nn, Cs.nn, cmap, p.dt, Fn.dQ,
                      View<double>{Fn.slot(Fn.U, p0, 0), fst}, View<double>{Fn.slot(Fn.F, p0, 0), fst}, Fn.fs,
                      View<double>{Cs.slot(Cs.U, p0, 0), cst}, View<double>{Cs.slot(Cs.Uold, p0, 0), cst},
                      View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, Cs.fs, s));
@@ -494,7 +494,7 @@ hipError_t Solver::spread_body()
     HC(k::copy(tl(Fn.n, P * Fn.nn), View<double>{ublock, 0}, View<double>{Fn.U, Fn.fs}, s));
     HC(k::apply_L(tl(Fn.n, P * Fn.nn), p.nu, View<double>{ublock, 0}, View<double>{Fn.F, Fn.fs}, s));
     if (nl > 1) {
-        HC(k::inject(tl(L[1].n, 1), Fn.n, View<double>{ublock, 0}, View<double>{ublock_c, 0}, s));
+        HC(k::inject(tl(L[1].n, 1), View<double>{ublock, 0}, View<double>{ublock_c, 0}, s));
         HC(k::apply_L(tl(L[1].n, 1), p.nu, View<double>{ublock_c, 0}, View<double>{fublock_c, 0}, s));
     }
     return predictor();
@@ -530,8 +530,8 @@ hipError_t Solver::residual_enqueue()
     const long fst = (long)Fn.nn * Fn.fs;
     HC(k::fill_u64(bits, 0, 2 * P * k::RSLOTS, s));
     tstart("colloc_resid", Fn.n, 8.0 * (2 * Fn.nn + 1), interior_points(Fn.n, dim) * P);
-    HC(k::colloc_resid(tl(Fn.n, P), Fn.nn, p.dt, Fn.dQ, View<double>{Fn.U, fst}, View<double>{Fn.F, fst}, Fn.fs,
-                       ublock, bits, bits + (long)P * k::RSLOTS, s));
+    HC(k::colloc_resid(tl(Fn.n, P), Fn.nn, P, p.dt, Fn.dQ, View<double>{Fn.U, fst}, View<double>{Fn.F, fst}, Fn.fs,
+                       View<double>{ublock, 0}, bits, bits + (long)P * k::RSLOTS, s));
     tstop();
     return hipSuccess;
 }

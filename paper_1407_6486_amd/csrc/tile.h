@@ -1,6 +1,11 @@
 // Point-per-thread tiling shared by the grid kernels.
 //
-// A launch covers `count` fields of one grid.  3D: a workgroup of 256
+// A launch covers `count` fields of one grid, or up to MAXSEG segments of
+// fields of different grids (the uneven problems of a batch advance in one
+// launch per multigrid level): segment s has its own n, field count, mask
+// and per-field scalar (the kernel's alpha, delta, nu or dt), and every View
+// its own base and stride per segment.  The workgroups of the segments
+// follow each other in launch order.  3D: a workgroup of 256
 // threads (4 wavefronts) owns a 64 x 4 patch of one z-plane of one field,
 // one wavefront per 64-point row segment, so every wavefront reads and
 // writes whole 512-byte (FP64) row segments.  1D: 256 consecutive points.
@@ -20,11 +25,60 @@ constexpr int TILE_X = 64;
 constexpr int TILE_Y = 4;
 constexpr int BLOCK = 256;
 
-struct Tiling {
-    int n, dim, count;
-    const int *mask;  // optional: fields whose mask is 0 are skipped
-    int noremap = 0;  // 1: keep the hardware workgroup order (no XCD grouping)
+constexpr int MAXSEG = 4;
+
+struct SegX {
+    int n, count;
+    const int *mask;
+    const double *coef;
 };
+
+struct Tiling {
+    int n, dim, count;              // segment 0
+    const int *mask;                // optional: fields whose mask is 0 are skipped
+    int noremap = 0;                // 1: keep the hardware workgroup order (no XCD grouping)
+    const double *coef = nullptr;   // optional per-field scalar of segment 0
+    int nseg = 1;
+    SegX x[MAXSEG - 1] = {};        // segments 1 .. nseg-1
+    __host__ __device__ int seg_n(int s) const { return s == 0 ? n : x[s - 1].n; }
+    __host__ __device__ int seg_count(int s) const { return s == 0 ? count : x[s - 1].count; }
+};
+
+// Where a workgroup landed: segment, field, grid size, per-field scalar.
+struct Pt {
+    int sg, item, n;
+    const double *coef;
+    __device__ double par(double x) const { return coef ? coef[item] : x; }
+};
+
+// Find the segment of local workgroup id `bid` (made segment-relative);
+// per_field(n) is the launch's workgroups per field.
+template <class PF>
+__host__ __device__ inline bool find_seg(const Tiling &t, unsigned &bid, Pt &q, const int *&mask, PF per_field)
+{
+    q.sg = 0;
+    q.n = t.n;
+    q.coef = t.coef;
+    mask = t.mask;
+    unsigned tiles = (unsigned)(per_field(t.n) * t.count);
+    for (int s = 1; s < t.nseg && bid >= tiles; ++s) {
+        bid -= tiles;
+        q.sg = s;
+        q.n = t.x[s - 1].n;
+        q.coef = t.x[s - 1].coef;
+        mask = t.x[s - 1].mask;
+        tiles = (unsigned)(per_field(q.n) * t.x[s - 1].count);
+    }
+    return bid < tiles;
+}
+
+template <class PF>
+__host__ inline long total_blocks(const Tiling &t, PF per_field)
+{
+    long b = 0;
+    for (int s = 0; s < t.nseg; ++s) b += per_field(t.seg_n(s)) * t.seg_count(s);
+    return b;
+}
 
 __host__ __device__ inline long tiles_per_field(int n, int dim)
 {
@@ -32,7 +86,17 @@ __host__ __device__ inline long tiles_per_field(int n, int dim)
     return (n + BLOCK - 1) / BLOCK;
 }
 
-__host__ inline long grid_blocks(const Tiling &t) { return tiles_per_field(t.n, t.dim) * t.count; }
+__host__ inline long grid_blocks(const Tiling &t)
+{
+    const int dim = t.dim;
+    return total_blocks(t, [dim](int n) { return tiles_per_field(n, dim); });
+}
+
+template <typename T>
+__device__ inline T *fp(const View<T> &v, const Pt &q)
+{
+    return q.sg == 0 ? v.p + (long)q.item * v.stride : v.px[q.sg - 1] + (long)q.item * v.sx[q.sg - 1];
+}
 
 __device__ inline unsigned xcd_remap(unsigned bid, unsigned nb)
 {
@@ -46,16 +110,18 @@ __device__ inline unsigned xcd_remap(unsigned bid, unsigned nb)
 // interior or its field is masked off.  i, j, k are 1-based interior
 // indices; `off` the element offset inside the field.
 template <int DIM>
-__device__ inline bool tile_point(const Tiling &t, int &item, int &i, int &j, int &k, long &off)
+__device__ inline bool tile_point(const Tiling &t, Pt &q, int &i, int &j, int &k, long &off)
 {
-    const unsigned bid = t.noremap ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
-    const int n = t.n;
+    unsigned bid = t.noremap ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+    const int *mask;
+    if (!find_seg(t, bid, q, mask, [](int n) { return tiles_per_field(n, DIM); })) return false;
+    const int n = q.n;
     if (DIM == 3) {
         const unsigned gx = (n + TILE_X - 1) / TILE_X, gy = (n + TILE_Y - 1) / TILE_Y;
         const unsigned per_plane = gx * gy;
         const unsigned per_field = per_plane * (unsigned)n;
-        item = (int)(bid / per_field);
-        unsigned rem = bid - (unsigned)item * per_field;
+        q.item = (int)(bid / per_field);
+        unsigned rem = bid - (unsigned)q.item * per_field;
         k = (int)(rem / per_plane) + 1;
         rem -= (unsigned)(k - 1) * per_plane;
         const unsigned jt = rem / gx, it = rem - jt * gx;
@@ -64,15 +130,26 @@ __device__ inline bool tile_point(const Tiling &t, int &item, int &i, int &j, in
         off = (long)i + (long)j * row_stride(n) + (long)k * plane_stride(n);
     } else {
         const unsigned per_field = (n + BLOCK - 1) / BLOCK;
-        item = (int)(bid / per_field);
-        const unsigned rem = bid - (unsigned)item * per_field;
+        q.item = (int)(bid / per_field);
+        const unsigned rem = bid - (unsigned)q.item * per_field;
         i = (int)(rem * BLOCK + threadIdx.x) + 1;
         j = k = 1;
         off = i;
     }
-    if (item >= t.count) return false;
-    if (t.mask && !t.mask[item]) return false;
+    if (mask && !mask[q.item]) return false;
     return i <= n && j <= n && k <= n;
+}
+
+// The field a workgroup of a point-tiled launch belongs to (all its threads
+// share it), or -1 past the end.
+template <int DIM>
+__device__ inline bool tile_block_item(const Tiling &t, Pt &q)
+{
+    unsigned bid = t.noremap ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+    const int *mask;
+    if (!find_seg(t, bid, q, mask, [](int n) { return tiles_per_field(n, DIM); })) return false;
+    q.item = (int)(bid / (unsigned)tiles_per_field(q.n, DIM));
+    return true;
 }
 
 // Column tiling for 3D streaming stencils: a thread owns one (i, j) column
@@ -85,15 +162,17 @@ __host__ __device__ inline long col_tiles_per_field(int n, int kz)
 }
 
 template <int KZ>
-__device__ inline bool tile_col(const Tiling &t, int &item, int &i, int &j, int &k0, int &nk, long &off)
+__device__ inline bool tile_col(const Tiling &t, Pt &q, int &i, int &j, int &k0, int &nk, long &off)
 {
-    const unsigned bid = t.noremap ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
-    const int n = t.n;
+    unsigned bid = t.noremap ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+    const int *mask;
+    if (!find_seg(t, bid, q, mask, [](int n) { return col_tiles_per_field(n, KZ); })) return false;
+    const int n = q.n;
     const unsigned gx = (n + TILE_X - 1) / TILE_X, gy = (n + TILE_Y - 1) / TILE_Y, gz = (n + KZ - 1) / KZ;
     const unsigned per_plane = gx * gy;
     const unsigned per_field = per_plane * gz;
-    item = (int)(bid / per_field);
-    unsigned rem = bid - (unsigned)item * per_field;
+    q.item = (int)(bid / per_field);
+    unsigned rem = bid - (unsigned)q.item * per_field;
     const int kc = (int)(rem / per_plane);
     rem -= (unsigned)kc * per_plane;
     const unsigned jt = rem / gx, it = rem - jt * gx;
@@ -102,9 +181,14 @@ __device__ inline bool tile_col(const Tiling &t, int &item, int &i, int &j, int 
     k0 = kc * KZ + 1;
     nk = n - k0 + 1 < KZ ? n - k0 + 1 : KZ;
     off = (long)i + (long)j * row_stride(n) + (long)k0 * plane_stride(n);
-    if (item >= t.count) return false;
-    if (t.mask && !t.mask[item]) return false;
+    if (mask && !mask[q.item]) return false;
     return i <= n && j <= n;
+}
+
+template <int KZ>
+__host__ inline long col_blocks(const Tiling &t)
+{
+    return total_blocks(t, [](int n) { return col_tiles_per_field(n, KZ); });
 }
 
 // Sum over dimensions of the 3-point second differences (not divided by h^2).

@@ -202,6 +202,59 @@ pfmg_status pfmg_timing_enable(pfmg_ctx *ctx, const char *kernel, int32_t enable
 pfmg_status pfmg_timing_read(pfmg_ctx *ctx, int64_t *launches, double *ms_total,
                              double *bytes_total);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent problems advanced together.
+ *
+ * The problems share every method parameter except n, nu and dt (the same
+ * dim, slices, nodes, smoother, sweeps, omega, V-cycles per solve >= 1,
+ * precision, pfasst_tol and pfasst_max_iter); each runs exactly the
+ * algorithm of a single context.  Problems of one grid size form a group
+ * and every kernel launch covers all groups (one launch per multigrid level
+ * and leg for every (problem, slice) pair that has that level; the fused
+ * red-black sweep's tile shape comes from the built-in autotuner).  After
+ * the first call, block starts and iterations replay captured HIP graphs.
+ * A problem whose block residual reaches pfasst_tol is frozen: later
+ * iterations skip it, so its state stays the one at its own convergence.
+ * At most 64 slices per problem.
+ * ---------------------------------------------------------------------- */
+typedef struct pfmg_batch pfmg_batch;
+
+/* Device bytes for a batch of n_problems problems (per_problem[0..n-1]). */
+pfmg_status pfmg_batch_workspace_bytes(const pfmg_params *per_problem, int32_t n_problems,
+                                       size_t *bytes_out);
+/* Create a batch; workspace and stream rules as for pfmg_create. */
+pfmg_status pfmg_batch_create(const pfmg_params *per_problem, int32_t n_problems, void *workspace,
+                              size_t bytes, void *hip_stream, pfmg_batch **out);
+pfmg_status pfmg_batch_destroy(pfmg_batch *b);
+/* Start a block for every problem: u0 holds the problems' dense initial
+ * values one after the other in problem order (n_q^dim float64 each), on
+ * the host or the device.  Runs each problem's predictor and makes every
+ * problem active again. */
+pfmg_status pfmg_batch_set_initial(pfmg_batch *b, const double *u0, int32_t on_device);
+/* One IPFASST iteration of every active problem.  res_out (may be NULL,
+ * else n_problems doubles) receives each problem's latest block residual
+ * (frozen problems keep the value they converged with). */
+pfmg_status pfmg_batch_pfasst_iter(pfmg_batch *b, double *res_out);
+/* set_initial, then iterations until every problem is frozen or
+ * pfasst_max_iter.  iters_out / res_out (may be NULL, else n_problems
+ * entries): iterations each problem ran, its final block residual.
+ * PFMG_NOT_CONVERGED if a problem did not reach pfasst_tol. */
+pfmg_status pfmg_batch_run(pfmg_batch *b, const double *u0, int32_t on_device, int32_t *iters_out,
+                           double *res_out);
+/* As pfmg_get, for problem `problem`. */
+pfmg_status pfmg_batch_get(pfmg_batch *b, int32_t problem, int32_t field, int32_t slice, int32_t node,
+                           double *dst, int32_t on_device);
+/* V-cycles run by node solves on level 0 / 1, summed over problems and
+ * slices. */
+pfmg_status pfmg_batch_vcycle_count(pfmg_batch *b, int32_t level, int64_t *count_out);
+
+/* Red-black launch-shape autotuner: the number of configurations in the
+ * process-wide table, and the entry for a key ("<arch>/rbgs/<f64|f32>/"
+ * followed by n x fields per segment joined by '+'), written to buf as
+ * "fused ty zchunk blocks" ("" if absent). */
+pfmg_status pfmg_tune_count(int32_t *count_out);
+pfmg_status pfmg_tune_lookup(const char *key, char *buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

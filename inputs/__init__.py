@@ -57,6 +57,8 @@ def sine_mode(n: int, k, dim: int = 3) -> np.ndarray:
 def draw_modes(rng: np.random.Generator, n: int, n_modes: int = 32, kmax: int | None = None) -> Modes:
     K = kmax if kmax is not None else min(16, (n + 1) // 4)
     K = max(K, 2)
+    # small grids have fewer distinct modes than asked for: take them all
+    n_modes = min(n_modes, K ** 3 - 1)
     seen = {(1, 1, 1)}
     ks = []
     while len(ks) < n_modes:

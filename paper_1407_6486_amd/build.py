@@ -15,7 +15,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfmg.so")
 ARCH = os.environ.get("PFMG_ARCH", "gfx950")
 
-SOURCES = ["mg_kernels.hip", "rbgs_fused.hip", "bottom.hip", "sdc_kernels.hip", "solver.hip", "capi.hip", "collocation.cpp"]
+SOURCES = ["mg_kernels.hip", "rbgs_fused.hip", "bottom.hip", "sdc_kernels.hip", "tune.hip", "solver.hip", "batch.hip",
+           "capi.hip",
+           "collocation.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

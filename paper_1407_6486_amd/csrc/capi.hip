@@ -4,14 +4,21 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
 
+#include "batch.h"
 #include "solver.h"
+#include "tune.h"
 
 struct pfmg_ctx {
     pfmg::Solver sv;
+};
+
+struct pfmg_batch {
+    pfmg::BatchSolver bs;
 };
 
 namespace {
@@ -317,6 +324,141 @@ pfmg_status pfmg_timing_read(pfmg_ctx *ctx, int64_t *launches, double *ms_total,
     if (launches) *launches = t.launches;
     if (ms_total) *ms_total = ms;
     if (bytes_total) *bytes_total = t.bytes;
+    return PFMG_OK;
+}
+
+// ------------------------------------------------------------------ batch
+pfmg_status pfmg_batch_workspace_bytes(const pfmg_params *pp, int32_t np, size_t *bytes_out)
+{
+    if (!pp || !bytes_out) return fail(PFMG_ERR_ARG, "null argument");
+    std::string why;
+    if (!pfmg::BatchSolver::validate(pp, np, why)) return fail(PFMG_ERR_ARG, why);
+    pfmg::BatchSolver tmp;
+    if (!tmp.init_host(pp, np, why)) return fail(PFMG_ERR_ARG, why);
+    *bytes_out = tmp.carve(nullptr);
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_batch_create(const pfmg_params *pp, int32_t np, void *workspace, size_t bytes, void *hip_stream,
+                              pfmg_batch **out)
+{
+    if (!pp || !out) return fail(PFMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    std::string why;
+    if (!pfmg::BatchSolver::validate(pp, np, why)) return fail(PFMG_ERR_ARG, why);
+    pfmg_batch *c = new (std::nothrow) pfmg_batch;
+    if (!c) return fail(PFMG_ERR_ARG, "out of host memory");
+    pfmg::BatchSolver &bs = c->bs;
+    if (!bs.init_host(pp, np, why)) { delete c; return fail(PFMG_ERR_ARG, why); }
+    const size_t need = bs.carve(nullptr);
+    if (!workspace || bytes < need) {
+        delete c;
+        return fail(PFMG_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    }
+    if (((uintptr_t)workspace & 255) != 0) { delete c; return fail(PFMG_ERR_WORKSPACE, "workspace must be 256-byte aligned"); }
+    bs.s = (hipStream_t)hip_stream;
+    bs.carve((char *)workspace);
+    const size_t nb = (size_t)2 * bs.total_items * pfmg::k::RSLOTS;
+    hipError_t e = hipHostMalloc((void **)&bs.hbits, sizeof(unsigned long long) * nb, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&bs.hact, sizeof(int) * bs.act_init.size(), hipHostMallocDefault);
+    // zero the whole workspace once: halos carry the Dirichlet data
+    if (e == hipSuccess) e = hipMemsetAsync(workspace, 0, need, bs.s);
+    if (e == hipSuccess) e = bs.upload();
+    if (e != hipSuccess) {
+        if (bs.hbits) (void)hipHostFree(bs.hbits);
+        if (bs.hact) (void)hipHostFree(bs.hact);
+        delete c;
+        return hip_fail(e, "pfmg_batch_create");
+    }
+    *out = c;
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_batch_destroy(pfmg_batch *b)
+{
+    if (!b) return PFMG_OK;
+    pfmg::BatchSolver &bs = b->bs;
+    (void)hipStreamSynchronize(bs.s);
+    bs.release();
+    if (bs.hbits) (void)hipHostFree(bs.hbits);
+    if (bs.hact) (void)hipHostFree(bs.hact);
+    delete b;
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_batch_set_initial(pfmg_batch *b, const double *u0, int32_t on_device)
+{
+    if (!b || !u0) return fail(PFMG_ERR_ARG, "null argument");
+    HIPCALL(b->bs.set_initial(u0, on_device != 0), "batch set_initial");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_batch_pfasst_iter(pfmg_batch *b, double *res_out)
+{
+    if (!b) return fail(PFMG_ERR_ARG, "null batch");
+    pfmg::BatchSolver &bs = b->bs;
+    if (!bs.has_state) return fail(PFMG_ERR_STATE, "set_initial first");
+    HIPCALL(bs.iterate(), "batch iteration");
+    if (res_out) std::memcpy(res_out, bs.res.data(), sizeof(double) * bs.NP);
+    if (bs.nan) return fail(PFMG_ERR_NAN, "a residual evaluated to NaN or Inf");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_batch_run(pfmg_batch *b, const double *u0, int32_t on_device, int32_t *iters_out, double *res_out)
+{
+    pfmg_status st = pfmg_batch_set_initial(b, u0, on_device);
+    if (st < 0) return st;
+    pfmg::BatchSolver &bs = b->bs;
+    for (int it = 0; it < bs.p.pfasst_max_iter; ++it) {
+        bool any = false;
+        for (char a : bs.active) any = any || a;
+        if (!any) break;
+        st = pfmg_batch_pfasst_iter(b, nullptr);
+        if (st < 0) return st;
+    }
+    bool all = true;
+    for (int q = 0; q < bs.NP; ++q) {
+        if (iters_out) iters_out[q] = bs.iters[q];
+        if (res_out) res_out[q] = bs.res[q];
+        all = all && !bs.active[q];
+    }
+    return all ? PFMG_OK : PFMG_NOT_CONVERGED;
+}
+
+pfmg_status pfmg_batch_get(pfmg_batch *b, int32_t problem, int32_t field, int32_t slice, int32_t node, double *dst,
+                           int32_t on_device)
+{
+    if (!b || !dst) return fail(PFMG_ERR_ARG, "null argument");
+    pfmg::BatchSolver &bs = b->bs;
+    if (problem < 0 || problem >= bs.NP) return fail(PFMG_ERR_ARG, "bad problem");
+    if (field < PFMG_U_FINE || field > PFMG_U_COARSE_OLD) return fail(PFMG_ERR_ARG, "bad field");
+    const bool coarse = field >= PFMG_U_COARSE;
+    if (coarse && bs.nl < 2) return fail(PFMG_ERR_ARG, "no coarse level");
+    if (slice < 0 || slice >= bs.P || node < 0 || node >= bs.nn[coarse ? 1 : 0])
+        return fail(PFMG_ERR_ARG, "bad slice or node");
+    HIPCALL(bs.get(problem, field, slice, node, dst, on_device != 0), "batch get");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_batch_vcycle_count(pfmg_batch *b, int32_t level, int64_t *count_out)
+{
+    if (!b || !count_out || level < 0 || level > 1) return fail(PFMG_ERR_ARG, "bad argument");
+    *count_out = b->bs.vcount[level];
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_tune_count(int32_t *count_out)
+{
+    if (!count_out) return fail(PFMG_ERR_ARG, "null argument");
+    *count_out = pfmg::tune_table_size();
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_tune_lookup(const char *key, char *buf, size_t len)
+{
+    if (!key || !buf || len == 0) return fail(PFMG_ERR_ARG, "null argument");
+    const std::string v = pfmg::tune_lookup(key);
+    std::snprintf(buf, len, "%s", v.c_str());
     return PFMG_OK;
 }
 

@@ -34,12 +34,13 @@ struct FusedShape {
     long blocks;
     size_t lds;
 };
-FusedShape rbgs_fused_shape(const Tiling &t, size_t elem);
+FusedShape rbgs_fused_shape(const Tiling &t, size_t elem, int ty = 0, int target_blocks = 0);
 // One whole red-black sweep out of place (3D, 31 <= n <= 255): uout =
 // RBGS(uin); zero_in treats uin as 0 (first sweep of a coarse correction).
+// shape: a shape from rbgs_fused_shape for this tiling (nullptr: default).
 template <typename T>
 hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in, View<T> b, View<T> uin,
-                      View<T> uout, hipStream_t s);
+                      View<T> uout, hipStream_t s, const FusedShape *shape = nullptr);
 // Red pass from u = 0: red points omega b / diag(H), black points 0.
 template <typename T>
 hipError_t rbgs_zero_red(const Tiling &t, double alpha, double omega, View<T> b, View<T> u,
@@ -80,9 +81,11 @@ hipError_t resid_norm(const Tiling &t, double alpha, View<double> b, View<double
 // ------------------------------------------------------------ method ops
 // F = nu L_h u
 hipError_t apply_L(const Tiling &t, double nu, View<double> u, View<double> F, hipStream_t s);
+// Node stacks: a view's field q points at node 0 of a slice; node m sits
+// m slot strides (node_stride of the grid) further.
 // I[m] = dt sum_i S[m][i] F[i], m = 0..nn-2, per slice (item = slice).
 hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, View<double> F,
-                         long f_node, View<double> I, long i_node, hipStream_t s);
+                         View<double> I, hipStream_t s);
 // b = U[m] - delta F[m+1] + I[m] (+ tau1 - tau0 when tau1.p != nullptr)
 hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> Fm1,
                    View<double> Im, View<double> tau1, View<double> tau0, View<double> b,
@@ -90,23 +93,21 @@ hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> 
 // FAS injection (t on the coarse grids): Uc[mc] = Uold[mc] = Uf[cmap[mc]] at
 // 2J, Tau[mc] = dt sum_i Qf[cmap[mc]][i] Ff[i] at 2J.
 hipError_t fas_inject(const Tiling &t, int nnf, int nnc, const int *cmap, double dt,
-                      const double *Qf, View<double> Uf, View<double> Ff, long f_node,
-                      View<double> Uc, View<double> Uold, View<double> Tau, long c_node,
-                      hipStream_t s);
+                      const double *Qf, View<double> Uf, View<double> Ff,
+                      View<double> Uc, View<double> Uold, View<double> Tau, hipStream_t s);
 // Tau[mc] -= dt sum_j Qc[mc][j] Fc[j]   (t.n = coarse n)
 hipError_t fas_tau(const Tiling &t, int nnc, double dt, const double *Qc, View<double> Fc,
-                   View<double> Tau, long c_node, hipStream_t s);
+                   View<double> Tau, hipStream_t s);
 // DC[m] = sum_mc Lt[m][mc] (Uc[mc] - Uold[mc]), m = 0..nnf-1 (t.n = coarse n)
 hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, View<double> Uc,
-                         View<double> Uold, long c_node, View<double> DC, long dc_node,
-                         hipStream_t s);
+                         View<double> Uold, View<double> DC, hipStream_t s);
 // Collocation residual (eq. resid) per slice; each slice's maxima go to
 // RSLOTS partial slots (res_bits[p * RSLOTS + w]); bits preset to 0.
 constexpr int RSLOTS = 64;
 // Fields are (problem, slice) pairs with P slices per problem; ublock holds
 // one block initial value per problem.
 hipError_t colloc_resid(const Tiling &t, int nn, int P, double dt, const double *Q, View<double> U,
-                        View<double> F, long node, View<double> ublock,
+                        View<double> F, View<double> ublock,
                         unsigned long long *res_bits, unsigned long long *u0_bits, hipStream_t s);
 // Point-wise injection uc(J) = uf(2J) (t on the coarse grids).
 hipError_t inject(const Tiling &t, View<double> uf, View<double> uc, hipStream_t s);

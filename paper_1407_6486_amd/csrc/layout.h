@@ -45,6 +45,10 @@ PFMG_HD inline long field_stride(int n, int dim, size_t elem_bytes)
     return (long)(bytes / elem_bytes);
 }
 
+// The nodes of one slice (and the slices of a level) sit in consecutive
+// slots, so the distance between node m and m+1 of a grid is its slot stride.
+PFMG_HD inline long node_stride(int n, int dim) { return field_stride(n, dim, sizeof(double)); }
+
 PFMG_HD inline long interior_points(int n, int dim)
 {
     return dim == 3 ? (long)n * n * n : (long)n;

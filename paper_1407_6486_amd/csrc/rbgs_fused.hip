@@ -180,23 +180,26 @@ namespace k {
 
 // Rows per workgroup and planes per z-chunk for a launch over the grids of
 // `t` (the same shape for every segment; LDS sized for the widest rows).
-FusedShape rbgs_fused_shape(const Tiling &t, size_t elem)
+// ty / target_blocks = 0 take the defaults (8 rows, 4 for 256-lane rows;
+// about 1024 workgroups); ty is halved until every thread owns at most QMAX
+// rows.
+FusedShape rbgs_fused_shape(const Tiling &t, size_t elem, int ty, int target_blocks)
 {
     int nmax = 0;
     long rows_total = 0;
     for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
     const int rowlanes = (nmax + 63) & ~63;
     FusedShape f;
-    f.ty = env_int("PFMG_RB_TY", rowlanes >= 256 ? 4 : 8);
+    f.ty = ty > 0 ? ty : env_int("PFMG_RB_TY", rowlanes >= 256 ? 4 : 8);
     for (int sg = 0; sg < t.nseg; ++sg) {
         const int rpp = BLOCK / ((t.seg_n(sg) + 63) & ~63);
         while (f.ty > 1 && (f.ty + 2 + rpp - 1) / rpp > QMAX) f.ty /= 2;
     }
     for (int sg = 0; sg < t.nseg; ++sg) rows_total += (long)t.seg_count(sg) * ((t.seg_n(sg) + f.ty - 1) / f.ty);
-    const int target = env_int("PFMG_RB_BLOCKS", 1024);
+    const int target = target_blocks > 0 ? target_blocks : env_int("PFMG_RB_BLOCKS", 1024);
     int zch = (int)std::min<long>(std::max<long>(1, (target + rows_total - 1) / std::max(1L, rows_total)),
                                   std::max(1, nmax / 4));
-    f.zchunk = env_int("PFMG_RB_ZCH", (nmax + zch - 1) / zch);
+    f.zchunk = target_blocks > 0 ? (nmax + zch - 1) / zch : env_int("PFMG_RB_ZCH", (nmax + zch - 1) / zch);
     f.blocks = 0;
     for (int sg = 0; sg < t.nseg; ++sg) {
         const int n = t.seg_n(sg);
@@ -208,12 +211,21 @@ FusedShape rbgs_fused_shape(const Tiling &t, size_t elem)
 
 template <typename T>
 hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in, View<T> b, View<T> uin,
-                      View<T> uout, hipStream_t s)
+                      View<T> uout, hipStream_t s, const FusedShape *shape)
 {
     if (t.dim != 3) return hipErrorInvalidValue;
     for (int sg = 0; sg < t.nseg; ++sg)
         if (t.seg_n(sg) < 31 || t.seg_n(sg) > 255) return hipErrorInvalidValue;
-    const FusedShape f = rbgs_fused_shape(t, sizeof(T));
+    const FusedShape f = shape ? *shape : rbgs_fused_shape(t, sizeof(T));
+    // the kernel derives its tiles from ty and zchunk: reject shapes the
+    // launch does not cover exactly
+    const FusedShape chk = rbgs_fused_shape(t, sizeof(T), f.ty, 1);
+    long blocks = 0;
+    for (int sg = 0; sg < t.nseg; ++sg) {
+        const int n = t.seg_n(sg);
+        blocks += (long)t.seg_count(sg) * ((n + f.ty - 1) / f.ty) * ((n + f.zchunk - 1) / f.zchunk);
+    }
+    if (f.ty < 1 || f.ty != chk.ty || f.zchunk < 1 || blocks != f.blocks || f.lds != chk.lds) return hipErrorInvalidValue;
     if (f.blocks == 0) return hipSuccess;
     rbgs_fused_kernel<T><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zero_in ? 1 : 0, alpha, omega, b,
                                                                    uin, uout);
@@ -221,9 +233,9 @@ hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in,
 }
 
 template hipError_t rbgs_fused<double>(const Tiling &, double, double, bool, View<double>, View<double>,
-                                       View<double>, hipStream_t);
+                                       View<double>, hipStream_t, const FusedShape *);
 template hipError_t rbgs_fused<float>(const Tiling &, double, double, bool, View<float>, View<float>, View<float>,
-                                      hipStream_t);
+                                      hipStream_t, const FusedShape *);
 
 }  // namespace k
 }  // namespace pfmg

@@ -72,11 +72,12 @@ __global__ __launch_bounds__(BLOCK) void apply_L_kz_kernel(Tiling t, double c, V
 // Per-field scalars (dt, delta) come from the segment when it has them.
 template <int DIM, int NN>
 __global__ __launch_bounds__(BLOCK) void sdc_integrals_kernel(Tiling t, int nn_rt, double dt, const double *__restrict__ S,
-                                                              View<double> F, long f_node, View<double> I, long i_node)
+                                                              View<double> F, View<double> I)
 {
     const int nn = NN > 0 ? NN : nn_rt;
     Pt q; int i, j, k; long o;
     if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    const long f_node = node_stride(q.n, DIM), i_node = f_node;
     const double h = q.par(dt);
     const double *f = fp(F, q) + o;
     double fv[MAXN];
@@ -108,13 +109,14 @@ struct IntMap {
 template <int DIM, int NNF, int NNC>
 __global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nnf_rt, int nnc_rt, IntMap cmap, double dt,
                                                            const double *__restrict__ Qf, View<double> Uf,
-                                                           View<double> Ff, long f_node, View<double> Uc,
-                                                           View<double> Uold, View<double> Tau, long c_node)
+                                                           View<double> Ff, View<double> Uc,
+                                                           View<double> Uold, View<double> Tau)
 {
     const int nnf = NNF > 0 ? NNF : nnf_rt, nnc = NNC > 0 ? NNC : nnc_rt;
     Pt q; int I, J, K; long o;
     if (!tile_point<DIM>(t, q, I, J, K, o)) return;
     const int nf = 2 * (q.n + 1) - 1;
+    const long f_node = node_stride(nf, DIM), c_node = node_stride(q.n, DIM);
     const double h = q.par(dt);
     const long fo = DIM == 3 ? 2L * I + 2L * J * row_stride(nf) + 2L * K * plane_stride(nf) : 2L * I;
     const double *uf = fp(Uf, q) + fo;
@@ -135,11 +137,12 @@ __global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nnf_rt,
 
 template <int DIM, int NNC>
 __global__ __launch_bounds__(BLOCK) void fas_tau_kernel(Tiling t, int nnc_rt, double dt, const double *__restrict__ Qc,
-                                                        View<double> Fc, View<double> Tau, long c_node)
+                                                        View<double> Fc, View<double> Tau)
 {
     const int nnc = NNC > 0 ? NNC : nnc_rt;
     Pt q; int I, J, K; long o;
     if (!tile_point<DIM>(t, q, I, J, K, o)) return;
+    const long c_node = node_stride(q.n, DIM);
     const double h = q.par(dt);
     const double *fc = fp(Fc, q) + o;
     double fv[MAXN];
@@ -154,12 +157,12 @@ __global__ __launch_bounds__(BLOCK) void fas_tau_kernel(Tiling t, int nnc_rt, do
 
 template <int DIM, int NNF, int NNC>
 __global__ __launch_bounds__(BLOCK) void interp_coarse_kernel(Tiling t, int nnf_rt, int nnc_rt, const double *__restrict__ Lt,
-                                                              View<double> Uc, View<double> Uold, long c_node,
-                                                              View<double> DC, long dc_node)
+                                                              View<double> Uc, View<double> Uold, View<double> DC)
 {
     const int nnf = NNF > 0 ? NNF : nnf_rt, nnc = NNC > 0 ? NNC : nnc_rt;
     Pt q; int I, J, K; long o;
     if (!tile_point<DIM>(t, q, I, J, K, o)) return;
+    const long c_node = node_stride(q.n, DIM), dc_node = c_node;
     const double *uc = fp(Uc, q) + o, *uo = fp(Uold, q) + o;
     double d[MAXN];
     for (int mc = 0; mc < nnc; ++mc) d[mc] = uc[mc * c_node] - uo[mc * c_node];
@@ -190,7 +193,7 @@ __device__ inline unsigned long long wave_max(unsigned long long v)
 template <int DIM, int NN>
 __global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt, int P, double dt,
                                                              const double *__restrict__ Q, View<double> U,
-                                                             View<double> F, long node, View<double> ublock,
+                                                             View<double> F, View<double> ublock,
                                                              unsigned long long *res_bits,
                                                              unsigned long long *u0_bits)
 {
@@ -199,6 +202,7 @@ __global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt
     const bool ok = tile_point<DIM>(t, q, i, j, k, o);
     unsigned long long rm = 0, um = 0;
     if (ok) {
+        const long node = node_stride(q.n, DIM);
         const double h = q.par(dt);
         double u0;
         if (q.item % P == 0) {
@@ -314,13 +318,13 @@ hipError_t apply_L(const Tiling &t, double nu, View<double> u, View<double> F, h
     PFMG_DISPATCH(t, apply_L_kernel, t, nu, u, F);
 }
 
-hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, View<double> F, long f_node,
-                         View<double> I, long i_node, hipStream_t s)
+hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, View<double> F, View<double> I,
+                         hipStream_t s)
 {
     if (nn > MAXN) return hipErrorInvalidValue;
-    if (nn == 5) PFMG_DISPATCH_N(t, sdc_integrals_kernel, 5, t, nn, dt, S, F, f_node, I, i_node);
-    if (nn == 3) PFMG_DISPATCH_N(t, sdc_integrals_kernel, 3, t, nn, dt, S, F, f_node, I, i_node);
-    PFMG_DISPATCH_N(t, sdc_integrals_kernel, 0, t, nn, dt, S, F, f_node, I, i_node);
+    if (nn == 5) PFMG_DISPATCH_N(t, sdc_integrals_kernel, 5, t, nn, dt, S, F, I);
+    if (nn == 3) PFMG_DISPATCH_N(t, sdc_integrals_kernel, 3, t, nn, dt, S, F, I);
+    PFMG_DISPATCH_N(t, sdc_integrals_kernel, 0, t, nn, dt, S, F, I);
 }
 
 hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> Fm1, View<double> Im,
@@ -330,42 +334,40 @@ hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> 
 }
 
 hipError_t fas_inject(const Tiling &t, int nnf, int nnc, const int *cmap, double dt, const double *Qf,
-                      View<double> Uf, View<double> Ff, long f_node, View<double> Uc, View<double> Uold,
-                      View<double> Tau, long c_node, hipStream_t s)
+                      View<double> Uf, View<double> Ff, View<double> Uc, View<double> Uold, View<double> Tau,
+                      hipStream_t s)
 {
     if (nnf > MAXN || nnc > MAXN) return hipErrorInvalidValue;
     IntMap m{};
     for (int w = 0; w < nnc; ++w) m.v[w] = cmap[w];
     if (nnf == 5 && nnc == 3)
-        PFMG_DISPATCH_N2(t, fas_inject_kernel, 5, 3, t, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
-    PFMG_DISPATCH_N2(t, fas_inject_kernel, 0, 0, t, nnf, nnc, m, dt, Qf, Uf, Ff, f_node, Uc, Uold, Tau, c_node);
+        PFMG_DISPATCH_N2(t, fas_inject_kernel, 5, 3, t, nnf, nnc, m, dt, Qf, Uf, Ff, Uc, Uold, Tau);
+    PFMG_DISPATCH_N2(t, fas_inject_kernel, 0, 0, t, nnf, nnc, m, dt, Qf, Uf, Ff, Uc, Uold, Tau);
 }
 
 hipError_t fas_tau(const Tiling &t, int nnc, double dt, const double *Qc, View<double> Fc, View<double> Tau,
-                   long c_node, hipStream_t s)
+                   hipStream_t s)
 {
     if (nnc > MAXN) return hipErrorInvalidValue;
-    if (nnc == 3) PFMG_DISPATCH_N(t, fas_tau_kernel, 3, t, nnc, dt, Qc, Fc, Tau, c_node);
-    PFMG_DISPATCH_N(t, fas_tau_kernel, 0, t, nnc, dt, Qc, Fc, Tau, c_node);
+    if (nnc == 3) PFMG_DISPATCH_N(t, fas_tau_kernel, 3, t, nnc, dt, Qc, Fc, Tau);
+    PFMG_DISPATCH_N(t, fas_tau_kernel, 0, t, nnc, dt, Qc, Fc, Tau);
 }
 
 hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, View<double> Uc,
-                         View<double> Uold, long c_node, View<double> DC, long dc_node, hipStream_t s)
+                         View<double> Uold, View<double> DC, hipStream_t s)
 {
     if (nnf > MAXN || nnc > MAXN) return hipErrorInvalidValue;
-    if (nnf == 5 && nnc == 3)
-        PFMG_DISPATCH_N2(t, interp_coarse_kernel, 5, 3, t, nnf, nnc, Lt, Uc, Uold, c_node, DC, dc_node);
-    PFMG_DISPATCH_N2(t, interp_coarse_kernel, 0, 0, t, nnf, nnc, Lt, Uc, Uold, c_node, DC, dc_node);
+    if (nnf == 5 && nnc == 3) PFMG_DISPATCH_N2(t, interp_coarse_kernel, 5, 3, t, nnf, nnc, Lt, Uc, Uold, DC);
+    PFMG_DISPATCH_N2(t, interp_coarse_kernel, 0, 0, t, nnf, nnc, Lt, Uc, Uold, DC);
 }
 
 hipError_t colloc_resid(const Tiling &t, int nn, int P, double dt, const double *Q, View<double> U,
-                        View<double> F, long node, View<double> ublock, unsigned long long *res_bits,
+                        View<double> F, View<double> ublock, unsigned long long *res_bits,
                         unsigned long long *u0_bits, hipStream_t s)
 {
     if (nn > MAXN || P < 1) return hipErrorInvalidValue;
-    if (nn == 5)
-        PFMG_DISPATCH_N(t, colloc_resid_kernel, 5, t, nn, P, dt, Q, U, F, node, ublock, res_bits, u0_bits);
-    PFMG_DISPATCH_N(t, colloc_resid_kernel, 0, t, nn, P, dt, Q, U, F, node, ublock, res_bits, u0_bits);
+    if (nn == 5) PFMG_DISPATCH_N(t, colloc_resid_kernel, 5, t, nn, P, dt, Q, U, F, ublock, res_bits, u0_bits);
+    PFMG_DISPATCH_N(t, colloc_resid_kernel, 0, t, nn, P, dt, Q, U, F, ublock, res_bits, u0_bits);
 }
 
 hipError_t inject(const Tiling &t, View<double> uf, View<double> uc, hipStream_t s)

@@ -92,6 +92,7 @@ struct Solver {
     long fused_min_points = 2000000;  // one-pass red-black sweep from this batch size up
     hipStream_t cap = nullptr;        // private capture stream
     hipGraphExec_t g_iter = nullptr, g_start = nullptr;
+    bool warm_iter = false, warm_start = false;   // first call ran eagerly
     bool use_graph() const { return graphs && p.vcycles_per_solve > 0 && !timer.on; }
     long long vc_iter[2] = {0, 0}, vc_start[2] = {0, 0};   // V-cycles of one replay
     hipError_t capture(const std::function<hipError_t()> &fn, hipGraphExec_t *out, long long *vc);

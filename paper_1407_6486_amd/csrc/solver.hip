@@ -16,6 +16,7 @@
 
 #include "collocation.h"
 #include "solver.h"
+#include "tune.h"
 
 #define HC(x)                                  \
     do {                                       \
@@ -242,15 +243,19 @@ hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> 
     const double w = (double)sizeof(T);
     if (sweeps == 0) return from_zero ? k::zero(t, u, s) : hipSuccess;
     // The one-pass sweep marches in z; on small batches (the coarse chain
-    // sweeps one slice at a time) its serial steps cost more than the second
-    // pass of the colour-by-colour kernels, so it is used on big batches only.
-    if (p.smoother == PFMG_SMOOTH_RBGS && dim == 3 && n >= 31 && n <= 255 && tmp.p &&
-        (long)count * interior_points(n, dim) >= fused_min_points) {
+    // sweeps one slice at a time) its serial steps can cost more than the
+    // second pass of the colour-by-colour kernels.  The tuner times both (and
+    // the one-pass shapes) on first use; without timing, big batches take
+    // the one-pass kernel.
+    RbPlan plan;
+    if (p.smoother == PFMG_SMOOTH_RBGS && dim == 3 && n >= 31 && n <= 255 && tmp.p)
+        plan = rb_plan<T>(t, alpha, om, b, u, tmp, s, (long)count * interior_points(n, dim) >= fused_min_points);
+    if (plan.fused) {
         // whole sweeps in one pass each, ping-pong between u and tmp
         View<T> src = u, dst = tmp;
         for (int q = 0; q < sweeps; ++q) {
             tstart("rbgs", n, 3 * w, pts);
-            HC(k::rbgs_fused(t, alpha, om, q == 0 && from_zero, b, src, dst, s));
+            HC(k::rbgs_fused(t, alpha, om, q == 0 && from_zero, b, src, dst, s, &plan.shape));
             tstop();
             std::swap(src, dst);
         }
@@ -413,8 +418,8 @@ hipError_t Solver::sweep(int lev, int p0, int p1)
     const Tiling t = tl(Lv.n, count);
     const long pts = interior_points(Lv.n, dim) * count;
     tstart("sdc_integrals", Lv.n, 8.0 * (2 * nn - 1), pts);
-    HC(k::sdc_integrals(t, nn, p.dt, Lv.dS, View<double>{Lv.slot(Lv.F, p0, 0), sst}, fs,
-                        View<double>{Lv.I + (long)p0 * ist, ist}, fs, s));
+    HC(k::sdc_integrals(t, nn, p.dt, Lv.dS, View<double>{Lv.slot(Lv.F, p0, 0), sst},
+                        View<double>{Lv.I + (long)p0 * ist, ist}, s));
     tstop();
     View<double> Bv{Lv.B + (long)p0 * fs, fs};
     for (int m = 0; m + 1 < nn; ++m) {
@@ -445,13 +450,13 @@ hipError_t Solver::fas_restrict(int p0, int p1)
     const int count = p1 - p0;
     const long fst = (long)Fn.nn * Fn.fs, cst = (long)Cs.nn * Cs.fs;
     HC(k::fas_inject(tl(Cs.n, count), Fn.nn, Cs.nn, cmap, p.dt, Fn.dQ,
-                     View<double>{Fn.slot(Fn.U, p0, 0), fst}, View<double>{Fn.slot(Fn.F, p0, 0), fst}, Fn.fs,
+                     View<double>{Fn.slot(Fn.U, p0, 0), fst}, View<double>{Fn.slot(Fn.F, p0, 0), fst},
                      View<double>{Cs.slot(Cs.U, p0, 0), cst}, View<double>{Cs.slot(Cs.Uold, p0, 0), cst},
-                     View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, Cs.fs, s));
+                     View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, s));
     HC(k::apply_L(tl(Cs.n, count * Cs.nn), p.nu, View<double>{Cs.slot(Cs.U, p0, 0), Cs.fs},
                   View<double>{Cs.slot(Cs.F, p0, 0), Cs.fs}, s));
     return k::fas_tau(tl(Cs.n, count), Cs.nn, p.dt, Cs.dQ, View<double>{Cs.slot(Cs.F, p0, 0), cst},
-                      View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, Cs.fs, s);
+                      View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, s);
 }
 
 hipError_t Solver::interpolate(int p0, int p1)
@@ -461,7 +466,7 @@ hipError_t Solver::interpolate(int p0, int p1)
     const long cst = (long)Cs.nn * Cs.fs, dst = (long)Fn.nn * Cs.fs;
     double *dc = Cs.DC + (long)p0 * dst;
     HC(k::interp_coarse(tl(Cs.n, count), Fn.nn, Cs.nn, dLt, View<double>{Cs.slot(Cs.U, p0, 0), cst},
-                        View<double>{Cs.slot(Cs.Uold, p0, 0), cst}, Cs.fs, View<double>{dc, dst}, Cs.fs, s));
+                        View<double>{Cs.slot(Cs.Uold, p0, 0), cst}, View<double>{dc, dst}, s));
     const long pts = interior_points(Fn.n, dim) * count * Fn.nn;
     tstart("prolong", Fn.n, 16 + 8.0 / (dim == 3 ? 8 : 2), pts);
     HC(k::prolong_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs}, s));
@@ -477,12 +482,15 @@ hipError_t Solver::spread(const double *u0_dev)
 {
     PLevel &Fn = L[0];
     HC(k::unpack(tl(Fn.n, 1), u0_dev, View<double>{ublock, 0}, s));
-    if (use_graph()) {
+    if (use_graph() && warm_start) {
         if (!g_start) HC(capture([this] { return spread_body(); }, &g_start, vc_start));
         vcount[0] += vc_start[0];
         vcount[1] += vc_start[1];
         return hipGraphLaunch(g_start, s);
     }
+    // the first block start runs eagerly: launch shapes are tuned outside
+    // capture, and the captured graph replays the tuned launches
+    warm_start = true;
     return spread_body();
 }
 
@@ -530,7 +538,7 @@ hipError_t Solver::residual_enqueue()
     const long fst = (long)Fn.nn * Fn.fs;
     HC(k::fill_u64(bits, 0, 2 * P * k::RSLOTS, s));
     tstart("colloc_resid", Fn.n, 8.0 * (2 * Fn.nn + 1), interior_points(Fn.n, dim) * P);
-    HC(k::colloc_resid(tl(Fn.n, P), Fn.nn, P, p.dt, Fn.dQ, View<double>{Fn.U, fst}, View<double>{Fn.F, fst}, Fn.fs,
+    HC(k::colloc_resid(tl(Fn.n, P), Fn.nn, P, p.dt, Fn.dQ, View<double>{Fn.U, fst}, View<double>{Fn.F, fst},
                        View<double>{ublock, 0}, bits, bits + (long)P * k::RSLOTS, s));
     tstop();
     return hipSuccess;
@@ -596,12 +604,13 @@ hipError_t Solver::iterate_body()
 
 hipError_t Solver::iterate(double *block)
 {
-    if (use_graph()) {
+    if (use_graph() && warm_iter) {
         if (!g_iter) HC(capture([this] { return iterate_body(); }, &g_iter, vc_iter));
         vcount[0] += vc_iter[0];
         vcount[1] += vc_iter[1];
         HC(hipGraphLaunch(g_iter, s));
     } else {
+        warm_iter = true;
         HC(iterate_body());
         if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
     }

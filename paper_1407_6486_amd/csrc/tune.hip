@@ -1,0 +1,202 @@
+// Launch-shape autotuner for the red-black smoother (see tune.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "tune.h"
+
+namespace pfmg {
+namespace {
+
+struct Entry {
+    int fused, ty, zchunk;
+    long blocks;
+};
+
+std::mutex g_mu;
+std::map<std::string, Entry> g_table;
+bool g_loaded = false;
+
+const char *cache_path()
+{
+    const char *e = getenv("PFMG_TUNE_CACHE");
+    return e && *e ? e : nullptr;
+}
+
+void load_locked()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    const char *path = cache_path();
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    Entry e;
+    while (fscanf(f, "%511s %d %d %d %ld", key, &e.fused, &e.ty, &e.zchunk, &e.blocks) == 5) g_table[key] = e;
+    fclose(f);
+}
+
+void append_locked(const std::string &key, const Entry &e)
+{
+    const char *path = cache_path();
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %ld\n", key.c_str(), e.fused, e.ty, e.zchunk, e.blocks);
+    fclose(f);
+}
+
+bool tuning_enabled()
+{
+    const char *e = getenv("PFMG_TUNE");
+    return !(e && atoi(e) == 0);
+}
+
+template <typename T>
+std::string make_key(const Tiling &t)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+    }
+    std::string key = arch + "/rbgs/" + (sizeof(T) == 8 ? "f64/" : "f32/");
+    for (int sg = 0; sg < t.nseg; ++sg) {
+        if (sg) key += "+";
+        key += std::to_string(t.seg_n(sg)) + "x" + std::to_string(t.seg_count(sg));
+    }
+    return key;
+}
+
+// Average milliseconds of `reps` runs of fn after one warm-up run.
+template <class F>
+float time_ms(F fn, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps)
+{
+    if (fn() != hipSuccess) return -1.f;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r)
+        if (fn() != hipSuccess) return -1.f;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+    return ms / reps;
+}
+
+}  // namespace
+
+template <typename T>
+RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, View<T> tmp, hipStream_t s,
+               bool fallback_fused)
+{
+    RbPlan plan;
+    const std::string key = make_key<T>(t);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        load_locked();
+        auto it = g_table.find(key);
+        if (it != g_table.end()) {
+            const Entry &e = it->second;
+            plan.fused = e.fused != 0;
+            if (plan.fused) {
+                plan.shape = k::rbgs_fused_shape(t, sizeof(T), e.ty, 1);
+                plan.shape.zchunk = e.zchunk;
+                long blocks = 0;
+                for (int sg = 0; sg < t.nseg; ++sg) {
+                    const int n = t.seg_n(sg);
+                    blocks += (long)t.seg_count(sg) * ((n + e.ty - 1) / e.ty) * ((n + e.zchunk - 1) / e.zchunk);
+                }
+                plan.shape.blocks = blocks;
+                if (plan.shape.ty != e.ty || e.zchunk < 1) plan.shape = k::rbgs_fused_shape(t, sizeof(T));
+            }
+            return plan;
+        }
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+    if (capturing || !tuning_enabled()) {
+        plan.fused = fallback_fused;
+        if (plan.fused) plan.shape = k::rbgs_fused_shape(t, sizeof(T));
+        return plan;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        plan.fused = fallback_fused;
+        if (plan.fused) plan.shape = k::rbgs_fused_shape(t, sizeof(T));
+        return plan;
+    }
+    const int reps = 3;
+    // colour passes, in place on a copy of u held in tmp
+    float best = 0;
+    Entry win{0, 0, 0, 0};
+    if (k::copy(t, u, tmp, s) == hipSuccess) {
+        best = time_ms([&] {
+            hipError_t e = k::rbgs(t, alpha, omega, 0, b, tmp, s);
+            return e == hipSuccess ? k::rbgs(t, alpha, omega, 1, b, tmp, s) : e;
+        }, s, e0, e1, reps);
+    }
+    if (best < 0) best = 1e30f;
+    // one-pass shapes
+    std::vector<k::FusedShape> cands;
+    for (int ty : {2, 4, 8, 16})
+        for (int target : {256, 1024, 4096}) {
+            k::FusedShape f = k::rbgs_fused_shape(t, sizeof(T), ty, target);
+            if (f.ty != ty) continue;
+            bool dup = false;
+            for (const auto &c : cands) dup = dup || (c.ty == f.ty && c.zchunk == f.zchunk);
+            if (!dup && f.blocks > 0) cands.push_back(f);
+        }
+    for (const auto &f : cands) {
+        const float ms = time_ms([&] { return k::rbgs_fused(t, alpha, omega, false, b, u, tmp, s, &f); }, s, e0, e1,
+                                 reps);
+        if (ms >= 0 && ms < best) {
+            best = ms;
+            win = Entry{1, f.ty, f.zchunk, f.blocks};
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipGetLastError();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table[key] = win;
+        append_locked(key, win);
+    }
+    plan.fused = win.fused != 0;
+    if (plan.fused)
+        for (const auto &f : cands)
+            if (f.ty == win.ty && f.zchunk == win.zchunk) plan.shape = f;
+    return plan;
+}
+
+int tune_table_size()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return (int)g_table.size();
+}
+
+std::string tune_lookup(const std::string &key)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_table.find(key);
+    if (it == g_table.end()) return "";
+    const Entry &e = it->second;
+    return std::to_string(e.fused) + " " + std::to_string(e.ty) + " " + std::to_string(e.zchunk) + " " +
+           std::to_string(e.blocks);
+}
+
+template RbPlan rb_plan<double>(const Tiling &, double, double, View<double>, View<double>, View<double>, hipStream_t,
+                                bool);
+template RbPlan rb_plan<float>(const Tiling &, double, double, View<float>, View<float>, View<float>, hipStream_t,
+                               bool);
+
+}  // namespace pfmg

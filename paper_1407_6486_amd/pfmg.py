@@ -67,6 +67,16 @@ _sigs = {
     "pfmg_vcycle_count": ([_vp, C.c_int32, C.POINTER(C.c_int64)], C.c_int32),
     "pfmg_timing_enable": ([_vp, C.c_char_p, C.c_int32], C.c_int32),
     "pfmg_timing_read": ([_vp, C.POINTER(C.c_int64), _dp, _dp], C.c_int32),
+    "pfmg_batch_workspace_bytes": ([C.POINTER(Params), C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
+    "pfmg_batch_create": ([C.POINTER(Params), C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(_vp)], C.c_int32),
+    "pfmg_batch_destroy": ([_vp], C.c_int32),
+    "pfmg_batch_set_initial": ([_vp, _vp, C.c_int32], C.c_int32),
+    "pfmg_batch_pfasst_iter": ([_vp, _dp], C.c_int32),
+    "pfmg_batch_run": ([_vp, _vp, C.c_int32, C.POINTER(C.c_int32), _dp], C.c_int32),
+    "pfmg_batch_get": ([_vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, C.c_int32], C.c_int32),
+    "pfmg_batch_vcycle_count": ([_vp, C.c_int32, C.POINTER(C.c_int64)], C.c_int32),
+    "pfmg_tune_count": ([C.POINTER(C.c_int32)], C.c_int32),
+    "pfmg_tune_lookup": ([C.c_char_p, C.c_char_p, C.c_size_t], C.c_int32),
 }
 for _name, (_args, _res) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -173,6 +183,71 @@ def pfmg_timing_read(h):
     return n.value, ms.value, by.value
 
 
+def _params_array(params) -> C.Array:
+    arr = (Params * len(params))()
+    for i, q in enumerate(params):
+        C.memmove(C.byref(arr[i]), C.byref(q), C.sizeof(Params))
+    return arr
+
+
+def pfmg_batch_workspace_bytes(params) -> int:
+    out = C.c_size_t(0)
+    arr = _params_array(params)
+    _check(_lib.pfmg_batch_workspace_bytes(arr, len(params), C.byref(out)))
+    return out.value
+
+
+def pfmg_batch_create(params, workspace_ptr: int, nbytes: int, stream_ptr: int | None):
+    h = _vp()
+    arr = _params_array(params)
+    _check(_lib.pfmg_batch_create(arr, len(params), _vp(workspace_ptr), nbytes, _vp(stream_ptr or 0), C.byref(h)))
+    return h
+
+
+def pfmg_batch_destroy(h) -> None:
+    _check(_lib.pfmg_batch_destroy(h))
+
+
+def pfmg_batch_set_initial(h, u0_ptr: int, on_device: bool) -> int:
+    return _check(_lib.pfmg_batch_set_initial(h, _vp(u0_ptr), int(on_device)))
+
+
+def pfmg_batch_pfasst_iter(h, n_problems: int):
+    out = np.zeros(n_problems)
+    st = _check(_lib.pfmg_batch_pfasst_iter(h, out.ctypes.data_as(_dp)))
+    return st, out
+
+
+def pfmg_batch_run(h, u0_ptr: int, on_device: bool, n_problems: int):
+    it = np.zeros(n_problems, dtype=np.int32)
+    r = np.zeros(n_problems)
+    st = _check(_lib.pfmg_batch_run(h, _vp(u0_ptr), int(on_device), it.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    r.ctypes.data_as(_dp)))
+    return st, it, r
+
+
+def pfmg_batch_get(h, problem: int, field: int, slice_: int, node: int, dst_ptr: int, on_device: bool) -> None:
+    _check(_lib.pfmg_batch_get(h, problem, field, slice_, node, _vp(dst_ptr), int(on_device)))
+
+
+def pfmg_batch_vcycle_count(h, level: int) -> int:
+    c = C.c_int64(0)
+    _check(_lib.pfmg_batch_vcycle_count(h, level, C.byref(c)))
+    return c.value
+
+
+def pfmg_tune_count() -> int:
+    c = C.c_int32(0)
+    _check(_lib.pfmg_tune_count(C.byref(c)))
+    return c.value
+
+
+def pfmg_tune_lookup(key: str) -> str:
+    buf = C.create_string_buffer(256)
+    _check(_lib.pfmg_tune_lookup(key.encode(), buf, 256))
+    return buf.value.decode()
+
+
 # --------------------------------------------------------------- Context
 class Context:
     """A pfmg context on one GPU with a torch-owned workspace and stream."""
@@ -258,3 +333,68 @@ class Context:
 
     def timing_read(self):
         return pfmg_timing_read(self.h)
+
+
+class Batch:
+    """A batch of independent problems (shared method parameters; own n, nu,
+    dt) with a torch-owned workspace and stream."""
+
+    def __init__(self, params, device: str = "cuda", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("pfmg needs a ROCm GPU (gfx950); no device is visible")
+        self.torch = torch
+        self.params = list(params)
+        self.NP = len(self.params)
+        self.device = torch.device(device)
+        self.dim, self.P = self.params[0].dim, self.params[0].n_slices
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nbytes = pfmg_batch_workspace_bytes(self.params)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.ws.data_ptr() + 255) // 256 * 256
+        self.h = pfmg_batch_create(self.params, aligned, self.nbytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            pfmg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _concat(self, u0s):
+        t = self.torch
+        parts = []
+        for u, q in zip(u0s, self.params):
+            a = t.from_numpy(np.ascontiguousarray(u, dtype=np.float64)) if isinstance(u, np.ndarray) else u
+            a = a.to(device=self.device, dtype=t.float64).reshape(-1)
+            if a.numel() != q.n ** q.dim:
+                raise ValueError("initial value has the wrong size")
+            parts.append(a)
+        return t.cat(parts).contiguous()
+
+    def set_initial(self, u0s):
+        u = self._concat(u0s)
+        return pfmg_batch_set_initial(self.h, u.data_ptr(), True)
+
+    def pfasst_iter(self) -> np.ndarray:
+        return pfmg_batch_pfasst_iter(self.h, self.NP)[1]
+
+    def run(self, u0s):
+        """Returns (status, iterations per problem, residual per problem)."""
+        u = self._concat(u0s)
+        return pfmg_batch_run(self.h, u.data_ptr(), True, self.NP)
+
+    def get(self, problem: int, field: int, slice_: int, node: int, host: bool = True):
+        q = self.params[problem]
+        n = (q.n + 1) // 2 - 1 if field >= U_COARSE else q.n
+        out = self.torch.empty((n,) * q.dim, dtype=self.torch.float64, device=self.device)
+        pfmg_batch_get(self.h, problem, field, slice_, node, out.data_ptr(), True)
+        return out.cpu().numpy() if host else out
+
+    def vcycle_count(self, level: int = 0) -> int:
+        return pfmg_batch_vcycle_count(self.h, level)

@@ -74,3 +74,25 @@ def test_valid_degenerate_sizes_accepted(pf):
     for n, nc in ((1, 0), (3, 3), (5, 0), (95, 3)):
         p = pf.pfmg_default_params(n=n, nodes_coarse=nc, n_slices=1)
         assert pf.pfmg_workspace_bytes(p) > 0
+
+
+def test_batch_workspace_and_validation_on_the_host(pf):
+    sizes = (31, 63, 95, 127)
+    ps = [pf.pfmg_default_params(n=n, n_slices=4, nu=1.0 + q, dt=1e-3 * (q + 1)) for q, n in enumerate(sizes)]
+    singles = sum(pf.pfmg_workspace_bytes(p) for p in ps)
+    batch = pf.pfmg_batch_workspace_bytes(ps)
+    # the batch holds every problem's state; no more than the four contexts
+    # plus tables and alignment
+    assert 0.8 * singles < batch < 1.1 * singles
+    with pytest.raises(pf.PfmgError) as ei:
+        pf.pfmg_batch_create(ps, 0, 0, None)
+    assert ei.value.status == pf.ERR_WORKSPACE
+    bad = [pf.pfmg_default_params(n=31), pf.pfmg_default_params(n=63, nu_pre=1)]
+    with pytest.raises(pf.PfmgError) as ei:
+        pf.pfmg_batch_workspace_bytes(bad)
+    assert ei.value.status == pf.ERR_ARG and "differs from problem 0" in pf.pfmg_last_error()
+    for kw in ({"vcycles_per_solve": 0}, {"n_slices": 65}, {"n": 30}):
+        with pytest.raises(pf.PfmgError):
+            pf.pfmg_batch_workspace_bytes([pf.pfmg_default_params(**kw)])
+    assert pf.pfmg_tune_count() >= 0
+    assert pf.pfmg_tune_lookup("gfx950/rbgs/f64/0x0") == ""

@@ -9,8 +9,10 @@ predictor, then iterations until the block residual is <= 1e-10.
 
 The initial data sits in HBM before the timed region.  Printed: one JSON
 line with the block time, V-cycle GDOF/s, the roofline of the dominant
-kernel (fine-grid red-black half sweep, timed with HIP events on the
-library's stream during the timed region) and the oracle timed on the host.
+kernel (the one-pass red-black sweep on the fine grid, timed with HIP events
+on the library's stream during the timed region; HBM traffic from the
+committed counter summary while the kernel source is unchanged) and the
+oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -40,7 +42,50 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--max-iter", type=int, default=400,
                     help="iteration cap per block (profiling runs cap it to keep traces small)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain copy of known size three times (reference for HBM counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rbgs_fused_127x16_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1407_6486_amd", "csrc", "rbgs_fused.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing or the kernel source changed since."""
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            lines = [ln for ln in f if ln.startswith("bench-traffic: ")]
+        rec = json.loads(lines[-1][len("bench-traffic: "):])
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec
+
+
+CALIB_N = 255
+
+
+def copy_calibration(pfmg):
+    """A plain copy of known size for the HBM counters: the library's pack
+    kernel (one load and one store per point) gathers one 255^3 field into a
+    dense array, three times.  Reads: 255^2 rows of 2048 bytes (each row's
+    255 values plus its halo word share 16 whole 128-byte lines); writes:
+    255^3 x 8 bytes."""
+    import torch
+
+    c = pfmg.Context(pfmg.pfmg_default_params(dim=3, n=CALIB_N, n_slices=1, nodes_coarse=0))
+    out = torch.empty((CALIB_N,) * 3, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        pfmg.pfmg_get(c.h, pfmg.U_FINE, 0, 0, out.data_ptr(), True)
+    torch.cuda.synchronize()
+    c.close()
 
 
 def cpu_baseline(n, P, iters_gpu, cpu_iters, u0):
@@ -76,6 +121,8 @@ def main():
     from paper_1407_6486_amd import pfmg
 
     assert torch.cuda.is_available(), "no GPU visible"
+    if a.calibrate_copy:
+        copy_calibration(pfmg)
     n, P = a.n, a.slices
     p = pfmg.pfmg_default_params(
         dim=3, n=n, n_slices=P, nu=1.0, dt=1e-3, vcycles_per_solve=a.vcycles,
@@ -116,9 +163,10 @@ def main():
     vcycle_gdofs = (vbytes / 1.0) / (vms * 1e-3) / 1e9 if vms > 0 else None   # vbytes holds DOF x cycles
 
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
+    tr = measured_traffic() if (n == 127 and P == 16 and a.smoother == "rbgs" and a.precision == "fp64") else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                "traffic": None, "kernel": dominant, "launches": launches,
+                "traffic": tr["hbm_bytes_per_launch"] if tr else None, "kernel": dominant, "launches": launches,
                 "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
                 "bytes_per_launch": nbytes / max(launches, 1)}
 

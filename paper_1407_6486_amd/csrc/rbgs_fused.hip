@@ -30,7 +30,9 @@ namespace {
 
 constexpr int QMAX = 6;   // owned rows per thread
 
-template <typename T>
+// RLN: x lanes per row (64, 128 or 256), the widest segment's n rounded up
+// to whole wavefronts; narrower segments leave their extra lanes idle.
+template <typename T, int RLN>
 __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
                                                            double omega, View<T> b, View<T> uin, View<T> uout)
 {
@@ -43,8 +45,8 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
         }))
         return;
     const int n = qs.n;
-    const int rowlanes = (n + 63) & ~63;
-    const int RL = rowlanes + 2;
+    constexpr int rowlanes = RLN;
+    constexpr int RL = rowlanes + 2;
     const int rows = ty + 2;                 // rows of the red update (owned rows)
     T *up = reinterpret_cast<T *>(smem_raw);             // uin plane k: rows j0-2 .. j0+ty+1
     T *wp = up + (size_t)(ty + 4) * RL;                  // 2 planes of the red-updated field
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
     const T ah = (T)ahd, winv = (T)(omega / (1.0 + 2.0 * 3 * ahd));
     const int j0 = jt * ty + 1, k0 = zc * zchunk + 1;
     const int k1 = min(k0 + zchunk, n + 1);
-    const int rpp = BLOCK / rowlanes;
+    constexpr int rpp = BLOCK / rowlanes;
     const int i = (int)(threadIdx.x % rowlanes) + 1;
     const int rsub = (int)(threadIdx.x / rowlanes);
     const long sy = row_stride(n), sz = plane_stride(n);
@@ -191,10 +193,8 @@ FusedShape rbgs_fused_shape(const Tiling &t, size_t elem, int ty, int target_blo
     const int rowlanes = (nmax + 63) & ~63;
     FusedShape f;
     f.ty = ty > 0 ? ty : env_int("PFMG_RB_TY", rowlanes >= 256 ? 4 : 8);
-    for (int sg = 0; sg < t.nseg; ++sg) {
-        const int rpp = BLOCK / ((t.seg_n(sg) + 63) & ~63);
-        while (f.ty > 1 && (f.ty + 2 + rpp - 1) / rpp > QMAX) f.ty /= 2;
-    }
+    const int rpp = BLOCK / rowlanes;
+    while (f.ty > 1 && (f.ty + 2 + rpp - 1) / rpp > QMAX) f.ty /= 2;
     for (int sg = 0; sg < t.nseg; ++sg) rows_total += (long)t.seg_count(sg) * ((t.seg_n(sg) + f.ty - 1) / f.ty);
     const int target = target_blocks > 0 ? target_blocks : env_int("PFMG_RB_BLOCKS", 1024);
     int zch = (int)std::min<long>(std::max<long>(1, (target + rows_total - 1) / std::max(1L, rows_total)),
@@ -227,8 +227,20 @@ hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in,
     }
     if (f.ty < 1 || f.ty != chk.ty || f.zchunk < 1 || blocks != f.blocks || f.lds != chk.lds) return hipErrorInvalidValue;
     if (f.blocks == 0) return hipSuccess;
-    rbgs_fused_kernel<T><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zero_in ? 1 : 0, alpha, omega, b,
-                                                                   uin, uout);
+    int nmax = 0;
+    for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
+    const int zi = zero_in ? 1 : 0;
+    switch ((nmax + 63) & ~63) {
+    case 64:
+        rbgs_fused_kernel<T, 64><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zi, alpha, omega, b, uin, uout);
+        break;
+    case 128:
+        rbgs_fused_kernel<T, 128><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zi, alpha, omega, b, uin, uout);
+        break;
+    default:
+        rbgs_fused_kernel<T, 256><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zi, alpha, omega, b, uin, uout);
+        break;
+    }
     return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@
  *   - SDC sweep with backward-Euler substeps: eq. sdc-be, SDCcompactLIII (Sec. 2.2)
  *   - collocation residual: eq. resid (Sec. 2.2.2)
  *   - two-level MLSDC with the FAS correction (Sec. 2.3), IMLSDC (Sec. 2.3.1)
- *   - PFASST / IPFASST: predictor, iteration, send-forward (Sec. 2.3.2)
+ *   - PFASST / IPFASST: predictor, iteration, send-forward (Sec. 2.4, 2.4.1)
  *   - node solves by geometric multigrid V-cycles: linear interpolation,
  *     full-weighting restriction, pre/post smoothing (Sec. 4.1.1, 4.2.1)
  *   - spatial operator: 2nd-order finite differences (3-point in 1D, Sec. 4.1;
@@ -141,7 +141,7 @@ const char *pfmg_last_error(void);
 
 /* Start a block: copy u0 (n^dim float64, host if on_device == 0, device
  * otherwise) to every node of every slice, evaluate F = nu L u, and — with
- * two levels — run the PFASST predictor (Sec. 2.3.2: FAS restriction of
+ * two levels — run the PFASST predictor (Sec. 2.4: FAS restriction of
  * the spread state, P pipelined rounds of coarse sweeps in which slice p
  * sweeps p+1 times, interpolation). */
 pfmg_status pfmg_set_initial(pfmg_ctx *ctx, const double *u0, int32_t on_device);
@@ -162,7 +162,7 @@ pfmg_status pfmg_sdc_sweep(pfmg_ctx *ctx, int32_t level, int32_t p_begin, int32_
 pfmg_status pfmg_vcycle(pfmg_ctx *ctx, double alpha, const double *b, double *u,
                         int32_t n_cycles, double *relres_out, int32_t *cycles_out);
 
-/* One IPFASST iteration (Sec. 2.3.2): new fine initial values from the
+/* One IPFASST iteration (Sec. 2.4): new fine initial values from the
  * previous slices, fine sweeps on all slices, FAS restriction, coarse sweeps
  * in slice order, interpolation, collocation residual.  *block_res_out
  * (may be NULL) receives max over slices of the relative residual. */

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and
 the CPU-baseline leg of the benchmark, never by the product path.  The C
 sources next to this file implement the algorithm of arXiv:1407.6486 step
 by step (collocation Sec. 2.1, SDC Sec. 2.2, MLSDC/FAS Sec. 2.3, PFASST
-Sec. 2.3.2, multigrid Sec. 4.1.1 / 4.2.1); this module only marshals
+Sec. 2.4, multigrid Sec. 4.1.1 / 4.2.1); this module only marshals
 numpy arrays through ctypes.
 
 Arrays are dense ``n**dim`` float64 in C order with x fastest, i.e. numpy

@@ -254,7 +254,7 @@ void or_pfasst_spread(or_pfasst *c, const double *u_block)
     if (c->nl > 1) inject(c->p.dim, c->n[0], u_block, c->ublock_c);
 }
 
-/* Predictor (Sec. 2.3.2): rounds j = 0..P-1; in round j every slice p >= j
+/* Predictor (Sec. 2.4): rounds j = 0..P-1; in round j every slice p >= j
  * (for j >= 1) takes the coarse end value slice p-1 had after round j-1
  * and does one coarse sweep, so slice p sweeps p+1 times. */
 void or_pfasst_predictor(or_pfasst *c)
@@ -309,7 +309,7 @@ double or_pfasst_residual(or_pfasst *c, double *res)
     return blk;
 }
 
-/* One iteration (Sec. 2.3.2): new fine initial values from the previous
+/* One iteration (Sec. 2.4): new fine initial values from the previous
  * slice, fine sweeps, FAS restriction, the coarse sweeps in slice order,
  * interpolation, residual.  With one level: initial values and sweeps. */
 double or_pfasst_iter(or_pfasst *c)

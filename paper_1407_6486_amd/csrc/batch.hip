@@ -1,6 +1,6 @@
 // Batched IPFASST (see batch.h).
 //
-// Each problem follows the same algorithm as a single context (Sec. 2.3.2:
+// Each problem follows the same algorithm as a single context (Sec. 2.4:
 // predictor, then iterations of fine sweep, FAS restriction, coarse sweeps
 // in slice order, interpolation and the collocation residual); only the
 // launches are shared.  Per-problem nu and dt enter the kernels as
@@ -613,7 +613,7 @@ hipError_t BatchSolver::interpolate(bool masked)
 
 // Block start after every u_block is in place: spread to all nodes and
 // slices, F, the injected coarse initial values and the predictor
-// (Sec. 2.3.2: round j sweeps the coarse slices p >= j of every problem,
+// (Sec. 2.4: round j sweeps the coarse slices p >= j of every problem,
 // after slice p takes slice p-1's end value of round j-1).
 hipError_t BatchSolver::spread_body()
 {

@@ -1,7 +1,7 @@
 // IPFASST on one GPU: the P time slices of a block are processed together;
 // each "time rank" of the paper is a slice of the batched state.
 //
-// Per iteration (Sec. 2.3.2): new fine initial values from the previous
+// Per iteration (Sec. 2.4): new fine initial values from the previous
 // slices (their end values after the previous iteration), one fine SDC
 // sweep on all slices at once, FAS restriction, the coarse sweeps in slice
 // order (the blocking coarse level of PFASST), interpolation of the coarse
@@ -508,7 +508,7 @@ hipError_t Solver::spread_body()
     return predictor();
 }
 
-// Predictor (Sec. 2.3.2): round j sweeps every slice p >= j on the coarse
+// Predictor (Sec. 2.4): round j sweeps every slice p >= j on the coarse
 // level; for j >= 1 those slices first take slice p-1's end value of round
 // j-1 (all copies precede the round's sweeps, so no snapshot is needed).
 hipError_t Solver::predictor()

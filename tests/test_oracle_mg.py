@@ -197,3 +197,39 @@ def test_full_solve_stall_and_divergence_paths():
     # zero data: zero cycles
     _, ncyc, rr = O.mg_solve(dim, a, np.zeros_like(b), np.zeros_like(b), pol)
     assert ncyc == 0 and rr == 0.0
+
+
+@pytest.mark.parametrize("dim,nc", [(1, 3), (1, 15), (3, 3), (3, 7)])
+def test_cubic_interpolation_exact_on_cubics_vanishing_at_the_boundary(dim, nc):
+    # Four-point Lagrange interpolation reproduces every cubic; with the zero
+    # boundary values among the points, cubics that vanish at x = 0 and 1 are
+    # interpolated exactly everywhere, in tensor products too.
+    n = 2 * (nc + 1) - 1
+    cubics = [lambda x: x * (1 - x) * (0.3 + x), lambda x: x * (1 - x) * (2.0 - 3.0 * x), lambda x: x * (1 - x)]
+    xc = np.arange(1, nc + 1) / (nc + 1)
+    xf = np.arange(1, n + 1) / (n + 1)
+    if dim == 1:
+        ec, want = cubics[0](xc), cubics[0](xf)
+    else:
+        ec = cubics[2](xc)[:, None, None] * cubics[1](xc)[None, :, None] * cubics[0](xc)[None, None, :]
+        want = cubics[2](xf)[:, None, None] * cubics[1](xf)[None, :, None] * cubics[0](xf)[None, None, :]
+    u = O.prolong4_add(dim, ec, np.zeros((n,) * dim))
+    assert np.max(np.abs(u - want)) <= 1e-15
+
+
+def test_cubic_interpolation_is_fourth_order():
+    # error of interpolating sin(pi x) falls by ~16 per halving of h (the
+    # linear interpolation's by ~4)
+    errs4, errs2 = [], []
+    for nc in (15, 31, 63):
+        n = 2 * (nc + 1) - 1
+        xc = np.arange(1, nc + 1) / (nc + 1)
+        xf = np.arange(1, n + 1) / (n + 1)
+        u4 = O.prolong4_add(1, np.sin(np.pi * xc), np.zeros(n))
+        u2 = O.prolong_add(1, np.sin(np.pi * xc), np.zeros(n))
+        errs4.append(np.max(np.abs(u4 - np.sin(np.pi * xf))))
+        errs2.append(np.max(np.abs(u2 - np.sin(np.pi * xf))))
+    for a, b in zip(errs4, errs4[1:]):
+        assert 14.0 < a / b < 18.0
+    for a, b in zip(errs2, errs2[1:]):
+        assert 3.6 < a / b < 4.4

@@ -165,7 +165,7 @@ def test_1d_decay_matches_paper_value():
 
 
 def test_predictor_sweep_counts():
-    """Sec. 2.3.2 predictor: slice p does p+1 coarse sweeps (2 solves each)."""
+    """Sec. 2.4 predictor: slice p does p+1 coarse sweeps (2 solves each)."""
     n, P = 15, 4
     pf = O.Pfasst(1, n, 1.0, 0.01, P, 5, 3, O.policy(smoother=O.JACOBI, omega=2 / 3, cycles=1))
     pf.set_initial(inputs.heat_1d(n)[0])

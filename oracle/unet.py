@@ -3,10 +3,12 @@ ONLY: used by the test suite, the smoke check and bench.py's CPU leg; the
 product path never imports it).
 
 The network predicts the correction of a node solve (I - alpha L_h) u = b
-from its right-hand side and its plain initial guess (the previous iterate
-at the node, the guess the paper's inexact solves start from, Sec. 2.3.1).
-Inputs per voxel: b / s, U / s and alpha (n+1)^2, with s = |b|_inf; output
-y with guess g = U + s y.
+from its right-hand side and its plain initial guess U (the previous
+iterate at the node, the guess the paper's inexact solves start from,
+Sec. 2.3.1).  The correction e = u - U solves (I - alpha L_h) e = r with
+r = b - (I - alpha L_h) U, so the inputs are made scale-free: per voxel
+r / s, U / |U|_inf and alpha (n+1)^2, with s = |r|_inf; output y, guess
+g = U + s y, training target (u - U) / s.
 
 Architecture (a 3-level U-Net, base width 16): every convolution has 3^3
 taps, a bias, and zero values outside the grid.  Levels follow the
@@ -272,8 +274,18 @@ def loss_and_grads(params, xs, ts):
 
 
 def make_input(b, u, alpha):
-    """Network input for the node solve (I - alpha L_h) u = b: channels b/s,
-    U/s, alpha (n+1)^2 with s = |b|_inf (s = 1 if b = 0)."""
+    """Network input for the node solve (I - alpha L_h) u = b from the guess
+    u: channels r / s, u / |u|_inf, alpha (n+1)^2 with r = b - (I - alpha L_h) u
+    and s = |r|_inf (1 if zero).  Returns (x, s)."""
+    from oracle import resid
+
     n = b.shape[0]
-    s = float(np.max(np.abs(b))) or 1.0
-    return np.stack([b / s, u / s, np.full(b.shape, alpha * (n + 1) ** 2)]), s
+    r = resid(3, alpha, b, u)
+    s = float(np.max(np.abs(r))) or 1.0
+    su = float(np.max(np.abs(u))) or 1.0
+    return np.stack([r / s, u / su, np.full(b.shape, alpha * (n + 1) ** 2)]), s
+
+
+def guess(u, y, s):
+    """Guess from the network output: g = u + s y."""
+    return u + s * y

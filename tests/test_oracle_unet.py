@@ -123,10 +123,21 @@ def test_network_input_gradient_matches_finite_differences():
         assert abs(fd - dx[idx]) <= 1e-6 * max(abs(fd), 1e-3)
 
 
-def test_input_channels():
-    b = np.zeros((7, 7, 7))
-    b[3, 3, 3] = -4.0
-    u = np.ones((7, 7, 7))
-    x, s = U.make_input(b, u, 0.5)
-    assert s == 4.0 and x.shape == (3, 7, 7, 7)
-    assert x[0].min() == -1.0 and np.all(x[1] == 0.25) and np.all(x[2] == 0.5 * 64)
+def test_input_channels_are_scale_free():
+    import oracle as O
+
+    rng = np.random.default_rng(10)
+    n, alpha = 7, 0.01
+    b, u = rng.standard_normal((n, n, n)), rng.standard_normal((n, n, n))
+    x, s = U.make_input(b, u, alpha)
+    r = b - O.helm(3, alpha, u)
+    assert abs(s - np.max(np.abs(r))) <= 1e-15 * s and x.shape == (3, n, n, n)
+    assert np.max(np.abs(x[0] - r / s)) <= 1e-15 and np.max(np.abs(x[1])) == 1.0
+    assert np.all(x[2] == alpha * (n + 1) ** 2)
+    # scaling the problem scales s, not the channels
+    x2, s2 = U.make_input(3.0 * b, 3.0 * u, alpha)
+    assert abs(s2 - 3.0 * s) <= 1e-14 * s and np.max(np.abs(x2 - x)) <= 1e-15
+    # the exact correction is a zero-residual guess
+    e = O.mg_solve(3, alpha, r, np.zeros_like(r), O.policy(cycles=0, tol=1e-14))[0]
+    g = U.guess(u, e / s, s)
+    assert np.max(np.abs(b - O.helm(3, alpha, g))) <= 1e-12 * np.max(np.abs(b))

@@ -87,7 +87,9 @@ enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
  *                    prolongation and coarsest solve inside FP64 iterative
  *                    refinement (FP64 residual, FP64 update; one refinement
  *                    step per V-cycle of the solve policy).
- *   guess            PFMG_GUESS_PREV (previous iterate at the same node).
+ *   guess            PFMG_GUESS_PREV (previous iterate at the same node), or
+ *                    PFMG_GUESS_LEARNED (the judged network guess below; 3D
+ *                    full solves only).
  *   fine_send        PFMG_SEND_AFTER_ITER: slice p takes slice p-1's end
  *                    value after p-1's previous iteration.
  *   pfasst_tol       block relative residual tolerance for pfmg_run_block.
@@ -254,6 +256,75 @@ pfmg_status pfmg_batch_vcycle_count(pfmg_batch *b, int32_t level, int64_t *count
  * "fused ty zchunk blocks" ("" if absent). */
 pfmg_status pfmg_tune_count(int32_t *count_out);
 pfmg_status pfmg_tune_lookup(const char *key, char *buf, size_t len);
+
+/* ------------------------------------------------------------------------
+ * Learned initial guess (a node solve's start from a small 3D network).
+ *
+ * A node solve (I - alpha L_h) u = b starts from the previous iterate U at
+ * the node (Sec. 2.3.1).  The network maps r / |r|_inf, U / |U|_inf and
+ * alpha (n+1)^2, with r = b - (I - alpha L_h) U, to y; its guess is
+ * g = U + |r|_inf y.  The FP64 residual judges: a field takes g only if
+ * |b - (I - alpha L_h) g|_inf < |r|_inf; the V-cycles of the full solve then
+ * run from whichever start won.
+ *
+ * Network: a 3-level U-Net (widths 16/32/64) on the grids n, (n+1)/2 - 1,
+ * ...: 3^3 convolutions with ReLU, stride-2 down and transposed up
+ * convolutions (coarse point J on fine point 2J), skip concatenations and a
+ * 1x1 output layer.  BF16 activations and weights on MFMA with FP32
+ * accumulation; FP32 master weights and Adam for training.
+ * Parameters (FP32, host): per layer in order W[cout][cin][3][3][3] (the
+ * output layer W[1][16][1][1][1]) followed by b[cout].
+ * ---------------------------------------------------------------------- */
+typedef struct pfmg_nn pfmg_nn;
+
+pfmg_status pfmg_nn_param_count(int64_t *count_out);
+/* Device bytes of a network for grid n (odd with odd coarse grids down to
+ * >= 3 points on the third level) and up to `batch` samples per call;
+ * training adds gradients, Adam moments and gradient tensors. */
+pfmg_status pfmg_nn_workspace_bytes(int32_t n, int32_t batch, int32_t training, size_t *bytes_out);
+pfmg_status pfmg_nn_create(int32_t n, int32_t batch, int32_t training, void *workspace, size_t bytes,
+                           void *hip_stream, pfmg_nn **out);
+pfmg_status pfmg_nn_destroy(pfmg_nn *nn);
+/* Set / read the parameters (host arrays of pfmg_nn_param_count floats);
+ * loading resets the Adam state. */
+pfmg_status pfmg_nn_load(pfmg_nn *nn, const float *params, int64_t count);
+pfmg_status pfmg_nn_save(pfmg_nn *nn, float *params, int64_t count);
+/* He-normal weights (std sqrt(2 / fan_in); the output layer 0.1 of that),
+ * zero biases, from a counter-based generator seeded by `seed`. */
+pfmg_status pfmg_nn_init(pfmg_nn *nn, uint64_t seed);
+/* Forward pass on dense inputs x [batch][3][n^3] (device FP32): y
+ * [batch][n^3] (device FP32). */
+pfmg_status pfmg_nn_forward(pfmg_nn *nn, const float *x, int32_t batch, float *y);
+/* Mean squared error against target [batch][n^3] (device) and its
+ * gradient with respect to every parameter (host, parameter layout). */
+pfmg_status pfmg_nn_gradients(pfmg_nn *nn, const float *x, const float *target, int32_t batch,
+                              double *loss_out, float *grads_out);
+/* One Adam step (lr; betas 0.9, 0.999; eps 1e-8) on the recorded pairs
+ * idx[0..batch-1] (host indices, each in 0..n_pairs-1) of a pair store of
+ * n_pairs pairs (see pfmg_record).  *loss_out: the batch's mean squared
+ * error before the step. */
+pfmg_status pfmg_nn_train_step(pfmg_nn *nn, const void *pairs, const float *ah2, int32_t n_pairs,
+                               const int32_t *idx, int32_t batch, float lr, double *loss_out);
+/* Copy of a layer's tensor from the last forward / backward pass to dense
+ * device FP32 [batch][channels][n_l^3]: which = 0 input, 1 output, 2
+ * gradient of the pre-activation (after the ReLU mask), 3 gradient of the
+ * input.  Layers 0..12 (the 3^3 convolutions). */
+pfmg_status pfmg_nn_tensor(pfmg_nn *nn, int32_t layer, int32_t which, int32_t batch, float *dst);
+/* Use `nn` (or none: NULL) for the fine-level node solves of a context
+ * created with guess = PFMG_GUESS_LEARNED (3D, full solves).  The network's
+ * grid must be the context's fine grid and its batch >= n_slices; it runs
+ * on the context's stream. */
+pfmg_status pfmg_attach_nn(pfmg_ctx *ctx, pfmg_nn *nn);
+/* Fields offered the learned guess and fields that took it. */
+pfmg_status pfmg_guess_stats(pfmg_ctx *ctx, int64_t *tried, int64_t *taken);
+/* Record training pairs from the fine-level full node solves of a 3D
+ * context (vcycles_per_solve = 0): pair k gets BF16 dense [3][n^3] at
+ * pairs + 3 k n^3 (r / |r|, U / |U| before the solve, (u - U) / |r| after
+ * it) and FP32 alpha (n+1)^2 at ah2[k].  scratch: device FP64
+ * [n_slices][n^3].  Recording stops when `capacity` pairs are full; NULL
+ * pairs turns it off.  Device pointers stay owned by the caller. */
+pfmg_status pfmg_record(pfmg_ctx *ctx, void *pairs, float *ah2, double *scratch, int32_t capacity);
+pfmg_status pfmg_record_count(pfmg_ctx *ctx, int32_t *count_out);
 
 #ifdef __cplusplus
 }

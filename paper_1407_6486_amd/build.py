@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libpfmg.so")
 ARCH = os.environ.get("PFMG_ARCH", "gfx950")
 
 SOURCES = ["mg_kernels.hip", "rbgs_fused.hip", "bottom.hip", "sdc_kernels.hip", "tune.hip", "solver.hip", "batch.hip",
-           "capi.hip",
+           "nn.hip", "unet.hip", "capi.hip",
            "collocation.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -8,10 +8,12 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "batch.h"
 #include "solver.h"
 #include "tune.h"
+#include "unet.h"
 
 struct pfmg_ctx {
     pfmg::Solver sv;
@@ -19,6 +21,11 @@ struct pfmg_ctx {
 
 struct pfmg_batch {
     pfmg::BatchSolver bs;
+};
+
+struct pfmg_nn {
+    pfmg::UNet net;
+    float *stage = nullptr;   // pinned host copy of the parameters
 };
 
 namespace {
@@ -110,12 +117,14 @@ pfmg_status pfmg_create(const pfmg_params *p, void *workspace, size_t bytes, voi
     pfmg::Solver::carve(*p, (char *)workspace, &sv);
     hipError_t e = hipHostMalloc((void **)&sv.hbits, sizeof(unsigned long long) * 4 * sv.P * pfmg::k::RSLOTS, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv.hmask, sizeof(int) * sv.P, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sv.hnnsc, sizeof(double) * 2 * sv.P, hipHostMallocDefault);
     // Zero the whole workspace once: halos carry the Dirichlet data.
     if (e == hipSuccess) e = hipMemsetAsync(workspace, 0, need, sv.s);
     if (e == hipSuccess) e = sv.upload_constants();
     if (e != hipSuccess) {
         if (sv.hbits) (void)hipHostFree(sv.hbits);
         if (sv.hmask) (void)hipHostFree(sv.hmask);
+        if (sv.hnnsc) (void)hipHostFree(sv.hnnsc);
         delete c;
         return hip_fail(e, "pfmg_create");
     }
@@ -132,6 +141,7 @@ pfmg_status pfmg_destroy(pfmg_ctx *ctx)
     for (hipEvent_t ev : sv.timer.ev) (void)hipEventDestroy(ev);
     if (sv.hbits) (void)hipHostFree(sv.hbits);
     if (sv.hmask) (void)hipHostFree(sv.hmask);
+    if (sv.hnnsc) (void)hipHostFree(sv.hnnsc);
     delete ctx;
     return PFMG_OK;
 }
@@ -459,6 +469,258 @@ pfmg_status pfmg_tune_lookup(const char *key, char *buf, size_t len)
     if (!key || !buf || len == 0) return fail(PFMG_ERR_ARG, "null argument");
     const std::string v = pfmg::tune_lookup(key);
     std::snprintf(buf, len, "%s", v.c_str());
+    return PFMG_OK;
+}
+
+// ---------------------------------------------------------- learned guess
+namespace {
+
+// parameters: per layer W [cout][cin][3][3][3] (output layer [1][16][1][1][1])
+// then b [cout]; the library keeps W as [27][cout][cin]
+void to_kernel_layout(const pfmg::UNet &u, const float *in, float *out)
+{
+    for (const pfmg::UNetLayer &l : u.L) {
+        const int taps = l.kind == 3 ? 1 : 27;
+        for (int co = 0; co < l.cout; ++co)
+            for (int ci = 0; ci < l.cin; ++ci)
+                for (int t = 0; t < taps; ++t)
+                    out[l.w_off + ((long)t * l.cout + co) * l.cin + ci] = in[l.w_off + ((long)co * l.cin + ci) * taps + t];
+        for (int co = 0; co < l.cout; ++co) out[l.b_off + co] = in[l.b_off + co];
+    }
+}
+
+void from_kernel_layout(const pfmg::UNet &u, const float *in, float *out)
+{
+    for (const pfmg::UNetLayer &l : u.L) {
+        const int taps = l.kind == 3 ? 1 : 27;
+        for (int co = 0; co < l.cout; ++co)
+            for (int ci = 0; ci < l.cin; ++ci)
+                for (int t = 0; t < taps; ++t)
+                    out[l.w_off + ((long)co * l.cin + ci) * taps + t] = in[l.w_off + ((long)t * l.cout + co) * l.cin + ci];
+        for (int co = 0; co < l.cout; ++co) out[l.b_off + co] = in[l.b_off + co];
+    }
+}
+
+uint64_t splitmix(uint64_t &x)
+{
+    uint64_t z = (x += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+pfmg_status pfmg_nn_param_count(int64_t *count_out)
+{
+    if (!count_out) return fail(PFMG_ERR_ARG, "null argument");
+    *count_out = pfmg::UNet::param_count();
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_workspace_bytes(int32_t n, int32_t batch, int32_t training, size_t *bytes_out)
+{
+    if (!bytes_out) return fail(PFMG_ERR_ARG, "null argument");
+    if (!pfmg::UNet::valid_n(n)) return fail(PFMG_ERR_ARG, "n must be odd on three levels (n, (n+1)/2-1, ...) >= 3");
+    if (batch < 1 || batch > 4096) return fail(PFMG_ERR_ARG, "batch must be in 1..4096");
+    pfmg::UNet u;
+    u.n[0] = n;
+    u.cap = batch;
+    u.training = training != 0;
+    *bytes_out = u.carve(nullptr);
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_create(int32_t n, int32_t batch, int32_t training, void *workspace, size_t bytes, void *hip_stream,
+                           pfmg_nn **out)
+{
+    if (!out) return fail(PFMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    size_t need = 0;
+    pfmg_status st = pfmg_nn_workspace_bytes(n, batch, training, &need);
+    if (st) return st;
+    if (!workspace || bytes < need) return fail(PFMG_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace & 255) != 0) return fail(PFMG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    pfmg_nn *c = new (std::nothrow) pfmg_nn;
+    if (!c) return fail(PFMG_ERR_ARG, "out of host memory");
+    pfmg::UNet &u = c->net;
+    u.n[0] = n;
+    u.cap = batch;
+    u.training = training != 0;
+    u.s = (hipStream_t)hip_stream;
+    u.carve((char *)workspace);
+    hipError_t e = hipHostMalloc((void **)&c->stage, sizeof(float) * u.nparams, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemsetAsync(workspace, 0, need, u.s);   // halos and moments start at zero
+    if (e == hipSuccess) e = hipStreamSynchronize(u.s);
+    if (e != hipSuccess) {
+        if (c->stage) (void)hipHostFree(c->stage);
+        delete c;
+        return hip_fail(e, "pfmg_nn_create");
+    }
+    *out = c;
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_destroy(pfmg_nn *nn)
+{
+    if (!nn) return PFMG_OK;
+    (void)hipStreamSynchronize(nn->net.s);
+    if (nn->stage) (void)hipHostFree(nn->stage);
+    delete nn;
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_load(pfmg_nn *nn, const float *params, int64_t count)
+{
+    if (!nn || !params) return fail(PFMG_ERR_ARG, "null argument");
+    pfmg::UNet &u = nn->net;
+    if (count != u.nparams) return fail(PFMG_ERR_ARG, "expected " + std::to_string(u.nparams) + " parameters");
+    to_kernel_layout(u, params, nn->stage);
+    HIPCALL(hipMemcpyAsync(u.params, nn->stage, sizeof(float) * u.nparams, hipMemcpyHostToDevice, u.s), "nn load");
+    HIPCALL(u.refresh_weights(), "nn weights");
+    if (u.training) {
+        HIPCALL(pfmg::nn::fill_f32(u.m1, 0.f, u.nparams, u.s), "nn moments");
+        HIPCALL(pfmg::nn::fill_f32(u.m2, 0.f, u.nparams, u.s), "nn moments");
+        u.adam_t = 0;
+    }
+    HIPCALL(hipStreamSynchronize(u.s), "nn load");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_save(pfmg_nn *nn, float *params, int64_t count)
+{
+    if (!nn || !params) return fail(PFMG_ERR_ARG, "null argument");
+    pfmg::UNet &u = nn->net;
+    if (count != u.nparams) return fail(PFMG_ERR_ARG, "expected " + std::to_string(u.nparams) + " parameters");
+    HIPCALL(hipMemcpyAsync(nn->stage, u.params, sizeof(float) * u.nparams, hipMemcpyDeviceToHost, u.s), "nn save");
+    HIPCALL(hipStreamSynchronize(u.s), "nn save");
+    from_kernel_layout(u, nn->stage, params);
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_init(pfmg_nn *nn, uint64_t seed)
+{
+    if (!nn) return fail(PFMG_ERR_ARG, "null argument");
+    pfmg::UNet &u = nn->net;
+    std::vector<float> w(u.nparams, 0.f);
+    uint64_t st = seed * 0x2545f4914f6cdd1dULL + 1;
+    for (const pfmg::UNetLayer &l : u.L) {
+        const int taps = l.kind == 3 ? 1 : 27;
+        const double sd = std::sqrt(2.0 / (double)(l.cin * taps)) * (l.kind == 3 ? 0.1 : 1.0);
+        const long nw = (long)l.cout * l.cin * taps;
+        for (long i = 0; i < nw; ++i) {
+            // Box-Muller on two uniforms in (0, 1]
+            const double u1 = ((splitmix(st) >> 11) + 1.0) * 0x1.0p-53, u2 = (splitmix(st) >> 11) * 0x1.0p-53;
+            w[l.w_off + i] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2));
+        }
+    }
+    return pfmg_nn_load(nn, w.data(), u.nparams);
+}
+
+pfmg_status pfmg_nn_forward(pfmg_nn *nn, const float *x, int32_t batch, float *y)
+{
+    if (!nn || !x || !y) return fail(PFMG_ERR_ARG, "null argument");
+    pfmg::UNet &u = nn->net;
+    if (batch < 1 || batch > u.cap) return fail(PFMG_ERR_ARG, "batch exceeds the network's capacity");
+    HIPCALL(u.load_dense_input(x, batch), "nn input");
+    HIPCALL(u.forward(batch), "nn forward");
+    const long n3 = (long)u.n[0] * u.n[0] * u.n[0];
+    HIPCALL(hipMemcpyAsync(y, u.y, sizeof(float) * n3 * batch, hipMemcpyDeviceToDevice, u.s), "nn output");
+    HIPCALL(hipStreamSynchronize(u.s), "nn forward");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_gradients(pfmg_nn *nn, const float *x, const float *target, int32_t batch, double *loss_out,
+                              float *grads_out)
+{
+    if (!nn || !x || !target || !grads_out) return fail(PFMG_ERR_ARG, "null argument");
+    pfmg::UNet &u = nn->net;
+    if (!u.training) return fail(PFMG_ERR_STATE, "the network was created for inference only");
+    if (batch < 1 || batch > u.cap) return fail(PFMG_ERR_ARG, "batch exceeds the network's capacity");
+    const long n3 = (long)u.n[0] * u.n[0] * u.n[0];
+    HIPCALL(u.load_dense_input(x, batch), "nn input");
+    HIPCALL(hipMemcpyAsync(u.target, target, sizeof(float) * n3 * batch, hipMemcpyDeviceToDevice, u.s), "nn target");
+    HIPCALL(u.forward(batch), "nn forward");
+    HIPCALL(u.backward(batch, (double)n3 * batch), "nn backward");
+    double l = 0;
+    HIPCALL(hipMemcpyAsync(&l, u.loss, 8, hipMemcpyDeviceToHost, u.s), "nn loss");
+    HIPCALL(hipMemcpyAsync(nn->stage, u.grads, sizeof(float) * u.nparams, hipMemcpyDeviceToHost, u.s), "nn grads");
+    HIPCALL(hipStreamSynchronize(u.s), "nn gradients");
+    from_kernel_layout(u, nn->stage, grads_out);
+    if (loss_out) *loss_out = l / ((double)n3 * batch);
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_train_step(pfmg_nn *nn, const void *pairs, const float *ah2, int32_t n_pairs, const int32_t *idx,
+                               int32_t batch, float lr, double *loss_out)
+{
+    if (!nn || !pairs || !ah2 || !idx) return fail(PFMG_ERR_ARG, "null argument");
+    for (int q = 0; q < batch; ++q)
+        if (idx[q] < 0 || idx[q] >= n_pairs) return fail(PFMG_ERR_ARG, "pair index out of range");
+    pfmg::UNet &u = nn->net;
+    if (!u.training) return fail(PFMG_ERR_STATE, "the network was created for inference only");
+    if (batch < 1 || batch > u.cap) return fail(PFMG_ERR_ARG, "batch exceeds the network's capacity");
+    if (!(lr > 0)) return fail(PFMG_ERR_ARG, "lr must be positive");
+    HIPCALL(u.train_step((const pfmg::nn::bf16 *)pairs, ah2, idx, batch, lr, loss_out), "nn train step");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_nn_tensor(pfmg_nn *nn, int32_t layer, int32_t which, int32_t batch, float *dst)
+{
+    if (!nn || !dst) return fail(PFMG_ERR_ARG, "null argument");
+    pfmg::UNet &u = nn->net;
+    if (layer < 0 || layer > 12 || which < 0 || which > 3) return fail(PFMG_ERR_ARG, "layer in 0..12, which in 0..3");
+    if (batch < 1 || batch > u.cap) return fail(PFMG_ERR_ARG, "bad batch");
+    if (which >= 2 && !u.training) return fail(PFMG_ERR_STATE, "gradients need a training network");
+    if (which == 3 && layer == 0) return fail(PFMG_ERR_ARG, "the first layer has no input gradient");
+    const pfmg::UNetLayer &l = u.L[layer];
+    const pfmg::nn::Act a = which == 0 ? l.in : which == 1 ? l.out : which == 2 ? l.dout : l.din;
+    const int c = (which == 0 || which == 3) ? l.cin : l.cout;
+    HIPCALL(pfmg::nn::act_to_dense(a, c, batch, dst, u.s), "nn tensor");
+    HIPCALL(hipStreamSynchronize(u.s), "nn tensor");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_attach_nn(pfmg_ctx *ctx, pfmg_nn *nn)
+{
+    if (!ctx) return fail(PFMG_ERR_ARG, "null context");
+    pfmg::Solver &sv = ctx->sv;
+    if (nn) {
+        if (sv.p.guess != PFMG_GUESS_LEARNED) return fail(PFMG_ERR_ARG, "the context was created with guess = PFMG_GUESS_PREV");
+        if (nn->net.n[0] != sv.p.n) return fail(PFMG_ERR_ARG, "network grid differs from the context's fine grid");
+        if (nn->net.cap < sv.P) return fail(PFMG_ERR_ARG, "network batch must hold every slice");
+    }
+    sv.unet = nn ? &nn->net : nullptr;
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_guess_stats(pfmg_ctx *ctx, int64_t *tried, int64_t *taken)
+{
+    if (!ctx) return fail(PFMG_ERR_ARG, "null context");
+    if (tried) *tried = ctx->sv.guess_tried;
+    if (taken) *taken = ctx->sv.guess_taken;
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_record(pfmg_ctx *ctx, void *pairs, float *ah2, double *scratch, int32_t capacity)
+{
+    if (!ctx) return fail(PFMG_ERR_ARG, "null context");
+    pfmg::Solver &sv = ctx->sv;
+    if (pairs && (!ah2 || !scratch || capacity < sv.P)) return fail(PFMG_ERR_ARG, "recording needs pairs, ah2, scratch and capacity >= P");
+    if (pairs && (sv.p.dim != 3 || sv.p.vcycles_per_solve != 0))
+        return fail(PFMG_ERR_ARG, "recording takes the full node solves of a 3D context (vcycles_per_solve = 0)");
+    sv.rec_pairs = (__bf16 *)pairs;
+    sv.rec_ah2 = ah2;
+    sv.rec_scratch = scratch;
+    sv.rec_cap = pairs ? capacity : 0;
+    sv.rec_count = 0;
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_record_count(pfmg_ctx *ctx, int32_t *count_out)
+{
+    if (!ctx || !count_out) return fail(PFMG_ERR_ARG, "null argument");
+    *count_out = ctx->sv.rec_count;
     return PFMG_OK;
 }
 

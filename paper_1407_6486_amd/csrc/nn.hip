@@ -1,0 +1,698 @@
+// Network kernels of the learned initial guess (see nn.h).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: a workgroup
+// of 4 wavefronts computes 64 output voxels (16 per wavefront) times all
+// output channels; the K dimension runs over (tap, 8-channel block) groups,
+// four per MFMA.  Lane l of the MFMA holds A row l%16 and B column l%16
+// with k = 8 (l/16) .. 8 (l/16) + 7, and receives D rows 4 (l/16) .. + 3 of
+// column l%16.  A rows are voxels: each lane loads its voxel's 8 channels of
+// one tap with one 16-byte load (channels-last); B columns are output
+// channels, 16-byte loads of the weights [tap][cout][cin8].
+//
+// Weight gradients are GEMMs over voxels (K = voxels): 32 voxels of the
+// upstream gradient and of the layer input are staged in LDS per step, so
+// that the MFMA operands can be read voxel-major; one workgroup per tap and
+// chunk of voxels accumulates in registers and adds its partial sums
+// atomically.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "nn.h"
+
+namespace pfmg {
+namespace nn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline long vox(int n, int s, int z, int y, int x)
+{
+    const long m = n + 2;
+    return (((long)s * m + z) * m + y) * m + x;
+}
+
+// Domain of the M dimension of a convolution: SAME / DOWN iterate over the
+// output grid; UP iterates over one parity class of the output grid.
+struct Dom {
+    int cz, cy, cx;
+    int pz, py, px;
+};
+
+__device__ inline Dom domain(int mode, int nin, int nout, int cls)
+{
+    Dom d{nout, nout, nout, 0, 0, 0};
+    if (mode == UP) {
+        d.pz = (cls >> 2) & 1;
+        d.py = (cls >> 1) & 1;
+        d.px = cls & 1;
+        // fine 1-based i: even i = 2 (j+1), j < nc; odd i = 2 j + 1, j <= nc
+        d.cz = d.pz ? nin + 1 : nin;
+        d.cy = d.py ? nin + 1 : nin;
+        d.cx = d.px ? nin + 1 : nin;
+    }
+    return d;
+}
+
+template <int MODE, int NT>
+__global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_count, Act out, const bf16 *__restrict__ W,
+                                                   const float *__restrict__ bias, int relu, int batch)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nin = in.n, nout = out.n;
+    constexpr int cout = NT * 16;
+    const Dom D = domain(MODE, nin, nout, blockIdx.y);
+    const long total = (long)batch * D.cz * D.cy * D.cx;
+    const long vblk = (long)blockIdx.x * 64;
+    if (vblk >= total) return;
+    const long v0 = vblk + wave * 16;
+    const long va = v0 + (lane & 15);
+    const bool a_ok = va < total;
+    int s, iz, iy, ix;
+    {
+        long t = a_ok ? va : 0;
+        ix = (int)(t % D.cx);
+        t /= D.cx;
+        iy = (int)(t % D.cy);
+        t /= D.cy;
+        iz = (int)(t % D.cz);
+        s = (int)(t / D.cz);
+    }
+    int bz, by, bx;   // input point (halo'd) of tap offset 0
+    if (MODE == SAME) {
+        bz = iz + 1; by = iy + 1; bx = ix + 1;
+    } else if (MODE == DOWN) {
+        bz = 2 * (iz + 1); by = 2 * (iy + 1); bx = 2 * (ix + 1);
+    } else {
+        // even axis: J = j + 1 (d = 0); odd axis: J = j (d = +1) or j + 1 (d = -1)
+        bz = D.pz ? iz : iz + 1; by = D.py ? iy : iy + 1; bx = D.px ? ix : ix + 1;
+    }
+    const long m = nin + 2;
+    const bf16 *__restrict__ xin = in.p + vox(nin, s, bz, by, bx) * in.cs;
+    const int ntap = MODE == UP ? (1 << (D.pz + D.py + D.px)) : 27;
+    const int groups = ntap * cb_count;
+    const int ksteps = (groups + 3) >> 2;
+    const int cin8 = cb_count * 8;
+    const int kg = lane >> 4;
+    f4 acc[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < ksteps; ++ks) {
+        const int g = ks * 4 + kg;
+        const bool gok = g < groups;
+        bf16x8 a = {};
+        int tapw = 0, cb = 0;
+        if (gok) {
+            const int t = g / cb_count;
+            cb = g - t * cb_count;
+            int oz, oy, ox;
+            if (MODE == UP) {
+                int bit = 0, wz = 0, wy = 0, wx = 0;
+                oz = oy = ox = 0;
+                if (D.pz) { const int sel = (t >> bit++) & 1; wz = sel ? -1 : 1; oz = sel; }
+                if (D.py) { const int sel = (t >> bit++) & 1; wy = sel ? -1 : 1; oy = sel; }
+                if (D.px) { const int sel = (t >> bit++) & 1; wx = sel ? -1 : 1; ox = sel; }
+                tapw = (wz + 1) * 9 + (wy + 1) * 3 + (wx + 1);
+            } else {
+                oz = t / 9 - 1;
+                oy = (t / 3) % 3 - 1;
+                ox = t % 3 - 1;
+                tapw = t;
+            }
+            if (a_ok) a = *reinterpret_cast<const bf16x8 *>(xin + (((long)oz * m + oy) * m + ox) * in.cs + cb * 8);
+        }
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            bf16x8 b = {};
+            if (gok)
+                b = *reinterpret_cast<const bf16x8 *>(W + ((long)tapw * cout + q * 16 + (lane & 15)) * cin8 + cb * 8);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const long v = v0 + 4 * (lane >> 4) + t;
+        if (v >= total) continue;
+        long u = v;
+        const int ox = (int)(u % D.cx);
+        u /= D.cx;
+        const int oy = (int)(u % D.cy);
+        u /= D.cy;
+        const int oz = (int)(u % D.cz);
+        const int os = (int)(u / D.cz);
+        int z, y, x;
+        if (MODE == UP) {
+            z = D.pz ? 2 * oz + 1 : 2 * (oz + 1);
+            y = D.py ? 2 * oy + 1 : 2 * (oy + 1);
+            x = D.px ? 2 * ox + 1 : 2 * (ox + 1);
+        } else {
+            z = oz + 1; y = oy + 1; x = ox + 1;
+        }
+        bf16 *o = out.p + vox(nout, os, z, y, x) * out.cs;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const int co = q * 16 + (lane & 15);
+            float val = acc[q][t] + (bias ? bias[co] : 0.f);
+            if (relu) val = fmaxf(val, 0.f);
+            o[co] = (bf16)val;
+        }
+    }
+}
+
+// Weight gradient of one tap over a chunk of the base domain: SAME and DOWN
+// iterate over the output grid (dz at the point, x at the tap's input
+// point); UP iterates over the coarse input grid (x at J, dz at 2J + d).
+constexpr int WG_K = 32;
+constexpr int WG_LD = 64 + 8;   // LDS row length (bf16), padded
+
+template <int MODE>
+__global__ __launch_bounds__(256) void wgrad_kernel(Act x, int cin, Act dz, int cout, float *__restrict__ dW,
+                                                    int batch, long chunk)
+{
+    __shared__ bf16 sz[WG_K][WG_LD];
+    __shared__ bf16 sx[WG_K][WG_LD];
+    const int tap = blockIdx.y;
+    const int tz = tap / 9 - 1, ty = (tap / 3) % 3 - 1, tx = tap % 3 - 1;
+    const int nb = MODE == UP ? x.n : dz.n;
+    const long total = (long)batch * nb * nb * nb;
+    const long vb = (long)blockIdx.x * chunk;
+    if (vb >= total) return;
+    const long ve = vb + chunk < total ? vb + chunk : total;
+    const int cin16 = (cin + 15) & ~15;
+    const int cin8 = (cin + 7) & ~7;
+    const int MT = cout / 16, NTI = cin16 / 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    f4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    const int zv = cout / 8, xv = cin16 / 8;
+    for (long v = vb; v < ve; v += WG_K) {
+        for (int idx = threadIdx.x; idx < WG_K * (zv + xv); idx += 256) {
+            const bool isz = idx < WG_K * zv;
+            const int j = isz ? idx : idx - WG_K * zv;
+            const int per = isz ? zv : xv;
+            const int k = j / per, c8 = j - k * per;
+            const long vv = v + k;
+            bf16x8 val = {};
+            if (vv < ve && (isz || c8 * 8 < cin8)) {
+                long t = vv;
+                const int ox = (int)(t % nb);
+                t /= nb;
+                const int oy = (int)(t % nb);
+                t /= nb;
+                const int oz = (int)(t % nb);
+                const int s = (int)(t / nb);
+                int pz, py, px;
+                const Act &A = isz ? dz : x;
+                if (isz) {
+                    if (MODE == UP) { pz = 2 * (oz + 1) + tz; py = 2 * (oy + 1) + ty; px = 2 * (ox + 1) + tx; }
+                    else { pz = oz + 1; py = oy + 1; px = ox + 1; }
+                } else {
+                    if (MODE == SAME) { pz = oz + 1 + tz; py = oy + 1 + ty; px = ox + 1 + tx; }
+                    else if (MODE == DOWN) { pz = 2 * (oz + 1) + tz; py = 2 * (oy + 1) + ty; px = 2 * (ox + 1) + tx; }
+                    else { pz = oz + 1; py = oy + 1; px = ox + 1; }
+                }
+                val = *reinterpret_cast<const bf16x8 *>(A.p + vox(A.n, s, pz, py, px) * A.cs + c8 * 8);
+            }
+            bf16 *dst = isz ? &sz[k][c8 * 8] : &sx[k][c8 * 8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[e] = val[e];
+        }
+        __syncthreads();
+        int slot = 0;
+        for (int tile = wave; tile < MT * NTI; tile += 4, ++slot) {
+            const int mt = tile / NTI, nt = tile - mt * NTI;
+            bf16x8 a, b;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                a[e] = sz[(lane >> 4) * 8 + e][mt * 16 + (lane & 15)];
+                b[e] = sx[(lane >> 4) * 8 + e][nt * 16 + (lane & 15)];
+            }
+            if (slot == 0) acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[0], 0, 0, 0);
+            else if (slot == 1) acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[1], 0, 0, 0);
+            else if (slot == 2) acc[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[2], 0, 0, 0);
+            else acc[3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[3], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    int slot = 0;
+    for (int tile = wave; tile < MT * NTI; tile += 4, ++slot) {
+        const int mt = tile / NTI, nt = tile - mt * NTI;
+        const int ci = nt * 16 + (lane & 15);
+        if (ci >= cin) continue;
+        const f4 r = slot == 0 ? acc[0] : slot == 1 ? acc[1] : slot == 2 ? acc[2] : acc[3];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int co = mt * 16 + 4 * (lane >> 4) + t;
+            atomicAdd(dW + ((long)tap * cout + co) * cin + ci, r[t]);
+        }
+    }
+}
+
+__global__ void bias_grad_kernel(Act dz, int cout, float *db, long total, long chunk)
+{
+    __shared__ float part[256];
+    const int c = threadIdx.x % cout, lanes = 256 / cout, sub = threadIdx.x / cout;
+    const long vb = (long)blockIdx.x * chunk;
+    const long ve = vb + chunk < total ? vb + chunk : total;
+    const int n = dz.n;
+    float acc = 0.f;
+    if (sub < lanes)
+        for (long v = vb + sub; v < ve; v += lanes) {
+            long t = v;
+            const int ox = (int)(t % n);
+            t /= n;
+            const int oy = (int)(t % n);
+            t /= n;
+            const int oz = (int)(t % n);
+            const int s = (int)(t / n);
+            acc += (float)dz.p[vox(n, s, oz + 1, oy + 1, ox + 1) * dz.cs + c];
+        }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < cout) {
+        float sum = 0.f;
+        for (int q = 0; q < lanes; ++q) sum += part[q * cout + threadIdx.x];
+        atomicAdd(db + threadIdx.x, sum);
+    }
+}
+
+__global__ void relu_bwd_kernel(Act dy, Act dsk, Act y, Act dz, int c, long total)
+{
+    const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int groups = c / 8;
+    if (w >= total * groups) return;
+    const int g = (int)(w % groups);
+    long t = w / groups;
+    const int n = y.n;
+    const int ox = (int)(t % n);
+    t /= n;
+    const int oy = (int)(t % n);
+    t /= n;
+    const int oz = (int)(t % n);
+    const int s = (int)(t / n);
+    const long vv = vox(n, s, oz + 1, oy + 1, ox + 1);
+    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(dy.p + vv * dy.cs + g * 8);
+    const bf16x8 yy = *reinterpret_cast<const bf16x8 *>(y.p + vv * y.cs + g * 8);
+    bf16x8 k = {};
+    if (dsk.p) k = *reinterpret_cast<const bf16x8 *>(dsk.p + vv * dsk.cs + g * 8);
+    bf16x8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float v = (float)a[e] + (dsk.p ? (float)k[e] : 0.f);
+        r[e] = (bf16)((float)yy[e] > 0.f ? v : 0.f);
+    }
+    *reinterpret_cast<bf16x8 *>(dz.p + vv * dz.cs + g * 8) = r;
+}
+
+__global__ void pw_forward_kernel(Act x, const float *__restrict__ w, const float *__restrict__ b, float *y, long total)
+{
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= total) return;
+    const int n = x.n;
+    long t = v;
+    const int ox = (int)(t % n);
+    t /= n;
+    const int oy = (int)(t % n);
+    t /= n;
+    const int oz = (int)(t % n);
+    const int s = (int)(t / n);
+    const bf16 *p = x.p + vox(n, s, oz + 1, oy + 1, ox + 1) * x.cs;
+    const bf16x8 lo = *reinterpret_cast<const bf16x8 *>(p), hi = *reinterpret_cast<const bf16x8 *>(p + 8);
+    float acc = b[0];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc += w[e] * (float)lo[e] + w[8 + e] * (float)hi[e];
+    y[v] = acc;
+}
+
+__global__ void pw_loss_backward_kernel(Act x, const float *__restrict__ w, const float *__restrict__ y,
+                                        const float *__restrict__ tg, float scale, Act dx, float *dw, float *db,
+                                        double *loss, long total)
+{
+    __shared__ float part[18][256];
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    float contrib[16] = {}, g = 0.f, l2 = 0.f;
+    if (v < total) {
+        const int n = x.n;
+        long t = v;
+        const int ox = (int)(t % n);
+        t /= n;
+        const int oy = (int)(t % n);
+        t /= n;
+        const int oz = (int)(t % n);
+        const int s = (int)(t / n);
+        const long vv = vox(n, s, oz + 1, oy + 1, ox + 1);
+        const float r = y[v] - tg[v];
+        l2 = r * r;
+        g = scale * r;
+        const bf16 *p = x.p + vv * x.cs;
+        const bf16x8 lo = *reinterpret_cast<const bf16x8 *>(p), hi = *reinterpret_cast<const bf16x8 *>(p + 8);
+        bf16x8 dlo, dhi;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            contrib[e] = g * (float)lo[e];
+            contrib[8 + e] = g * (float)hi[e];
+            dlo[e] = (bf16)(g * w[e]);
+            dhi[e] = (bf16)(g * w[8 + e]);
+        }
+        bf16 *q = dx.p + vv * dx.cs;
+        *reinterpret_cast<bf16x8 *>(q) = dlo;
+        *reinterpret_cast<bf16x8 *>(q + 8) = dhi;
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) part[e][threadIdx.x] = contrib[e];
+    part[16][threadIdx.x] = g;
+    part[17][threadIdx.x] = l2;
+    __syncthreads();
+    if (threadIdx.x < 18) {
+        float sum = 0.f;
+        for (int q = 0; q < (int)blockDim.x; ++q) sum += part[threadIdx.x][q];
+        if (threadIdx.x < 16) atomicAdd(dw + threadIdx.x, sum);
+        else if (threadIdx.x == 16) atomicAdd(db, sum);
+        else atomicAdd(loss, (double)sum);
+    }
+}
+
+__global__ void weights_forward_kernel(const float *Wm, int cout, int cin, int cin8, bf16 *Wf)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = 27L * cout * cin8;
+    if (i >= total) return;
+    const int ci = (int)(i % cin8);
+    const long r = i / cin8;   // tap * cout + co
+    Wf[i] = (bf16)(ci < cin ? Wm[r * cin + ci] : 0.f);
+}
+
+__global__ void weights_backward_kernel(const float *Wm, int cout, int cin, int flip, bf16 *Wb)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = 27L * cout * cin;
+    if (i >= total) return;
+    // destination [tap'][ci][co]
+    const int co = (int)(i % cout);
+    const long r = i / cout;
+    const int ci = (int)(r % cin);
+    const int tp = (int)(r / cin);
+    const int tap = flip ? 26 - tp : tp;
+    Wb[i] = (bf16)Wm[((long)tap * cout + co) * cin + ci];
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, long count, float lr, float b1, float b2,
+                            float eps, float c1, float c2)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void fill_f32_kernel(float *p, float v, long count)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// ---- field <-> network (3D fields in the solver layout)
+__global__ __launch_bounds__(BLOCK) void make_input_kernel(Tiling t, double alpha, View<double> b, View<double> u,
+                                                           const double *sr, const double *su, Act x0)
+{
+    Pt q; int i, j, k; long o;
+    if (!tile_point<3>(t, q, i, j, k, o)) return;
+    const double *uu = fp(u, q);
+    const double ah = q.par(alpha) * (double)(q.n + 1) * (double)(q.n + 1);
+    const double hu = uu[o] - ah * d2sum<3>(uu, o, row_stride(q.n), plane_stride(q.n));
+    const double r = fp(b, q)[o] - hu;
+    bf16x8 v = {};
+    v[0] = (bf16)(float)(r / sr[q.item]);
+    v[1] = (bf16)(float)(uu[o] / su[q.item]);
+    v[2] = (bf16)(float)ah;
+    *reinterpret_cast<bf16x8 *>(x0.p + vox(q.n, q.item, k, j, i) * x0.cs) = v;
+}
+
+__global__ __launch_bounds__(BLOCK) void apply_guess_kernel(Tiling t, View<double> u, const float *y,
+                                                            const double *sr, View<double> g)
+{
+    Pt q; int i, j, k; long o;
+    if (!tile_point<3>(t, q, i, j, k, o)) return;
+    const long n = q.n;
+    const long d = (i - 1) + n * ((j - 1) + n * (long)(k - 1));
+    fp(g, q)[o] = fp(u, q)[o] + sr[q.item] * (double)y[(long)q.item * n * n * n + d];
+}
+
+__global__ void gather_batch_kernel(const bf16 *pairs, const float *ah2, const int *idx, int n, Act x0, float *tg,
+                                    long total)
+{
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= total) return;
+    const long n3 = (long)n * n * n;
+    const int s = (int)(v / n3);
+    const long d = v - s * n3;
+    const int ox = (int)(d % n), oy = (int)((d / n) % n), oz = (int)(d / ((long)n * n));
+    const long pr = idx[s];
+    bf16x8 val = {};
+    val[0] = pairs[(pr * 3 + 0) * n3 + d];
+    val[1] = pairs[(pr * 3 + 1) * n3 + d];
+    val[2] = (bf16)ah2[pr];
+    *reinterpret_cast<bf16x8 *>(x0.p + vox(n, s, oz + 1, oy + 1, ox + 1) * x0.cs) = val;
+    tg[v] = (float)pairs[(pr * 3 + 2) * n3 + d];
+}
+
+__global__ void act_to_dense_kernel(Act a, int c, float *dst, long total)
+{
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= total) return;
+    const int n = a.n;
+    const long n3 = (long)n * n * n;
+    const int s = (int)(v / n3);
+    const long d = v - s * n3;
+    const int ox = (int)(d % n), oy = (int)((d / n) % n), oz = (int)(d / ((long)n * n));
+    const bf16 *p = a.p + vox(n, s, oz + 1, oy + 1, ox + 1) * a.cs;
+    for (int q = 0; q < c; ++q) dst[((long)s * c + q) * n3 + d] = (float)p[q];
+}
+
+__global__ void load_input_dense_kernel(const float *xd, int n, Act x0, long total)
+{
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= total) return;
+    const long n3 = (long)n * n * n;
+    const int s = (int)(v / n3);
+    const long d = v - s * n3;
+    const int ox = (int)(d % n), oy = (int)((d / n) % n), oz = (int)(d / ((long)n * n));
+    bf16x8 val = {};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) val[c] = (bf16)xd[((long)s * 3 + c) * n3 + d];
+    *reinterpret_cast<bf16x8 *>(x0.p + vox(n, s, oz + 1, oy + 1, ox + 1) * x0.cs) = val;
+}
+
+__global__ __launch_bounds__(BLOCK) void record_inputs_kernel(Tiling t, double alpha, View<double> b, View<double> u,
+                                                              const double *sr, const double *su, bf16 *pairs,
+                                                              float *ah2, long slot0, double *u0)
+{
+    Pt q; int i, j, k; long o;
+    if (!tile_point<3>(t, q, i, j, k, o)) return;
+    const long n = q.n, n3 = n * n * n;
+    const long d = (i - 1) + n * ((j - 1) + n * (long)(k - 1));
+    const double *uu = fp(u, q);
+    const double ah = q.par(alpha) * (double)(n + 1) * (double)(n + 1);
+    const double r = fp(b, q)[o] - (uu[o] - ah * d2sum<3>(uu, o, row_stride(q.n), plane_stride(q.n)));
+    const long slot = slot0 + q.item;
+    pairs[(slot * 3 + 0) * n3 + d] = (bf16)(float)(r / sr[q.item]);
+    pairs[(slot * 3 + 1) * n3 + d] = (bf16)(float)(uu[o] / su[q.item]);
+    u0[(long)q.item * n3 + d] = uu[o];
+    if (d == 0) ah2[slot] = (float)ah;
+}
+
+__global__ __launch_bounds__(BLOCK) void record_target_kernel(Tiling t, View<double> u, const double *sr,
+                                                              const double *u0, bf16 *pairs, long slot0)
+{
+    Pt q; int i, j, k; long o;
+    if (!tile_point<3>(t, q, i, j, k, o)) return;
+    const long n = q.n, n3 = n * n * n;
+    const long d = (i - 1) + n * ((j - 1) + n * (long)(k - 1));
+    const long slot = slot0 + q.item;
+    pairs[(slot * 3 + 2) * n3 + d] = (bf16)(float)((fp(u, q)[o] - u0[(long)q.item * n3 + d]) / sr[q.item]);
+}
+
+inline unsigned blocks_of(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t conv(Mode mode, const Act &in, int cin8, const Act &out, int cout, const bf16 *W, const float *bias,
+                bool relu, int batch, hipStream_t s)
+{
+    if (cin8 % 8 || cout % 16 || cout > 64 || in.cs % 8 || out.cs % 8 || batch < 1) return hipErrorInvalidValue;
+    if (mode == SAME && in.n != out.n) return hipErrorInvalidValue;
+    if (mode == DOWN && out.n != (in.n + 1) / 2 - 1) return hipErrorInvalidValue;
+    if (mode == UP && in.n != (out.n + 1) / 2 - 1) return hipErrorInvalidValue;
+    const int cb = cin8 / 8;
+    long total;
+    dim3 grid;
+    if (mode == UP) {
+        total = (long)batch * (in.n + 1) * (in.n + 1) * (in.n + 1);
+        grid = dim3(blocks_of(total, 64), 8);
+    } else {
+        total = (long)batch * out.n * out.n * out.n;
+        grid = dim3(blocks_of(total, 64), 1);
+    }
+    const int r = relu ? 1 : 0;
+#define NN_CONV(MODE_, NT_) conv_kernel<MODE_, NT_><<<grid, 256, 0, s>>>(in, cb, out, W, bias, r, batch)
+#define NN_CONV_NT(MODE_)                     \
+    switch (cout / 16) {                      \
+    case 1: NN_CONV(MODE_, 1); break;         \
+    case 2: NN_CONV(MODE_, 2); break;         \
+    case 3: NN_CONV(MODE_, 3); break;         \
+    default: NN_CONV(MODE_, 4); break;        \
+    }
+    if (mode == SAME) NN_CONV_NT(SAME)
+    else if (mode == DOWN) NN_CONV_NT(DOWN)
+    else NN_CONV_NT(UP)
+#undef NN_CONV_NT
+#undef NN_CONV
+    return hipGetLastError();
+}
+
+hipError_t conv_wgrad(Mode mode, const Act &x, int cin, const Act &dz, int cout, float *dW, int batch, hipStream_t s)
+{
+    if (cout % 16 || cout > 64 || cin > 64 || cin < 1 || x.cs % 8 || dz.cs % 8) return hipErrorInvalidValue;
+    if ((cout / 16) * ((cin + 15) / 16) > 16) return hipErrorInvalidValue;
+    const int nb = mode == UP ? x.n : dz.n;
+    const long total = (long)batch * nb * nb * nb;
+    const long chunk = std::max<long>(WG_K, ((total + 255) / 256 + WG_K - 1) / WG_K * WG_K);
+    const dim3 grid(blocks_of(total, (int)chunk), 27);
+    if (mode == SAME) wgrad_kernel<SAME><<<grid, 256, 0, s>>>(x, cin, dz, cout, dW, batch, chunk);
+    else if (mode == DOWN) wgrad_kernel<DOWN><<<grid, 256, 0, s>>>(x, cin, dz, cout, dW, batch, chunk);
+    else wgrad_kernel<UP><<<grid, 256, 0, s>>>(x, cin, dz, cout, dW, batch, chunk);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(const Act &dz, int cout, float *db, int batch, hipStream_t s)
+{
+    if (cout < 1 || cout > 256 || 256 % cout) return hipErrorInvalidValue;
+    const long total = (long)batch * dz.n * dz.n * dz.n;
+    const long chunk = std::max<long>(256, (total + 511) / 512);
+    bias_grad_kernel<<<blocks_of(total, (int)chunk), 256, 0, s>>>(dz, cout, db, total, chunk);
+    return hipGetLastError();
+}
+
+hipError_t relu_bwd(const Act &dy, const Act &dskip, const Act &y, const Act &dz, int c, int batch, hipStream_t s)
+{
+    if (c % 8) return hipErrorInvalidValue;
+    const long total = (long)batch * y.n * y.n * y.n;
+    relu_bwd_kernel<<<blocks_of(total * (c / 8), 256), 256, 0, s>>>(dy, dskip, y, dz, c, total);
+    return hipGetLastError();
+}
+
+hipError_t pw_forward(const Act &x, const float *w, const float *b, float *y, int batch, hipStream_t s)
+{
+    const long total = (long)batch * x.n * x.n * x.n;
+    pw_forward_kernel<<<blocks_of(total, 256), 256, 0, s>>>(x, w, b, y, total);
+    return hipGetLastError();
+}
+
+hipError_t pw_loss_backward(const Act &x, const float *w, const float *y, const float *t, double count, const Act &dx,
+                            float *dw, float *db, double *loss_acc, int batch, hipStream_t s)
+{
+    const long total = (long)batch * x.n * x.n * x.n;
+    pw_loss_backward_kernel<<<blocks_of(total, 256), 256, 0, s>>>(x, w, y, t, (float)(2.0 / count), dx, dw, db,
+                                                                   loss_acc, total);
+    return hipGetLastError();
+}
+
+hipError_t weights_forward(const float *Wm, int cout, int cin, int cin8, bf16 *Wf, hipStream_t s)
+{
+    weights_forward_kernel<<<blocks_of(27L * cout * cin8, 256), 256, 0, s>>>(Wm, cout, cin, cin8, Wf);
+    return hipGetLastError();
+}
+
+hipError_t weights_backward(const float *Wm, int cout, int cin, bool flip, bf16 *Wb, hipStream_t s)
+{
+    weights_backward_kernel<<<blocks_of(27L * cout * cin, 256), 256, 0, s>>>(Wm, cout, cin, flip ? 1 : 0, Wb);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *p, const float *g, float *m, float *v, long count, float lr, float beta1, float beta2,
+                float eps, int t, hipStream_t s)
+{
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    adam_kernel<<<blocks_of(count, 256), 256, 0, s>>>(p, g, m, v, count, lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t fill_f32(float *p, float v, long count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    fill_f32_kernel<<<blocks_of(count, 256), 256, 0, s>>>(p, v, count);
+    return hipGetLastError();
+}
+
+hipError_t make_input(const Tiling &t, double alpha, View<double> b, View<double> u, const double *sr,
+                      const double *su, const Act &x0, hipStream_t s)
+{
+    if (t.dim != 3 || t.nseg != 1 || x0.n != t.n || x0.cs < 8) return hipErrorInvalidValue;
+    const long nb = grid_blocks(t);
+    if (nb == 0) return hipSuccess;
+    make_input_kernel<<<(unsigned)nb, BLOCK, 0, s>>>(t, alpha, b, u, sr, su, x0);
+    return hipGetLastError();
+}
+
+hipError_t apply_guess(const Tiling &t, View<double> u, const float *y, const double *sr, View<double> g,
+                       hipStream_t s)
+{
+    if (t.dim != 3 || t.nseg != 1) return hipErrorInvalidValue;
+    const long nb = grid_blocks(t);
+    if (nb == 0) return hipSuccess;
+    apply_guess_kernel<<<(unsigned)nb, BLOCK, 0, s>>>(t, u, y, sr, g);
+    return hipGetLastError();
+}
+
+hipError_t gather_batch(const bf16 *pairs, const float *ah2, const int *idx, int batch, int n, const Act &x0,
+                        float *target, hipStream_t s)
+{
+    if (x0.n != n || x0.cs < 8) return hipErrorInvalidValue;
+    const long total = (long)batch * n * n * n;
+    gather_batch_kernel<<<blocks_of(total, 256), 256, 0, s>>>(pairs, ah2, idx, n, x0, target, total);
+    return hipGetLastError();
+}
+
+hipError_t act_to_dense(const Act &a, int c, int batch, float *dst, hipStream_t s)
+{
+    const long total = (long)batch * a.n * a.n * a.n;
+    act_to_dense_kernel<<<blocks_of(total, 256), 256, 0, s>>>(a, c, dst, total);
+    return hipGetLastError();
+}
+
+hipError_t load_input_dense(const float *xd, int batch, int n, const Act &x0, hipStream_t s)
+{
+    if (x0.n != n || x0.cs < 8) return hipErrorInvalidValue;
+    const long total = (long)batch * n * n * n;
+    load_input_dense_kernel<<<blocks_of(total, 256), 256, 0, s>>>(xd, n, x0, total);
+    return hipGetLastError();
+}
+
+hipError_t record_inputs(const Tiling &t, double alpha, View<double> b, View<double> u, const double *sr,
+                         const double *su, bf16 *pairs, float *ah2, long slot0, double *u0, hipStream_t s)
+{
+    if (t.dim != 3 || t.nseg != 1) return hipErrorInvalidValue;
+    const long nb = grid_blocks(t);
+    if (nb == 0) return hipSuccess;
+    record_inputs_kernel<<<(unsigned)nb, BLOCK, 0, s>>>(t, alpha, b, u, sr, su, pairs, ah2, slot0, u0);
+    return hipGetLastError();
+}
+
+hipError_t record_target(const Tiling &t, View<double> u, const double *sr, const double *u0, bf16 *pairs, long slot0,
+                         hipStream_t s)
+{
+    if (t.dim != 3 || t.nseg != 1) return hipErrorInvalidValue;
+    const long nb = grid_blocks(t);
+    if (nb == 0) return hipSuccess;
+    record_target_kernel<<<(unsigned)nb, BLOCK, 0, s>>>(t, u, sr, u0, pairs, slot0);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace pfmg

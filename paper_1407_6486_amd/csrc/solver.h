@@ -32,6 +32,8 @@ struct PLevel {
     double *slot(double *base, int p, int m) const { return base + ((long)p * nn + m) * fs; }
 };
 
+struct UNet;
+
 struct Timer {
     std::string key;                  // kernel family "@" grid n, e.g. "rbgs@127"
     bool on = false;
@@ -95,6 +97,16 @@ struct Solver {
     bool warm_iter = false, warm_start = false;   // first call ran eagerly
     bool use_graph() const { return graphs && p.vcycles_per_solve > 0 && !timer.on; }
     long long vc_iter[2] = {0, 0}, vc_start[2] = {0, 0};   // V-cycles of one replay
+    // learned initial guess and the recording of training pairs
+    UNet *unet = nullptr;
+    double *nnsc = nullptr, *hnnsc = nullptr;   // per-field scale factors [2P], device and pinned host
+    __bf16 *rec_pairs = nullptr;
+    float *rec_ah2 = nullptr;
+    double *rec_scratch = nullptr;
+    int rec_cap = 0, rec_count = 0;
+    long long guess_tried = 0, guess_taken = 0;
+    hipError_t learned_guess(View<double> u, View<double> b, int count, double alpha, std::vector<double> &rold,
+                             bool rec);
     hipError_t capture(const std::function<hipError_t()> &fn, hipGraphExec_t *out, long long *vc);
     void release_graphs();
     hipError_t spread_body();

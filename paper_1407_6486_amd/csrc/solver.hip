@@ -17,6 +17,7 @@
 #include "collocation.h"
 #include "solver.h"
 #include "tune.h"
+#include "unet.h"
 
 #define HC(x)                                  \
     do {                                       \
@@ -68,7 +69,13 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
         why = "full solves need mg_max_cycles >= 1, mg_tol >= 0, mg_stall > 0"; return false;
     }
     if (p.precision != PFMG_FP64 && p.precision != PFMG_MIXED) { why = "bad precision"; return false; }
-    if (p.guess != PFMG_GUESS_PREV) { why = "this context supports guess = PFMG_GUESS_PREV"; return false; }
+    if (p.guess != PFMG_GUESS_PREV && p.guess != PFMG_GUESS_LEARNED) { why = "bad guess"; return false; }
+    if (p.guess == PFMG_GUESS_LEARNED && (p.dim != 3 || p.vcycles_per_solve != 0 || !UNet::valid_n(p.n) ||
+                                          (p.smoother == PFMG_SMOOTH_RBGS && p.n < 31))) {
+        why = "the learned guess needs 3D full solves (vcycles_per_solve = 0) and a network grid: n odd over three "
+              "levels, n >= 31 with red-black smoothing";
+        return false;
+    }
     if (p.fine_send != PFMG_SEND_AFTER_ITER) { why = "fine_send must be PFMG_SEND_AFTER_ITER"; return false; }
     if (p.pfasst_max_iter < 1) { why = "pfasst_max_iter must be >= 1"; return false; }
     return true;
@@ -149,6 +156,7 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
     double *lt = (double *)take(256 * 8);
     auto *bits = (unsigned long long *)take((size_t)4 * P * k::RSLOTS * 8);
     int *mask = (int *)take((size_t)P * 4);
+    double *nnsc = (double *)take((size_t)2 * P * 8);
     if (sv) {
         sv->ublock = ub;
         sv->vb = vb;
@@ -158,6 +166,7 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
         sv->dLt = lt;
         sv->bits = bits;
         sv->mask = mask;
+        sv->nnsc = nnsc;
     }
     return ((off + 255) & ~(size_t)255) + 256;
 }
@@ -367,11 +376,17 @@ hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, dou
     HC(hipMemcpyAsync(hbits, bits, sizeof(unsigned long long) * 2 * count, hipMemcpyDeviceToHost, s));
     HC(hipStreamSynchronize(s));
     std::vector<double> nb(count), rold(count);
-    int active = 0;
     for (int q = 0; q < count; ++q) {
         nb[q] = bits_to_double(hbits[q]);
         rold[q] = bits_to_double(hbits[count + q]);
         if (!std::isfinite(nb[q]) || !std::isfinite(rold[q])) { last_solve_status = PFMG_ERR_NAN; return hipSuccess; }
+    }
+    // fine-level node solves: record the training pair, try the learned guess
+    const bool rec = lev == 0 && rec_pairs && rec_count + count <= rec_cap && dim == 3;
+    const bool learned = lev == 0 && unet && p.guess == PFMG_GUESS_LEARNED;
+    if (rec || learned) HC(learned_guess(u, b, count, alpha, rold, rec));
+    int active = 0;
+    for (int q = 0; q < count; ++q) {
         hmask[q] = rold[q] > p.mg_tol * nb[q];
         active += hmask[q];
     }
@@ -402,9 +417,61 @@ hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, dou
     }
     if (relres_host)
         for (int q = 0; q < count; ++q) relres_host[q] = nb[q] > 0 ? rold[q] / nb[q] : rold[q];
+    if (rec) {
+        HC(nn::record_target(tl(n, count), u, nnsc, rec_scratch, rec_pairs, rec_count, s));
+        rec_count += count;
+    }
     if (stalled_any) last_solve_status = PFMG_STALLED;
     else if (active > 0) last_solve_status = PFMG_NOT_CONVERGED;
     return hipSuccess;
+}
+
+// Before the V-cycles of a full fine-level node solve: scale factors
+// sr = |b - H u|_inf, su = |u|_inf per field; record the pair's inputs; and
+// with an attached network, its guess g = u + sr y replaces u in every field
+// where |b - H g|_inf < |b - H u|_inf (the FP64 residual judges).  rold is
+// updated for the fields that take the guess.
+hipError_t Solver::learned_guess(View<double> u, View<double> b, int count, double alpha, std::vector<double> &rold,
+                                 bool rec)
+{
+    const int n = L[0].n;
+    const Tiling t = tl(n, count);
+    HC(k::fill_u64(bits + 2 * count, 0, count, s));
+    HC(k::norm_inf(t, u, bits + 2 * count, s));
+    HC(hipMemcpyAsync(hbits + 2 * count, bits + 2 * count, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    for (int q = 0; q < count; ++q) {
+        const double su = bits_to_double(hbits[2 * count + q]);
+        hnnsc[q] = rold[q] > 0 ? rold[q] : 1.0;
+        hnnsc[count + q] = su > 0 ? su : 1.0;
+    }
+    HC(hipMemcpyAsync(nnsc, hnnsc, sizeof(double) * 2 * count, hipMemcpyHostToDevice, s));
+    if (rec) HC(nn::record_inputs(t, alpha, b, u, nnsc, nnsc + count, rec_pairs, rec_ah2, rec_count, rec_scratch, s));
+    if (!(unet && p.guess == PFMG_GUESS_LEARNED)) return hipSuccess;
+    View<double> g = L[0].mg[0].t;
+    hipStream_t ns = unet->s;
+    unet->s = s;
+    hipError_t e = nn::make_input(t, alpha, b, u, nnsc, nnsc + count, unet->x0, s);
+    if (e == hipSuccess) e = unet->forward(count);
+    unet->s = ns;
+    HC(e);
+    HC(nn::apply_guess(t, u, unet->y, nnsc, g, s));
+    HC(k::fill_u64(bits + count, 0, count, s));
+    HC(k::resid_norm(t, alpha, b, g, bits + count, s));
+    HC(hipMemcpyAsync(hbits + count, bits + count, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, s));
+    HC(hipStreamSynchronize(s));
+    int taken = 0;
+    for (int q = 0; q < count; ++q) {
+        const double rg = bits_to_double(hbits[count + q]);
+        hmask[q] = std::isfinite(rg) && rg < rold[q];
+        if (hmask[q]) rold[q] = rg;
+        taken += hmask[q];
+    }
+    guess_tried += count;
+    guess_taken += taken;
+    if (taken == 0) return hipSuccess;
+    HC(hipMemcpyAsync(mask, hmask, sizeof(int) * count, hipMemcpyHostToDevice, s));
+    return k::copy(tl(n, count, mask), g, u, s);
 }
 
 // ------------------------------------------------------------------- SDC

@@ -77,6 +77,21 @@ _sigs = {
     "pfmg_batch_vcycle_count": ([_vp, C.c_int32, C.POINTER(C.c_int64)], C.c_int32),
     "pfmg_tune_count": ([C.POINTER(C.c_int32)], C.c_int32),
     "pfmg_tune_lookup": ([C.c_char_p, C.c_char_p, C.c_size_t], C.c_int32),
+    "pfmg_nn_param_count": ([C.POINTER(C.c_int64)], C.c_int32),
+    "pfmg_nn_workspace_bytes": ([C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
+    "pfmg_nn_create": ([C.c_int32, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(_vp)], C.c_int32),
+    "pfmg_nn_destroy": ([_vp], C.c_int32),
+    "pfmg_nn_load": ([_vp, _vp, C.c_int64], C.c_int32),
+    "pfmg_nn_save": ([_vp, _vp, C.c_int64], C.c_int32),
+    "pfmg_nn_init": ([_vp, C.c_uint64], C.c_int32),
+    "pfmg_nn_forward": ([_vp, _vp, C.c_int32, _vp], C.c_int32),
+    "pfmg_nn_gradients": ([_vp, _vp, _vp, C.c_int32, _dp, _vp], C.c_int32),
+    "pfmg_nn_train_step": ([_vp, _vp, _vp, C.c_int32, _vp, C.c_int32, C.c_float, _dp], C.c_int32),
+    "pfmg_nn_tensor": ([_vp, C.c_int32, C.c_int32, C.c_int32, _vp], C.c_int32),
+    "pfmg_attach_nn": ([_vp, _vp], C.c_int32),
+    "pfmg_guess_stats": ([_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int32),
+    "pfmg_record": ([_vp, _vp, _vp, _vp, C.c_int32], C.c_int32),
+    "pfmg_record_count": ([_vp, C.POINTER(C.c_int32)], C.c_int32),
 }
 for _name, (_args, _res) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -248,6 +263,86 @@ def pfmg_tune_lookup(key: str) -> str:
     return buf.value.decode()
 
 
+def pfmg_nn_param_count() -> int:
+    c = C.c_int64(0)
+    _check(_lib.pfmg_nn_param_count(C.byref(c)))
+    return c.value
+
+
+def pfmg_nn_workspace_bytes(n: int, batch: int, training: bool) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.pfmg_nn_workspace_bytes(n, batch, int(training), C.byref(out)))
+    return out.value
+
+
+def pfmg_nn_create(n: int, batch: int, training: bool, workspace_ptr: int, nbytes: int, stream_ptr: int | None):
+    h = _vp()
+    _check(_lib.pfmg_nn_create(n, batch, int(training), _vp(workspace_ptr), nbytes, _vp(stream_ptr or 0), C.byref(h)))
+    return h
+
+
+def pfmg_nn_destroy(h) -> None:
+    _check(_lib.pfmg_nn_destroy(h))
+
+
+def pfmg_nn_load(h, params: np.ndarray) -> None:
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_lib.pfmg_nn_load(h, a.ctypes.data, a.size))
+
+
+def pfmg_nn_save(h, count: int) -> np.ndarray:
+    a = np.zeros(count, dtype=np.float32)
+    _check(_lib.pfmg_nn_save(h, a.ctypes.data, count))
+    return a
+
+
+def pfmg_nn_init(h, seed: int) -> None:
+    _check(_lib.pfmg_nn_init(h, seed))
+
+
+def pfmg_nn_forward(h, x_ptr: int, batch: int, y_ptr: int) -> None:
+    _check(_lib.pfmg_nn_forward(h, _vp(x_ptr), batch, _vp(y_ptr)))
+
+
+def pfmg_nn_gradients(h, x_ptr: int, t_ptr: int, batch: int, count: int):
+    loss = C.c_double(0.0)
+    g = np.zeros(count, dtype=np.float32)
+    _check(_lib.pfmg_nn_gradients(h, _vp(x_ptr), _vp(t_ptr), batch, C.byref(loss), g.ctypes.data))
+    return loss.value, g
+
+
+def pfmg_nn_train_step(h, pairs_ptr: int, ah2_ptr: int, n_pairs: int, idx: np.ndarray, lr: float) -> float:
+    i = np.ascontiguousarray(idx, dtype=np.int32)
+    loss = C.c_double(0.0)
+    _check(_lib.pfmg_nn_train_step(h, _vp(pairs_ptr), _vp(ah2_ptr), n_pairs, i.ctypes.data, i.size, lr,
+                                   C.byref(loss)))
+    return loss.value
+
+
+def pfmg_nn_tensor(h, layer: int, which: int, batch: int, dst_ptr: int) -> None:
+    _check(_lib.pfmg_nn_tensor(h, layer, which, batch, _vp(dst_ptr)))
+
+
+def pfmg_attach_nn(ctx_h, nn_h) -> None:
+    _check(_lib.pfmg_attach_nn(ctx_h, nn_h))
+
+
+def pfmg_guess_stats(ctx_h):
+    a, b = C.c_int64(0), C.c_int64(0)
+    _check(_lib.pfmg_guess_stats(ctx_h, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def pfmg_record(ctx_h, pairs_ptr: int, ah2_ptr: int, scratch_ptr: int, capacity: int) -> None:
+    _check(_lib.pfmg_record(ctx_h, _vp(pairs_ptr), _vp(ah2_ptr), _vp(scratch_ptr), capacity))
+
+
+def pfmg_record_count(ctx_h) -> int:
+    c = C.c_int32(0)
+    _check(_lib.pfmg_record_count(ctx_h, C.byref(c)))
+    return c.value
+
+
 # --------------------------------------------------------------- Context
 class Context:
     """A pfmg context on one GPU with a torch-owned workspace and stream."""
@@ -334,6 +429,15 @@ class Context:
     def timing_read(self):
         return pfmg_timing_read(self.h)
 
+    def attach_nn(self, net) -> None:
+        pfmg_attach_nn(self.h, net.h if net is not None else None)
+
+    def guess_stats(self):
+        return pfmg_guess_stats(self.h)
+
+    def record_count(self) -> int:
+        return pfmg_record_count(self.h)
+
 
 class Batch:
     """A batch of independent problems (shared method parameters; own n, nu,
@@ -398,3 +502,83 @@ class Batch:
 
     def vcycle_count(self, level: int = 0) -> int:
         return pfmg_batch_vcycle_count(self.h, level)
+
+
+class Net:
+    """The learned-guess network with a torch-owned workspace and stream."""
+
+    def __init__(self, n: int, batch: int, training: bool, device: str = "cuda", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("pfmg needs a ROCm GPU (gfx950); no device is visible")
+        self.torch = torch
+        self.n, self.batch, self.training = n, batch, training
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nparams = pfmg_nn_param_count()
+        self.nbytes = pfmg_nn_workspace_bytes(n, batch, training)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.ws.data_ptr() + 255) // 256 * 256
+        self.h = pfmg_nn_create(n, batch, training, aligned, self.nbytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            pfmg_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, seed: int = 0):
+        pfmg_nn_init(self.h, seed)
+
+    def load(self, params):
+        pfmg_nn_load(self.h, np.asarray(params, dtype=np.float32).reshape(-1))
+
+    def save(self) -> np.ndarray:
+        return pfmg_nn_save(self.h, self.nparams)
+
+    def forward(self, x):
+        """x: [batch][3][n^3]-shaped array (numpy or tensor) -> y [batch][n^3] (numpy)."""
+        t = self.torch
+        xx = t.as_tensor(np.asarray(x, dtype=np.float32) if isinstance(x, np.ndarray) else x,
+                         dtype=t.float32, device=self.device).contiguous()
+        b = xx.shape[0]
+        y = t.empty((b, self.n ** 3), dtype=t.float32, device=self.device)
+        pfmg_nn_forward(self.h, xx.data_ptr(), b, y.data_ptr())
+        return y.cpu().numpy()
+
+    def gradients(self, x, target):
+        t = self.torch
+        xx = t.as_tensor(np.asarray(x, dtype=np.float32), device=self.device).contiguous()
+        tt = t.as_tensor(np.asarray(target, dtype=np.float32), device=self.device).contiguous()
+        return pfmg_nn_gradients(self.h, xx.data_ptr(), tt.data_ptr(), xx.shape[0], self.nparams)
+
+    def tensor(self, layer: int, which: int, batch: int, channels: int, n: int) -> np.ndarray:
+        out = self.torch.empty((batch, channels, n, n, n), dtype=self.torch.float32, device=self.device)
+        pfmg_nn_tensor(self.h, layer, which, batch, out.data_ptr())
+        return out.cpu().numpy()
+
+    def train_step(self, store, idx, lr: float, n_pairs: int | None = None) -> float:
+        return pfmg_nn_train_step(self.h, store.pairs.data_ptr(), store.ah2.data_ptr(),
+                                  store.capacity if n_pairs is None else n_pairs, idx, lr)
+
+
+class PairStore:
+    """Device storage of recorded training pairs (see pfmg_record)."""
+
+    def __init__(self, n: int, capacity: int, slices: int, device: str = "cuda"):
+        import torch
+
+        self.n, self.capacity = n, capacity
+        self.pairs = torch.zeros((capacity, 3, n ** 3), dtype=torch.bfloat16, device=device)
+        self.ah2 = torch.zeros(capacity, dtype=torch.float32, device=device)
+        self.scratch = torch.zeros((slices, n ** 3), dtype=torch.float64, device=device)
+
+    def attach(self, ctx: "Context", offset: int = 0):
+        pfmg_record(ctx.h, self.pairs[offset:].data_ptr(), self.ah2[offset:].data_ptr(), self.scratch.data_ptr(),
+                    self.capacity - offset)

@@ -96,3 +96,20 @@ def test_batch_workspace_and_validation_on_the_host(pf):
             pf.pfmg_batch_workspace_bytes([pf.pfmg_default_params(**kw)])
     assert pf.pfmg_tune_count() >= 0
     assert pf.pfmg_tune_lookup("gfx950/rbgs/f64/0x0") == ""
+
+
+def test_network_sizes_on_the_host(pf):
+    from oracle import unet as U
+
+    want = sum(w.size + b.size for w, b in U.init_params(0))
+    assert pf.pfmg_nn_param_count() == want
+    assert pf.pfmg_nn_workspace_bytes(63, 4, True) > pf.pfmg_nn_workspace_bytes(63, 4, False) > 0
+    for n in (62, 29, 7, 0):     # even, odd with an even level, too few levels
+        with pytest.raises(pf.PfmgError):
+            pf.pfmg_nn_workspace_bytes(n, 1, False)
+    with pytest.raises(pf.PfmgError) as ei:
+        pf.pfmg_nn_create(63, 4, False, 0, 0, None)
+    assert ei.value.status == pf.ERR_WORKSPACE
+    with pytest.raises(pf.PfmgError):   # learned guess needs full solves
+        pf.pfmg_workspace_bytes(pf.pfmg_default_params(n=63, guess=pf.GUESS_LEARNED))
+    assert pf.pfmg_workspace_bytes(pf.pfmg_default_params(n=63, guess=pf.GUESS_LEARNED, vcycles_per_solve=0)) > 0

@@ -302,8 +302,9 @@ pfmg_status pfmg_vcycle_count(pfmg_ctx *ctx, int32_t level, int64_t *count_out)
 pfmg_status pfmg_timing_enable(pfmg_ctx *ctx, const char *kernel, int32_t enable)
 {
     if (!ctx) return fail(PFMG_ERR_ARG, "null context");
-    pfmg::Timer &t = ctx->sv.timer;
-    HIPCALL(hipStreamSynchronize(ctx->sv.s), "timing");
+    pfmg::Solver &sv = ctx->sv;
+    pfmg::Timer &t = sv.timer;
+    HIPCALL(hipStreamSynchronize(sv.s), "timing");
     t.on = enable != 0;
     t.used = 0;
     t.depth = 0;

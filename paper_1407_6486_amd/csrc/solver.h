@@ -112,6 +112,13 @@ struct Solver {
     hipError_t spread_body();
     hipError_t iterate_body();
     hipError_t residual_enqueue();
+    hipError_t chain_step(int q);
+    hipError_t iterate_pipelined();
+    static constexpr int MAXGROUPS = 16;
+    int groups = 1;                   // slice groups of the pipelined iteration
+    std::vector<int> gbound;          // group g holds slices gbound[g] .. gbound[g+1]-1
+    hipStream_t s2 = nullptr;         // coarse-chain stream of the pipelined iteration
+    hipEvent_t ev[MAXGROUPS + 1] = {};
     hipError_t residual_read(double *per_slice, double *block);
     Tiling tl(int n, int count, const int *m = nullptr) const { return Tiling{n, dim, count, m, noremap}; }
     void tstart(const char *fam, int n, double bytes_per_point, long points);

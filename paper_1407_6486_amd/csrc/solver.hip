@@ -183,6 +183,32 @@ bool Solver::init_host(std::string &why)
     fused_min_points = e ? atol(e) : 2000000;
     dim = p.dim;
     P = p.n_slices;
+    // slice groups of the pipelined iteration: halving sizes (P/2, P/4, ...,
+    // at least 2 slices), so that the first fine sweeps are large launches
+    // and the coarse chain left after the last one is short.  PFMG_GROUPS:
+    // a count of equal groups, or a comma-separated list of group sizes.
+    gbound.assign(1, 0);
+    e = getenv("PFMG_GROUPS");
+    if (e && strchr(e, ',')) {
+        for (const char *c = e; *c;) {
+            const int sz = atoi(c);
+            if (sz > 0 && gbound.back() < P) gbound.push_back(std::min(P, gbound.back() + sz));
+            c = strchr(c, ',');
+            if (!c) break;
+            ++c;
+        }
+        if (gbound.back() < P) gbound.push_back(P);
+    } else if (e) {
+        const int g = std::max(1, std::min(atoi(e), P));
+        for (int q = 1; q <= g; ++q) gbound.push_back((int)((long)P * q / g));
+    } else if (P >= 8) {
+        for (int sz = P / 2; gbound.back() < P; sz = std::max(2, sz / 2))
+            gbound.push_back(std::min(P, gbound.back() + sz));
+    } else {
+        gbound.push_back(P);
+    }
+    if ((int)gbound.size() - 1 > MAXGROUPS) gbound = {0, P};
+    groups = (int)gbound.size() - 1;
     nl = p.nodes_coarse > 0 ? 2 : 1;
     for (int lev = 0; lev < nl; ++lev) {
         PLevel &Lv = L[lev];
@@ -646,26 +672,70 @@ hipError_t Solver::iterate_body()
     PLevel &Fn = L[0];
     const int M = Fn.nn - 1;
     const long fst = (long)Fn.nn * Fn.fs;
+    // new fine initial values from the previous iteration's end values, all
+    // slices at once, before any sweep changes them
     if (P > 1) {
         HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.U, 0, M), fst}, View<double>{Fn.slot(Fn.U, 1, 0), fst}, s));
         HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.F, 0, M), fst}, View<double>{Fn.slot(Fn.F, 1, 0), fst}, s));
     }
+    if (nl > 1 && groups > 1 && p.vcycles_per_solve > 0) return iterate_pipelined();
     HC(sweep(0, 0, P));
     if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
     if (nl > 1) {
-        PLevel &Cs = L[1];
-        const int Mc = Cs.nn - 1;
         HC(fas_restrict(0, P));
         for (int q = 0; q < P; ++q) {
-            const double *us = q == 0 ? ublock_c : Cs.slot(Cs.U, q - 1, Mc);
-            const double *fsrc = q == 0 ? fublock_c : Cs.slot(Cs.F, q - 1, Mc);
-            HC(k::copy(tl(Cs.n, 1), View<double>{const_cast<double *>(us), 0}, View<double>{Cs.slot(Cs.U, q, 0), 0}, s));
-            HC(k::copy(tl(Cs.n, 1), View<double>{const_cast<double *>(fsrc), 0}, View<double>{Cs.slot(Cs.F, q, 0), 0}, s));
-            HC(sweep(1, q, q + 1));
+            HC(chain_step(q));
             if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
         }
         HC(interpolate(0, P));
     }
+    return residual_enqueue();
+}
+
+// Coarse sweep of slice q with its new initial value: the block's injected
+// initial value for q = 0, else slice q-1's end value of this iteration.
+hipError_t Solver::chain_step(int q)
+{
+    PLevel &Cs = L[1];
+    const int Mc = Cs.nn - 1;
+    const double *us = q == 0 ? ublock_c : Cs.slot(Cs.U, q - 1, Mc);
+    const double *fsrc = q == 0 ? fublock_c : Cs.slot(Cs.F, q - 1, Mc);
+    HC(k::copy(tl(Cs.n, 1), View<double>{const_cast<double *>(us), 0}, View<double>{Cs.slot(Cs.U, q, 0), 0}, s));
+    HC(k::copy(tl(Cs.n, 1), View<double>{const_cast<double *>(fsrc), 0}, View<double>{Cs.slot(Cs.F, q, 0), 0}, s));
+    return sweep(1, q, q + 1);
+}
+
+// The same iteration with the slices in groups: the fine sweep and FAS
+// restriction of group g run on the main stream while the coarse chain and
+// interpolation of the earlier groups run on a second stream (chain step q
+// needs only slice q's restriction and slice q-1's coarse end value, and
+// interpolation of a group only its own coarse sweeps).  Every slice sees
+// the same operations in the same order as in the sequential schedule.
+// Fixed V-cycle counts only (full solves read norms back on the host).
+hipError_t Solver::iterate_pipelined()
+{
+    if (!s2) HC(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    for (int g = 0; g <= groups; ++g)
+        if (!ev[g]) HC(hipEventCreateWithFlags(&ev[g], hipEventDisableTiming));
+    const int G = groups;
+    auto first = [&](int g) { return gbound[g]; };
+    for (int g = 0; g < G; ++g) {
+        HC(sweep(0, first(g), first(g + 1)));
+        HC(fas_restrict(first(g), first(g + 1)));
+        HC(hipEventRecord(ev[g], s));
+    }
+    hipStream_t main = s;
+    s = s2;
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < G && e == hipSuccess; ++g) {
+        e = hipStreamWaitEvent(s2, ev[g], 0);
+        for (int q = first(g); q < first(g + 1) && e == hipSuccess; ++q) e = chain_step(q);
+        if (e == hipSuccess) e = interpolate(first(g), first(g + 1));
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[G], s2);
+    s = main;
+    HC(e);
+    HC(hipStreamWaitEvent(s, ev[G], 0));
     return residual_enqueue();
 }
 
@@ -718,8 +788,14 @@ void Solver::release_graphs()
     if (g_iter) (void)hipGraphExecDestroy(g_iter);
     if (g_start) (void)hipGraphExecDestroy(g_start);
     if (cap) (void)hipStreamDestroy(cap);
+    if (s2) (void)hipStreamDestroy(s2);
+    for (hipEvent_t &e : ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
     g_iter = g_start = nullptr;
-    cap = nullptr;
+    cap = s2 = nullptr;
 }
 
 template hipError_t Solver::smooth<double>(int, int, const int *, double, View<double>, View<double>, View<double>, int, bool);

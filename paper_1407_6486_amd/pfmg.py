@@ -13,6 +13,9 @@ import ctypes as C
 import os
 
 import numpy as np
+# PyTorch first: it brings its own HIP runtime, and the library must bind to
+# that same runtime (a second copy loaded before it sees no device).
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpfmg.so")

@@ -271,3 +271,29 @@ def test_nan_input_reports_err_nan(pf):
         c.set_initial(u0)
         c.pfasst_iter()
     assert ei.value.status == pf.ERR_NAN
+
+
+@pytest.mark.parametrize("groups", [2, 4, 5])
+def test_pipelined_iteration_matches_sequential(pf, groups):
+    """Slice groups whose fine sweeps overlap the coarse chain of earlier
+    groups (second stream) give the sequential schedule's results."""
+    import os
+
+    n, P = 31, 8
+    say(f"pipelined iteration, {groups} groups, n={n}, P={P}")
+    u0, _ = inputs.random_fourier(n, 4242)
+    states = {}
+    for g in (1, groups):
+        os.environ["PFMG_GROUPS"] = str(g)
+        try:
+            c = make(pf, n=n, n_slices=P)
+        finally:
+            del os.environ["PFMG_GROUPS"]
+        c.set_initial(u0)
+        res = [c.pfasst_iter() for _ in range(4)]
+        states[g] = (res, [c.get(O.UF, p, 4) for p in range(P)], [c.get(O.UC, p, 2) for p in range(P)])
+        c.close()
+    (r1, f1, c1), (rg, fg, cg) = states[1], states[groups]
+    assert all(abs(a - b) <= 1e-12 * a for a, b in zip(r1, rg)), (r1, rg)
+    for p in range(P):
+        assert pins.rel_err(fg[p], f1[p]) <= 1e-13 and pins.rel_err(cg[p], c1[p]) <= 1e-13, p

@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--max-iter", type=int, default=400,
                     help="iteration cap per block (profiling runs cap it to keep traces small)")
+    ap.add_argument("--form", choices=["mixed", "batched", "learned"], default=None,
+                    help="measure one of the method's forms against the plain FP64 path instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain copy of known size three times (reference for HBM counters)")
     return ap.parse_args()
@@ -110,6 +112,109 @@ def cpu_baseline(n, P, iters_gpu, cpu_iters, u0):
                       f"same block on the host, extrapolated to the {iters_gpu} iterations the block needs"}
 
 
+def _time_blocks(run, steps):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [run() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def form_mixed(pfmg, a):
+    """255^3, 16 slices (seed 1408): FP32 multigrid inside FP64 refinement
+    against the FP64 path, both to a block residual of 1e-10."""
+    import torch
+
+    import inputs
+
+    n, P = 255, 16
+    u0 = torch.from_numpy(inputs.random_fourier(n, 1408)[0]).to("cuda")
+    res = {}
+    for prec in ("fp64", "mixed"):
+        c = pfmg.Context(pfmg.pfmg_default_params(n=n, n_slices=P, pfasst_tol=1e-10, pfasst_max_iter=a.max_iter,
+                                                   precision=pfmg.MIXED if prec == "mixed" else pfmg.FP64))
+        for _ in range(a.warmup):
+            c.run_block(u0)
+        t, outs = _time_blocks(lambda: c.run_block(u0), a.steps)
+        res[prec] = (t, outs[-1][1], outs[-1][2])
+        c.close()
+        del c
+        torch.cuda.empty_cache()
+    return {"metric": "s to 1e-10 residual per PFASST block", "value": round(res["mixed"][0], 4), "unit": "s",
+            "form": "mixed precision (FP32 multigrid in FP64 refinement)", "plain_value": round(res["fp64"][0], 4),
+            "speedup_vs_plain": round(res["fp64"][0] / res["mixed"][0], 3),
+            "iterations": {"mixed": res["mixed"][1], "fp64": res["fp64"][1]},
+            "final_residual": {"mixed": res["mixed"][2], "fp64": res["fp64"][2]},
+            "higher_is_better": False, "dtype": "f64+f32", "data": "synthetic", "n_gpus": 1, "steps": a.steps,
+            "config": {"workload": "3D heat, 255^3, 16 slices, dt=1e-3, Lobatto 5/3, rbgs V(2,2), 1 V-cycle/solve, "
+                                   "seed 1408"}}
+
+
+def form_batched(pfmg, a):
+    """64 uneven problems (n in {31, 63, 95, 127}, nu and dt log-uniform,
+    P = 4): one batch against a loop over 64 single contexts."""
+    import torch
+
+    import inputs
+
+    probs = [inputs.batch_problem(q) for q in range(64)]
+    ps = [pfmg.pfmg_default_params(n=bp.n, nu=bp.nu, dt=bp.dt, n_slices=4, pfasst_tol=1e-10, pfasst_max_iter=1000)
+          for bp in probs]
+    u0s = [torch.from_numpy(bp.u0).to("cuda") for bp in probs]
+    b = pfmg.Batch(ps)
+    for _ in range(a.warmup):
+        b.run(u0s)
+    tb, outs = _time_blocks(lambda: b.run(u0s), a.steps)
+    its = outs[-1][1]
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    ctxs = [pfmg.Context(p) for p in ps]
+    for c, u in zip(ctxs, u0s):
+        c.run_block(u)
+    tl, _ = _time_blocks(lambda: [c.run_block(u) for c, u in zip(ctxs, u0s)], 1)
+    for c in ctxs:
+        c.close()
+    dof = sum(bp.n ** 3 for bp in probs)
+    return {"metric": "s to 1e-10 residual per PFASST block", "value": round(tb, 4), "unit": "s",
+            "form": "batched (64 uneven problems, shared multi-segment launches, graphs)",
+            "plain_value": round(tl, 4), "plain": "loop over 64 single contexts",
+            "speedup_vs_plain": round(tl / tb, 3), "iterations_min_max": [int(its.min()), int(its.max())],
+            "higher_is_better": False, "dtype": "f64", "data": "synthetic", "n_gpus": 1, "steps": a.steps,
+            "config": {"workload": f"64 problems, n in {{31,63,95,127}}, {dof / 1e6:.1f} M DOF per slice, P=4, "
+                                   "nu 10^U(-1,1), dt 10^U(-4,-2), seeds [6486, q]"}}
+
+
+def form_learned(pfmg, a):
+    """Learned initial guess: record 20k pairs at 63^3, train, evaluate at
+    127^3 with 16 slices and full node solves against the plain guess."""
+    import numpy as np
+
+    from paper_1407_6486_amd import learned as L
+
+    quiet = lambda m: None
+    store, count = L.record(pfmg, 63, 20000, log=quiet)
+    net, losses, t_train = L.train(pfmg, store, count, 2000, 8, 2e-3, log=quiet)
+    params = net.save()
+    net.close()
+    del store
+    t_inf = L.inference_time(pfmg, params, 127, 16)
+    ev = L.evaluate(pfmg, params, 127, 16, (0.0, 1e-4), log=quiet)
+    best = min((k for k in ev if k != "plain"), key=lambda k: ev[k]["s_per_block"])
+    return {"metric": "s to 1e-10 residual per PFASST block", "value": round(ev[best]["s_per_block"], 4),
+            "unit": "s", "form": f"learned initial guess ({best})", "plain_value": round(ev["plain"]["s_per_block"], 4),
+            "speedup_vs_plain": round(ev["plain"]["s_per_block"] / ev[best]["s_per_block"], 3),
+            "eval": ev, "train_pairs": count, "train_steps": 2000, "train_s": round(t_train, 1),
+            "loss_first_last": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
+            "inference_ms_16x127": round(t_inf * 1e3, 2),
+            "inference_tflops": round(L.flops_per_voxel() * 127 ** 3 * 16 / t_inf / 1e12, 1),
+            "higher_is_better": False, "dtype": "f64 solver, bf16 network", "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": "train 63^3 (seeds [20000, r], dt 10^U(-3,-2), P=4); evaluate 127^3, 16 slices, "
+                                   "dt=1e-3, seed 1407, full solves to 1e-12"}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -123,6 +228,10 @@ def main():
     from paper_1407_6486_amd import pfmg
 
     assert torch.cuda.is_available(), "no GPU visible"
+    if a.form:
+        fn = {"mixed": form_mixed, "batched": form_batched, "learned": form_learned}[a.form]
+        print(json.dumps(fn(pfmg, a), default=float), flush=True)
+        return
     if a.calibrate_copy:
         copy_calibration(pfmg)
     n, P = a.n, a.slices
@@ -140,7 +249,8 @@ def main():
         ctx.run_block(u0)
     torch.cuda.synchronize()
 
-    # timed region: whole blocks as the library runs them (graph replays)
+    # timed region: whole blocks as the library runs them (graph replays);
+    # --steps 0 skips it (profiling runs of the event-timed blocks alone)
     v0 = ctx.vcycle_count(0)
     iters = []
     torch.cuda.synchronize()
@@ -150,8 +260,8 @@ def main():
         iters.append(it)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    fine_vcycles = (ctx.vcycle_count(0) - v0) / a.steps
-    s_per_block = (t1 - t0) / a.steps
+    fine_vcycles = (ctx.vcycle_count(0) - v0) / max(a.steps, 1)
+    s_per_block = (t1 - t0) / a.steps if a.steps > 0 else None
 
     # dominant kernel: one more block with HIP events around each of its
     # launches on the stream it runs on (event brackets run the block from
@@ -174,7 +284,7 @@ def main():
     per_launch = nbytes / max(launches, 1)
     traffic = None
     if tr and abs(tr["algorithmic_bytes_per_launch"] - per_launch) <= 1e-6 * per_launch:
-        traffic = tr["hbm_bytes_per_launch"]
+        traffic = round(tr["hbm_bytes_per_launch"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic, "kernel": dominant, "launches": launches,
@@ -182,12 +292,12 @@ def main():
 
     out = {
         "metric": "s to 1e-10 residual per PFASST block",
-        "value": round(s_per_block, 5),
+        "value": round(s_per_block, 5) if s_per_block else None,
         "unit": "s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(s_per_block * 1e3, 3),
+        "ms_per_step": round(s_per_block * 1e3, 3) if s_per_block else None,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -198,12 +308,12 @@ def main():
                    "n": n, "slices": P, "vcycles_per_solve": a.vcycles, "smoother": a.smoother,
                    "precision": a.precision, "parallelism": "single GPU, slices batched"},
         "iterations_per_block": iters,
-        "final_residual": res,
+        "final_residual": res if iters else None,
         "fine_vcycles_per_block": fine_vcycles,
         "vcycle_gdofs": round(vcycle_gdofs, 2) if vcycle_gdofs else None,
         "roofline": roofline,
     }
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and iters:
         out["cpu_baseline"] = cpu_baseline(n, P, iters[-1], a.cpu_iters, u0_host)
     print(json.dumps(out), flush=True)
 

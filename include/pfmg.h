@@ -94,6 +94,9 @@ enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
  *                    value after p-1's previous iteration.
  *   pfasst_tol       block relative residual tolerance for pfmg_run_block.
  *   pfasst_max_iter  iteration cap for pfmg_run_block.
+ *   guess_min_relres with PFMG_GUESS_LEARNED: a node solve is offered the
+ *                    network's guess only while its plain guess has
+ *                    |b - H U|_inf > guess_min_relres |b|_inf (0: always).
  */
 typedef struct pfmg_params {
     int32_t dim;
@@ -117,6 +120,7 @@ typedef struct pfmg_params {
     int32_t fine_send;
     double pfasst_tol;
     int32_t pfasst_max_iter;
+    double guess_min_relres;
 } pfmg_params;
 
 /* Fills *p with the defaults: 3D, n = 127, nu = 1, dt = 1e-3, 16 slices,

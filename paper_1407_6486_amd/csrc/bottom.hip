@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "../../include/pfmg.h"
 #include "kernels.h"
@@ -29,11 +30,11 @@ template <int DIM, class F>
 __device__ inline void for_points(int n, F f)
 {
     if (DIM == 3) {
-        for (int k = threadIdx.z; k < n; k += 4)
-            for (int j = threadIdx.y; j < n; j += 16)
-                for (int i = threadIdx.x; i < n; i += 16) f(i + n * (j + n * k), i, j, k);
+        for (int k = threadIdx.z; k < n; k += blockDim.z)
+            for (int j = threadIdx.y; j < n; j += blockDim.y)
+                for (int i = threadIdx.x; i < n; i += blockDim.x) f(i + n * (j + n * k), i, j, k);
     } else {
-        for (int i = threadIdx.x; i < n; i += BT) f(i, i, 0, 0);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) f(i, i, 0, 0);
     }
 }
 
@@ -304,8 +305,15 @@ hipError_t vcycle_bottom(const Tiling &t, double alpha, int smoother, double ome
     }
     if (items == 0) return hipSuccess;
     if (lds > BOTTOM_LDS_MAX) return hipErrorInvalidValue;
+    // workgroup shape (x, y, z threads; x fastest) for the largest grid of
+    // the launch: every thread owns a few points of each pass
+    static const int shape = [] {
+        const char *e = getenv("PFMG_BOTTOM_THREADS");
+        return e ? atoi(e) : 1024;
+    }();
+    const dim3 blk = shape == 256 ? dim3(8, 8, 4) : shape == 512 ? dim3(16, 8, 4) : dim3(16, 16, 4);
     if (t.dim == 3)
-        vcycle_bottom_kernel<3, T><<<(unsigned)items, dim3(16, 16, 4), lds, s>>>(t, alpha, smoother, omega, nu1, nu2,
+        vcycle_bottom_kernel<3, T><<<(unsigned)items, blk, lds, s>>>(t, alpha, smoother, omega, nu1, nu2,
                                                                                  zero_init ? 1 : 0, b, u);
     else
         vcycle_bottom_kernel<1, T><<<(unsigned)items, dim3(BT, 1, 1), lds, s>>>(t, alpha, smoother, omega, nu1, nu2,

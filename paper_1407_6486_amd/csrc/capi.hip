@@ -86,6 +86,7 @@ pfmg_status pfmg_default_params(pfmg_params *p)
     p->fine_send = PFMG_SEND_AFTER_ITER;
     p->pfasst_tol = 1e-10;
     p->pfasst_max_iter = 200;
+    p->guess_min_relres = 0.0;
     return PFMG_OK;
 }
 

@@ -105,8 +105,8 @@ struct Solver {
     double *rec_scratch = nullptr;
     int rec_cap = 0, rec_count = 0;
     long long guess_tried = 0, guess_taken = 0;
-    hipError_t learned_guess(View<double> u, View<double> b, int count, double alpha, std::vector<double> &rold,
-                             bool rec);
+    hipError_t learned_guess(View<double> u, View<double> b, int count, double alpha, const std::vector<double> &nb,
+                             std::vector<double> &rold, bool rec);
     hipError_t capture(const std::function<hipError_t()> &fn, hipGraphExec_t *out, long long *vc);
     void release_graphs();
     hipError_t spread_body();

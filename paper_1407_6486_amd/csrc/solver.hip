@@ -78,6 +78,7 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
     }
     if (p.fine_send != PFMG_SEND_AFTER_ITER) { why = "fine_send must be PFMG_SEND_AFTER_ITER"; return false; }
     if (p.pfasst_max_iter < 1) { why = "pfasst_max_iter must be >= 1"; return false; }
+    if (!(p.guess_min_relres >= 0)) { why = "guess_min_relres must be >= 0"; return false; }
     return true;
 }
 
@@ -410,7 +411,7 @@ hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, dou
     // fine-level node solves: record the training pair, try the learned guess
     const bool rec = lev == 0 && rec_pairs && rec_count + count <= rec_cap && dim == 3;
     const bool learned = lev == 0 && unet && p.guess == PFMG_GUESS_LEARNED;
-    if (rec || learned) HC(learned_guess(u, b, count, alpha, rold, rec));
+    if (rec || learned) HC(learned_guess(u, b, count, alpha, nb, rold, rec));
     int active = 0;
     for (int q = 0; q < count; ++q) {
         hmask[q] = rold[q] > p.mg_tol * nb[q];
@@ -457,8 +458,8 @@ hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, dou
 // with an attached network, its guess g = u + sr y replaces u in every field
 // where |b - H g|_inf < |b - H u|_inf (the FP64 residual judges).  rold is
 // updated for the fields that take the guess.
-hipError_t Solver::learned_guess(View<double> u, View<double> b, int count, double alpha, std::vector<double> &rold,
-                                 bool rec)
+hipError_t Solver::learned_guess(View<double> u, View<double> b, int count, double alpha,
+                                 const std::vector<double> &nb, std::vector<double> &rold, bool rec)
 {
     const int n = L[0].n;
     const Tiling t = tl(n, count);
@@ -474,6 +475,14 @@ hipError_t Solver::learned_guess(View<double> u, View<double> b, int count, doub
     HC(hipMemcpyAsync(nnsc, hnnsc, sizeof(double) * 2 * count, hipMemcpyHostToDevice, s));
     if (rec) HC(nn::record_inputs(t, alpha, b, u, nnsc, nnsc + count, rec_pairs, rec_ah2, rec_count, rec_scratch, s));
     if (!(unet && p.guess == PFMG_GUESS_LEARNED)) return hipSuccess;
+    // offer the guess only to fields whose plain guess is still far off
+    std::vector<char> offer(count);
+    int offered = 0;
+    for (int q = 0; q < count; ++q) {
+        offer[q] = rold[q] > p.guess_min_relres * nb[q];
+        offered += offer[q];
+    }
+    if (offered == 0) return hipSuccess;
     View<double> g = L[0].mg[0].t;
     hipStream_t ns = unet->s;
     unet->s = s;
@@ -489,11 +498,11 @@ hipError_t Solver::learned_guess(View<double> u, View<double> b, int count, doub
     int taken = 0;
     for (int q = 0; q < count; ++q) {
         const double rg = bits_to_double(hbits[count + q]);
-        hmask[q] = std::isfinite(rg) && rg < rold[q];
+        hmask[q] = offer[q] && std::isfinite(rg) && rg < rold[q];
         if (hmask[q]) rold[q] = rg;
         taken += hmask[q];
     }
-    guess_tried += count;
+    guess_tried += offered;
     guess_taken += taken;
     if (taken == 0) return hipSuccess;
     HC(hipMemcpyAsync(mask, hmask, sizeof(int) * count, hipMemcpyHostToDevice, s));

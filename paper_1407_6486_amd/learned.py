@@ -61,22 +61,27 @@ def train(pf, store, count: int, steps: int, batch: int = 8, lr: float = 2e-3, s
     return net, losses, time.perf_counter() - t0
 
 
-def evaluate(pf, params, n: int, slices: int, seed: int = 1407, log=print):
-    """One block of the C2-type problem with full solves, plain vs learned."""
+def evaluate(pf, params, n: int, slices: int, thresholds=(0.0,), seed: int = 1407, mg_tol: float = 1e-12,
+             log=print):
+    """One block of the C2-type problem with full node solves (to mg_tol),
+    plain guess against the learned guess offered to solves whose plain
+    guess has relative residual above each threshold."""
     import torch
 
     import inputs
 
     u0, _ = inputs.random_fourier(n, seed)
-    kw = dict(n=n, n_slices=slices, nu=1.0, dt=1e-3, vcycles_per_solve=0, mg_tol=1e-10, pfasst_tol=1e-10,
+    kw = dict(n=n, n_slices=slices, nu=1.0, dt=1e-3, vcycles_per_solve=0, mg_tol=mg_tol, pfasst_tol=1e-10,
               pfasst_max_iter=400)
     out = {}
-    for mode in ("plain", "learned"):
-        c = pf.Context(pf.pfmg_default_params(guess=pf.GUESS_LEARNED if mode == "learned" else pf.GUESS_PREV, **kw))
-        net = None
-        if mode == "learned":
-            net = pf.Net(n, slices, training=False)
-            net.load(params)
+    net = pf.Net(n, slices, training=False)
+    net.load(params)
+    ref = None
+    for mode in ["plain"] + [f"learned@{t:g}" for t in thresholds]:
+        learned = mode != "plain"
+        extra = dict(guess=pf.GUESS_LEARNED, guess_min_relres=float(mode.split("@")[1])) if learned else {}
+        c = pf.Context(pf.pfmg_default_params(**kw, **extra))
+        if learned:
             c.attach_nn(net)
         c.run_block(u0)                       # warm-up (tuning, first-touch)
         v0 = c.vcycle_count(0), c.vcycle_count(1)
@@ -87,20 +92,18 @@ def evaluate(pf, params, n: int, slices: int, seed: int = 1407, log=print):
         torch.cuda.synchronize()
         dt_block = time.perf_counter() - t0
         g1 = c.guess_stats()
-        out[mode] = {"s_per_block": dt_block, "iterations": it, "residual": res,
+        end = [c.get(0, p, 4) for p in (0, slices - 1)]
+        if ref is None:
+            ref = end
+        diff = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(end, ref))
+        out[mode] = {"s_per_block": dt_block, "iterations": it, "residual": res, "status": st,
                      "fine_vcycles": c.vcycle_count(0) - v0[0], "coarse_vcycles": c.vcycle_count(1) - v0[1],
-                     "guesses_offered": g1[0] - g0[0], "guesses_taken": g1[1] - g0[1],
-                     "end_state": [c.get(0, p, 4) for p in (0, slices - 1)]}
-        log(f"  {mode}: {dt_block:.3f} s, {it} iterations, fine V-cycles {out[mode]['fine_vcycles']}, "
-            f"guess taken {out[mode]['guesses_taken']} of {out[mode]['guesses_offered']}")
+                     "guesses_offered": g1[0] - g0[0], "guesses_taken": g1[1] - g0[1], "end_state_rel_diff": diff}
+        log(f"  {mode}: {dt_block:.3f} s, {it} iterations, residual {res:.2e}, fine V-cycles "
+            f"{out[mode]['fine_vcycles']}, guess taken {out[mode]['guesses_taken']} of "
+            f"{out[mode]['guesses_offered']}, end state vs plain {diff:.1e}")
         c.close()
-        if net is not None:
-            net.close()
-    diff = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
-               for a, b in zip(out["learned"]["end_state"], out["plain"]["end_state"]))
-    for m in out.values():
-        del m["end_state"]
-    out["end_state_rel_diff"] = diff
+    net.close()
     return out
 
 
@@ -142,6 +145,9 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval-n", type=int, default=127)
     ap.add_argument("--eval-slices", type=int, default=16)
+    ap.add_argument("--thresholds", default="0,1e-6,1e-4",
+                    help="guess_min_relres values to evaluate (comma-separated)")
+    ap.add_argument("--mg-tol", type=float, default=1e-12, help="per-solve relative tolerance")
     ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
     a = ap.parse_args()
     from paper_1407_6486_amd import pfmg as pf
@@ -161,7 +167,8 @@ def main():
     fl = flops_per_voxel() * a.eval_n ** 3 * a.eval_slices
     log(f"inference {a.eval_slices} x {a.eval_n}^3: {t_inf * 1e3:.2f} ms, {fl / t_inf / 1e12:.1f} TFLOP/s")
     log(f"evaluating at {a.eval_n}^3, {a.eval_slices} slices")
-    ev = evaluate(pf, params, a.eval_n, a.eval_slices, log=log)
+    ev = evaluate(pf, params, a.eval_n, a.eval_slices, [float(t) for t in a.thresholds.split(",")],
+                  mg_tol=a.mg_tol, log=log)
     print(json.dumps({"pairs": count, "record_s": round(t_rec, 1), "train_steps": a.steps, "train_s": round(t_train, 1),
                       "loss_first": float(np.mean(losses[:50])), "loss_last": float(np.mean(losses[-50:])),
                       "inference_ms": round(t_inf * 1e3, 3), "inference_tflops": round(fl / t_inf / 1e12, 2),

@@ -417,7 +417,7 @@ hipError_t BatchSolver::vcycle(std::vector<Leg<T>> legs, bool zero_top)
         std::vector<Leg<T>> go, next;
         for (const Leg<T> &x : legs) {
             const bool zero = dd > 0 || zero_top;
-            if (use_bottom && k::vcycle_bottom_lds(x.n, dim, p.smoother, sizeof(T)) <= k::BOTTOM_LDS_MAX) {
+            if (use_bottom && k::vcycle_bottom_lds(x.n, dim, p.smoother, sizeof(T)) <= k::bottom_lds_max()) {
                 bottom[zero ? 1 : 0].push_back(x);
             } else if (x.n <= 2) {
                 exact.push_back(x);

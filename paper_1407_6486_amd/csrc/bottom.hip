@@ -9,11 +9,16 @@
 // with full-weighting restriction, recursive correction from zero,
 // d-linear prolongation, smoothing; exact solve on n in {1, 2}.  Grids are
 // stored densely in LDS (no halo); neighbours outside the grid are the zero
-// Dirichlet data.
+// Dirichlet data.  Each level holds u, b and a third array t (Jacobi's
+// target, and the residual before restriction), so that every residual is
+// computed once rather than once per coarse neighbour.
+//
+// The kernel is latency-bound (a single-field coarse solve sits on the
+// serial coarse chain of PFASST), so passes spread their points evenly over
+// all threads: a red-black colour pass visits only its own colour.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdlib>
 
 #include "../../include/pfmg.h"
 #include "kernels.h"
@@ -25,16 +30,62 @@ constexpr int MAXL = 16;
 constexpr int BT = 1024;          // 3D: 16 x 16 x 4 threads; 1D: 1024 x 1 x 1
 
 // Visit every point of an n^DIM grid: coordinates come from the thread
-// index (no integer division), p is the dense index.
+// index (no integer division), p is the dense index.  Rows of 16 threads:
+// the global loads and stores of the top grid.
 template <int DIM, class F>
 __device__ inline void for_points(int n, F f)
 {
     if (DIM == 3) {
-        for (int k = threadIdx.z; k < n; k += blockDim.z)
-            for (int j = threadIdx.y; j < n; j += blockDim.y)
-                for (int i = threadIdx.x; i < n; i += blockDim.x) f(i + n * (j + n * k), i, j, k);
+        for (int k = threadIdx.z; k < n; k += 4)
+            for (int j = threadIdx.y; j < n; j += 16)
+                for (int i = threadIdx.x; i < n; i += 16) f(i + n * (j + n * k), i, j, k);
     } else {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) f(i, i, 0, 0);
+        for (int i = threadIdx.x; i < n; i += BT) f(i, i, 0, 0);
+    }
+}
+
+template <int DIM>
+__device__ inline int flat_tid()
+{
+    return DIM == 3 ? (int)(threadIdx.x + 16 * (threadIdx.y + 16 * threadIdx.z)) : (int)threadIdx.x;
+}
+
+// Every point of an n^DIM grid, dense index order, BT points per round.
+template <int DIM, class F>
+__device__ inline void for_flat(int n, F f)
+{
+    if (DIM == 3) {
+        const int nn = n * n;
+        for (int p = flat_tid<DIM>(); p < nn * n; p += BT) {
+            const int k = p / nn, r = p - k * nn;
+            const int j = r / n, i = r - j * n;
+            f(p, i, j, k);
+        }
+    } else {
+        for (int i = flat_tid<DIM>(); i < n; i += BT) f(i, i, 0, 0);
+    }
+}
+
+// The points of one colour: 1-based parity (i + j + k + 3) & 1 == colour,
+// i.e. i runs over every other point of its row, starting where the row's
+// parity puts the colour.
+template <int DIM, class F>
+__device__ inline void for_colour(int n, int colour, F f)
+{
+    const int h = (n + 1) / 2;
+    if (DIM == 3) {
+        const int hn = h * n;
+        for (int q = flat_tid<DIM>(); q < hn * n; q += BT) {
+            const int k = q / hn, r = q - k * hn;
+            const int j = r / h, i2 = r - j * h;
+            const int i = 2 * i2 + ((colour + j + k + 1) & 1);
+            if (i < n) f(i + n * (j + n * k), i, j, k);
+        }
+    } else {
+        for (int i2 = flat_tid<DIM>(); i2 < h; i2 += BT) {
+            const int i = 2 * i2 + ((colour + 1) & 1);
+            if (i < n) f(i, i, 0, 0);
+        }
     }
 }
 
@@ -44,22 +95,34 @@ template <int DIM, typename T>
 struct Grid {
     T *u, *b, *t;
     int n;
+    // Value at (i, j, k), zero outside the grid.  The read is unconditional
+    // (from point 0 when outside) and the zero is a select: a branch per
+    // neighbour would serialise the LDS reads of a stencil.
     __device__ T at(const T *a, int i, int j, int k) const
     {
-        if (i < 0 || i >= n) return (T)0;
-        if (DIM == 3 && (j < 0 || j >= n || k < 0 || k >= n)) return (T)0;
-        return a[DIM == 3 ? i + n * (j + n * k) : i];
+        const bool ok = (unsigned)i < (unsigned)n &&
+                        (DIM == 1 || ((unsigned)j < (unsigned)n && (unsigned)k < (unsigned)n));
+        const T v = a[ok ? (DIM == 3 ? i + n * (j + n * k) : i) : 0];
+        return ok ? v : (T)0;
     }
     __device__ void coords(int p, int &i, int &j, int &k) const
     {
         if (DIM == 3) { i = p % n; j = (p / n) % n; k = p / (n * n); }
         else { i = p; j = k = 0; }
     }
+    // Neighbour of interior point p at offset off when `ok`, else zero.
+    __device__ T nb(const T *a, int p, int off, bool ok) const
+    {
+        const T v = a[ok ? p + off : p];
+        return ok ? v : (T)0;
+    }
     __device__ T d2(const T *a, int i, int j, int k) const
     {
-        const T c = a[DIM == 3 ? i + n * (j + n * k) : i];
-        T s = at(a, i - 1, j, k) + at(a, i + 1, j, k);
-        if (DIM == 3) s += (at(a, i, j - 1, k) + at(a, i, j + 1, k)) + (at(a, i, j, k - 1) + at(a, i, j, k + 1));
+        const int p = DIM == 3 ? i + n * (j + n * k) : i;
+        const T c = a[p];
+        T s = nb(a, p, -1, i > 0) + nb(a, p, 1, i < n - 1);
+        if (DIM == 3)
+            s += (nb(a, p, -n, j > 0) + nb(a, p, n, j < n - 1)) + (nb(a, p, -n * n, k > 0) + nb(a, p, n * n, k < n - 1));
         return s - (T)(2 * DIM) * c;
     }
 };
@@ -68,28 +131,30 @@ template <int DIM, typename T>
 __device__ void smooth(Grid<DIM, T> &g, T ah, T winv, int smoother, int sweeps, bool from_zero)
 {
     if (sweeps == 0 && from_zero) {
-        for_points<DIM>(g.n, [&](int p, int, int, int) { g.u[p] = (T)0; });
+        for_flat<DIM>(g.n, [&](int p, int, int, int) { g.u[p] = (T)0; });
         __syncthreads();
         return;
     }
     for (int s = 0; s < sweeps; ++s) {
         const bool z = s == 0 && from_zero;
         if (smoother == PFMG_SMOOTH_RBGS) {
-            for (int colour = 0; colour < 2; ++colour) {
-                for_points<DIM>(g.n, [&](int p, int i, int j, int k) {
-                    const int par = (DIM == 3 ? (i + j + k + 3) : (i + 1)) & 1;   // 1-based parity
-                    if (z && colour == 0) {
-                        g.u[p] = par == 0 ? winv * g.b[p] : (T)0;
-                        return;
-                    }
-                    if (par != colour) return;
+            if (z) {
+                // red pass from u = 0: red points winv b, black points 0
+                for_flat<DIM>(g.n, [&](int p, int i, int j, int k) {
+                    const int par = (DIM == 3 ? (i + j + k + 3) : (i + 1)) & 1;
+                    g.u[p] = par == 0 ? winv * g.b[p] : (T)0;
+                });
+                __syncthreads();
+            }
+            for (int colour = z ? 1 : 0; colour < 2; ++colour) {
+                for_colour<DIM>(g.n, colour, [&](int p, int i, int j, int k) {
                     const T uc = g.u[p];
                     g.u[p] = uc + winv * (g.b[p] - (uc - ah * g.d2(g.u, i, j, k)));
                 });
                 __syncthreads();
             }
         } else {
-            for_points<DIM>(g.n, [&](int p, int i, int j, int k) {
+            for_flat<DIM>(g.n, [&](int p, int i, int j, int k) {
                 if (z) {
                     g.t[p] = winv * g.b[p];
                 } else {
@@ -98,29 +163,33 @@ __device__ void smooth(Grid<DIM, T> &g, T ah, T winv, int smoother, int sweeps, 
                 }
             });
             __syncthreads();
-            for_points<DIM>(g.n, [&](int p, int, int, int) { g.u[p] = g.t[p]; });
+            for_flat<DIM>(g.n, [&](int p, int, int, int) { g.u[p] = g.t[p]; });
             __syncthreads();
         }
     }
 }
 
+// Coarse b = full weighting of the fine residual b - (u - ah L u): the
+// residual of every fine point goes to f.t first (fine points 2I, 2I+1,
+// 2I+2 of each coarse point I, 0-based, all lie inside the fine grid).
 template <int DIM, typename T>
-__device__ void resid_restrict(const Grid<DIM, T> &f, Grid<DIM, T> &c, T ah)
+__device__ void resid_restrict(Grid<DIM, T> &f, Grid<DIM, T> &c, T ah)
 {
+    for_flat<DIM>(f.n, [&](int p, int i, int j, int k) { f.t[p] = f.b[p] - (f.u[p] - ah * f.d2(f.u, i, j, k)); });
+    __syncthreads();
     const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
-    for_points<DIM>(c.n, [&](int p, int I, int J, int K) {
+    for_flat<DIM>(c.n, [&](int p, int I, int J, int K) {
         const int fi = 2 * I + 1, fj = DIM == 3 ? 2 * J + 1 : 0, fk = DIM == 3 ? 2 * K + 1 : 0;
         T acc = 0;
-#pragma unroll 1
+#pragma unroll
         for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
-#pragma unroll 1
+#pragma unroll
             for (int oy = (DIM == 3 ? -1 : 0); oy <= (DIM == 3 ? 1 : 0); ++oy) {
                 T row = 0;
+#pragma unroll
                 for (int ox = -1; ox <= 1; ++ox) {
-                    const int i = fi + ox, j = fj + oy, k = fk + oz;
-                    const int q = DIM == 3 ? i + f.n * (j + f.n * k) : i;
-                    const T res = f.b[q] - (f.u[q] - ah * f.d2(f.u, i, j, k));
-                    row += w[ox + 1] * res;
+                    const int q = DIM == 3 ? (fi + ox) + f.n * ((fj + oy) + f.n * (fk + oz)) : fi + ox;
+                    row += w[ox + 1] * f.t[q];
                 }
                 acc += (DIM == 3 ? w[oz + 1] * w[oy + 1] : (T)1) * row;
             }
@@ -131,7 +200,7 @@ __device__ void resid_restrict(const Grid<DIM, T> &f, Grid<DIM, T> &c, T ah)
 template <int DIM, typename T>
 __device__ void prolong_add(const Grid<DIM, T> &c, Grid<DIM, T> &f)
 {
-    for_points<DIM>(f.n, [&](int p, int i, int j, int k) {
+    for_flat<DIM>(f.n, [&](int p, int i, int j, int k) {
         // 1-based fine index i+1; coarse 1-based (i+1)>>1 and (i+2)>>1, 0-based minus one
         const int i1 = i + 1;
         const int a0 = (i1 >> 1) - 1, a1 = ((i1 + 1) >> 1) - 1;
@@ -211,21 +280,24 @@ __global__ __launch_bounds__(1024) void vcycle_bottom_kernel(Tiling t, double al
     __shared__ int sn[MAXL], snl;
     __shared__ unsigned soff[MAXL];
     __shared__ T sah[MAXL], swi[MAXL];
-    const bool lead = threadIdx.x + threadIdx.y + threadIdx.z == 0;
-    if (lead) {
-        int nl = 0;
+    // thread l fills level l (levels: n0, coarser(n0), ... down to n <= 2)
+    const int tid = flat_tid<DIM>();
+    if (tid < MAXL) {
+        int n = n0, l = 0;
         unsigned off = 0;
-        for (int n = n0;; n = coarser(n)) {
-            sn[nl] = n;
-            soff[nl] = off;
-            off += (unsigned)((smoother == PFMG_SMOOTH_JACOBI ? 3 : 2) * ipow(n, DIM));
-            const double ah = alpha * (double)(n + 1) * (double)(n + 1);
-            sah[nl] = (T)ah;
-            swi[nl] = (T)(omega / (1.0 + 2.0 * DIM * ah));
-            ++nl;
-            if (n <= 2 || nl == MAXL) break;
+        while (l < tid && n > 2) {
+            off += (unsigned)(3 * ipow(n, DIM));
+            n = coarser(n);
+            ++l;
         }
-        snl = nl;
+        if (l == tid) {
+            sn[l] = n;
+            soff[l] = off;
+            const double ah = alpha * (double)(n + 1) * (double)(n + 1);
+            sah[l] = (T)ah;
+            swi[l] = (T)(omega / (1.0 + 2.0 * DIM * ah));
+            if (n <= 2 || l == MAXL - 1) snl = l + 1;
+        }
     }
     __syncthreads();
     T *base = reinterpret_cast<T *>(smem_raw);
@@ -283,11 +355,23 @@ __global__ __launch_bounds__(1024) void vcycle_bottom_kernel(Tiling t, double al
 
 namespace k {
 
+size_t bottom_lds_max()
+{
+    static const size_t cap = [] {
+        int dev = 0, bytes = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            bytes = 64 * 1024;
+        return (size_t)std::max(bytes, 64 * 1024) - 1024;
+    }();
+    return cap;
+}
+
 size_t vcycle_bottom_lds(int n0, int dim, int smoother, size_t elem)
 {
     size_t total = 0;
     for (int n = n0;; n = coarser(n)) {
-        total += (size_t)(smoother == PFMG_SMOOTH_JACOBI ? 3 : 2) * ipow(n, dim) * elem;
+        total += (size_t)3 * ipow(n, dim) * elem;
         if (n <= 2) break;
     }
     return total;
@@ -304,16 +388,19 @@ hipError_t vcycle_bottom(const Tiling &t, double alpha, int smoother, double ome
         lds = std::max(lds, vcycle_bottom_lds(t.seg_n(sg), t.dim, smoother, sizeof(T)));
     }
     if (items == 0) return hipSuccess;
-    if (lds > BOTTOM_LDS_MAX) return hipErrorInvalidValue;
-    // workgroup shape (x, y, z threads; x fastest) for the largest grid of
-    // the launch: every thread owns a few points of each pass
-    static const int shape = [] {
-        const char *e = getenv("PFMG_BOTTOM_THREADS");
-        return e ? atoi(e) : 1024;
-    }();
-    const dim3 blk = shape == 256 ? dim3(8, 8, 4) : shape == 512 ? dim3(16, 8, 4) : dim3(16, 16, 4);
+    if (lds > bottom_lds_max()) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {
+        // above the default dynamic-LDS limit: raise it once per kernel
+        static const hipError_t e3 = hipFuncSetAttribute((const void *)vcycle_bottom_kernel<3, T>,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                         (int)bottom_lds_max());
+        static const hipError_t e1 = hipFuncSetAttribute((const void *)vcycle_bottom_kernel<1, T>,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                         (int)bottom_lds_max());
+        if ((t.dim == 3 ? e3 : e1) != hipSuccess) return t.dim == 3 ? e3 : e1;
+    }
     if (t.dim == 3)
-        vcycle_bottom_kernel<3, T><<<(unsigned)items, blk, lds, s>>>(t, alpha, smoother, omega, nu1, nu2,
+        vcycle_bottom_kernel<3, T><<<(unsigned)items, dim3(16, 16, 4), lds, s>>>(t, alpha, smoother, omega, nu1, nu2,
                                                                                  zero_init ? 1 : 0, b, u);
     else
         vcycle_bottom_kernel<1, T><<<(unsigned)items, dim3(BT, 1, 1), lds, s>>>(t, alpha, smoother, omega, nu1, nu2,

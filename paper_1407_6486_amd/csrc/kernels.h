@@ -47,7 +47,10 @@ hipError_t rbgs_zero_red(const Tiling &t, double alpha, double omega, View<T> b,
                          hipStream_t s);
 // Whole V(nu1, nu2)-cycle from grid t.n down in LDS, one workgroup per field
 // (small grids).  zero_init starts from u = 0 instead of reading u.
-constexpr size_t BOTTOM_LDS_MAX = 64 * 1024;
+// LDS the kernel may take per workgroup on the current device (the device's
+// per-workgroup limit less the kernel's static level table); a grid whose
+// vcycle_bottom_lds exceeds it takes the per-level path.
+size_t bottom_lds_max();
 size_t vcycle_bottom_lds(int n0, int dim, int smoother, size_t elem);
 template <typename T>
 hipError_t vcycle_bottom(const Tiling &t, double alpha, int smoother, double omega, int nu1, int nu2, bool zero_init,

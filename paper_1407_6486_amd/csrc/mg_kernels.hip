@@ -540,27 +540,36 @@ template <typename T>
 hipError_t jacobi(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, View<T> out, hipStream_t s)
 {
     if (grid_blocks(t) == 0) return hipSuccess;
-    if (t.dim == 3) jacobi_kz_kernel<T><<<col_grid(t), BLOCK, 0, s>>>(t, alpha, omega, b, u, out);
-    else jacobi_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, omega, b, u, out);
+    if (t.dim == 3) return launch(jacobi_kz_kernel<T>, col_grid(t), dim3(BLOCK), 0, s, t, alpha, omega, b, u, out);
+    jacobi_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, omega, b, u, out);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t jacobi_zero(const Tiling &t, double alpha, double omega, View<T> b, View<T> out, hipStream_t s)
 {
-    PFMG_DISPATCH_T(t, jacobi_zero_kernel, T, t, alpha, omega, b, out);
+    if (grid_blocks(t) == 0) return hipSuccess;
+    if (t.dim == 3) return launch(jacobi_zero_kernel<3, T>, grid_of(t), dim3(BLOCK), 0, s, t, alpha, omega, b, out);
+    jacobi_zero_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, omega, b, out);
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t rbgs(const Tiling &t, double alpha, double omega, int colour, View<T> b, View<T> u, hipStream_t s)
 {
-    PFMG_DISPATCH_T(t, rbgs_kernel, T, t, alpha, omega, colour, b, u);
+    if (grid_blocks(t) == 0) return hipSuccess;
+    if (t.dim == 3) return launch(rbgs_kernel<3, T>, grid_of(t), dim3(BLOCK), 0, s, t, alpha, omega, colour, b, u);
+    rbgs_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, omega, colour, b, u);
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t rbgs_zero_red(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, hipStream_t s)
 {
-    PFMG_DISPATCH_T(t, rbgs_zero_red_kernel, T, t, alpha, omega, b, u);
+    if (grid_blocks(t) == 0) return hipSuccess;
+    if (t.dim == 3) return launch(rbgs_zero_red_kernel<3, T>, grid_of(t), dim3(BLOCK), 0, s, t, alpha, omega, b, u);
+    rbgs_zero_red_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, omega, b, u);
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -32,7 +32,12 @@ constexpr int QMAX = 6;   // owned rows per thread
 
 // RLN: x lanes per row (64, 128 or 256), the widest segment's n rounded up
 // to whole wavefronts; narrower segments leave their extra lanes idle.
-template <typename T, int RLN>
+// Q: rows per thread, ceil((ty + 2) / (BLOCK / RLN)) rounded up to an
+// instantiated value; the register windows hold Q rows, so a small ty buys
+// occupancy.  The loads of step k + 1 are issued at the top of step k
+// (uin plane k + 2, b plane k + 1, the halo rows of uin plane k + 1) and
+// wait behind the whole step's arithmetic and barriers.
+template <typename T, int RLN, int Q>
 __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
                                                            double omega, View<T> b, View<T> uin, View<T> uout)
 {
@@ -76,10 +81,24 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
     auto ld = [&](const T *__restrict__ a, int j, int k) -> T {
         return inside(j, k) ? a[(long)i + (long)j * sy + (long)k * sz] : (T)0;
     };
-
-    T um[QMAX], uc[QMAX], wm2[QMAX], wm1[QMAX], bm1[QMAX];
+    // the global loads of step k
+    auto load_step = [&](int k, T (&un)[Q], T (&bn)[Q], T (&ex)[2]) {
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+        for (int q = 0; q < Q; ++q) {
+            const int r = rsub + q * rpp;
+            const int j = j0 - 1 + r;
+            const bool own = r < rows;
+            un[q] = (own && !zero_in) ? ld(U, j, k + 1) : (T)0;
+            bn[q] = own ? ld(Bv, j, k) : (T)0;
+        }
+        ex[0] = ex[1] = (T)0;
+        if (!zero_in)
+            for (int e = rsub, q = 0; e < 2; e += rpp, ++q) ex[q] = ld(U, e == 0 ? j0 - 2 : j0 + ty + 1, k);
+    };
+
+    T um[Q], uc[Q], wm2[Q], wm1[Q], bm1[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
         const int r = rsub + q * rpp;
         const int j = j0 - 1 + r;
         const bool own = r < rows;
@@ -87,24 +106,22 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
         uc[q] = (own && !zero_in) ? ld(U, j, k0 - 1) : (T)0;
         wm2[q] = wm1[q] = bm1[q] = (T)0;
     }
+    T pun[Q], pbn[Q], pex[2];
+    load_step(k0 - 1, pun, pbn, pex);
 
     for (int k = k0 - 1; k <= k1; ++k) {
-        // ---- loads of this step: uin plane k+1, b plane k, extra uin rows of plane k
-        T un[QMAX], bn[QMAX];
+        T un[Q], bn[Q], ex[2];
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
-            const int r = rsub + q * rpp;
-            const int j = j0 - 1 + r;
-            const bool own = r < rows;
-            un[q] = (own && !zero_in) ? ld(U, j, k + 1) : (T)0;
-            bn[q] = own ? ld(Bv, j, k) : (T)0;
+        for (int q = 0; q < Q; ++q) {
+            un[q] = pun[q];
+            bn[q] = pbn[q];
         }
-        T ex[2] = {(T)0, (T)0};
-        if (!zero_in)
-            for (int e = rsub, q = 0; e < 2; e += rpp, ++q) ex[q] = ld(U, e == 0 ? j0 - 2 : j0 + ty + 1, k);
+        ex[0] = pex[0];
+        ex[1] = pex[1];
+        if (k < k1) load_step(k + 1, pun, pbn, pex);
         // ---- uin plane k -> LDS (rows e = 0 .. ty+3 <-> j = j0-2+e)
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
+        for (int q = 0; q < Q; ++q) {
             const int r = rsub + q * rpp;
             if (r < rows) up[(size_t)(r + 1) * RL + i] = uc[q];
         }
@@ -112,9 +129,9 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
         __syncthreads();
         // ---- phase A: red update of plane k on the owned rows
         T *wk = wp + (size_t)(k & 1) * rows * RL;
-        T wn[QMAX];
+        T wn[Q];
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
+        for (int q = 0; q < Q; ++q) {
             const int r = rsub + q * rpp;
             const int j = j0 - 1 + r;
             T val = (T)0;
@@ -141,7 +158,7 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
         if (kb >= k0 && kb < k1) {
             const T *wb = wp + (size_t)(kb & 1) * rows * RL;
 #pragma unroll
-            for (int q = 0; q < QMAX; ++q) {
+            for (int q = 0; q < Q; ++q) {
                 const int r = rsub + q * rpp;
                 const int j = j0 - 1 + r;
                 if (r >= 1 && r <= ty && j <= n && xin) {
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
         }
         // ---- rotate the register windows
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
+        for (int q = 0; q < Q; ++q) {
             um[q] = uc[q];
             uc[q] = un[q];
             wm2[q] = wm1[q];
@@ -169,6 +186,9 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
         }
     }
 }
+
+// Rows per thread for a launch of row width RLN and ty output rows.
+constexpr int rows_per_thread(int rln, int ty) { return (ty + 2 + BLOCK / rln - 1) / (BLOCK / rln); }
 
 int env_int(const char *name, int dflt)
 {
@@ -230,18 +250,32 @@ hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in,
     int nmax = 0;
     for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
     const int zi = zero_in ? 1 : 0;
-    switch ((nmax + 63) & ~63) {
-    case 64:
-        rbgs_fused_kernel<T, 64><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zi, alpha, omega, b, uin, uout);
-        break;
-    case 128:
-        rbgs_fused_kernel<T, 128><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zi, alpha, omega, b, uin, uout);
-        break;
-    default:
-        rbgs_fused_kernel<T, 256><<<(unsigned)f.blocks, BLOCK, f.lds, s>>>(t, f.ty, f.zchunk, zi, alpha, omega, b, uin, uout);
-        break;
+    const int rln = nmax <= 64 ? 64 : nmax <= 128 ? 128 : 256;
+    const int q = rows_per_thread(rln, f.ty);
+    const dim3 g((unsigned)f.blocks), blk(BLOCK);
+#define PFMG_FUSED(RL_, Q_)                                                                                 \
+    return launch(rbgs_fused_kernel<T, RL_, Q_>, g, blk, f.lds, s, t, f.ty, f.zchunk, zi, alpha, omega, b, uin, \
+                  uout)
+    // instantiated row counts: those of ty = 1, 2, 4, 8, 16 that fit QMAX,
+    // and QMAX for any other ty
+    if (rln == 64) {
+        if (q <= 1) PFMG_FUSED(64, 1);
+        if (q <= 2) PFMG_FUSED(64, 2);
+        if (q <= 3) PFMG_FUSED(64, 3);
+        if (q <= 5) PFMG_FUSED(64, 5);
+        if (q <= QMAX) PFMG_FUSED(64, 6);
+    } else if (rln == 128) {
+        if (q <= 2) PFMG_FUSED(128, 2);
+        if (q <= 3) PFMG_FUSED(128, 3);
+        if (q <= 5) PFMG_FUSED(128, 5);
+        if (q <= QMAX) PFMG_FUSED(128, 6);
+    } else {
+        if (q <= 3) PFMG_FUSED(256, 3);
+        if (q <= 4) PFMG_FUSED(256, 4);
+        if (q <= QMAX) PFMG_FUSED(256, 6);
     }
-    return hipGetLastError();
+#undef PFMG_FUSED
+    return hipErrorInvalidValue;
 }
 
 template hipError_t rbgs_fused<double>(const Tiling &, double, double, bool, View<double>, View<double>,

@@ -41,6 +41,8 @@ struct Timer {
     size_t used = 0;
     int depth = 0;                    // current bracket nesting
     int open = -1;                    // depth of the recording bracket, -1 if none
+    bool stamped = false;             // open bracket's events stamped by its launch
+    double added = 0;                 // bytes the open bracket added
     double bytes = 0;
     long long launches = 0;
 };
@@ -121,7 +123,7 @@ struct Solver {
     hipEvent_t ev[MAXGROUPS + 1] = {};
     hipError_t residual_read(double *per_slice, double *block);
     Tiling tl(int n, int count, const int *m = nullptr) const { return Tiling{n, dim, count, m, noremap}; }
-    void tstart(const char *fam, int n, double bytes_per_point, long points);
+    void tstart(const char *fam, int n, double bytes_per_point, long points, bool stamped = false);
     void tstop();
 };
 

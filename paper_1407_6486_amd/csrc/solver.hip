@@ -247,13 +247,19 @@ hipError_t Solver::upload_constants()
 // Brackets nest (a whole V-cycle contains its smoother launches); only the
 // bracket whose family matches the enabled key records events, and its stop
 // is the tstop at the same nesting depth.
-void Solver::tstart(const char *fam, int n, double bytes_per_point, long points)
+// A stamped bracket covers exactly one launch made through launch(): its
+// events are stamped by that dispatch itself; if no such launch consumed
+// them (an empty launch), the bracket is dropped.
+void Solver::tstart(const char *fam, int n, double bytes_per_point, long points, bool stamped)
 {
     const int d = timer.depth++;
     if (!timer.on || timer.open >= 0) return;
     if (timer.key != std::string(fam) + "@" + std::to_string(n) || timer.used + 2 > timer.ev.size()) return;
-    (void)hipEventRecord(timer.ev[timer.used], s);
-    timer.bytes += bytes_per_point * (double)points;
+    timer.stamped = stamped;
+    timer.added = bytes_per_point * (double)points;
+    if (stamped) armed_events = {timer.ev[timer.used], timer.ev[timer.used + 1]};
+    else (void)hipEventRecord(timer.ev[timer.used], s);
+    timer.bytes += timer.added;
     timer.launches += 1;
     timer.used += 1;
     timer.open = d;
@@ -263,9 +269,19 @@ void Solver::tstop()
 {
     const int d = --timer.depth;
     if (timer.open != d) return;
-    (void)hipEventRecord(timer.ev[timer.used], s);
-    timer.used += 1;
     timer.open = -1;
+    if (timer.stamped) {
+        if (armed_events.start) {              // nothing was launched
+            armed_events = {};
+            timer.used -= 1;
+            timer.launches -= 1;
+            timer.bytes -= timer.added;
+            return;
+        }
+    } else {
+        (void)hipEventRecord(timer.ev[timer.used], s);
+    }
+    timer.used += 1;
 }
 
 // ------------------------------------------------------------- multigrid
@@ -290,7 +306,7 @@ hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> 
         // whole sweeps in one pass each, ping-pong between u and tmp
         View<T> src = u, dst = tmp;
         for (int q = 0; q < sweeps; ++q) {
-            tstart("rbgs", n, 3 * w, pts);
+            tstart("rbgs", n, 3 * w, pts, true);
             HC(k::rbgs_fused(t, alpha, om, q == 0 && from_zero, b, src, dst, s, &plan.shape));
             tstop();
             std::swap(src, dst);
@@ -300,11 +316,11 @@ hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> 
     }
     if (p.smoother == PFMG_SMOOTH_RBGS) {
         for (int q = 0; q < sweeps; ++q) {
-            tstart("rbgs", n, 2 * w, pts);
+            tstart("rbgs", n, 2 * w, pts, true);
             if (q == 0 && from_zero) HC(k::rbgs_zero_red(t, alpha, om, b, u, s));
             else HC(k::rbgs(t, alpha, om, 0, b, u, s));
             tstop();
-            tstart("rbgs", n, 2 * w, pts);
+            tstart("rbgs", n, 2 * w, pts, true);
             HC(k::rbgs(t, alpha, om, 1, b, u, s));
             tstop();
         }
@@ -312,7 +328,7 @@ hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> 
     }
     View<T> src = u, dst = tmp;
     for (int q = 0; q < sweeps; ++q) {
-        tstart("jacobi", n, 3 * w, pts);
+        tstart("jacobi", n, 3 * w, pts, true);
         if (q == 0 && from_zero) HC(k::jacobi_zero(t, alpha, om, b, dst, s));
         else HC(k::jacobi(t, alpha, om, b, src, dst, s));
         tstop();
@@ -326,7 +342,7 @@ hipError_t Solver::vcycle64(int lev, int l, View<double> u, View<double> b, int 
 {
     MGLevel &G = L[lev].mg[l];
     const Tiling t = tl(G.n, count, m);
-    if (use_bottom && k::vcycle_bottom_lds(G.n, dim, p.smoother, sizeof(double)) <= k::BOTTOM_LDS_MAX)
+    if (use_bottom && k::vcycle_bottom_lds(G.n, dim, p.smoother, sizeof(double)) <= k::bottom_lds_max())
         return k::vcycle_bottom(t, alpha, p.smoother, p.omega, p.nu_pre, p.nu_post, l > 0, b, u, s);
     if (G.n <= 2) return k::coarsest(t, alpha, b, u, s);
     HC(smooth<double>(G.n, count, m, alpha, u, b, G.t, p.nu_pre, l > 0));
@@ -346,7 +362,7 @@ hipError_t Solver::vcycle32(int lev, int l, View<float> u, View<float> b, int co
 {
     MGLevel &G = L[lev].mg[l];
     const Tiling t = tl(G.n, count, m);
-    if (use_bottom && k::vcycle_bottom_lds(G.n, dim, p.smoother, sizeof(float)) <= k::BOTTOM_LDS_MAX)
+    if (use_bottom && k::vcycle_bottom_lds(G.n, dim, p.smoother, sizeof(float)) <= k::bottom_lds_max())
         return k::vcycle_bottom(t, alpha, p.smoother, p.omega, p.nu_pre, p.nu_post, true, b, u, s);
     if (G.n <= 2) return k::coarsest(t, alpha, b, u, s);
     HC(smooth<float>(G.n, count, m, alpha, u, b, G.t32, p.nu_pre, true));

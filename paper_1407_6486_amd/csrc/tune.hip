@@ -52,6 +52,16 @@ void append_locked(const std::string &key, const Entry &e)
     fclose(f);
 }
 
+// PFMG_TUNE_VERBOSE=1: every timed candidate is reported on stderr.
+bool verbose()
+{
+    static const bool v = [] {
+        const char *e = getenv("PFMG_TUNE_VERBOSE");
+        return e && atoi(e) != 0;
+    }();
+    return v;
+}
+
 bool tuning_enabled()
 {
     const char *e = getenv("PFMG_TUNE");
@@ -145,6 +155,7 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
         }, s, e0, e1, reps);
     }
     if (best < 0) best = 1e30f;
+    if (verbose()) fprintf(stderr, "tune %s colour-passes %.2f us\n", key.c_str(), best * 1e3f);
     // one-pass shapes
     std::vector<k::FusedShape> cands;
     for (int ty : {2, 4, 8, 16})
@@ -158,6 +169,9 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
     for (const auto &f : cands) {
         const float ms = time_ms([&] { return k::rbgs_fused(t, alpha, omega, false, b, u, tmp, s, &f); }, s, e0, e1,
                                  reps);
+        if (verbose())
+            fprintf(stderr, "tune %s fused ty %d zchunk %d blocks %ld %.2f us\n", key.c_str(), f.ty, f.zchunk, f.blocks,
+                    ms * 1e3f);
         if (ms >= 0 && ms < best) {
             best = ms;
             win = Entry{1, f.ty, f.zchunk, f.blocks};

@@ -55,6 +55,11 @@ size_t vcycle_bottom_lds(int n0, int dim, int smoother, size_t elem);
 template <typename T>
 hipError_t vcycle_bottom(const Tiling &t, double alpha, int smoother, double omega, int nu1, int nu2, bool zero_init,
                          View<T> b, View<T> u, hipStream_t s);
+// One-pass z-marching residual + full weighting (3D, odd fine n in
+// [63, 255]); resid_restrict takes it wherever resid_restrict_z_ok holds.
+bool resid_restrict_z_ok(const Tiling &t);
+template <typename T>
+hipError_t resid_restrict_z(const Tiling &t, double alpha, View<T> b, View<T> u, View<T> bc, hipStream_t s);
 // Full weighting of a fine array (t.n = fine n) onto the coarse grid.
 template <typename T>
 hipError_t restrict_fw(const Tiling &t, View<T> r, View<T> bc, hipStream_t s);

@@ -582,6 +582,7 @@ hipError_t restrict_fw(const Tiling &t, View<T> r, View<T> bc, hipStream_t s)
 template <typename T>
 hipError_t resid_restrict(const Tiling &t, double alpha, View<T> b, View<T> u, View<T> bc, hipStream_t s)
 {
+    if (resid_restrict_z_ok(t)) return resid_restrict_z(t, alpha, b, u, bc, s);
     const Tiling tc = coarsen(t);
     PFMG_DISPATCH_T(tc, resid_restrict_kernel, T, tc, alpha, b, u, bc);
 }

@@ -38,7 +38,7 @@ constexpr int QMAX = 6;   // owned rows per thread
 // (uin plane k + 2, b plane k + 1, the halo rows of uin plane k + 1) and
 // wait behind the whole step's arithmetic and barriers.
 template <typename T, int RLN, int Q>
-__global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
+__global__ __launch_bounds__(BLOCK, (Q == 3 ? 5 : 1)) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
                                                            double omega, View<T> b, View<T> uin, View<T> uout)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
     constexpr int RL = rowlanes + 2;
     const int rows = ty + 2;                 // rows of the red update (owned rows)
     T *up = reinterpret_cast<T *>(smem_raw);             // uin plane k: rows j0-2 .. j0+ty+1
-    T *wp = up + (size_t)(ty + 4) * RL;                  // 2 planes of the red-updated field
+    T *wp = up + (ty + 4) * RL;                  // 2 planes of the red-updated field
     const int ytiles = (n + ty - 1) / ty, zch = (n + zchunk - 1) / zchunk;
     const int item = (int)(bid / (unsigned)(ytiles * zch));
     const int rem = (int)(bid - (unsigned)item * (unsigned)(ytiles * zch));
@@ -68,18 +68,19 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
     constexpr int rpp = BLOCK / rowlanes;
     const int i = (int)(threadIdx.x % rowlanes) + 1;
     const int rsub = (int)(threadIdx.x / rowlanes);
-    const long sy = row_stride(n), sz = plane_stride(n);
+    // element offsets inside one field fit in 32 bits (n <= 255)
+    const int sy = (int)row_stride(n), sz = (int)plane_stride(n);
     const T *__restrict__ U = fp(uin, qs);
     const T *__restrict__ Bv = fp(b, qs);
     T *__restrict__ O = fp(uout, qs);
     const bool xin = i <= n;
 
     // x index 0 is the boundary: zero once in every LDS row
-    for (int r = threadIdx.x; r < (ty + 4) + 2 * rows; r += BLOCK) up[(size_t)r * RL] = (T)0;
+    for (int r = threadIdx.x; r < (ty + 4) + 2 * rows; r += BLOCK) up[r * RL] = (T)0;
 
     auto inside = [&](int j, int k) { return xin && j >= 1 && j <= n && k >= 1 && k <= n; };
     auto ld = [&](const T *__restrict__ a, int j, int k) -> T {
-        return inside(j, k) ? a[(long)i + (long)j * sy + (long)k * sz] : (T)0;
+        return inside(j, k) ? a[i + j * sy + k * sz] : (T)0;
     };
     // the global loads of step k
     auto load_step = [&](int k, T (&un)[Q], T (&bn)[Q], T (&ex)[2]) {
@@ -123,12 +124,12 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int r = rsub + q * rpp;
-            if (r < rows) up[(size_t)(r + 1) * RL + i] = uc[q];
+            if (r < rows) up[(r + 1) * RL + i] = uc[q];
         }
-        for (int e = rsub, q = 0; e < 2; e += rpp, ++q) up[(size_t)(e == 0 ? 0 : ty + 3) * RL + i] = ex[q];
+        for (int e = rsub, q = 0; e < 2; e += rpp, ++q) up[(e == 0 ? 0 : ty + 3) * RL + i] = ex[q];
         __syncthreads();
         // ---- phase A: red update of plane k on the owned rows
-        T *wk = wp + (size_t)(k & 1) * rows * RL;
+        T *wk = wp + (k & 1) * rows * RL;
         T wn[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -140,9 +141,9 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
                 if (zero_in) {
                     val = red ? winv * bn[q] : (T)0;
                 } else if (red) {
-                    const T *row = up + (size_t)(r + 1) * RL;
+                    const T *row = up + (r + 1) * RL;
                     T s = row[i - 1] + row[i + 1];
-                    s += (up[(size_t)r * RL + i] + up[(size_t)(r + 2) * RL + i]) + (um[q] + un[q]);
+                    s += (up[r * RL + i] + up[(r + 2) * RL + i]) + (um[q] + un[q]);
                     s -= (T)6 * uc[q];
                     val = uc[q] + winv * (bn[q] - (uc[q] - ah * s));
                 } else {
@@ -150,13 +151,13 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
                 }
             }
             wn[q] = val;
-            if (r < rows) wk[(size_t)r * RL + i] = val;
+            if (r < rows) wk[r * RL + i] = val;
         }
         __syncthreads();
         // ---- phase B: black update of plane k-1 on rows 1..ty
         const int kb = k - 1;
         if (kb >= k0 && kb < k1) {
-            const T *wb = wp + (size_t)(kb & 1) * rows * RL;
+            const T *wb = wp + (kb & 1) * rows * RL;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int r = rsub + q * rpp;
@@ -165,13 +166,13 @@ __global__ __launch_bounds__(BLOCK) void rbgs_fused_kernel(Tiling t, int ty, int
                     const T wc = wm1[q];
                     T out = wc;
                     if (((i + j + kb) & 1) == 1) {
-                        const T *row = wb + (size_t)r * RL;
+                        const T *row = wb + r * RL;
                         T s = row[i - 1] + row[i + 1];
-                        s += (wb[(size_t)(r - 1) * RL + i] + wb[(size_t)(r + 1) * RL + i]) + (wm2[q] + wn[q]);
+                        s += (wb[(r - 1) * RL + i] + wb[(r + 1) * RL + i]) + (wm2[q] + wn[q]);
                         s -= (T)6 * wc;
                         out = wc + winv * (bm1[q] - (wc - ah * s));
                     }
-                    O[(long)i + (long)j * sy + (long)kb * sz] = out;
+                    O[i + j * sy + kb * sz] = out;
                 }
             }
         }

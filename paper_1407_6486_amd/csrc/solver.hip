@@ -184,10 +184,13 @@ bool Solver::init_host(std::string &why)
     fused_min_points = e ? atol(e) : 2000000;
     dim = p.dim;
     P = p.n_slices;
-    // slice groups of the pipelined iteration: halving sizes (P/2, P/4, ...,
-    // at least 2 slices), so that the first fine sweeps are large launches
-    // and the coarse chain left after the last one is short.  PFMG_GROUPS:
-    // a count of equal groups, or a comma-separated list of group sizes.
+    // slice groups of the pipelined iteration: four groups of (nearly)
+    // equal size for P >= 8, so that the coarse chain of one group runs
+    // under the fine sweeps of the next ones while the fine launches stay
+    // large enough to stream well (measured at 127^3 x 16: 4 x 4 slices
+    // 1.60 s per block, halving sizes 8,4,2,2 1.66 s, 2 x 8 1.67 s).
+    // PFMG_GROUPS: a count of equal groups, or a comma-separated list of
+    // group sizes.
     gbound.assign(1, 0);
     e = getenv("PFMG_GROUPS");
     if (e && strchr(e, ',')) {
@@ -203,8 +206,7 @@ bool Solver::init_host(std::string &why)
         const int g = std::max(1, std::min(atoi(e), P));
         for (int q = 1; q <= g; ++q) gbound.push_back((int)((long)P * q / g));
     } else if (P >= 8) {
-        for (int sz = P / 2; gbound.back() < P; sz = std::max(2, sz / 2))
-            gbound.push_back(std::min(P, gbound.back() + sz));
+        for (int q = 1; q <= 4; ++q) gbound.push_back((int)((long)P * q / 4));
     } else {
         gbound.push_back(P);
     }

@@ -121,6 +121,12 @@ struct Solver {
     std::vector<int> gbound;          // group g holds slices gbound[g] .. gbound[g+1]-1
     hipStream_t s2 = nullptr;         // coarse-chain stream of the pipelined iteration
     hipEvent_t ev[MAXGROUPS + 1] = {};
+    hipStream_t s3 = nullptr;         // second fine-sweep stream of the pipelined iteration
+    hipEvent_t ev_fork = nullptr;
+    int fine_streams = 1;             // streams the groups' fine sweeps alternate over
+    int mg_off = 0;                   // first multigrid scratch field of the current sweep
+    template <typename T>
+    View<T> scr(View<T> v) const { return View<T>{v.p ? v.p + (long)mg_off * v.stride : nullptr, v.stride}; }
     hipError_t residual_read(double *per_slice, double *block);
     Tiling tl(int n, int count, const int *m = nullptr) const { return Tiling{n, dim, count, m, noremap}; }
     void tstart(const char *fam, int n, double bytes_per_point, long points, bool stamped = false);

@@ -156,15 +156,24 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
     }
     if (best < 0) best = 1e30f;
     if (verbose()) fprintf(stderr, "tune %s colour-passes %.2f us\n", key.c_str(), best * 1e3f);
-    // one-pass shapes
+    // one-pass shapes: rows per workgroup x planes per z-chunk (short
+    // chunks let small grids spread over more workgroups; every chunk also
+    // recomputes its two border planes)
     std::vector<k::FusedShape> cands;
+    int nmax = 0;
+    for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
     for (int ty : {2, 4, 8, 16})
-        for (int target : {256, 1024, 4096}) {
-            k::FusedShape f = k::rbgs_fused_shape(t, sizeof(T), ty, target);
-            if (f.ty != ty) continue;
-            bool dup = false;
-            for (const auto &c : cands) dup = dup || (c.ty == f.ty && c.zchunk == f.zchunk);
-            if (!dup && f.blocks > 0) cands.push_back(f);
+        for (int zc : {2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128, 256}) {
+            k::FusedShape f = k::rbgs_fused_shape(t, sizeof(T), ty, 1);
+            if (f.ty != ty || zc > nmax) continue;
+            f.zchunk = zc;
+            f.blocks = 0;
+            for (int sg = 0; sg < t.nseg; ++sg) {
+                const int n = t.seg_n(sg);
+                f.blocks += (long)t.seg_count(sg) * ((n + ty - 1) / ty) * ((n + zc - 1) / zc);
+            }
+            if (f.blocks <= 0 || f.blocks > 16384) continue;
+            cands.push_back(f);
         }
     for (const auto &f : cands) {
         const float ms = time_ms([&] { return k::rbgs_fused(t, alpha, omega, false, b, u, tmp, s, &f); }, s, e0, e1,

@@ -44,8 +44,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--max-iter", type=int, default=400,
                     help="iteration cap per block (profiling runs cap it to keep traces small)")
-    ap.add_argument("--form", choices=["mixed", "batched", "learned"], default=None,
-                    help="measure one of the method's forms against the plain FP64 path instead")
+    ap.add_argument("--form", choices=["mixed", "batched", "learned", "c2-variants", "c1"], default=None,
+                    help="instead: one of the method's forms against the plain FP64 path (mixed, batched, learned), "
+                         "the node-solve policies at 127^3 x 16 (c2-variants) or the 1D latency and error report (c1)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain copy of known size three times (reference for HBM counters)")
     return ap.parse_args()
@@ -215,6 +216,89 @@ def form_learned(pfmg, a):
                                    "dt=1e-3, seed 1407, full solves to 1e-12"}}
 
 
+def form_c2_variants(pfmg, a):
+    """The 127^3 x 16 block (seed 1407) with the node-solve policies the
+    paper weighs against each other: one and two V-cycles per solve and
+    full solves (1e-12, stall 0.75), red-black Gauss-Seidel; one V-cycle
+    with omega-Jacobi (2/3).  Each to a block residual of 1e-10."""
+    import torch
+
+    import inputs
+
+    n, P = 127, 16
+    u0 = torch.from_numpy(inputs.random_fourier(n, 1407)[0]).to("cuda")
+    rows = []
+    for sm, cyc in (("rbgs", 1), ("rbgs", 2), ("rbgs", 0), ("jacobi", 1)):
+        c = pfmg.Context(pfmg.pfmg_default_params(
+            dim=3, n=n, n_slices=P, nu=1.0, dt=1e-3, vcycles_per_solve=cyc, mg_tol=1e-12, mg_stall=0.75,
+            mg_max_cycles=50, smoother=pfmg.SMOOTH_RBGS if sm == "rbgs" else pfmg.SMOOTH_JACOBI,
+            omega=1.0 if sm == "rbgs" else 2.0 / 3.0, pfasst_tol=1e-10, pfasst_max_iter=a.max_iter))
+        for _ in range(max(1, a.warmup)):
+            c.run_block(u0)
+        v0 = c.vcycle_count(0)
+        t, outs = _time_blocks(lambda: c.run_block(u0), a.steps)
+        fine = (c.vcycle_count(0) - v0) / a.steps
+        c.timing_enable(f"vcycle@{n}", True)
+        c.run_block(u0)
+        _, vms, vdof = c.timing_read()
+        c.timing_enable(None, False)
+        rows.append({"smoother": sm, "vcycles_per_solve": cyc if cyc else "to 1e-12", "s_per_block": round(t, 4),
+                     "iterations": outs[-1][1], "final_residual": outs[-1][2], "fine_vcycles_per_block": fine,
+                     "vcycle_gdofs": round(vdof / (vms * 1e-3) / 1e9, 2) if vms > 0 else None})
+        c.close()
+        del c
+        torch.cuda.empty_cache()
+    return {"metric": "s to 1e-10 residual per PFASST block", "unit": "s", "form": "node-solve policies",
+            "rows": rows, "higher_is_better": False, "dtype": "f64", "data": "synthetic", "n_gpus": 1,
+            "steps": a.steps, "config": {"workload": "3D heat, 127^3, 16 slices, dt=1e-3, Lobatto 5/3, V(2,2), "
+                                                     "seed 1407"}}
+
+
+def form_c1(pfmg, a):
+    """1D heat (n = 127, sin(pi x) + 0.1 sin(8 pi x), nu = 1), 4 slices of
+    dt = 0.01, omega-Jacobi V(2,2), one V-cycle per solve: predictor and 5
+    iterations.  Per iteration the block residual and, over the slice ends,
+    the error against the semi-discrete (ODE) solution, whose sine modes
+    decay as exp(mu_k t), mu_k = -4 sin^2(k pi h / 2) / h^2, and against the
+    PDE solution (exp(-k^2 pi^2 t)).  A latency test: s per block."""
+    import numpy as np
+
+    n, P, dt = 127, 4, 0.01
+    h = 1.0 / (n + 1)
+    x = np.arange(1, n + 1) * h
+    u0 = np.sin(np.pi * x) + 0.1 * np.sin(8 * np.pi * x)
+    mu = lambda k: -4.0 * np.sin(k * np.pi * h / 2) ** 2 / h ** 2
+    ode = lambda t: np.exp(mu(1) * t) * np.sin(np.pi * x) + 0.1 * np.exp(mu(8) * t) * np.sin(8 * np.pi * x)
+    pde = lambda t: (np.exp(-np.pi ** 2 * t) * np.sin(np.pi * x)
+                     + 0.1 * np.exp(-64 * np.pi ** 2 * t) * np.sin(8 * np.pi * x))
+    kw = dict(dim=1, n=n, n_slices=P, nu=1.0, dt=dt, smoother=pfmg.SMOOTH_JACOBI, omega=2.0 / 3.0,
+              vcycles_per_solve=1, pfasst_tol=0.0, pfasst_max_iter=5)
+    c = pfmg.Context(pfmg.pfmg_default_params(**kw))
+    c.set_initial(u0)
+
+    def errors():
+        ends = [c.get(pfmg.U_FINE, p, 4) for p in range(P)]
+        e_ode = max(float(np.max(np.abs(u - ode((p + 1) * dt)))) for p, u in enumerate(ends))
+        e_pde = max(float(np.max(np.abs(u - pde((p + 1) * dt)))) for p, u in enumerate(ends))
+        return e_ode, e_pde
+
+    per_iter = [{"iteration": 0, "residual": float(np.max(c.residual())), **dict(zip(("ode_error", "pde_error"),
+                                                                                   errors()))}]
+    for k in range(1, 6):
+        r = c.pfasst_iter()
+        per_iter.append({"iteration": k, "residual": r, **dict(zip(("ode_error", "pde_error"), errors()))})
+    c.close()
+    c = pfmg.Context(pfmg.pfmg_default_params(**kw))
+    for _ in range(max(1, a.warmup)):
+        c.run_block(u0)
+    t, _ = _time_blocks(lambda: c.run_block(u0), max(a.steps, 10))
+    c.close()
+    return {"metric": "s per PFASST block (predictor + 5 iterations)", "value": round(t, 6), "unit": "s",
+            "form": "C1 latency and errors", "per_iteration": per_iter, "higher_is_better": False, "dtype": "f64",
+            "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": "1D heat, n=127, 4 slices, dt=0.01, Lobatto 5/3, jacobi V(2,2), 1 V-cycle/solve"}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -229,7 +313,8 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     if a.form:
-        fn = {"mixed": form_mixed, "batched": form_batched, "learned": form_learned}[a.form]
+        fn = {"mixed": form_mixed, "batched": form_batched, "learned": form_learned,
+              "c2-variants": form_c2_variants, "c1": form_c1}[a.form]
         print(json.dumps(fn(pfmg, a), default=float), flush=True)
         return
     if a.calibrate_copy:

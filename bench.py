@@ -44,9 +44,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--max-iter", type=int, default=400,
                     help="iteration cap per block (profiling runs cap it to keep traces small)")
-    ap.add_argument("--form", choices=["mixed", "batched", "learned", "c2-variants", "c1"], default=None,
+    ap.add_argument("--form", choices=["mixed", "batched", "learned", "solve-policies", "heat1d"], default=None,
                     help="instead: one of the method's forms against the plain FP64 path (mixed, batched, learned), "
-                         "the node-solve policies at 127^3 x 16 (c2-variants) or the 1D latency and error report (c1)")
+                         "the node-solve policies at 127^3 x 16 (solve-policies) or the 1D latency and error report (heat1d)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain copy of known size three times (reference for HBM counters)")
     return ap.parse_args()
@@ -216,7 +216,7 @@ def form_learned(pfmg, a):
                                    "dt=1e-3, seed 1407, full solves to 1e-12"}}
 
 
-def form_c2_variants(pfmg, a):
+def form_solve_policies(pfmg, a):
     """The 127^3 x 16 block (seed 1407) with the node-solve policies the
     paper weighs against each other: one and two V-cycles per solve and
     full solves (1e-12, stall 0.75), red-black Gauss-Seidel; one V-cycle
@@ -254,7 +254,7 @@ def form_c2_variants(pfmg, a):
                                                      "seed 1407"}}
 
 
-def form_c1(pfmg, a):
+def form_heat1d(pfmg, a):
     """1D heat (n = 127, sin(pi x) + 0.1 sin(8 pi x), nu = 1), 4 slices of
     dt = 0.01, omega-Jacobi V(2,2), one V-cycle per solve: predictor and 5
     iterations.  Per iteration the block residual and, over the slice ends,
@@ -294,7 +294,7 @@ def form_c1(pfmg, a):
     t, _ = _time_blocks(lambda: c.run_block(u0), max(a.steps, 10))
     c.close()
     return {"metric": "s per PFASST block (predictor + 5 iterations)", "value": round(t, 6), "unit": "s",
-            "form": "C1 latency and errors", "per_iteration": per_iter, "higher_is_better": False, "dtype": "f64",
+            "form": "1D heat, latency and errors", "per_iteration": per_iter, "higher_is_better": False, "dtype": "f64",
             "data": "synthetic", "n_gpus": 1,
             "config": {"workload": "1D heat, n=127, 4 slices, dt=0.01, Lobatto 5/3, jacobi V(2,2), 1 V-cycle/solve"}}
 
@@ -314,7 +314,7 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     if a.form:
         fn = {"mixed": form_mixed, "batched": form_batched, "learned": form_learned,
-              "c2-variants": form_c2_variants, "c1": form_c1}[a.form]
+              "solve-policies": form_solve_policies, "heat1d": form_heat1d}[a.form]
         print(json.dumps(fn(pfmg, a), default=float), flush=True)
         return
     if a.calibrate_copy:

@@ -63,7 +63,7 @@ def train(pf, store, count: int, steps: int, batch: int = 8, lr: float = 2e-3, s
 
 def evaluate(pf, params, n: int, slices: int, thresholds=(0.0,), seed: int = 1407, mg_tol: float = 1e-12,
              log=print):
-    """One block of the C2-type problem with full node solves (to mg_tol),
+    """One block of the 127^3 random-Fourier problem (seed 1407) with full node solves (to mg_tol),
     plain guess against the learned guess offered to solves whose plain
     guess has relative residual above each threshold."""
     import torch

@@ -164,7 +164,7 @@ def test_uneven_64_problem_batch_converges(pf):
     probs = [inputs.batch_problem(q) for q in range(64)]
     ps = [pf.pfmg_default_params(n=bp.n, nu=bp.nu, dt=bp.dt, n_slices=P, pfasst_tol=1e-10, pfasst_max_iter=1000)
           for bp in probs]
-    say(f"C4: sizes {sorted(set(bp.n for bp in probs))}, {sum(bp.n ** 3 for bp in probs) / 1e6:.1f} M DOF per slice")
+    say(f"64 uneven problems: sizes {sorted(set(bp.n for bp in probs))}, {sum(bp.n ** 3 for bp in probs) / 1e6:.1f} M DOF per slice")
     b = pf.Batch(ps)
     st, its, res = b.run([bp.u0 for bp in probs])
     say(f"  iterations min {its.min()} max {its.max()} mean {its.mean():.1f}; worst residual {res.max():.2e}")

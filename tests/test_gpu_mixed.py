@@ -71,7 +71,7 @@ def test_mixed_converged_matches_fp64_oracle(pf, n, P, sm):
     assert max(errs) <= 1e-9
 
 
-def test_c3_mixed_full_size_per_slice_error(pf):
+def test_mixed_255x16_per_slice_error(pf):
     """255^3, 16 slices, dt = 1e-3, seed 1408: mixed and FP64 reach 1e-10 in
     the same number of iterations; per-slice error against the collocation
     closed form is reported and bounded."""
@@ -80,7 +80,7 @@ def test_c3_mixed_full_size_per_slice_error(pf):
     u0, modes = inputs.random_fourier(n, 1408)
     out = {}
     for prec in ("mixed",):
-        say(f"C3 {prec}")
+        say(f"255^3 x 16 slices, {prec}")
         c = pf.Context(pf.pfmg_default_params(dim=3, n=n, n_slices=P, precision=pf.MIXED,
                                                pfasst_tol=1e-10, pfasst_max_iter=600))
         st, iters, res = c.run_block(u0)

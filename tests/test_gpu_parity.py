@@ -157,10 +157,10 @@ def compare_state(c, orc, P, two_levels=True, tol=TOL):
                     assert pins.rel_err(c.get(O.TAU, p, m), t_or) <= 1e-10, ("tau", p, m)
 
 
-def test_c1_predictor_and_five_iterations_match_oracle(pf):
+def test_heat1d_127_predictor_and_five_iterations_match_oracle(pf):
     """1D heat, N=127, P=4, dt=0.01, 5/3 Lobatto, coarse N=63, weighted
     Jacobi 2/3 V(2,2), one V-cycle per solve, predictor + 5 iterations."""
-    say("C1 parity")
+    say("1D heat n=127, 4 slices: predictor + 5 iterations")
     n, P, nu, dt = 127, 4, 1.0, 0.01
     c = make(pf, dim=1, n=n, n_slices=P, nu=nu, dt=dt, smoother=pf.SMOOTH_JACOBI, omega=2 / 3)
     orc = O.Pfasst(1, n, nu, dt, P, 5, 3, O.policy(smoother=O.JACOBI, omega=2 / 3, cycles=1))
@@ -209,8 +209,8 @@ def test_single_level_isdc_matches_oracle(pf):
     compare_state(c, orc, P, two_levels=False)
 
 
-def test_c1_converges_to_pade_closed_form(pf):
-    say("C1 to convergence")
+def test_heat1d_127_converges_to_pade_closed_form(pf):
+    say("1D heat n=127, 4 slices: to convergence")
     g = pins.golden("lobatto_iiia.json")
     n, P, nu, dt = 127, 4, 1.0, 0.01
     c = make(pf, dim=1, n=n, n_slices=P, nu=nu, dt=dt, smoother=pf.SMOOTH_JACOBI, omega=2 / 3,
@@ -224,11 +224,11 @@ def test_c1_converges_to_pade_closed_form(pf):
         assert pins.rel_err(c.get(O.UF, p, 4), want) <= 1e-11
 
 
-def test_c2_full_size_first_iteration_matches_oracle(pf):
+def test_heat3d_127x16_first_iteration_matches_oracle(pf):
     """127^3, 16 slices, dt = 1e-3, RB-GS V(2,2), one V-cycle per solve:
     predictor + one iteration, compared element by element (the launch
     configuration the benchmark times)."""
-    say("C2 full size parity: predictor + 1 iteration")
+    say("127^3 x 16 slices: predictor + 1 iteration")
     n, P = 127, 16
     c = make(pf, dim=3, n=n, n_slices=P)
     orc = O.Pfasst(3, n, 1.0, 1e-3, P, 5, 3, O.policy(cycles=1))
@@ -243,10 +243,10 @@ def test_c2_full_size_first_iteration_matches_oracle(pf):
         assert pins.rel_err(c.get(O.UC, p, 2), orc.field(O.UC, p, 2)) <= TOL
 
 
-def test_c2_full_size_converges_to_collocation_closed_form(pf):
+def test_heat3d_127x16_converges_to_collocation_closed_form(pf):
     """At convergence every slice's end value is sum_j a_j R44(z_j)^(p+1) phi_j
     (Lobatto IIIA), a property that holds at any size."""
-    say("C2 full size to 1e-10")
+    say("127^3 x 16 slices: to 1e-10")
     g = pins.golden("lobatto_iiia.json")
     n, P, nu, dt = 127, 16, 1.0, 1e-3
     c = make(pf, dim=3, n=n, n_slices=P)

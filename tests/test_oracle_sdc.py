@@ -128,8 +128,8 @@ def test_pfasst_converges_to_composite_collocation(dim, n, P, cyc):
             assert pins.rel_err(pf.field(O.UF, p, m).ravel(), Us[p][m]) <= 1e-11
 
 
-def test_c1_end_values_match_pade_closed_form():
-    """C1 (1D, N=127, P=4, dt=0.01, 5/3 Lobatto, Jacobi 2/3 V(2,2), one
+def test_heat1d_127_end_values_match_pade_closed_form():
+    """The 1D case (N=127, P=4, dt=0.01, 5/3 Lobatto, Jacobi 2/3 V(2,2), one
     V-cycle per solve) iterated to convergence: each slice's end value is
     sum_j a_j R44(dt nu mu_j)^(p+1) phi_j, R44 the (4,4) Pade approximant
     (Lobatto IIIA, eq. BT)."""

@@ -89,11 +89,13 @@ hipError_t resid_norm(const Tiling &t, double alpha, View<double> b, View<double
 // ------------------------------------------------------------ method ops
 // F = nu L_h u
 hipError_t apply_L(const Tiling &t, double nu, View<double> u, View<double> F, hipStream_t s);
-// z-marching F = c L_h u (3D, 31 <= n <= 255, at least 2^21 points in the
-// launch; u and F must not overlap); apply_L takes it wherever
-// apply_L_z_ok holds.
-bool apply_L_z_ok(const Tiling &t);
+// z-marching F = c L_h u and omega-Jacobi sweep (3D, 31 <= n <= 255, at
+// least 2^20 points in the launch; input and output must not overlap);
+// apply_L and jacobi take them wherever stencil_z_ok holds.
+bool stencil_z_ok(const Tiling &t);
 hipError_t apply_L_z(const Tiling &t, double c, View<double> u, View<double> F, hipStream_t s);
+template <typename T>
+hipError_t jacobi_z(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, View<T> out, hipStream_t s);
 // Node stacks: a view's field q points at node 0 of a slice; node m sits
 // m slot strides (node_stride of the grid) further.
 // I[m] = dt sum_i S[m][i] F[i], m = 0..nn-2, per slice (item = slice).

@@ -539,6 +539,7 @@ hipError_t resid_round(const Tiling &t, double alpha, View<double> b, View<doubl
 template <typename T>
 hipError_t jacobi(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, View<T> out, hipStream_t s)
 {
+    if (stencil_z_ok(t)) return jacobi_z(t, alpha, omega, b, u, out, s);
     if (grid_blocks(t) == 0) return hipSuccess;
     if (t.dim == 3) return launch(jacobi_kz_kernel<T>, col_grid(t), dim3(BLOCK), 0, s, t, alpha, omega, b, u, out);
     jacobi_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, alpha, omega, b, u, out);

@@ -311,7 +311,7 @@ namespace k {
 
 hipError_t apply_L(const Tiling &t, double nu, View<double> u, View<double> F, hipStream_t s)
 {
-    if (apply_L_z_ok(t)) return apply_L_z(t, nu, u, F, s);
+    if (stencil_z_ok(t)) return apply_L_z(t, nu, u, F, s);
     if (t.dim == 3 && grid_blocks(t) > 0) {
         apply_L_kz_kernel<<<(unsigned)col_blocks<KZ>(t), BLOCK, 0, s>>>(t, nu, u, F);
         return hipGetLastError();

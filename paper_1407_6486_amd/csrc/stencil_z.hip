@@ -1,15 +1,18 @@
-// F = c L_h u in one z-marching pass (3D, 31 <= n <= 255): the F = nu L_h U
-// of every node after its solve and after the spatial interpolation of
-// PFASST (Sec. 2.4).
+// Out-of-place 7-point stencils in one z-marching pass (3D, 31 <= n <= 255):
+//   F = c L_h u: the F = nu L_h U of every node after its solve and after
+//     the spatial interpolation of PFASST (Sec. 2.4), 16 bytes per point;
+//   u' = u + w (b - (u - ah L u)): one omega-Jacobi sweep of the V-cycle
+//     (Sec. 4.1.1, w = omega / (1 + 6 ah), ah = alpha (n+1)^2), 24 bytes
+//     per point.
 //
 // A workgroup owns full x-rows, TY output rows and a chunk of z planes and
 // marches upwards in z.  At step k the rows j0-1 .. j0+TY of plane k go into
-// one of three LDS buffers and F is computed on plane k-1 from the x and y
-// neighbours in LDS and the z neighbours in registers; u is read once (plus
-// the halo rows that neighbouring tiles also read) and F written once:
-// 16 bytes per point in FP64.  The loads of step k + 1 are issued before
-// step k's arithmetic.  The arithmetic per point is that of the
-// column-blocked kernel it replaces.
+// one of three LDS buffers and the output is computed on plane k-1 from the
+// x and y neighbours in LDS and the z neighbours in registers; u is read
+// once (plus the halo rows that neighbouring tiles also read) and the output
+// written once.  The loads of step k + 1 are issued before step k's
+// arithmetic.  The arithmetic per point is that of the column-blocked
+// kernels they replace.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,16 +25,17 @@ namespace {
 constexpr int TY = 4;   // output rows per workgroup
 
 // RLN: x lanes per row; Q = ceil((TY + 2) / (BLOCK / RLN)) rows per thread.
-template <int RLN, int Q>
-__global__ __launch_bounds__(BLOCK) void apply_L_z_kernel(Tiling t, int zchunk, double c, View<double> u,
-                                                          View<double> F)
+// JAC: Jacobi sweep (b read, c = alpha, omega given) instead of F = c L u.
+template <typename T, int RLN, int Q, bool JAC>
+__global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, double c, double omega, View<T> b,
+                                                          View<T> u, View<T> F)
 {
     constexpr int RL = RLN + 2;
     constexpr int RPP = BLOCK / RLN;
     constexpr int ROWS = TY + 2;             // rows j0-1 .. j0+TY
     static_assert(Q * RPP >= ROWS, "rows per thread");
     extern __shared__ unsigned char smem_raw[];
-    double *lp = reinterpret_cast<double *>(smem_raw);   // 3 planes of ROWS rows
+    T *lp = reinterpret_cast<T *>(smem_raw);             // 3 planes of ROWS rows
 
     unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
     Pt qs;
@@ -48,6 +52,8 @@ __global__ __launch_bounds__(BLOCK) void apply_L_z_kernel(Tiling t, int zchunk, 
     if (mask && !mask[item]) return;
     qs.item = item;
     const double cc = qs.par(c), ih2 = (double)(n + 1) * (double)(n + 1);
+    const double ahd = cc * (double)(n + 1) * (double)(n + 1);
+    const T ah = (T)ahd, winv = (T)(omega / (1.0 + 2.0 * 3 * ahd));
     const int j0 = jt * TY + 1, k0 = zc * zchunk + 1;
     const int k1 = min(k0 + zchunk, n + 1);  // F on planes k0 .. k1-1
     const int i = (int)(threadIdx.x % RLN) + 1;
@@ -55,40 +61,47 @@ __global__ __launch_bounds__(BLOCK) void apply_L_z_kernel(Tiling t, int zchunk, 
     const bool xin = i <= n;
     // element offsets inside one field fit in 32 bits (n <= 255)
     const int sy = (int)row_stride(n), sz = (int)plane_stride(n);
-    const double *__restrict__ U = fp(u, qs);
-    double *__restrict__ Fo = fp(F, qs);
+    const T *__restrict__ U = fp(u, qs);
+    const T *__restrict__ Bv = JAC ? fp(b, qs) : nullptr;
+    T *__restrict__ Fo = fp(F, qs);
 
-    for (int r = threadIdx.x; r < 3 * ROWS; r += BLOCK) lp[r * RL] = 0.0;
+    for (int r = threadIdx.x; r < 3 * ROWS; r += BLOCK) lp[r * RL] = (T)0;
 
     auto inside = [&](int j, int k) { return xin && j >= 1 && j <= n && k >= 1 && k <= n; };
-    double pu[Q];
+    // pu: u plane k + 1 (prefetched); pb: b plane k, used at step k + 1
+    T pu[Q], pb[Q], bk[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int r = rsub + q * RPP, j = j0 - 1 + r;
-        pu[q] = (r < ROWS && inside(j, k0 - 1)) ? U[i + j * sy + (k0 - 1) * sz] : 0.0;
+        pu[q] = (r < ROWS && inside(j, k0 - 1)) ? U[i + j * sy + (k0 - 1) * sz] : (T)0;
+        pb[q] = bk[q] = (T)0;
     }
-    double wm2[Q], wm1[Q];
+    T wm2[Q], wm1[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) wm2[q] = wm1[q] = 0.0;
+    for (int q = 0; q < Q; ++q) wm2[q] = wm1[q] = (T)0;
 
     for (int k = k0 - 1; k <= k1; ++k) {
-        double uk[Q];
+        T uk[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) uk[q] = pu[q];
+        for (int q = 0; q < Q; ++q) {
+            uk[q] = pu[q];
+            bk[q] = pb[q];   // b on plane k - 1
+        }
         if (k < k1) {
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int r = rsub + q * RPP, j = j0 - 1 + r;
-                pu[q] = (r < ROWS && inside(j, k + 1)) ? U[i + j * sy + (k + 1) * sz] : 0.0;
+                pu[q] = (r < ROWS && inside(j, k + 1)) ? U[i + j * sy + (k + 1) * sz] : (T)0;
+                if (JAC) pb[q] = (r >= 1 && r <= TY && inside(j, k)) ? Bv[i + j * sy + k * sz] : (T)0;
             }
         }
         // ---- u plane k -> LDS
-        double wn[Q];
-        double *buf = lp + (k % 3 + 3) % 3 * ROWS * RL;
+        T wn[Q];
+        T *buf = lp + (k % 3 + 3) % 3 * ROWS * RL;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int r = rsub + q * RPP, j = j0 - 1 + r;
-            const double v = (r < ROWS && inside(j, k)) ? uk[q] : 0.0;
+            const T v = (r < ROWS && inside(j, k)) ? uk[q] : (T)0;
             wn[q] = v;
             if (r < ROWS) buf[r * RL + i] = v;
         }
@@ -97,16 +110,21 @@ __global__ __launch_bounds__(BLOCK) void apply_L_z_kernel(Tiling t, int zchunk, 
         // rewritten before every thread has passed the next barrier)
         const int kb = k - 1;
         if (kb >= k0 && kb < k1) {
-            const double *bb = lp + (kb % 3 + 3) % 3 * ROWS * RL;
+            const T *bb = lp + (kb % 3 + 3) % 3 * ROWS * RL;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int r = rsub + q * RPP, j = j0 - 1 + r;
                 if (r >= 1 && r <= TY && j <= n && xin) {
-                    const double *row = bb + r * RL;
-                    double s = row[i - 1] + row[i + 1];
+                    const T *row = bb + r * RL;
+                    T s = row[i - 1] + row[i + 1];
                     s += (bb[(r - 1) * RL + i] + bb[(r + 1) * RL + i]) + (wm2[q] + wn[q]);
-                    s -= 6.0 * wm1[q];
-                    Fo[i + j * sy + kb * sz] = cc * (ih2 * s);
+                    s -= (T)6 * wm1[q];
+                    if (JAC) {
+                        const T res = bk[q] - (wm1[q] - ah * s);
+                        Fo[i + j * sy + kb * sz] = wm1[q] + winv * res;
+                    } else {
+                        Fo[i + j * sy + kb * sz] = (T)(cc * (ih2 * (double)s));
+                    }
                 }
             }
         }
@@ -124,7 +142,7 @@ namespace k {
 
 // Small launches (a single 63^3 field of the coarse chain) take the
 // column-blocked kernel: with few workgroups the z march is latency-bound.
-bool apply_L_z_ok(const Tiling &t)
+bool stencil_z_ok(const Tiling &t)
 {
     if (t.dim != 3) return false;
     long points = 0;
@@ -132,12 +150,13 @@ bool apply_L_z_ok(const Tiling &t)
         if (t.seg_count(sg) > 0 && (t.seg_n(sg) < 31 || t.seg_n(sg) > 255)) return false;
         points += (long)t.seg_count(sg) * t.seg_n(sg) * t.seg_n(sg) * t.seg_n(sg);
     }
-    return points >= (1L << 21);
+    return points >= (1L << 20);
 }
 
-hipError_t apply_L_z(const Tiling &t, double c, View<double> u, View<double> F, hipStream_t s)
+template <typename T, bool JAC>
+hipError_t stencil_z(const Tiling &t, double c, double omega, View<T> b, View<T> u, View<T> F, hipStream_t s)
 {
-    if (!apply_L_z_ok(t)) return hipErrorInvalidValue;
+    if (!stencil_z_ok(t)) return hipErrorInvalidValue;
     int nmax = 0;
     long rows_total = 0;
     for (int sg = 0; sg < t.nseg; ++sg) {
@@ -154,12 +173,28 @@ hipError_t apply_L_z(const Tiling &t, double c, View<double> u, View<double> F, 
         blocks += (long)t.seg_count(sg) * ((n + TY - 1) / TY) * ((n + zchunk - 1) / zchunk);
     }
     const int rln = nmax <= 64 ? 64 : nmax <= 128 ? 128 : 256;
-    const size_t lds = (size_t)3 * (TY + 2) * (rln + 2) * sizeof(double);
+    const size_t lds = (size_t)3 * (TY + 2) * (rln + 2) * sizeof(T);
     const dim3 g((unsigned)blocks), blk(BLOCK);
-    if (rln == 64) return launch(apply_L_z_kernel<64, 2>, g, blk, lds, s, t, zchunk, c, u, F);
-    if (rln == 128) return launch(apply_L_z_kernel<128, 3>, g, blk, lds, s, t, zchunk, c, u, F);
-    return launch(apply_L_z_kernel<256, 6>, g, blk, lds, s, t, zchunk, c, u, F);
+    if (rln == 64) return launch(stencil_z_kernel<T, 64, 2, JAC>, g, blk, lds, s, t, zchunk, c, omega, b, u, F);
+    if (rln == 128) return launch(stencil_z_kernel<T, 128, 3, JAC>, g, blk, lds, s, t, zchunk, c, omega, b, u, F);
+    return launch(stencil_z_kernel<T, 256, 6, JAC>, g, blk, lds, s, t, zchunk, c, omega, b, u, F);
 }
+
+hipError_t apply_L_z(const Tiling &t, double c, View<double> u, View<double> F, hipStream_t s)
+{
+    return stencil_z<double, false>(t, c, 0.0, View<double>{nullptr, 0}, u, F, s);
+}
+
+template <typename T>
+hipError_t jacobi_z(const Tiling &t, double alpha, double omega, View<T> b, View<T> u, View<T> out, hipStream_t s)
+{
+    return stencil_z<T, true>(t, alpha, omega, b, u, out, s);
+}
+
+template hipError_t jacobi_z<double>(const Tiling &, double, double, View<double>, View<double>, View<double>,
+                                     hipStream_t);
+template hipError_t jacobi_z<float>(const Tiling &, double, double, View<float>, View<float>, View<float>,
+                                    hipStream_t);
 
 }  // namespace k
 }  // namespace pfmg

@@ -177,7 +177,7 @@ def test_heat1d_127_predictor_and_five_iterations_match_oracle(pf):
 
 
 @pytest.mark.parametrize("n,P,sm,cycles", [(31, 4, "rb", 1), (15, 16, "rb", 2), (63, 2, "jac", 1), (3, 2, "rb", 1),
-                                           (15, 3, "rb", 0)])
+                                           (15, 3, "rb", 0), (127, 2, "jac", 1)])
 def test_pfasst_3d_matches_oracle(pf, n, P, sm, cycles):
     say(f"PFASST 3D n={n} P={P} smoother={sm} cycles={cycles}")
     psm, osm, om = smoother_args(pf, sm)

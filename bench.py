@@ -28,6 +28,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense
+
+
+def stamped_roofline(ctx, u0, family, n):
+    """One more block with the launches of kernel family `family` at grid n
+    bracketed by dispatch-stamped events: algorithmic bytes per launch over
+    the average launch duration."""
+    ctx.timing_enable(f"{family}@{n}", True)
+    ctx.run_block(u0)
+    launches, ms, nbytes = ctx.timing_read()
+    ctx.timing_enable(None, False)
+    if launches == 0 or ms <= 0:
+        return None
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"{family}@{n}",
+            "launches": launches, "avg_launch_us": round(ms * 1e3 / launches, 2), "bytes_per_launch": nbytes / launches}
 
 
 def parse():
@@ -139,7 +156,7 @@ def form_mixed(pfmg, a):
         for _ in range(a.warmup):
             c.run_block(u0)
         t, outs = _time_blocks(lambda: c.run_block(u0), a.steps)
-        res[prec] = (t, outs[-1][1], outs[-1][2])
+        res[prec] = (t, outs[-1][1], outs[-1][2], stamped_roofline(c, u0, "rbgs", n))
         c.close()
         del c
         torch.cuda.empty_cache()
@@ -148,6 +165,7 @@ def form_mixed(pfmg, a):
             "speedup_vs_plain": round(res["fp64"][0] / res["mixed"][0], 3),
             "iterations": {"mixed": res["mixed"][1], "fp64": res["fp64"][1]},
             "final_residual": {"mixed": res["mixed"][2], "fp64": res["fp64"][2]},
+            "roofline": res["mixed"][3], "roofline_fp64_path": res["fp64"][3],
             "higher_is_better": False, "dtype": "f64+f32", "data": "synthetic", "n_gpus": 1, "steps": a.steps,
             "config": {"workload": "3D heat, 255^3, 16 slices, dt=1e-3, Lobatto 5/3, rbgs V(2,2), 1 V-cycle/solve, "
                                    "seed 1408"}}
@@ -172,6 +190,28 @@ def form_batched(pfmg, a):
     b.close()
     del b
     torch.cuda.empty_cache()
+    # the batch's dominant sweeps (launches whose largest grid is 127^3),
+    # timed on a block of 6 iterations in which no problem stops early, so
+    # that every launch covers all fields (the byte count assumes it)
+    pr = [pfmg.pfmg_default_params(n=bp.n, nu=bp.nu, dt=bp.dt, n_slices=4, pfasst_tol=0.0, pfasst_max_iter=6)
+          for bp in probs]
+    b = pfmg.Batch(pr)
+    b.run(u0s)
+    b.timing_enable("rbgs@127", True)
+    b.run(u0s)
+    nl, ms, nbytes = b.timing_read()
+    b.timing_enable(None, False)
+    roof = None
+    if nl and ms > 0:
+        ach = nbytes / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "rbgs@127 (multi-segment one-pass sweeps led by the 127^3 problems; 6-iteration block, "
+                          "no problem frozen)", "launches": nl,
+                "avg_launch_us": round(ms * 1e3 / nl, 2), "bytes_per_launch": nbytes / nl}
+    b.close()
+    del b
+    torch.cuda.empty_cache()
     ctxs = [pfmg.Context(p) for p in ps]
     for c, u in zip(ctxs, u0s):
         c.run_block(u)
@@ -183,6 +223,7 @@ def form_batched(pfmg, a):
             "form": "batched (64 uneven problems, shared multi-segment launches, graphs)",
             "plain_value": round(tl, 4), "plain": "loop over 64 single contexts",
             "speedup_vs_plain": round(tl / tb, 3), "iterations_min_max": [int(its.min()), int(its.max())],
+            "roofline": roof,
             "higher_is_better": False, "dtype": "f64", "data": "synthetic", "n_gpus": 1, "steps": a.steps,
             "config": {"workload": f"64 problems, n in {{31,63,95,127}}, {dof / 1e6:.1f} M DOF per slice, P=4, "
                                    "nu 10^U(-1,1), dt 10^U(-4,-2), seeds [6486, q]"}}
@@ -211,6 +252,11 @@ def form_learned(pfmg, a):
             "loss_first_last": [float(np.mean(losses[:50])), float(np.mean(losses[-50:]))],
             "inference_ms_16x127": round(t_inf * 1e3, 2),
             "inference_tflops": round(L.flops_per_voxel() * 127 ** 3 * 16 / t_inf / 1e12, 1),
+            "roofline": {"bound": "mfma", "kernel": "network forward, 16 x 127^3 (BF16 MFMA, FP32 accumulate)",
+                         "achieved": round(L.flops_per_voxel() * 127 ** 3 * 16 / t_inf / 1e12, 1),
+                         "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(L.flops_per_voxel() * 127 ** 3 * 16 / t_inf / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4),
+                         "traffic": None},
             "higher_is_better": False, "dtype": "f64 solver, bf16 network", "data": "synthetic", "n_gpus": 1,
             "config": {"workload": "train 63^3 (seeds [20000, r], dt 10^U(-3,-2), P=4); evaluate 127^3, 16 slices, "
                                    "dt=1e-3, seed 1407, full solves to 1e-12"}}

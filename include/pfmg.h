@@ -200,10 +200,14 @@ pfmg_status pfmg_set(pfmg_ctx *ctx, int32_t field, int32_t slice, int32_t node,
 pfmg_status pfmg_vcycle_count(pfmg_ctx *ctx, int32_t level, int64_t *count_out);
 
 /* Kernel timing for measurement: while enabled, every launch of the named
- * kernel family is bracketed by HIP events on the context's stream.
- * pfmg_timing_read returns the launches recorded, their summed duration in
- * milliseconds and the algorithmic bytes they move (interior points times
- * the per-point byte count of the kernel). */
+ * kernel family ("<family>@<n>", e.g. "rbgs@127", "vcycle@127") is
+ * bracketed by HIP events on the context's stream; the smoother's launches
+ * carry events that the dispatch itself stamps (hipExtLaunchKernel), the
+ * others events recorded around them.  Blocks run launch by launch (no
+ * graph replay) while timing is on.  pfmg_timing_read returns the launches
+ * recorded, their summed duration in milliseconds and the algorithmic bytes
+ * they move (interior points times the per-point byte count of the kernel).
+ * Enabling resets the counters; both calls synchronise the stream. */
 pfmg_status pfmg_timing_enable(pfmg_ctx *ctx, const char *kernel, int32_t enable);
 pfmg_status pfmg_timing_read(pfmg_ctx *ctx, int64_t *launches, double *ms_total,
                              double *bytes_total);
@@ -253,6 +257,12 @@ pfmg_status pfmg_batch_get(pfmg_batch *b, int32_t problem, int32_t field, int32_
 /* V-cycles run by node solves on level 0 / 1, summed over problems and
  * slices. */
 pfmg_status pfmg_batch_vcycle_count(pfmg_batch *b, int32_t level, int64_t *count_out);
+/* Launch timing as pfmg_timing_enable / pfmg_timing_read, for the batch's
+ * one-pass red-black sweeps: family "rbgs@<n>", n the largest grid of a
+ * multi-segment launch; the bytes count every segment's points. */
+pfmg_status pfmg_batch_timing_enable(pfmg_batch *b, const char *kernel, int32_t enable);
+pfmg_status pfmg_batch_timing_read(pfmg_batch *b, int64_t *launches, double *ms_total,
+                                   double *bytes_total);
 
 /* Red-black launch-shape autotuner: the number of configurations in the
  * process-wide table, and the entry for a key ("<arch>/rbgs/<f64|f32>/"

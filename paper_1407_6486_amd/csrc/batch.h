@@ -76,6 +76,8 @@ struct BatchSolver {
     hipStream_t cap = nullptr;
     hipGraphExec_t g_iter = nullptr, g_start = nullptr;
     bool warm_iter = false, warm_start = false;
+    Timer timer;                       // launch timing (blocks run eagerly while on)
+    bool use_graph() const { return graphs && !timer.on; }
 
     static bool validate(const pfmg_params *pp, int np, std::string &why);
     bool init_host(const pfmg_params *pp, int np, std::string &why);   // groups, tables

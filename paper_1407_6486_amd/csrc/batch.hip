@@ -378,9 +378,15 @@ hipError_t BatchSolver::smooth(const std::vector<Leg<T>> &legs, int sweeps, bool
         RbPlan plan;
         if (fusable) plan = rb_plan<T>(t, 0.0, om, b, u, tmp, s, pts >= fused_min_points);
         if (plan.fused) {
+            // timing family "rbgs@<largest n of the launch>"
+            int nmax = 0;
+            for (int w = 0; w < ns; ++w) nmax = std::max(nmax, x[w].n);
             View<T> src = u, dst = tmp;
             for (int q = 0; q < sweeps; ++q) {
-                HC(k::rbgs_fused(t, 0.0, om, q == 0 && from_zero, b, src, dst, s, &plan.shape));
+                timer.start("rbgs", nmax, 3.0 * sizeof(T), pts, true, s);
+                const hipError_t e = k::rbgs_fused(t, 0.0, om, q == 0 && from_zero, b, src, dst, s, &plan.shape);
+                timer.stop(s);
+                HC(e);
                 std::swap(src, dst);
             }
             if (src.p != u.p) HC(k::copy(t, src, u, s));
@@ -763,7 +769,7 @@ hipError_t BatchSolver::set_initial(const double *u0, bool on_device)
     res.assign(NP, INFINITY);
     iters.assign(NP, 0);
     nan = false;
-    if (graphs && warm_start) {
+    if (use_graph() && warm_start) {
         if (!g_start) HC(capture([this] { return spread_body(); }, &g_start));
         HC(hipGraphLaunch(g_start, s));
     } else {
@@ -803,7 +809,7 @@ hipError_t BatchSolver::iterate()
     }
     long act_items = 0;
     for (int q = 0; q < NP; ++q) act_items += active[q] ? P : 0;
-    if (graphs && warm_iter) {
+    if (use_graph() && warm_iter) {
         if (!g_iter) HC(capture([this] { return iterate_body(); }, &g_iter));
         HC(hipGraphLaunch(g_iter, s));
     } else {

@@ -139,7 +139,7 @@ pfmg_status pfmg_destroy(pfmg_ctx *ctx)
     pfmg::Solver &sv = ctx->sv;
     (void)hipStreamSynchronize(sv.s);
     sv.release_graphs();
-    for (hipEvent_t ev : sv.timer.ev) (void)hipEventDestroy(ev);
+    sv.timer.release();
     if (sv.hbits) (void)hipHostFree(sv.hbits);
     if (sv.hmask) (void)hipHostFree(sv.hmask);
     if (sv.hnnsc) (void)hipHostFree(sv.hnnsc);
@@ -303,39 +303,19 @@ pfmg_status pfmg_vcycle_count(pfmg_ctx *ctx, int32_t level, int64_t *count_out)
 pfmg_status pfmg_timing_enable(pfmg_ctx *ctx, const char *kernel, int32_t enable)
 {
     if (!ctx) return fail(PFMG_ERR_ARG, "null context");
-    pfmg::Solver &sv = ctx->sv;
-    pfmg::Timer &t = sv.timer;
-    HIPCALL(hipStreamSynchronize(sv.s), "timing");
-    t.on = enable != 0;
-    t.used = 0;
-    t.depth = 0;
-    t.open = -1;
-    t.bytes = 0;
-    t.launches = 0;
-    if (!t.on) return PFMG_OK;
-    if (!kernel) return fail(PFMG_ERR_ARG, "kernel name required");
-    t.key = kernel;
-    if (t.ev.empty()) {
-        t.ev.resize(1 << 16);
-        for (auto &ev : t.ev) HIPCALL(hipEventCreate(&ev), "event");
-    }
+    HIPCALL(hipStreamSynchronize(ctx->sv.s), "timing");
+    if (enable && !kernel) return fail(PFMG_ERR_ARG, "kernel name required");
+    HIPCALL(ctx->sv.timer.enable(kernel, enable != 0), "timing events");
     return PFMG_OK;
 }
 
 pfmg_status pfmg_timing_read(pfmg_ctx *ctx, int64_t *launches, double *ms_total, double *bytes_total)
 {
     if (!ctx) return fail(PFMG_ERR_ARG, "null context");
-    pfmg::Timer &t = ctx->sv.timer;
     HIPCALL(hipStreamSynchronize(ctx->sv.s), "timing");
-    double ms = 0;
-    for (size_t q = 0; q + 1 < t.used; q += 2) {
-        float e = 0;
-        HIPCALL(hipEventElapsedTime(&e, t.ev[q], t.ev[q + 1]), "elapsed");
-        ms += e;
-    }
-    if (launches) *launches = t.launches;
-    if (ms_total) *ms_total = ms;
-    if (bytes_total) *bytes_total = t.bytes;
+    long long nl = 0;
+    HIPCALL(ctx->sv.timer.read(&nl, ms_total, bytes_total), "elapsed");
+    if (launches) *launches = nl;
     return PFMG_OK;
 }
 
@@ -392,6 +372,7 @@ pfmg_status pfmg_batch_destroy(pfmg_batch *b)
     pfmg::BatchSolver &bs = b->bs;
     (void)hipStreamSynchronize(bs.s);
     bs.release();
+    bs.timer.release();
     if (bs.hbits) (void)hipHostFree(bs.hbits);
     if (bs.hact) (void)hipHostFree(bs.hact);
     delete b;
@@ -449,6 +430,25 @@ pfmg_status pfmg_batch_get(pfmg_batch *b, int32_t problem, int32_t field, int32_
     if (slice < 0 || slice >= bs.P || node < 0 || node >= bs.nn[coarse ? 1 : 0])
         return fail(PFMG_ERR_ARG, "bad slice or node");
     HIPCALL(bs.get(problem, field, slice, node, dst, on_device != 0), "batch get");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_batch_timing_enable(pfmg_batch *b, const char *kernel, int32_t enable)
+{
+    if (!b) return fail(PFMG_ERR_ARG, "null batch");
+    HIPCALL(hipStreamSynchronize(b->bs.s), "timing");
+    if (enable && !kernel) return fail(PFMG_ERR_ARG, "kernel name required");
+    HIPCALL(b->bs.timer.enable(kernel, enable != 0), "timing events");
+    return PFMG_OK;
+}
+
+pfmg_status pfmg_batch_timing_read(pfmg_batch *b, int64_t *launches, double *ms_total, double *bytes_total)
+{
+    if (!b) return fail(PFMG_ERR_ARG, "null batch");
+    HIPCALL(hipStreamSynchronize(b->bs.s), "timing");
+    long long nl = 0;
+    HIPCALL(b->bs.timer.read(&nl, ms_total, bytes_total), "elapsed");
+    if (launches) *launches = nl;
     return PFMG_OK;
 }
 

@@ -34,6 +34,12 @@ struct PLevel {
 
 struct UNet;
 
+// Launch timing for one kernel family: brackets nest (a whole V-cycle
+// contains its smoother launches); only the bracket whose family matches
+// the enabled key records events, and its stop is the one at the same
+// nesting depth.  A stamped bracket covers exactly one launch made through
+// launch(): its events are stamped by that dispatch itself; if no such
+// launch consumed them (an empty launch), the bracket is dropped.
 struct Timer {
     std::string key;                  // kernel family "@" grid n, e.g. "rbgs@127"
     bool on = false;
@@ -45,6 +51,11 @@ struct Timer {
     double added = 0;                 // bytes the open bracket added
     double bytes = 0;
     long long launches = 0;
+    void start(const char *fam, int n, double bytes_per_point, long points, bool stamped_launch, hipStream_t s);
+    void stop(hipStream_t s);
+    hipError_t enable(const char *kernel, bool enable);          // resets the counters
+    hipError_t read(long long *nl, double *ms, double *nbytes);  // stream already synchronised
+    void release();
 };
 
 struct Solver {

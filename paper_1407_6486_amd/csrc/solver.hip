@@ -252,45 +252,86 @@ hipError_t Solver::upload_constants()
 }
 
 // ------------------------------------------------------------------ timing
-// Brackets nest (a whole V-cycle contains its smoother launches); only the
-// bracket whose family matches the enabled key records events, and its stop
-// is the tstop at the same nesting depth.
-// A stamped bracket covers exactly one launch made through launch(): its
-// events are stamped by that dispatch itself; if no such launch consumed
-// them (an empty launch), the bracket is dropped.
-void Solver::tstart(const char *fam, int n, double bytes_per_point, long points, bool stamped)
+void Timer::start(const char *fam, int n, double bytes_per_point, long points, bool stamped_launch, hipStream_t s)
 {
-    const int d = timer.depth++;
-    if (!timer.on || timer.open >= 0) return;
-    if (timer.key != std::string(fam) + "@" + std::to_string(n) || timer.used + 2 > timer.ev.size()) return;
-    timer.stamped = stamped;
-    timer.added = bytes_per_point * (double)points;
-    if (stamped) armed_events = {timer.ev[timer.used], timer.ev[timer.used + 1]};
-    else (void)hipEventRecord(timer.ev[timer.used], s);
-    timer.bytes += timer.added;
-    timer.launches += 1;
-    timer.used += 1;
-    timer.open = d;
+    const int d = depth++;
+    if (!on || open >= 0) return;
+    if (key != std::string(fam) + "@" + std::to_string(n) || used + 2 > ev.size()) return;
+    stamped = stamped_launch;
+    added = bytes_per_point * (double)points;
+    if (stamped) armed_events = {ev[used], ev[used + 1]};
+    else (void)hipEventRecord(ev[used], s);
+    bytes += added;
+    launches += 1;
+    used += 1;
+    open = d;
 }
 
-void Solver::tstop()
+void Timer::stop(hipStream_t s)
 {
-    const int d = --timer.depth;
-    if (timer.open != d) return;
-    timer.open = -1;
-    if (timer.stamped) {
+    const int d = --depth;
+    if (open != d) return;
+    open = -1;
+    if (stamped) {
         if (armed_events.start) {              // nothing was launched
             armed_events = {};
-            timer.used -= 1;
-            timer.launches -= 1;
-            timer.bytes -= timer.added;
+            used -= 1;
+            launches -= 1;
+            bytes -= added;
             return;
         }
     } else {
-        (void)hipEventRecord(timer.ev[timer.used], s);
+        (void)hipEventRecord(ev[used], s);
     }
-    timer.used += 1;
+    used += 1;
 }
+
+hipError_t Timer::enable(const char *kernel, bool en)
+{
+    on = en;
+    used = 0;
+    depth = 0;
+    open = -1;
+    bytes = 0;
+    launches = 0;
+    if (!on) return hipSuccess;
+    if (!kernel) return hipErrorInvalidValue;
+    key = kernel;
+    if (ev.empty()) {
+        ev.resize(1 << 16);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+    }
+    return hipSuccess;
+}
+
+hipError_t Timer::read(long long *nl, double *ms, double *nbytes)
+{
+    double tot = 0;
+    for (size_t q = 0; q + 1 < used; q += 2) {
+        float e = 0;
+        const hipError_t r = hipEventElapsedTime(&e, ev[q], ev[q + 1]);
+        if (r != hipSuccess) return r;
+        tot += e;
+    }
+    if (nl) *nl = launches;
+    if (ms) *ms = tot;
+    if (nbytes) *nbytes = bytes;
+    return hipSuccess;
+}
+
+void Timer::release()
+{
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+}
+
+void Solver::tstart(const char *fam, int n, double bytes_per_point, long points, bool stamped)
+{
+    timer.start(fam, n, bytes_per_point, points, stamped, s);
+}
+
+void Solver::tstop() { timer.stop(s); }
 
 // ------------------------------------------------------------- multigrid
 template <typename T>

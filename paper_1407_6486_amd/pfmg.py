@@ -70,6 +70,8 @@ _sigs = {
     "pfmg_vcycle_count": ([_vp, C.c_int32, C.POINTER(C.c_int64)], C.c_int32),
     "pfmg_timing_enable": ([_vp, C.c_char_p, C.c_int32], C.c_int32),
     "pfmg_timing_read": ([_vp, C.POINTER(C.c_int64), _dp, _dp], C.c_int32),
+    "pfmg_batch_timing_enable": ([_vp, C.c_char_p, C.c_int32], C.c_int32),
+    "pfmg_batch_timing_read": ([_vp, C.POINTER(C.c_int64), _dp, _dp], C.c_int32),
     "pfmg_batch_workspace_bytes": ([C.POINTER(Params), C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
     "pfmg_batch_create": ([C.POINTER(Params), C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(_vp)], C.c_int32),
     "pfmg_batch_destroy": ([_vp], C.c_int32),
@@ -198,6 +200,18 @@ def pfmg_timing_read(h):
     ms = C.c_double(0.0)
     by = C.c_double(0.0)
     _check(_lib.pfmg_timing_read(h, C.byref(n), C.byref(ms), C.byref(by)))
+    return n.value, ms.value, by.value
+
+
+def pfmg_batch_timing_enable(h, kernel: str | None, enable: bool) -> None:
+    _check(_lib.pfmg_batch_timing_enable(h, kernel.encode() if kernel else None, int(enable)))
+
+
+def pfmg_batch_timing_read(h):
+    n = C.c_int64(0)
+    ms = C.c_double(0.0)
+    by = C.c_double(0.0)
+    _check(_lib.pfmg_batch_timing_read(h, C.byref(n), C.byref(ms), C.byref(by)))
     return n.value, ms.value, by.value
 
 
@@ -505,6 +519,12 @@ class Batch:
 
     def vcycle_count(self, level: int = 0) -> int:
         return pfmg_batch_vcycle_count(self.h, level)
+
+    def timing_enable(self, kernel: str | None, enable: bool = True):
+        pfmg_batch_timing_enable(self.h, kernel, enable)
+
+    def timing_read(self):
+        return pfmg_batch_timing_read(self.h)
 
 
 class Net:

@@ -1,9 +1,11 @@
 // Network kernels of the learned initial guess (see nn.h).
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16: a workgroup
-// of 4 wavefronts computes 64 output voxels (16 per wavefront) times all
-// output channels; the K dimension runs over (tap, 8-channel block) groups,
-// four per MFMA.  Lane l of the MFMA holds A row l%16 and B column l%16
+// of 4 wavefronts computes 64 MB output voxels (MB groups of 16 per
+// wavefront) times all output channels; the K dimension runs over (tap,
+// 8-channel block) groups, four per MFMA.  Each weight fragment loaded
+// feeds the MB voxel groups of its wavefront, so the weights (read through
+// the caches by every wavefront) cost 1/MB of their traffic per voxel.  Lane l of the MFMA holds A row l%16 and B column l%16
 // with k = 8 (l/16) .. 8 (l/16) + 7, and receives D rows 4 (l/16) .. + 3 of
 // column l%16.  A rows are voxels: each lane loads its voxel's 8 channels of
 // one tap with one 16-byte load (channels-last); B columns are output
@@ -55,6 +57,8 @@ __device__ inline Dom domain(int mode, int nin, int nout, int cls)
     return d;
 }
 
+constexpr int MB = 4;   // 16-voxel groups per wavefront
+
 template <int MODE, int NT>
 __global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_count, Act out, const bf16 *__restrict__ W,
                                                    const float *__restrict__ bias, int relu, int batch)
@@ -64,44 +68,48 @@ __global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_count, Act out
     constexpr int cout = NT * 16;
     const Dom D = domain(MODE, nin, nout, blockIdx.y);
     const long total = (long)batch * D.cz * D.cy * D.cx;
-    const long vblk = (long)blockIdx.x * 64;
+    const long vblk = (long)blockIdx.x * 64 * MB;
     if (vblk >= total) return;
-    const long v0 = vblk + wave * 16;
-    const long va = v0 + (lane & 15);
-    const bool a_ok = va < total;
-    int s, iz, iy, ix;
-    {
-        long t = a_ok ? va : 0;
-        ix = (int)(t % D.cx);
-        t /= D.cx;
-        iy = (int)(t % D.cy);
-        t /= D.cy;
-        iz = (int)(t % D.cz);
-        s = (int)(t / D.cz);
-    }
-    int bz, by, bx;   // input point (halo'd) of tap offset 0
-    if (MODE == SAME) {
-        bz = iz + 1; by = iy + 1; bx = ix + 1;
-    } else if (MODE == DOWN) {
-        bz = 2 * (iz + 1); by = 2 * (iy + 1); bx = 2 * (ix + 1);
-    } else {
-        // even axis: J = j + 1 (d = 0); odd axis: J = j (d = +1) or j + 1 (d = -1)
-        bz = D.pz ? iz : iz + 1; by = D.py ? iy : iy + 1; bx = D.px ? ix : ix + 1;
-    }
     const long m = nin + 2;
-    const bf16 *__restrict__ xin = in.p + vox(nin, s, bz, by, bx) * in.cs;
+    // this lane's A row (voxel) in each of the wavefront's MB groups
+    const bf16 *xin[MB];
+    bool a_ok[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const long va = vblk + (wave * MB + mb) * 16 + (lane & 15);
+        a_ok[mb] = va < total;
+        long t = a_ok[mb] ? va : 0;
+        const int ix = (int)(t % D.cx);
+        t /= D.cx;
+        const int iy = (int)(t % D.cy);
+        t /= D.cy;
+        const int iz = (int)(t % D.cz);
+        const int s = (int)(t / D.cz);
+        int bz, by, bx;   // input point (halo'd) of tap offset 0
+        if (MODE == SAME) {
+            bz = iz + 1; by = iy + 1; bx = ix + 1;
+        } else if (MODE == DOWN) {
+            bz = 2 * (iz + 1); by = 2 * (iy + 1); bx = 2 * (ix + 1);
+        } else {
+            // even axis: J = j + 1 (d = 0); odd axis: J = j (d = +1) or j + 1 (d = -1)
+            bz = D.pz ? iz : iz + 1; by = D.py ? iy : iy + 1; bx = D.px ? ix : ix + 1;
+        }
+        xin[mb] = in.p + vox(nin, s, bz, by, bx) * in.cs;
+    }
     const int ntap = MODE == UP ? (1 << (D.pz + D.py + D.px)) : 27;
     const int groups = ntap * cb_count;
     const int ksteps = (groups + 3) >> 2;
     const int cin8 = cb_count * 8;
     const int kg = lane >> 4;
-    f4 acc[NT];
+    f4 acc[MB][NT];
 #pragma unroll
-    for (int q = 0; q < NT; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[mb][q] = f4{0.f, 0.f, 0.f, 0.f};
     for (int ks = 0; ks < ksteps; ++ks) {
         const int g = ks * 4 + kg;
         const bool gok = g < groups;
-        bf16x8 a = {};
+        long aoff = 0;
         int tapw = 0, cb = 0;
         if (gok) {
             const int t = g / cb_count;
@@ -120,42 +128,55 @@ __global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_count, Act out
                 ox = t % 3 - 1;
                 tapw = t;
             }
-            if (a_ok) a = *reinterpret_cast<const bf16x8 *>(xin + (((long)oz * m + oy) * m + ox) * in.cs + cb * 8);
+            aoff = (((long)oz * m + oy) * m + ox) * in.cs + cb * 8;
+        }
+        bf16x8 a[MB], bw[NT];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            a[mb] = bf16x8{};
+            if (gok && a_ok[mb]) a[mb] = *reinterpret_cast<const bf16x8 *>(xin[mb] + aoff);
         }
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
-            bf16x8 b = {};
+            bw[q] = bf16x8{};
             if (gok)
-                b = *reinterpret_cast<const bf16x8 *>(W + ((long)tapw * cout + q * 16 + (lane & 15)) * cin8 + cb * 8);
-            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
+                bw[q] = *reinterpret_cast<const bf16x8 *>(W + ((long)tapw * cout + q * 16 + (lane & 15)) * cin8 + cb * 8);
         }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int q = 0; q < NT; ++q) acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bw[q], acc[mb][q], 0, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const long v = v0 + 4 * (lane >> 4) + t;
-        if (v >= total) continue;
-        long u = v;
-        const int ox = (int)(u % D.cx);
-        u /= D.cx;
-        const int oy = (int)(u % D.cy);
-        u /= D.cy;
-        const int oz = (int)(u % D.cz);
-        const int os = (int)(u / D.cz);
-        int z, y, x;
-        if (MODE == UP) {
-            z = D.pz ? 2 * oz + 1 : 2 * (oz + 1);
-            y = D.py ? 2 * oy + 1 : 2 * (oy + 1);
-            x = D.px ? 2 * ox + 1 : 2 * (ox + 1);
-        } else {
-            z = oz + 1; y = oy + 1; x = ox + 1;
-        }
-        bf16 *o = out.p + vox(nout, os, z, y, x) * out.cs;
+    for (int mb = 0; mb < MB; ++mb) {
+        const long v0 = vblk + (wave * MB + mb) * 16;
 #pragma unroll
-        for (int q = 0; q < NT; ++q) {
-            const int co = q * 16 + (lane & 15);
-            float val = acc[q][t] + (bias ? bias[co] : 0.f);
-            if (relu) val = fmaxf(val, 0.f);
-            o[co] = (bf16)val;
+        for (int t = 0; t < 4; ++t) {
+            const long v = v0 + 4 * (lane >> 4) + t;
+            if (v >= total) continue;
+            long u = v;
+            const int ox = (int)(u % D.cx);
+            u /= D.cx;
+            const int oy = (int)(u % D.cy);
+            u /= D.cy;
+            const int oz = (int)(u % D.cz);
+            const int os = (int)(u / D.cz);
+            int z, y, x;
+            if (MODE == UP) {
+                z = D.pz ? 2 * oz + 1 : 2 * (oz + 1);
+                y = D.py ? 2 * oy + 1 : 2 * (oy + 1);
+                x = D.px ? 2 * ox + 1 : 2 * (ox + 1);
+            } else {
+                z = oz + 1; y = oy + 1; x = ox + 1;
+            }
+            bf16 *o = out.p + vox(nout, os, z, y, x) * out.cs;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                const int co = q * 16 + (lane & 15);
+                float val = acc[mb][q][t] + (bias ? bias[co] : 0.f);
+                if (relu) val = fmaxf(val, 0.f);
+                o[co] = (bf16)val;
+            }
         }
     }
 }
@@ -534,10 +555,10 @@ hipError_t conv(Mode mode, const Act &in, int cin8, const Act &out, int cout, co
     dim3 grid;
     if (mode == UP) {
         total = (long)batch * (in.n + 1) * (in.n + 1) * (in.n + 1);
-        grid = dim3(blocks_of(total, 64), 8);
+        grid = dim3(blocks_of(total, 64 * MB), 8);
     } else {
         total = (long)batch * out.n * out.n * out.n;
-        grid = dim3(blocks_of(total, 64), 1);
+        grid = dim3(blocks_of(total, 64 * MB), 1);
     }
     const int r = relu ? 1 : 0;
 #define NN_CONV(MODE_, NT_) conv_kernel<MODE_, NT_><<<grid, 256, 0, s>>>(in, cb, out, W, bias, r, batch)

@@ -120,10 +120,13 @@ hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, Vi
 // RSLOTS partial slots (res_bits[p * RSLOTS + w]); bits preset to 0.
 constexpr int RSLOTS = 64;
 // Fields are (problem, slice) pairs with P slices per problem; ublock holds
-// one block initial value per problem.
+// one block initial value per problem.  first: the pair index of the
+// launch's field 0 (a launch over slices p0 .. p1-1 of one problem passes
+// p0 with U, F and the bits offset to slice p0; the field before it is then
+// read from U's previous slot).
 hipError_t colloc_resid(const Tiling &t, int nn, int P, double dt, const double *Q, View<double> U,
                         View<double> F, View<double> ublock,
-                        unsigned long long *res_bits, unsigned long long *u0_bits, hipStream_t s);
+                        unsigned long long *res_bits, unsigned long long *u0_bits, hipStream_t s, int first = 0);
 // Point-wise injection uc(J) = uf(2J) (t on the coarse grids).
 hipError_t inject(const Tiling &t, View<double> uf, View<double> uc, hipStream_t s);
 // dense (n^dim, x fastest) <-> field

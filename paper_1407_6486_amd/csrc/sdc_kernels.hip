@@ -191,7 +191,7 @@ __device__ inline unsigned long long wave_max(unsigned long long v)
 // Fields are (problem, slice) pairs, P slices per problem, slice fastest.
 // U0 = the problem's block initial value for slice 0, else U[item-1][nn-1].
 template <int DIM, int NN>
-__global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt, int P, double dt,
+__global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt, int P, int first, double dt,
                                                              const double *__restrict__ Q, View<double> U,
                                                              View<double> F, View<double> ublock,
                                                              unsigned long long *res_bits,
@@ -205,9 +205,9 @@ __global__ __launch_bounds__(BLOCK) void colloc_resid_kernel(Tiling t, int nn_rt
         const long node = node_stride(q.n, DIM);
         const double h = q.par(dt);
         double u0;
-        if (q.item % P == 0) {
+        if ((first + q.item) % P == 0) {
             Pt qp = q;
-            qp.item = q.item / P;
+            qp.item = (first + q.item) / P;
             u0 = fp(ublock, qp)[o];
         } else {
             Pt qm = q;
@@ -364,11 +364,12 @@ hipError_t interp_coarse(const Tiling &t, int nnf, int nnc, const double *Lt, Vi
 
 hipError_t colloc_resid(const Tiling &t, int nn, int P, double dt, const double *Q, View<double> U,
                         View<double> F, View<double> ublock, unsigned long long *res_bits,
-                        unsigned long long *u0_bits, hipStream_t s)
+                        unsigned long long *u0_bits, hipStream_t s, int first)
 {
-    if (nn > MAXN || P < 1) return hipErrorInvalidValue;
-    if (nn == 5) PFMG_DISPATCH_N(t, colloc_resid_kernel, 5, t, nn, P, dt, Q, U, F, ublock, res_bits, u0_bits);
-    PFMG_DISPATCH_N(t, colloc_resid_kernel, 0, t, nn, P, dt, Q, U, F, ublock, res_bits, u0_bits);
+    if (nn > MAXN || P < 1 || first < 0) return hipErrorInvalidValue;
+    if (nn == 5)
+        PFMG_DISPATCH_N(t, colloc_resid_kernel, 5, t, nn, P, first, dt, Q, U, F, ublock, res_bits, u0_bits);
+    PFMG_DISPATCH_N(t, colloc_resid_kernel, 0, t, nn, P, first, dt, Q, U, F, ublock, res_bits, u0_bits);
 }
 
 hipError_t inject(const Tiling &t, View<double> uf, View<double> uc, hipStream_t s)

@@ -125,6 +125,7 @@ struct Solver {
     hipError_t spread_body();
     hipError_t iterate_body();
     hipError_t residual_enqueue();
+    hipError_t residual_slices(int p0, int p1);
     hipError_t chain_step(int q);
     hipError_t iterate_pipelined();
     static constexpr int MAXGROUPS = 16;

@@ -706,12 +706,21 @@ hipError_t Solver::predictor()
 // atomics); the host takes the maximum over the slots.
 hipError_t Solver::residual_enqueue()
 {
+    HC(k::fill_u64(bits, 0, 2 * P * k::RSLOTS, s));
+    return residual_slices(0, P);
+}
+
+// Residual partials of slices p0 .. p1-1 (bits cleared beforehand); slice
+// p0 > 0 takes its initial value from slice p0-1's last node.
+hipError_t Solver::residual_slices(int p0, int p1)
+{
     PLevel &Fn = L[0];
     const long fst = (long)Fn.nn * Fn.fs;
-    HC(k::fill_u64(bits, 0, 2 * P * k::RSLOTS, s));
-    tstart("colloc_resid", Fn.n, 8.0 * (2 * Fn.nn + 1), interior_points(Fn.n, dim) * P);
-    HC(k::colloc_resid(tl(Fn.n, P), Fn.nn, P, p.dt, Fn.dQ, View<double>{Fn.U, fst}, View<double>{Fn.F, fst},
-                       View<double>{ublock, 0}, bits, bits + (long)P * k::RSLOTS, s));
+    const int count = p1 - p0;
+    tstart("colloc_resid", Fn.n, 8.0 * (2 * Fn.nn + 1), interior_points(Fn.n, dim) * count);
+    HC(k::colloc_resid(tl(Fn.n, count), Fn.nn, P, p.dt, Fn.dQ, View<double>{Fn.U + (long)p0 * fst, fst},
+                       View<double>{Fn.F + (long)p0 * fst, fst}, View<double>{ublock, 0},
+                       bits + (long)p0 * k::RSLOTS, bits + (long)(P + p0) * k::RSLOTS, s, p0));
     tstop();
     return hipSuccess;
 }
@@ -802,6 +811,7 @@ hipError_t Solver::iterate_pipelined()
     // multigrid scratch offset to their first slice, disjoint scratch, so
     // they may alternate over two streams (fine_streams = 2).
     hipStream_t main = s;
+    HC(k::fill_u64(bits, 0, 2 * P * k::RSLOTS, main));   // residual partials, filled per group below
     const int nfs = fine_streams > 1 && G > 1 ? 2 : 1;
     if (nfs > 1) {
         if (!s3) HC(hipStreamCreateWithFlags(&s3, hipStreamNonBlocking));
@@ -821,16 +831,19 @@ hipError_t Solver::iterate_pipelined()
     }
     s = s2;
     hipError_t e = hipSuccess;
+    // each group's collocation residual follows its interpolation (its
+    // first slice reads the previous group's end value, interpolated
+    // before), so only the last group's is left after the fine sweeps
     for (int g = 0; g < G && e == hipSuccess; ++g) {
         e = hipStreamWaitEvent(s2, ev[g], 0);
         for (int q = first(g); q < first(g + 1) && e == hipSuccess; ++q) e = chain_step(q);
         if (e == hipSuccess) e = interpolate(first(g), first(g + 1));
+        if (e == hipSuccess) e = residual_slices(first(g), first(g + 1));
     }
     if (e == hipSuccess) e = hipEventRecord(ev[G], s2);
     s = main;
     HC(e);
-    HC(hipStreamWaitEvent(s, ev[G], 0));
-    return residual_enqueue();
+    return hipStreamWaitEvent(s, ev[G], 0);
 }
 
 hipError_t Solver::iterate(double *block)

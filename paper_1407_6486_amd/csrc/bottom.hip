@@ -50,10 +50,27 @@ __device__ inline int flat_tid()
     return DIM == 3 ? (int)(threadIdx.x + 16 * (threadIdx.y + 16 * threadIdx.z)) : (int)threadIdx.x;
 }
 
-// Every point of an n^DIM grid, dense index order, BT points per round.
+// Every point of an n^DIM grid, BT points per round.  3D grids with n <= 8
+// take 8 x 16 x 8 points per round from the 16 x 16 x 4 thread block (x
+// lanes split in two z halves), n <= 16 take 16 x 16 x 4; both without
+// integer division.  Larger grids go in dense index order.
 template <int DIM, class F>
 __device__ inline void for_flat(int n, F f)
 {
+    if (DIM == 3 && n <= 8) {
+        const int i = threadIdx.x & 7, j = threadIdx.y;
+        if (i < n && j < n)
+            for (int k = 2 * threadIdx.z + (threadIdx.x >> 3); k < n; k += 8) f(i + n * (j + n * k), i, j, k);
+        return;
+    }
+    if (DIM == 3 && n <= 16) {
+        if (threadIdx.x < n && threadIdx.y < n)
+            for (int k = threadIdx.z; k < n; k += 4) {
+                const int i = threadIdx.x, j = threadIdx.y;
+                f(i + n * (j + n * k), i, j, k);
+            }
+        return;
+    }
     if (DIM == 3) {
         const int nn = n * n;
         for (int p = flat_tid<DIM>(); p < nn * n; p += BT) {
@@ -73,6 +90,16 @@ template <int DIM, class F>
 __device__ inline void for_colour(int n, int colour, F f)
 {
     const int h = (n + 1) / 2;
+    if (DIM == 3 && n <= 16) {
+        // 8 x 16 x 8 (i/2, j, k) slots per round, no integer division
+        const int i2 = threadIdx.x & 7, j = threadIdx.y;
+        if (i2 < h && j < n)
+            for (int k = 2 * threadIdx.z + (threadIdx.x >> 3); k < n; k += 8) {
+                const int i = 2 * i2 + ((colour + j + k + 1) & 1);
+                if (i < n) f(i + n * (j + n * k), i, j, k);
+            }
+        return;
+    }
     if (DIM == 3) {
         const int hn = h * n;
         for (int q = flat_tid<DIM>(); q < hn * n; q += BT) {

@@ -130,6 +130,29 @@ def cpu_baseline(n, P, iters_gpu, cpu_iters, u0):
                       f"same block on the host, extrapolated to the {iters_gpu} iterations the block needs"}
 
 
+def copy_bandwidth_gbs(nbytes=1 << 30, reps=10):
+    """Read + write bytes per second of a plain device-to-device copy of
+    nbytes (torch's copy kernel): the bandwidth a streaming kernel can
+    expect on this GPU, next to the 8 TB/s spec peak."""
+    import torch
+
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def _time_blocks(run, steps):
     import torch
 
@@ -424,7 +447,8 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic, "kernel": dominant, "launches": launches,
                 "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2), "bytes_per_launch": per_launch,
-                "eager_block_s": round(eager_block_s, 4)}
+                "eager_block_s": round(eager_block_s, 4),
+                "copy_gbs": round(copy_bandwidth_gbs(), 1)}
 
     out = {
         "metric": "s to 1e-10 residual per PFASST block",

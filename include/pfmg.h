@@ -270,6 +270,19 @@ pfmg_status pfmg_batch_timing_read(pfmg_batch *b, int64_t *launches, double *ms_
  * "fused ty zchunk blocks" ("" if absent). */
 pfmg_status pfmg_tune_count(int32_t *count_out);
 pfmg_status pfmg_tune_lookup(const char *key, char *buf, size_t len);
+/* Pins the table entry for a key of the form above, in place of timing:
+ * every later red-black smoothing of that configuration in this process
+ * takes it.  fused: 0 the two colour passes (ty, zchunk ignored); 1 the
+ * one-pass kernel with 256-thread workgroups; 2 with 512; -1 drops the
+ * entry, so that the next smoothing times the candidates.  ty: grid rows
+ * per workgroup (1..n); zchunk: planes per z-chunk (>= 1).  PFMG_ERR_ARG for
+ * a null or malformed key (n in 1..255 per segment) or a one-pass shape
+ * without a compiled kernel: more than 6 rows per thread (ty + 2 rows over
+ * threads / row lanes, row lanes = the widest n rounded up to 64), or more
+ * than 3 with 512 threads.  The entry is not written to PFMG_TUNE_CACHE.
+ * Thread-safe; a pin made while another thread smooths that configuration
+ * takes effect from that thread's next smoothing. */
+pfmg_status pfmg_tune_set(const char *key, int32_t fused, int32_t ty, int32_t zchunk);
 
 /* ------------------------------------------------------------------------
  * Learned initial guess (a node solve's start from a small 3D network).

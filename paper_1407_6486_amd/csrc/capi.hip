@@ -474,6 +474,13 @@ pfmg_status pfmg_tune_lookup(const char *key, char *buf, size_t len)
     return PFMG_OK;
 }
 
+pfmg_status pfmg_tune_set(const char *key, int32_t fused, int32_t ty, int32_t zchunk)
+{
+    if (!key) return fail(PFMG_ERR_ARG, "null key");
+    if (!pfmg::tune_set(key, fused, ty, zchunk)) return fail(PFMG_ERR_ARG, "malformed key or unsupported shape");
+    return PFMG_OK;
+}
+
 // ---------------------------------------------------------- learned guess
 namespace {
 

@@ -33,8 +33,12 @@ struct FusedShape {
     int ty, zchunk;
     long blocks;
     size_t lds;
+    int nt = 256;   // threads per workgroup: 256 or 512
 };
-FusedShape rbgs_fused_shape(const Tiling &t, size_t elem, int ty = 0, int target_blocks = 0);
+FusedShape rbgs_fused_shape(const Tiling &t, size_t elem, int ty = 0, int target_blocks = 0, int nt = 256);
+// Whether the one-pass kernel is instantiated for ty rows per workgroup
+// on grids up to nmax points a side with nt (256 or 512) threads.
+bool rbgs_fused_ty_ok(int nmax, int ty, int nt);
 // One whole red-black sweep out of place (3D, 31 <= n <= 255): uout =
 // RBGS(uin); zero_in treats uin as 0 (first sweep of a coarse correction).
 // shape: a shape from rbgs_fused_shape for this tiling (nullptr: default).

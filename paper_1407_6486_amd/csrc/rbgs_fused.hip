@@ -32,13 +32,15 @@ constexpr int QMAX = 6;   // owned rows per thread
 
 // RLN: x lanes per row (64, 128 or 256), the widest segment's n rounded up
 // to whole wavefronts; narrower segments leave their extra lanes idle.
-// Q: rows per thread, ceil((ty + 2) / (BLOCK / RLN)) rounded up to an
+// NT: threads per workgroup (256 or 512: a larger workgroup owns more rows
+// at the same register footprint, so fewer halo rows are re-read).
+// Q: rows per thread, ceil((ty + 2) / (NT / RLN)) rounded up to an
 // instantiated value; the register windows hold Q rows, so a small ty buys
 // occupancy.  The loads of step k + 1 are issued at the top of step k
 // (uin plane k + 2, b plane k + 1, the halo rows of uin plane k + 1) and
 // wait behind the whole step's arithmetic and barriers.
-template <typename T, int RLN, int Q>
-__global__ __launch_bounds__(BLOCK, (Q == 3 ? 5 : 1)) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
+template <typename T, int RLN, int Q, int NT>
+__global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
                                                            double omega, View<T> b, View<T> uin, View<T> uout)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(BLOCK, (Q == 3 ? 5 : 1)) void rbgs_fused_kernel(Til
     const T ah = (T)ahd, winv = (T)(omega / (1.0 + 2.0 * 3 * ahd));
     const int j0 = jt * ty + 1, k0 = zc * zchunk + 1;
     const int k1 = min(k0 + zchunk, n + 1);
-    constexpr int rpp = BLOCK / rowlanes;
+    constexpr int rpp = NT / rowlanes;
     const int i = (int)(threadIdx.x % rowlanes) + 1;
     const int rsub = (int)(threadIdx.x / rowlanes);
     // element offsets inside one field fit in 32 bits (n <= 255)
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(BLOCK, (Q == 3 ? 5 : 1)) void rbgs_fused_kernel(Til
     const bool xin = i <= n;
 
     // x index 0 is the boundary: zero once in every LDS row
-    for (int r = threadIdx.x; r < (ty + 4) + 2 * rows; r += BLOCK) up[r * RL] = (T)0;
+    for (int r = threadIdx.x; r < (ty + 4) + 2 * rows; r += NT) up[r * RL] = (T)0;
 
     auto inside = [&](int j, int k) { return xin && j >= 1 && j <= n && k >= 1 && k <= n; };
     auto ld = [&](const T *__restrict__ a, int j, int k) -> T {
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(BLOCK, (Q == 3 ? 5 : 1)) void rbgs_fused_kernel(Til
 }
 
 // Rows per thread for a launch of row width RLN and ty output rows.
-constexpr int rows_per_thread(int rln, int ty) { return (ty + 2 + BLOCK / rln - 1) / (BLOCK / rln); }
+constexpr int rows_per_thread(int rln, int ty, int nt) { return (ty + 2 + nt / rln - 1) / (nt / rln); }
 
 int env_int(const char *name, int dflt)
 {
@@ -201,21 +203,30 @@ int env_int(const char *name, int dflt)
 
 namespace k {
 
+bool rbgs_fused_ty_ok(int nmax, int ty, int nt)
+{
+    if (nmax < 1 || nmax > 256 || ty < 1 || (nt != 256 && nt != 512)) return false;
+    const int rln = (nmax + 63) & ~63;
+    // 512-thread workgroups are instantiated for up to 3 rows per thread
+    return rows_per_thread(rln, ty, nt) <= (nt == 512 ? 3 : QMAX);
+}
+
 // Rows per workgroup and planes per z-chunk for a launch over the grids of
 // `t` (the same shape for every segment; LDS sized for the widest rows).
 // ty / target_blocks = 0 take the defaults (8 rows, 4 for 256-lane rows;
-// about 1024 workgroups); ty is halved until every thread owns at most QMAX
-// rows.
-FusedShape rbgs_fused_shape(const Tiling &t, size_t elem, int ty, int target_blocks)
+// about 1024 workgroups); nt: 256 or 512 threads per workgroup; ty is
+// halved until every thread owns at most the instantiated row count (QMAX,
+// 3 for 512 threads).
+FusedShape rbgs_fused_shape(const Tiling &t, size_t elem, int ty, int target_blocks, int nt)
 {
     int nmax = 0;
     long rows_total = 0;
     for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
     const int rowlanes = (nmax + 63) & ~63;
     FusedShape f;
+    f.nt = nt == 512 ? 512 : 256;
     f.ty = ty > 0 ? ty : env_int("PFMG_RB_TY", rowlanes >= 256 ? 4 : 8);
-    const int rpp = BLOCK / rowlanes;
-    while (f.ty > 1 && (f.ty + 2 + rpp - 1) / rpp > QMAX) f.ty /= 2;
+    while (f.ty > 1 && !rbgs_fused_ty_ok(nmax, f.ty, f.nt)) f.ty /= 2;
     for (int sg = 0; sg < t.nseg; ++sg) rows_total += (long)t.seg_count(sg) * ((t.seg_n(sg) + f.ty - 1) / f.ty);
     const int target = target_blocks > 0 ? target_blocks : env_int("PFMG_RB_BLOCKS", 1024);
     int zch = (int)std::min<long>(std::max<long>(1, (target + rows_total - 1) / std::max(1L, rows_total)),
@@ -240,40 +251,54 @@ hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in,
     const FusedShape f = shape ? *shape : rbgs_fused_shape(t, sizeof(T));
     // the kernel derives its tiles from ty and zchunk: reject shapes the
     // launch does not cover exactly
-    const FusedShape chk = rbgs_fused_shape(t, sizeof(T), f.ty, 1);
+    const FusedShape chk = rbgs_fused_shape(t, sizeof(T), f.ty, 1, f.nt);
     long blocks = 0;
     for (int sg = 0; sg < t.nseg; ++sg) {
         const int n = t.seg_n(sg);
         blocks += (long)t.seg_count(sg) * ((n + f.ty - 1) / f.ty) * ((n + f.zchunk - 1) / f.zchunk);
     }
-    if (f.ty < 1 || f.ty != chk.ty || f.zchunk < 1 || blocks != f.blocks || f.lds != chk.lds) return hipErrorInvalidValue;
+    if (f.ty < 1 || f.ty != chk.ty || f.zchunk < 1 || blocks != f.blocks || f.lds != chk.lds || f.nt != chk.nt)
+        return hipErrorInvalidValue;
     if (f.blocks == 0) return hipSuccess;
     int nmax = 0;
     for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
     const int zi = zero_in ? 1 : 0;
     const int rln = nmax <= 64 ? 64 : nmax <= 128 ? 128 : 256;
-    const int q = rows_per_thread(rln, f.ty);
-    const dim3 g((unsigned)f.blocks), blk(BLOCK);
-#define PFMG_FUSED(RL_, Q_)                                                                                 \
-    return launch(rbgs_fused_kernel<T, RL_, Q_>, g, blk, f.lds, s, t, f.ty, f.zchunk, zi, alpha, omega, b, uin, \
+    const int q = rows_per_thread(rln, f.ty, f.nt);
+    const dim3 g((unsigned)f.blocks), blk(f.nt);
+#define PFMG_FUSED(RL_, Q_, NT_)                                                                                \
+    return launch(rbgs_fused_kernel<T, RL_, Q_, NT_>, g, blk, f.lds, s, t, f.ty, f.zchunk, zi, alpha, omega, b, uin, \
                   uout)
     // instantiated row counts: those of ty = 1, 2, 4, 8, 16 that fit QMAX,
-    // and QMAX for any other ty
+    // and QMAX for any other ty; 512-thread workgroups for up to 3 rows
+    if (f.nt == 512) {
+        if (rln == 64) {
+            if (q <= 1) PFMG_FUSED(64, 1, 512);
+            if (q <= 2) PFMG_FUSED(64, 2, 512);
+            if (q <= 3) PFMG_FUSED(64, 3, 512);
+        } else if (rln == 128) {
+            if (q <= 2) PFMG_FUSED(128, 2, 512);
+            if (q <= 3) PFMG_FUSED(128, 3, 512);
+        } else {
+            if (q <= 3) PFMG_FUSED(256, 3, 512);
+        }
+        return hipErrorInvalidValue;
+    }
     if (rln == 64) {
-        if (q <= 1) PFMG_FUSED(64, 1);
-        if (q <= 2) PFMG_FUSED(64, 2);
-        if (q <= 3) PFMG_FUSED(64, 3);
-        if (q <= 5) PFMG_FUSED(64, 5);
-        if (q <= QMAX) PFMG_FUSED(64, 6);
+        if (q <= 1) PFMG_FUSED(64, 1, 256);
+        if (q <= 2) PFMG_FUSED(64, 2, 256);
+        if (q <= 3) PFMG_FUSED(64, 3, 256);
+        if (q <= 5) PFMG_FUSED(64, 5, 256);
+        if (q <= QMAX) PFMG_FUSED(64, 6, 256);
     } else if (rln == 128) {
-        if (q <= 2) PFMG_FUSED(128, 2);
-        if (q <= 3) PFMG_FUSED(128, 3);
-        if (q <= 5) PFMG_FUSED(128, 5);
-        if (q <= QMAX) PFMG_FUSED(128, 6);
+        if (q <= 2) PFMG_FUSED(128, 2, 256);
+        if (q <= 3) PFMG_FUSED(128, 3, 256);
+        if (q <= 5) PFMG_FUSED(128, 5, 256);
+        if (q <= QMAX) PFMG_FUSED(128, 6, 256);
     } else {
-        if (q <= 3) PFMG_FUSED(256, 3);
-        if (q <= 4) PFMG_FUSED(256, 4);
-        if (q <= QMAX) PFMG_FUSED(256, 6);
+        if (q <= 3) PFMG_FUSED(256, 3, 256);
+        if (q <= 4) PFMG_FUSED(256, 4, 256);
+        if (q <= QMAX) PFMG_FUSED(256, 6, 256);
     }
 #undef PFMG_FUSED
     return hipErrorInvalidValue;

@@ -36,7 +36,12 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
 
 // Number of configurations tuned or loaded so far (for tests and reports).
 int tune_table_size();
-// The entry for a key ("" if none), as "fused ty zchunk blocks".
+// The entry for a key ("" if none), as "fused ty zchunk blocks" (fused: 0
+// colour passes, 1 one-pass kernel with 256-thread workgroups, 2 with 512).
 std::string tune_lookup(const std::string &key);
+// Pins the entry for a key, replacing any timed or loaded one (not written
+// to the cache file); fused = -1 drops the entry.  False for a malformed key
+// or a one-pass shape the kernel is not instantiated for.
+bool tune_set(const std::string &key, int fused, int ty, int zchunk);
 
 }  // namespace pfmg

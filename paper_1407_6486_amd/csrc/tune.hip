@@ -117,7 +117,8 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
             const Entry &e = it->second;
             plan.fused = e.fused != 0;
             if (plan.fused) {
-                plan.shape = k::rbgs_fused_shape(t, sizeof(T), e.ty, 1);
+                // fused = 2: 512-thread workgroups
+                plan.shape = k::rbgs_fused_shape(t, sizeof(T), e.ty, 1, e.fused == 2 ? 512 : 256);
                 plan.shape.zchunk = e.zchunk;
                 long blocks = 0;
                 for (int sg = 0; sg < t.nseg; ++sg) {
@@ -162,9 +163,10 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
     std::vector<k::FusedShape> cands;
     int nmax = 0;
     for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
-    for (int ty : {2, 4, 8, 16})
+    for (int nt : {256, 512})
+    for (int ty : {2, 4, 6, 8, 10, 16})
         for (int zc : {2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128, 256}) {
-            k::FusedShape f = k::rbgs_fused_shape(t, sizeof(T), ty, 1);
+            k::FusedShape f = k::rbgs_fused_shape(t, sizeof(T), ty, 1, nt);
             if (f.ty != ty || zc > nmax) continue;
             f.zchunk = zc;
             f.blocks = 0;
@@ -179,11 +181,11 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
         const float ms = time_ms([&] { return k::rbgs_fused(t, alpha, omega, false, b, u, tmp, s, &f); }, s, e0, e1,
                                  reps);
         if (verbose())
-            fprintf(stderr, "tune %s fused ty %d zchunk %d blocks %ld %.2f us\n", key.c_str(), f.ty, f.zchunk, f.blocks,
-                    ms * 1e3f);
+            fprintf(stderr, "tune %s fused nt %d ty %d zchunk %d blocks %ld %.2f us\n", key.c_str(), f.nt, f.ty,
+                    f.zchunk, f.blocks, ms * 1e3f);
         if (ms >= 0 && ms < best) {
             best = ms;
-            win = Entry{1, f.ty, f.zchunk, f.blocks};
+            win = Entry{f.nt == 512 ? 2 : 1, f.ty, f.zchunk, f.blocks};
         }
     }
     (void)hipEventDestroy(e0);
@@ -197,7 +199,7 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
     plan.fused = win.fused != 0;
     if (plan.fused)
         for (const auto &f : cands)
-            if (f.ty == win.ty && f.zchunk == win.zchunk) plan.shape = f;
+            if (f.ty == win.ty && f.zchunk == win.zchunk && f.nt == (win.fused == 2 ? 512 : 256)) plan.shape = f;
     return plan;
 }
 
@@ -215,6 +217,52 @@ std::string tune_lookup(const std::string &key)
     const Entry &e = it->second;
     return std::to_string(e.fused) + " " + std::to_string(e.ty) + " " + std::to_string(e.zchunk) + " " +
            std::to_string(e.blocks);
+}
+
+bool tune_set(const std::string &key, int fused, int ty, int zchunk)
+{
+    // "<arch>/rbgs/<f64|f32>/" then n x count per segment, joined by '+'
+    const size_t p0 = key.find("/rbgs/");
+    if (p0 == std::string::npos || p0 == 0) return false;
+    const std::string prec = key.substr(p0 + 6, 4);
+    if (prec != "f64/" && prec != "f32/") return false;
+    std::vector<std::pair<int, long>> segs;
+    const char *c = key.c_str() + p0 + 10;
+    while (true) {
+        char *end = nullptr;
+        const long n = strtol(c, &end, 10);
+        if (end == c || *end != 'x' || n < 1 || n > 255) return false;
+        c = end + 1;
+        const long cnt = strtol(c, &end, 10);
+        if (end == c || cnt < 1 || cnt > (1L << 20)) return false;
+        segs.emplace_back((int)n, cnt);
+        c = end;
+        if (*c == 0) break;
+        if (*c != '+') return false;
+        ++c;
+    }
+    if (fused < -1 || fused > 2) return false;
+    if (fused == -1) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        load_locked();
+        g_table.erase(key);
+        return true;
+    }
+    Entry e{0, 0, 0, 0};
+    if (fused != 0) {
+        int nmax = 0;
+        for (const auto &sc : segs) nmax = std::max(nmax, sc.first);
+        if (zchunk < 1 || ty > nmax || !k::rbgs_fused_ty_ok(nmax, ty, fused == 2 ? 512 : 256)) return false;
+        long blocks = 0;
+        for (const auto &sc : segs)
+            blocks += sc.second * ((sc.first + ty - 1) / ty) * ((sc.first + zchunk - 1) / zchunk);
+        if (blocks > (1L << 30)) return false;
+        e = Entry{fused, ty, zchunk, blocks};
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    g_table[key] = e;
+    return true;
 }
 
 template RbPlan rb_plan<double>(const Tiling &, double, double, View<double>, View<double>, View<double>, hipStream_t,

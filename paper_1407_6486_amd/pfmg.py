@@ -82,6 +82,7 @@ _sigs = {
     "pfmg_batch_vcycle_count": ([_vp, C.c_int32, C.POINTER(C.c_int64)], C.c_int32),
     "pfmg_tune_count": ([C.POINTER(C.c_int32)], C.c_int32),
     "pfmg_tune_lookup": ([C.c_char_p, C.c_char_p, C.c_size_t], C.c_int32),
+    "pfmg_tune_set": ([C.c_char_p, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
     "pfmg_nn_param_count": ([C.POINTER(C.c_int64)], C.c_int32),
     "pfmg_nn_workspace_bytes": ([C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
     "pfmg_nn_create": ([C.c_int32, C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(_vp)], C.c_int32),
@@ -278,6 +279,10 @@ def pfmg_tune_lookup(key: str) -> str:
     buf = C.create_string_buffer(256)
     _check(_lib.pfmg_tune_lookup(key.encode(), buf, 256))
     return buf.value.decode()
+
+
+def pfmg_tune_set(key: str, fused: int, ty: int = 0, zchunk: int = 0) -> None:
+    _check(_lib.pfmg_tune_set(key.encode(), fused, ty, zchunk))
 
 
 def pfmg_nn_param_count() -> int:

@@ -98,6 +98,36 @@ def test_batch_workspace_and_validation_on_the_host(pf):
     assert pf.pfmg_tune_lookup("gfx950/rbgs/f64/0x0") == ""
 
 
+def test_tune_pins_are_checked_on_the_host(pf):
+    key = "testarch/rbgs/f64/127x4+63x8"
+    pf.pfmg_tune_set(key, 0)
+    assert pf.pfmg_tune_lookup(key) == "0 0 0 0"
+    # 127 rows need 128 lanes: 2 rows a pass with 256 threads, 4 with 512
+    pf.pfmg_tune_set(key, 1, 10, 16)          # (10 + 2) / 2 = 6 rows per thread
+    assert pf.pfmg_tune_lookup(key) == f"1 10 16 {4 * 13 * 8 + 8 * 7 * 4}"
+    pf.pfmg_tune_set(key, 2, 10, 5)           # (10 + 2) / 4 = 3
+    assert pf.pfmg_tune_lookup(key) == f"2 10 5 {4 * 13 * 26 + 8 * 7 * 13}"
+    bad = [(key, 1, 11, 16),                  # 7 rows per thread
+           (key, 2, 11, 16),                  # 4 with 512 threads
+           (key, 3, 8, 8), (key, -2, 8, 8), (key, 1, 0, 8), (key, 1, 8, 0), (key, 1, 128, 8),
+           ("testarch/rbgs/f64/256x1", 1, 2, 8), ("testarch/rbgs/f16/63x1", 0, 0, 0),
+           ("testarch/rbgs/f64/63x1+", 0, 0, 0), ("testarch/rbgs/f64/63y1", 0, 0, 0),
+           ("rbgs/f64/63x1", 0, 0, 0), ("testarch/rbgs/f64/63x0", 0, 0, 0)]
+    for args in bad:
+        with pytest.raises(pf.PfmgError) as ei:
+            pf.pfmg_tune_set(*args)
+        assert ei.value.status == pf.ERR_ARG, args
+    assert pf.pfmg_tune_lookup(key) == f"2 10 5 {4 * 13 * 26 + 8 * 7 * 13}"
+    # 255 rows: 256 lanes, one row a pass with 256 threads, two with 512
+    pf.pfmg_tune_set("testarch/rbgs/f32/255x1", 1, 4, 8)
+    pf.pfmg_tune_set("testarch/rbgs/f32/255x1", 2, 4, 8)
+    with pytest.raises(pf.PfmgError):
+        pf.pfmg_tune_set("testarch/rbgs/f32/255x1", 1, 5, 8)
+    for k in (key, "testarch/rbgs/f32/255x1"):
+        pf.pfmg_tune_set(k, -1)
+        assert pf.pfmg_tune_lookup(k) == ""
+
+
 def test_network_sizes_on_the_host(pf):
     from oracle import unet as U
 

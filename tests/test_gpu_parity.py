@@ -62,6 +62,60 @@ def test_vcycle_matches_oracle(pf, dim, n, sm, cycles):
     assert abs(rr - r_or) <= 1e-10 * r_or + 1e-15
 
 
+# Rows per workgroup that select each compiled one-pass sweep: row lanes
+# (n rounded up to 64) -> ty values; rows per thread = ceil((ty + 2) /
+# (threads / lanes)) gives 1, 2, 3, 5, 6 (64 lanes), 2, 3, 5, 6 (128) and 3,
+# 4, 6 (256) with 256 threads, 1, 2, 3 / 2, 3 / 3 with 512 (a row count
+# below a compiled one runs the next one up).
+SWEEP_TY = {256: {64: [2, 4, 8, 14, 22], 128: [2, 4, 8, 10], 256: [1, 2, 4]},
+            512: {64: [6, 14, 22], 128: [2, 10], 256: [4]}}
+SWEEP_ZC = [5, 7, 3, 16, 9, 64, 2, 31]
+
+
+def sweep_cases():
+    for nt, by_lanes in SWEEP_TY.items():
+        for top in (63, 127, 255):
+            for i in range(len(by_lanes[(top + 63) // 64 * 64])):
+                yield nt, top, i
+
+
+@pytest.mark.parametrize("nt,n,i", list(sweep_cases()))
+def test_vcycle_every_sweep_shape_matches_oracle(pf, nt, n, i):
+    """Each level's one-pass sweep pinned to a shape (ragged row tiles and
+    z-chunks; the top level from a given guess, the coarser ones from zero)."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    levels, m = [], n
+    while m >= 31:
+        levels.append(m)
+        m = (m - 1) // 2
+    pins_set = {}
+    for d, lv in enumerate(levels):
+        tys = SWEEP_TY[nt][(lv + 63) // 64 * 64]
+        pins_set[f"{arch}/rbgs/f64/{lv}x1"] = (2 if nt == 512 else 1, tys[(i + d) % len(tys)],
+                                                SWEEP_ZC[(i + 2 * d + lv) % len(SWEEP_ZC)])
+    say(f"vcycle sweep shapes nt={nt} n={n} pins={pins_set}")
+    try:
+        for key, (f, ty, zc) in pins_set.items():
+            pf.pfmg_tune_set(key, f, ty, zc)
+        c = make(pf, dim=3, n=n, n_slices=1, nodes_coarse=0, smoother=pf.SMOOTH_RBGS, omega=1.0)
+        alpha = 3.0 / (n + 1) ** 2
+        b = inputs.random_field((n,) * 3, 300 + n + i)
+        u0 = inputs.random_field((n,) * 3, 400 + n + i)
+        c.timing_enable(f"rbgs@{n}")
+        u_gpu, st, rr, nc = c.vcycle(alpha, b, u0, 1)
+        launches, _, nbytes = c.timing_read()
+        c.timing_enable(None, False)
+    finally:
+        for key in pins_set:
+            pf.pfmg_tune_set(key, -1)
+    assert st == pf.OK and nc == 1
+    # the one-pass kernel ran on the top level: 24 bytes a point a launch
+    assert launches > 0 and nbytes == launches * 24 * n ** 3
+    u_or = O.vcycle(3, alpha, b, u0.copy(), O.RBGS, 1.0)
+    assert pins.rel_err(u_gpu.cpu().numpy(), u_or) <= TOL
+
+
 @pytest.mark.parametrize("dim,n,sm", [(3, 31, "rb"), (1, 63, "jac")])
 def test_full_solve_matches_oracle(pf, dim, n, sm):
     say(f"full solve dim={dim} n={n} smoother={sm}")

@@ -135,7 +135,9 @@ struct Solver {
     hipEvent_t ev[MAXGROUPS + 1] = {};
     hipStream_t s3 = nullptr;         // second fine-sweep stream of the pipelined iteration
     hipEvent_t ev_fork = nullptr;
+    hipEvent_t evc[2] = {};           // coarse chain done through group G-2 / G-1
     int fine_streams = 1;             // streams the groups' fine sweeps alternate over
+    bool late_interp = true;          // interpolation and residual of the early groups under the last chain
     int mg_off = 0;                   // first multigrid scratch field of the current sweep
     template <typename T>
     View<T> scr(View<T> v) const { return View<T>{v.p ? v.p + (long)mg_off * v.stride : nullptr, v.stride}; }

@@ -198,6 +198,10 @@ bool Solver::init_host(std::string &why)
     // group, and the coarse chain behind it, more than they hide.
     e = getenv("PFMG_FINE_STREAMS");
     fine_streams = e ? std::max(1, atoi(e)) : 1;
+    // PFMG_LATE_INTERP=0: each group's interpolation and residual follow
+    // its coarse chain on the chain stream (the earlier schedule).
+    e = getenv("PFMG_LATE_INTERP");
+    late_interp = !(e && atoi(e) == 0);
     e = getenv("PFMG_GROUPS");
     if (e && strchr(e, ',')) {
         for (const char *c = e; *c;) {
@@ -794,12 +798,12 @@ hipError_t Solver::chain_step(int q)
 }
 
 // The same iteration with the slices in groups: the fine sweep and FAS
-// restriction of group g run on the main stream while the coarse chain and
-// interpolation of the earlier groups run on a second stream (chain step q
-// needs only slice q's restriction and slice q-1's coarse end value, and
-// interpolation of a group only its own coarse sweeps).  Every slice sees
-// the same operations in the same order as in the sequential schedule.
-// Fixed V-cycle counts only (full solves read norms back on the host).
+// restriction of group g run on the main stream while the coarse chain of
+// the earlier groups runs on a second stream (chain step q needs only slice
+// q's restriction and slice q-1's coarse end value, and interpolation of a
+// group only its own coarse sweeps).  Every slice sees the same operations
+// in the same order as in the sequential schedule.  Fixed V-cycle counts
+// only (full solves read norms back on the host).
 hipError_t Solver::iterate_pipelined()
 {
     if (!s2) HC(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
@@ -831,19 +835,44 @@ hipError_t Solver::iterate_pipelined()
     }
     s = s2;
     hipError_t e = hipSuccess;
-    // each group's collocation residual follows its interpolation (its
-    // first slice reads the previous group's end value, interpolated
-    // before), so only the last group's is left after the fine sweeps
+    if (!late_interp) {
+        // each group's collocation residual follows its interpolation (its
+        // first slice reads the previous group's end value, interpolated
+        // before), so only the last group's is left after the fine sweeps
+        for (int g = 0; g < G && e == hipSuccess; ++g) {
+            e = hipStreamWaitEvent(s2, ev[g], 0);
+            for (int q = first(g); q < first(g + 1) && e == hipSuccess; ++q) e = chain_step(q);
+            if (e == hipSuccess) e = interpolate(first(g), first(g + 1));
+            if (e == hipSuccess) e = residual_slices(first(g), first(g + 1));
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev[G], s2);
+        s = main;
+        HC(e);
+        return hipStreamWaitEvent(s, ev[G], 0);
+    }
+    // Interpolation and residual stream through HBM and would slow the fine
+    // sweeps they overlap by about their own duration; the coarse chain is
+    // latency-bound and leaves HBM mostly idle.  So the chain stream runs
+    // the chain alone, and the main stream, once its last fine sweep is
+    // done, interpolates groups 0 .. G-2 (one launch each) while the last
+    // group's chain runs, then the last group.
+    for (int i = 0; i < 2; ++i)
+        if (!evc[i]) HC(hipEventCreateWithFlags(&evc[i], hipEventDisableTiming));
     for (int g = 0; g < G && e == hipSuccess; ++g) {
         e = hipStreamWaitEvent(s2, ev[g], 0);
         for (int q = first(g); q < first(g + 1) && e == hipSuccess; ++q) e = chain_step(q);
-        if (e == hipSuccess) e = interpolate(first(g), first(g + 1));
-        if (e == hipSuccess) e = residual_slices(first(g), first(g + 1));
+        if (e == hipSuccess && g >= G - 2) e = hipEventRecord(evc[g - (G - 2)], s2);
     }
-    if (e == hipSuccess) e = hipEventRecord(ev[G], s2);
     s = main;
     HC(e);
-    return hipStreamWaitEvent(s, ev[G], 0);
+    // the residual of a group's first slice reads the previous group's end
+    // value: interpolation of groups 0 .. G-2 comes before the last residual
+    HC(hipStreamWaitEvent(main, evc[0], 0));
+    HC(interpolate(0, first(G - 1)));
+    HC(residual_slices(0, first(G - 1)));
+    HC(hipStreamWaitEvent(main, evc[1], 0));
+    HC(interpolate(first(G - 1), P));
+    return residual_slices(first(G - 1), P);
 }
 
 hipError_t Solver::iterate(double *block)
@@ -898,6 +927,11 @@ void Solver::release_graphs()
     if (s2) (void)hipStreamDestroy(s2);
     if (s3) (void)hipStreamDestroy(s3);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (hipEvent_t &e : evc)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
     for (hipEvent_t &e : ev)
         if (e) {
             (void)hipEventDestroy(e);

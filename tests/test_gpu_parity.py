@@ -327,25 +327,30 @@ def test_nan_input_reports_err_nan(pf):
     assert ei.value.status == pf.ERR_NAN
 
 
-@pytest.mark.parametrize("n,groups,streams", [(31, 2, 2), (31, 4, 2), (31, 5, 2), (31, 4, 1), (63, 4, 2)])
-def test_pipelined_iteration_matches_sequential(pf, n, groups, streams):
+@pytest.mark.parametrize("n,groups,streams,late", [(31, 2, 2, 1), (31, 4, 2, 1), (31, 5, 2, 1), (31, 4, 1, 1),
+                                                   (63, 4, 2, 1), (31, 3, 1, 0), (63, 4, 1, 0)])
+def test_pipelined_iteration_matches_sequential(pf, n, groups, streams, late):
     """Slice groups whose fine sweeps overlap the coarse chain of earlier
     groups (second stream), and each other (fine sweeps alternating over
-    two streams), give the sequential schedule's results."""
+    two streams), give the sequential schedule's results, with the early
+    groups' interpolation and residual on the main stream under the last
+    chain (late = 1) or behind each group's chain (late = 0)."""
     import os
 
     P = 8
-    say(f"pipelined iteration, {groups} groups, {streams} fine stream(s), n={n}, P={P}")
+    say(f"pipelined iteration, {groups} groups, {streams} fine stream(s), late interpolation {late}, n={n}, P={P}")
     u0, _ = inputs.random_fourier(n, 4242)
     states = {}
     for g in (1, groups):
         os.environ["PFMG_GROUPS"] = str(g)
         os.environ["PFMG_FINE_STREAMS"] = str(streams)
+        os.environ["PFMG_LATE_INTERP"] = str(late)
         try:
             c = make(pf, n=n, n_slices=P)
         finally:
             del os.environ["PFMG_GROUPS"]
             del os.environ["PFMG_FINE_STREAMS"]
+            del os.environ["PFMG_LATE_INTERP"]
         c.set_initial(u0)
         res = [c.pfasst_iter() for _ in range(4)]
         states[g] = (res, [c.get(O.UF, p, 4) for p in range(P)], [c.get(O.UC, p, 2) for p in range(P)])

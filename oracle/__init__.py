@@ -22,6 +22,7 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 _lib = None
 
 JACOBI, RBGS = 0, 1
+LOBATTO, UNIFORM = 0, 1          # node families
 UF, FF, UC, FC, TAU, UCOLD = range(6)
 
 _dp = C.POINTER(C.c_double)
@@ -37,7 +38,7 @@ class MGPolicy(C.Structure):
 class Params(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int), ("nu", C.c_double), ("dt", C.c_double),
                 ("n_slices", C.c_int), ("nodes_fine", C.c_int), ("nodes_coarse", C.c_int),
-                ("mg", MGPolicy), ("interp_order", C.c_int)]
+                ("mg", MGPolicy), ("interp_order", C.c_int), ("node_family", C.c_int)]
 
 
 def lib():
@@ -49,6 +50,8 @@ def lib():
         L = C.CDLL(_LIB_PATH)
         L.or_lobatto_nodes.argtypes = [C.c_int, _dp]
         L.or_qmat.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
+        L.or_uniform_nodes.argtypes = [C.c_int, _dp]
+        L.or_qmat_family.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp, _dp]
         L.or_interp_matrix.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp]
         L.or_lap.argtypes = [C.c_int, C.c_int, _dp, _dp]
         L.or_helm.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _dp]
@@ -107,12 +110,22 @@ def lobatto_nodes(nnodes: int) -> np.ndarray:
     return s
 
 
-def qmat(s: np.ndarray):
+def uniform_nodes(nnodes: int) -> np.ndarray:
+    s = np.zeros(nnodes)
+    assert lib().or_uniform_nodes(nnodes, _p(s)) == 0
+    return s
+
+
+def nodes(nnodes: int, family: int = LOBATTO) -> np.ndarray:
+    return uniform_nodes(nnodes) if family == UNIFORM else lobatto_nodes(nnodes)
+
+
+def qmat(s: np.ndarray, family: int = LOBATTO):
     """(Q, S, d): integration matrix, node-to-node rows, substep lengths."""
     s = np.ascontiguousarray(s, dtype=np.float64)
     nn = len(s)
     Q = np.zeros((nn, nn)); S = np.zeros((nn - 1, nn)); d = np.zeros(nn)
-    assert lib().or_qmat(nn, _p(s), _p(Q), _p(S), _p(d)) == 0
+    assert lib().or_qmat_family(nn, _p(s), family, _p(Q), _p(S), _p(d)) == 0
     return Q, S, d
 
 
@@ -194,9 +207,9 @@ class Pfasst:
     ``nodes_coarse == 0``)."""
 
     def __init__(self, dim, n, nu, dt, n_slices, nodes_fine=5, nodes_coarse=3,
-                 mg: MGPolicy | None = None, interp_order: int = 2):
+                 mg: MGPolicy | None = None, interp_order: int = 2, node_family: int = LOBATTO):
         self.prm = Params(dim, n, nu, dt, n_slices, nodes_fine, nodes_coarse,
-                          mg if mg is not None else policy(), interp_order)
+                          mg if mg is not None else policy(), interp_order, node_family)
         self.dim, self.n, self.P = dim, n, n_slices
         self.nn = [nodes_fine, nodes_coarse]
         self.nc = (n + 1) // 2 - 1

@@ -4,8 +4,11 @@
  * Quadrature nodes and the integration matrix of Sec. 2.1 (the q_{m,i}
  * with int_{t0}^{tm} g ~ dt sum_i q_{m,i} g(t_i)), the node-to-node
  * differences used in eq. sdc-be, and the backward-Euler substeps of
- * eq. Qbe.  The node family is Gauss-Lobatto: its first row of Q is zero
- * (node 0 is the left end point) but q_{m,0} != 0 for m >= 1.
+ * eq. Qbe.  Two node families: Gauss-Lobatto, whose first row of Q is
+ * zero (node 0 is the left end point) but q_{m,0} != 0 for m >= 1; and the
+ * uniform nodes of the paper's second- and fourth-order methods (Sec. 3),
+ * whose quadrature leaves out the left end point: f is interpolated
+ * through nodes 1..M only, so the whole column q_{.,0} is zero.
  */
 #include <math.h>
 #include <string.h>
@@ -75,6 +78,54 @@ static void lagrange_coeffs(int nn, const ld *s, int i, ld *c)
         denom *= (s[i] - s[j]);
     }
     for (int k = 0; k < nn; ++k) c[k] /= denom;
+}
+
+int or_uniform_nodes(int nnodes, double *s)
+{
+    if (nnodes < 2 || nnodes > 16) return -1;
+    for (int i = 0; i < nnodes; ++i) s[i] = (double)i / (double)(nnodes - 1);
+    return 0;
+}
+
+/* Uniform nodes without the left end point: Lagrange basis of the M nodes
+ * s_1..s_M (a polynomial of degree M-1 through f_1..f_M), integrated from
+ * 0 to every s_m.  Node values are m/M formed in long double. */
+static int qmat_uniform(int nnodes, double *Q, double *S, double *d)
+{
+    const int M = nnodes - 1;
+    ld s[16], Ql[16 * 16], c[17];
+    for (int i = 0; i <= M; ++i) s[i] = (ld)i / (ld)M;
+    for (int q = 0; q < nnodes * nnodes; ++q) Ql[q] = 0.0L;
+    for (int i = 1; i <= M; ++i) {
+        /* basis polynomial of node i over the nodes 1..M */
+        lagrange_coeffs(M, s + 1, i - 1, c);
+        for (int m = 0; m <= M; ++m) {
+            ld acc = 0.0L, pw = s[m];
+            for (int k = 0; k < M; ++k) {
+                acc += c[k] * pw / (k + 1);
+                pw *= s[m];
+            }
+            Ql[m * nnodes + i] = acc;
+        }
+    }
+    for (int q = 0; q < nnodes * nnodes; ++q) Q[q] = (double)Ql[q];
+    if (S)
+        for (int m = 0; m < M; ++m)
+            for (int i = 0; i < nnodes; ++i)
+                S[m * nnodes + i] = (double)(Ql[(m + 1) * nnodes + i] - Ql[m * nnodes + i]);
+    if (d) {
+        d[0] = 0.0;
+        for (int m = 1; m <= M; ++m) d[m] = (double)(s[m] - s[m - 1]);
+    }
+    return 0;
+}
+
+int or_qmat_family(int nnodes, const double *s, int family, double *Q, double *S, double *d)
+{
+    if (nnodes < 2 || nnodes > 16) return -1;
+    if (family == OR_NODES_UNIFORM) return qmat_uniform(nnodes, Q, S, d);
+    if (family != OR_NODES_LOBATTO) return -1;
+    return or_qmat(nnodes, s, Q, S, d);
 }
 
 int or_qmat(int nnodes, const double *s_in, double *Q, double *S, double *d)

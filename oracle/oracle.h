@@ -32,6 +32,18 @@ extern "C" {
  * the derivative of the Legendre polynomial, rounded once to double. */
 int or_lobatto_nodes(int nnodes, double *s);
 
+/* Node families: Gauss-Lobatto (the quadrature uses every node), and the
+ * paper's uniform nodes s_m = m/M whose quadrature leaves out the left end
+ * point (Sec. 3: q_{m,0} = 0, the interpolant of f runs through nodes
+ * 1..M; M = 1 is backward Euler, M = 2 the second-order and M = 4 the
+ * fourth-order method of the 3D runs in Sec. 4). */
+enum { OR_NODES_LOBATTO = 0, OR_NODES_UNIFORM = 1 };
+/* s_m = m / (nnodes - 1), exactly. */
+int or_uniform_nodes(int nnodes, double *s);
+/* As or_qmat for either family: family OR_NODES_UNIFORM builds every row
+ * from the Lagrange basis of the nodes s_1..s_M (column 0 stays zero). */
+int or_qmat_family(int nnodes, const double *s, int family, double *Q, double *S, double *d);
+
 /* Integration matrix Q[m][i] = int_0^{s_m} l_i(s) ds (Sec. 2.1; first row
  * zero), the node-to-node matrix S[m][i] = Q[m+1][i]-Q[m][i] (eq. sdc-be,
  * (M)x(M+1)), and the backward-Euler substeps d[m] = s_m - s_{m-1}
@@ -118,6 +130,7 @@ typedef struct or_params {
     int nodes_coarse;        /* M_c + 1, 0 = single level (ISDC) */
     or_mg_policy mg;         /* policy for every node solve (both levels) */
     int interp_order;        /* PFASST spatial interpolation: 2 d-linear, 4 cubic */
+    int node_family;         /* OR_NODES_LOBATTO / OR_NODES_UNIFORM */
 } or_params;
 
 typedef struct or_pfasst or_pfasst;

@@ -77,6 +77,7 @@ or_pfasst *or_pfasst_create(const or_params *prm)
 {
     if (prm->dim < 1 || prm->dim > 3 || prm->n < 1 || prm->n_slices < 1) return NULL;
     if (prm->nodes_fine < 2 || prm->nodes_fine > 16) return NULL;
+    if (prm->node_family != OR_NODES_LOBATTO && prm->node_family != OR_NODES_UNIFORM) return NULL;
     or_pfasst *c = (or_pfasst *)calloc(1, sizeof(or_pfasst));
     c->p = *prm;
     c->nl = prm->nodes_coarse > 0 ? 2 : 1;
@@ -89,8 +90,9 @@ or_pfasst *or_pfasst_create(const or_params *prm)
     }
     for (int l = 0; l < c->nl; ++l) {
         c->len[l] = glen(prm->dim, c->n[l]);
-        or_lobatto_nodes(c->nn[l], c->s[l]);
-        or_qmat(c->nn[l], c->s[l], c->Q[l], c->S[l], c->d[l]);
+        if (prm->node_family == OR_NODES_UNIFORM) or_uniform_nodes(c->nn[l], c->s[l]);
+        else or_lobatto_nodes(c->nn[l], c->s[l]);
+        or_qmat_family(c->nn[l], c->s[l], prm->node_family, c->Q[l], c->S[l], c->d[l]);
         size_t tot = (size_t)prm->n_slices * c->nn[l] * c->len[l];
         c->U[l] = (double *)calloc(tot, sizeof(double));
         c->F[l] = (double *)calloc(tot, sizeof(double));

@@ -61,9 +61,14 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--max-iter", type=int, default=400,
                     help="iteration cap per block (profiling runs cap it to keep traces small)")
-    ap.add_argument("--form", choices=["mixed", "batched", "learned", "solve-policies", "heat1d"], default=None,
+    ap.add_argument("--form", choices=["mixed", "batched", "learned", "solve-policies", "heat1d", "table1"],
+                    default=None,
                     help="instead: one of the method's forms against the plain FP64 path (mixed, batched, learned), "
-                         "the node-solve policies at 127^3 x 16 (solve-policies) or the 1D latency and error report (heat1d)")
+                         "the node-solve policies at 127^3 x 16 (solve-policies), the 1D latency and error report "
+                         "(heat1d) or the paper's 3D strong-scaling problem with its uniform nodes, ISDC / IMLSDC / "
+                         "IPFASST (table1)")
+    ap.add_argument("--table1-config", choices=["2nd/2nd", "2nd/4th"], default=None,
+                    help="with --form table1: only this temporal-order configuration")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain copy of known size three times (reference for HBM counters)")
     return ap.parse_args()
@@ -368,6 +373,92 @@ def form_heat1d(pfmg, a):
             "config": {"workload": "1D heat, n=127, 4 slices, dt=0.01, Lobatto 5/3, jacobi V(2,2), 1 V-cycle/solve"}}
 
 
+# Table 1 of Sec. 4.3 (speedup of IPFASST over ISDC with the same spatial
+# resources; N_p = 1 is IMLSDC), for context next to the single-GPU figures.
+PAPER_TABLE1 = {
+    "2nd/2nd": {1: 0.8, 2: 1.2, 4: 2.1, 8: 3.5, 16: 5.6, 32: 8.6},
+    "2nd/4th": {1: 0.9, 2: 1.4, 4: 2.6, 8: 4.6, 12: 5.9, 24: 7.2},
+}
+
+
+def form_table1(pfmg, a):
+    """The 3D strong-scaling problem of Sec. 4.3 (nu = 1/3, T = 1,
+    u0 = sin(pi x) sin(pi y) sin(pi z), zero Dirichlet data; h = 1/128, i.e.
+    127^3 interior points), with the paper's uniform nodes whose quadrature
+    leaves out the left end point: second order in time (3 fine nodes over
+    backward Euler, 128 steps) and fourth order (5 fine nodes over 3, 24
+    steps).  Each solve is two V(2,2) red-black cycles; each step or block
+    iterates to a relative residual of 1e-9.  On one GPU the paper's time
+    ranks become slices of one block, advanced together: serial ISDC (one
+    level, one slice a block), serial IMLSDC (two levels, one slice) and
+    IPFASST with N_p slices a block are timed over the whole interval, and
+    the speedup over ISDC is reported next to the paper's Table 1.  Errors
+    are the max-norm distance of the final state to the PDE solution
+    exp(-pi^2 T) sin sin sin and to the semi-discrete one."""
+    import numpy as np
+    import torch
+
+    import inputs
+
+    n, nu, T = 127, 1.0 / 3.0, 1.0
+    h = 1.0 / (n + 1)
+    u0 = torch.from_numpy(inputs.sine_mode(n, (1, 1, 1), 3)).to("cuda")
+    shape0 = inputs.sine_mode(n, (1, 1, 1), 3)
+    pde = np.exp(-np.pi ** 2 * T) * shape0
+    mu = 3 * (-4.0 * np.sin(np.pi * h / 2) ** 2 / h ** 2)
+    ode = np.exp(nu * mu * T) * shape0
+    configs = {"2nd/2nd": dict(nf=3, nc=2, steps=128, nps=(2, 4, 8, 16, 32)),
+               "2nd/4th": dict(nf=5, nc=3, steps=24, nps=(2, 4, 8, 12, 24))}
+    if a.table1_config:
+        configs = {k: v for k, v in configs.items() if k == a.table1_config}
+    out = {}
+    for name, cf in configs.items():
+        dt = T / cf["steps"]
+        rows = []
+        runs = [("ISDC", 1, 0)] + [("IMLSDC", 1, cf["nc"])] + [("IPFASST", npr, cf["nc"]) for npr in cf["nps"]]
+        for kind, P, nc in runs:
+            c = pfmg.Context(pfmg.pfmg_default_params(
+                dim=3, n=n, nu=nu, dt=dt, n_slices=P, nodes_fine=cf["nf"], nodes_coarse=nc,
+                node_family=pfmg.NODES_UNIFORM, smoother=pfmg.SMOOTH_RBGS, omega=1.0, vcycles_per_solve=2,
+                pfasst_tol=1e-9, pfasst_max_iter=50))
+            nblocks = cf["steps"] // P
+
+            def interval():
+                u, its, ok = u0, [], True
+                for _ in range(nblocks):
+                    st, it, res = c.run_block(u)
+                    its.append(it)
+                    ok = ok and st == pfmg.OK
+                    u = c.get(pfmg.U_FINE, P - 1, cf["nf"] - 1, host=False)
+                return u, its, ok
+
+            for _ in range(max(1, a.warmup)):
+                interval()
+            t, outs = _time_blocks(interval, max(1, a.steps))
+            u_end, its, ok = outs[-1]
+            ue = u_end.cpu().numpy()
+            rows.append({"method": kind, "n_p": P, "blocks": nblocks, "s": round(t, 4), "converged": ok,
+                         "iterations_per_block": round(float(np.mean(its)), 2), "iterations_max": int(max(its)),
+                         "pde_error": float(np.max(np.abs(ue - pde))), "ode_error": float(np.max(np.abs(ue - ode)))})
+            c.close()
+            del c
+            torch.cuda.empty_cache()
+        t_isdc = rows[0]["s"]
+        for r in rows:
+            r["speedup_vs_isdc"] = round(t_isdc / r["s"], 3)
+            r["paper_speedup"] = PAPER_TABLE1[name].get(r["n_p"]) if r["method"] != "ISDC" else None
+        out[name] = rows
+    conv = [(r["s"], name, r["method"], r["n_p"]) for name, rows in out.items() for r in rows if r["converged"]]
+    best = min(conv) if conv else (None, None, None, None)
+    return {"metric": "s to T = 1 (3D heat, Sec. 4.3 strong-scaling problem)", "value": best[0], "unit": "s",
+            "form": "paper's uniform nodes: ISDC / IMLSDC / IPFASST over the whole interval (Table 1)",
+            "best": {"config": best[1], "method": best[2], "n_p": best[3]}, "configs": out,
+            "higher_is_better": False,
+            "dtype": "f64", "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": "3D heat, 127^3, nu=1/3, T=1, sin sin sin, uniform nodes 3/2 (128 steps) and "
+                                   "5/3 (24 steps), rbgs V(2,2), 2 V-cycles/solve, residual 1e-9"}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -383,7 +474,7 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     if a.form:
         fn = {"mixed": form_mixed, "batched": form_batched, "learned": form_learned,
-              "solve-policies": form_solve_policies, "heat1d": form_heat1d}[a.form]
+              "solve-policies": form_solve_policies, "heat1d": form_heat1d, "table1": form_table1}[a.form]
         print(json.dumps(fn(pfmg, a), default=float), flush=True)
         return
     if a.calibrate_copy:

@@ -51,7 +51,7 @@ enum {
     PFMG_ERR_NAN = -5         /* a norm evaluated to NaN or Inf              */
 };
 
-enum { PFMG_NODES_LOBATTO = 0 };
+enum { PFMG_NODES_LOBATTO = 0, PFMG_NODES_UNIFORM = 1 };
 enum { PFMG_SMOOTH_JACOBI = 0, PFMG_SMOOTH_RBGS = 1 };
 enum { PFMG_FP64 = 0, PFMG_MIXED = 1 };
 enum { PFMG_GUESS_PREV = 0, PFMG_GUESS_LEARNED = 1 };
@@ -69,11 +69,19 @@ enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
  *                    n in {1, 2}, which is solved exactly.
  *   nu, dt           diffusion coefficient (> 0) and slice length (> 0).
  *   n_slices         P, the time slices of one PFASST block (>= 1).
- *   nodes_fine       Gauss-Lobatto nodes per slice on the fine level (2..9).
+ *   nodes_fine       nodes per slice on the fine level (2..9), the left end
+ *                    point included.
  *   nodes_coarse     nodes on the coarse PFASST level (a subset of the fine
- *                    nodes: 3 with 5 fine nodes), or 0 for a single level
- *                    (ISDC).  The coarse level uses the grid (n+1)/2 - 1.
- *   node_family      PFMG_NODES_LOBATTO.
+ *                    nodes: 3 with 5 fine nodes, 2 with 3), or 0 for a
+ *                    single level (ISDC).  The coarse level uses the grid
+ *                    (n+1)/2 - 1.
+ *   node_family      PFMG_NODES_LOBATTO: Gauss-Lobatto nodes, the quadrature
+ *                    through every node (Sec. 2.1).  PFMG_NODES_UNIFORM:
+ *                    nodes m/M (M = nodes - 1) with a quadrature that leaves
+ *                    out the left end point (q_{m,0} = 0, f interpolated
+ *                    through nodes 1..M), the paper's second-order (3 nodes)
+ *                    and fourth-order (5 nodes) methods of Sec. 3 and 4.3;
+ *                    2 nodes give backward Euler.
  *   smoother         PFMG_SMOOTH_JACOBI (weighted, omega) or
  *                    PFMG_SMOOTH_RBGS (red = (i+j+k) even in 1-based
  *                    interior indices, red then black, weight omega).

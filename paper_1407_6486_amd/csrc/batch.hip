@@ -173,8 +173,10 @@ bool BatchSolver::init_host(const pfmg_params *pp, int np, std::string &why)
         total_items += B.items;
     }
     for (int lev = 0; lev < nl; ++lev) {
-        if (!lobatto_nodes_ld(nn[lev], s_ld[lev])) { why = "node construction failed"; return false; }
-        if (!collocation_matrices(nn[lev], s_ld[lev], Q[lev], S[lev], d[lev])) { why = "Q construction failed"; return false; }
+        if (!family_nodes_ld(p.node_family, nn[lev], s_ld[lev])) { why = "node construction failed"; return false; }
+        if (!collocation_matrices(nn[lev], s_ld[lev], Q[lev], S[lev], d[lev], p.node_family == PFMG_NODES_UNIFORM ? 1 : 0)) {
+            why = "Q construction failed"; return false;
+        }
     }
     if (nl > 1)
         for (int mc = 0; mc < nn[1]; ++mc) {

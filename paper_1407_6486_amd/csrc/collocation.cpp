@@ -1,16 +1,19 @@
 // Collocation matrices of the library (host, long double, rounded once).
 //
 // Gauss-Lobatto nodes on [0, 1]: the end points plus the roots of P'_M,
-// bracketed by sign changes on a fine grid and polished by Newton.  The
-// integration matrix of Sec. 2.1, Q[m][i] = int_0^{s_m} l_i, is obtained
-// from exactness on monomials: sum_i Q[m][i] s_i^j = s_m^{j+1} / (j+1),
-// j = 0..M, a Vandermonde system solved by Gaussian elimination with
-// partial pivoting.  S[m][i] = Q[m+1][i] - Q[m][i] are the node-to-node
-// integrals of eq. sdc-be; d[m] = s_m - s_{m-1} the backward-Euler substeps
-// of eq. Qbe.
+// bracketed by sign changes on a fine grid and polished by Newton.  Uniform
+// nodes: m / M, with a quadrature that leaves out the left end point (the
+// second- and fourth-order methods of Sec. 3).  The integration matrix of
+// Sec. 2.1, Q[m][i] = int_0^{s_m} l_i, is obtained from exactness on
+// monomials: sum_i Q[m][i] s_i^j = s_m^{j+1} / (j+1) over the quadrature's
+// nodes (all of them, or 1..M) and degrees j below their count, a
+// Vandermonde system solved by Gaussian elimination with partial pivoting.
+// S[m][i] = Q[m+1][i] - Q[m][i] are the node-to-node integrals of eq.
+// sdc-be; d[m] = s_m - s_{m-1} the backward-Euler substeps of eq. Qbe.
 #include <cmath>
 #include <vector>
 
+#include "../../include/pfmg.h"
 #include "collocation.h"
 
 namespace pfmg {
@@ -75,16 +78,27 @@ bool lobatto_nodes_ld(int nnodes, long double *s)
     return true;
 }
 
-bool collocation_matrices(int nnodes, const long double *s, double *Q, double *S, double *d)
+bool family_nodes_ld(int family, int nnodes, long double *s)
 {
-    const int nn = nnodes;
-    if (nn < 2 || nn > 16) return false;
-    std::vector<ld> Ql(nn * nn);
-    for (int m = 0; m < nn; ++m) {
-        // V^T x = rhs with V[i][j] = s_i^j: rows j, columns i.
+    if (family == PFMG_NODES_LOBATTO) return lobatto_nodes_ld(nnodes, s);
+    if (family != PFMG_NODES_UNIFORM || nnodes < 2 || nnodes > 16) return false;
+    for (int m = 0; m < nnodes; ++m) s[m] = (ld)m / (ld)(nnodes - 1);
+    return true;
+}
+
+bool collocation_matrices(int nnodes, const long double *s, double *Q, double *S, double *d, int first)
+{
+    if (nnodes < 2 || nnodes > 16 || first < 0 || first > 1) return false;
+    // the quadrature's nodes are s[first .. nnodes-1]: nq of them
+    const int nq = nnodes - first;
+    const long double *sq = s + first;
+    const int nn = nq;
+    std::vector<ld> Ql(nnodes * nnodes, 0.0L);
+    for (int m = 0; m < nnodes; ++m) {
+        // V^T x = rhs with V[i][j] = sq_i^j: rows j, columns i.
         std::vector<ld> A(nn * nn), r(nn);
         for (int j = 0; j < nn; ++j) {
-            for (int i = 0; i < nn; ++i) A[j * nn + i] = std::pow(s[i], (ld)j);
+            for (int i = 0; i < nn; ++i) A[j * nn + i] = std::pow(sq[i], (ld)j);
             r[j] = std::pow(s[m], (ld)(j + 1)) / (j + 1);
         }
         for (int c = 0; c < nn; ++c) {
@@ -107,13 +121,13 @@ bool collocation_matrices(int nnodes, const long double *s, double *Q, double *S
             for (int w = c + 1; w < nn; ++w) acc -= A[c * nn + w] * r[w];
             r[c] = acc / A[c * nn + c];
         }
-        for (int i = 0; i < nn; ++i) Ql[m * nn + i] = (m == 0) ? 0.0L : r[i];
+        for (int i = 0; i < nn; ++i) Ql[m * nnodes + first + i] = (m == 0) ? 0.0L : r[i];
     }
-    for (int q = 0; q < nn * nn; ++q) Q[q] = (double)Ql[q];
-    for (int m = 0; m + 1 < nn; ++m)
-        for (int i = 0; i < nn; ++i) S[m * nn + i] = (double)(Ql[(m + 1) * nn + i] - Ql[m * nn + i]);
+    for (int q = 0; q < nnodes * nnodes; ++q) Q[q] = (double)Ql[q];
+    for (int m = 0; m + 1 < nnodes; ++m)
+        for (int i = 0; i < nnodes; ++i) S[m * nnodes + i] = (double)(Ql[(m + 1) * nnodes + i] - Ql[m * nnodes + i]);
     d[0] = 0;
-    for (int m = 1; m < nn; ++m) d[m] = (double)(s[m] - s[m - 1]);
+    for (int m = 1; m < nnodes; ++m) d[m] = (double)(s[m] - s[m - 1]);
     return true;
 }
 

@@ -45,11 +45,14 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
     }
     if (p.n_slices < 1 || p.n_slices > 4096) { why = "n_slices must be in 1..4096"; return false; }
     if (p.nodes_fine < 2 || p.nodes_fine > 9) { why = "nodes_fine must be in 2..9"; return false; }
+    if (p.node_family != PFMG_NODES_LOBATTO && p.node_family != PFMG_NODES_UNIFORM) {
+        why = "node_family must be PFMG_NODES_LOBATTO or PFMG_NODES_UNIFORM"; return false;
+    }
     if (p.nodes_coarse != 0) {
         if (p.nodes_coarse < 2 || p.nodes_coarse > p.nodes_fine) { why = "bad nodes_coarse"; return false; }
         if (p.n < 3) { why = "two levels need n >= 3"; return false; }
         long double sf[16], sc[16];
-        if (!lobatto_nodes_ld(p.nodes_fine, sf) || !lobatto_nodes_ld(p.nodes_coarse, sc)) {
+        if (!family_nodes_ld(p.node_family, p.nodes_fine, sf) || !family_nodes_ld(p.node_family, p.nodes_coarse, sc)) {
             why = "node construction failed"; return false;
         }
         for (int mc = 0; mc < p.nodes_coarse; ++mc) {
@@ -58,7 +61,6 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
             if (!found) { why = "coarse nodes must be a subset of the fine nodes (injection in time)"; return false; }
         }
     }
-    if (p.node_family != PFMG_NODES_LOBATTO) { why = "only Lobatto nodes are supported"; return false; }
     if (p.smoother != PFMG_SMOOTH_JACOBI && p.smoother != PFMG_SMOOTH_RBGS) { why = "bad smoother"; return false; }
     if (p.nu_pre < 0 || p.nu_post < 0 || p.nu_pre + p.nu_post == 0 || p.nu_pre > 16 || p.nu_post > 16) {
         why = "smoothing sweeps must be in 0..16 and not both 0"; return false;
@@ -226,9 +228,11 @@ bool Solver::init_host(std::string &why)
     for (int lev = 0; lev < nl; ++lev) {
         PLevel &Lv = L[lev];
         const int nn = lev == 0 ? p.nodes_fine : p.nodes_coarse;
-        if (!lobatto_nodes_ld(nn, Lv.s_ld)) { why = "node construction failed"; return false; }
+        if (!family_nodes_ld(p.node_family, nn, Lv.s_ld)) { why = "node construction failed"; return false; }
         for (int q = 0; q < nn; ++q) Lv.s[q] = (double)Lv.s_ld[q];
-        if (!collocation_matrices(nn, Lv.s_ld, Lv.Q, Lv.S, Lv.d)) { why = "Q construction failed"; return false; }
+        if (!collocation_matrices(nn, Lv.s_ld, Lv.Q, Lv.S, Lv.d, p.node_family == PFMG_NODES_UNIFORM ? 1 : 0)) {
+            why = "Q construction failed"; return false;
+        }
     }
     if (nl > 1) {
         for (int mc = 0; mc < p.nodes_coarse; ++mc) {

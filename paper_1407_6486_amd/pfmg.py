@@ -28,7 +28,7 @@ _lib = C.CDLL(LIB_PATH)
 # statuses and enums (include/pfmg.h)
 OK, NOT_CONVERGED, STALLED = 0, 1, 2
 ERR_ARG, ERR_WORKSPACE, ERR_HIP, ERR_STATE, ERR_NAN = -1, -2, -3, -4, -5
-NODES_LOBATTO = 0
+NODES_LOBATTO, NODES_UNIFORM = 0, 1
 SMOOTH_JACOBI, SMOOTH_RBGS = 0, 1
 FP64, MIXED = 0, 1
 GUESS_PREV, GUESS_LEARNED = 0, 1

@@ -70,6 +70,22 @@ def test_small_workspace_rejected_without_touching_the_gpu(pf):
     assert ei.value.status == pf.ERR_WORKSPACE
 
 
+def test_node_families_on_the_host(pf):
+    """Uniform nodes: 5/3 and 3/2 (coarse nodes a subset of the fine ones)
+    and 5/2 are accepted; 5/4 (0, 1/3, 2/3, 1) is not a subset; an unknown
+    family is rejected."""
+    U = pf.NODES_UNIFORM
+    for nf, nc in ((5, 3), (3, 2), (5, 2), (5, 0), (2, 0)):
+        assert pf.pfmg_workspace_bytes(pf.pfmg_default_params(n=31, nodes_fine=nf, nodes_coarse=nc,
+                                                              node_family=U)) > 0
+    for kw in ({"nodes_fine": 5, "nodes_coarse": 4, "node_family": U},
+               {"nodes_fine": 4, "nodes_coarse": 3, "node_family": U},
+               {"node_family": 2}):
+        with pytest.raises(pf.PfmgError) as ei:
+            pf.pfmg_workspace_bytes(pf.pfmg_default_params(n=31, **kw))
+        assert ei.value.status == pf.ERR_ARG
+
+
 def test_valid_degenerate_sizes_accepted(pf):
     for n, nc in ((1, 0), (3, 3), (5, 0), (95, 3)):
         p = pf.pfmg_default_params(n=n, nodes_coarse=nc, n_slices=1)

@@ -109,6 +109,18 @@ hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, Vi
 hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> Fm1,
                    View<double> Im, View<double> tau1, View<double> tau0, View<double> b,
                    hipStream_t s);
+// sdc_integrals and the first node's sdc_rhs in one pass (node 0 of U and F
+// first copied from Usrc / Fsrc when they are set; tau: all coarse nodes,
+// or null on the fine level).
+hipError_t sdc_start(const Tiling &t, int nn, double dt, const double *S, double delta1, View<double> U,
+                     View<double> F, View<double> Usrc, View<double> Fsrc, View<double> I, View<double> tau,
+                     View<double> b, hipStream_t s);
+// apply_L into F and, from the same loads of u, sdc_rhs of the next node
+// (Fn1, In, t1, t0 as sdc_rhs's Fm1, Im, tau1, tau0); for launches that
+// apply_L would run column-blocked (3D, below the z-marching size).
+bool apply_L_rhs_ok(const Tiling &t);
+hipError_t apply_L_rhs(const Tiling &t, double nu, View<double> u, View<double> F, double delta, View<double> Fn1,
+                       View<double> In, View<double> t1, View<double> t0, View<double> b, hipStream_t s);
 // FAS injection (t on the coarse grids): Uc[mc] = Uold[mc] = Uf[cmap[mc]] at
 // 2J, Tau[mc] = dt sum_i Qf[cmap[mc]][i] Ff[i] at 2J.
 hipError_t fas_inject(const Tiling &t, int nnf, int nnc, const int *cmap, double dt,

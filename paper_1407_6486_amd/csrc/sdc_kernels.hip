@@ -6,6 +6,11 @@
 //                all M node-to-node integrals of one slice in one pass.
 //  sdc_rhs       right-hand side of the node solve of eq. SDCcompactLIII in
 //                node-to-node form, plus the FAS difference on level 1.
+//  sdc_start     the start of a sweep in one pass: node 0 taken from a
+//                source (the previous slice's last node) when given, all
+//                integrals, and the first node solve's right-hand side.
+//  apply_L_rhs   F at one node and the next node solve's right-hand side
+//                from the same loads (column-blocked small launches).
 //  fas_inject /  FAS coarsening (Sec. 2.3): point-wise injection of U and
 //  fas_tau       of the fine node integrals dt Q_f F_f, minus the coarse
 //                integrals dt Q_c F_c of the injected state.
@@ -99,6 +104,93 @@ __global__ __launch_bounds__(BLOCK) void sdc_rhs_kernel(Tiling t, double delta, 
     double v = fp(Um, q)[o] - q.par(delta) * fp(Fm1, q)[o] + fp(Im, q)[o];
     if (t1.p) v = v + (fp(t1, q)[o] - fp(t0, q)[o]);
     fp(b, q)[o] = v;
+}
+
+// sdc_integrals followed by sdc_rhs for the first node, with the same
+// arithmetic; with Usrc / Fsrc set, node 0 of U and F is first copied from
+// them (the send-forward of the coarse chain and of the predictor rounds).
+template <int DIM, int NN>
+__global__ __launch_bounds__(BLOCK) void sdc_start_kernel(Tiling t, int nn_rt, double dt, const double *__restrict__ S,
+                                                          double delta1, View<double> U, View<double> F,
+                                                          View<double> Usrc, View<double> Fsrc, View<double> I,
+                                                          View<double> tau, View<double> b)
+{
+    const int nn = NN > 0 ? NN : nn_rt;
+    Pt q; int i, j, k; long o;
+    if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    const long f_node = node_stride(q.n, DIM);
+    const double h = q.par(dt);
+    double *u = fp(U, q) + o;
+    double *f = fp(F, q) + o;
+    double fv[MAXN];
+    double u0;
+    if (Usrc.p) {
+        u0 = fp(Usrc, q)[o];
+        fv[0] = fp(Fsrc, q)[o];
+    } else {
+        u0 = u[0];
+        fv[0] = f[0];
+    }
+    for (int w = 1; w < nn; ++w) fv[w] = f[w * f_node];
+    if (Usrc.p) {
+        u[0] = u0;
+        f[0] = fv[0];
+    }
+    double *out = fp(I, q) + o;
+    double i0 = 0.0;
+    for (int m = 0; m + 1 < nn; ++m) {
+        double acc = 0.0;
+        for (int w = 0; w < nn; ++w) acc += S[m * nn + w] * fv[w];
+        const double v = h * acc;
+        out[m * f_node] = v;
+        if (m == 0) i0 = v;
+    }
+    double v = u0 - q.par(delta1) * fv[1] + i0;
+    if (tau.p) v = v + (fp(tau, q)[o + f_node] - fp(tau, q)[o]);
+    fp(b, q)[o] = v;
+}
+
+// apply_L_kz plus, from the same column loads, the next node solve's
+// right-hand side b = u - delta Fn1 + In (+ t1 - t0), the sdc_rhs
+// arithmetic (Fn1: the old F of the next node, In its integral).
+__global__ __launch_bounds__(BLOCK) void apply_L_rhs_kz_kernel(Tiling t, double c, View<double> u, View<double> F,
+                                                               double delta, View<double> Fn1, View<double> In,
+                                                               View<double> t1, View<double> t0, View<double> b)
+{
+    Pt q; int i, j, k0, nk; long o;
+    if (!tile_col<KZ>(t, q, i, j, k0, nk, o)) return;
+    const long sy = row_stride(q.n), sz = plane_stride(q.n);
+    const double *__restrict__ uu = fp(u, q);
+    double *__restrict__ ff = fp(F, q);
+    const double *__restrict__ fn = fp(Fn1, q);
+    const double *__restrict__ in = fp(In, q);
+    double *__restrict__ bb = fp(b, q);
+    const double ih2 = (double)(q.n + 1) * (double)(q.n + 1);
+    const double cc = q.par(c), dl = q.par(delta);
+    double col[KZ + 2], xs[KZ], ys[KZ], rv[KZ];
+#pragma unroll
+    for (int w = 0; w < KZ + 2; ++w) col[w] = w <= nk + 1 ? uu[o + (long)(w - 1) * sz] : 0.0;
+#pragma unroll
+    for (int w = 0; w < KZ; ++w) {
+        if (w < nk) {
+            const long ow = o + (long)w * sz;
+            xs[w] = uu[ow - 1] + uu[ow + 1];
+            ys[w] = uu[ow - sy] + uu[ow + sy];
+            double v = col[w + 1] - dl * fn[ow] + in[ow];
+            if (t1.p) v = v + (fp(t1, q)[ow] - fp(t0, q)[ow]);
+            rv[w] = v;
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < KZ; ++w) {
+        if (w < nk) {
+            double s = xs[w];
+            s += ys[w] + (col[w] + col[w + 2]);
+            s -= 6.0 * col[w + 1];
+            ff[o + (long)w * sz] = cc * (ih2 * s);
+            bb[o + (long)w * sz] = rv[w];
+        }
+    }
 }
 
 struct IntMap {
@@ -326,6 +418,27 @@ hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, Vi
     if (nn == 5) PFMG_DISPATCH_N(t, sdc_integrals_kernel, 5, t, nn, dt, S, F, I);
     if (nn == 3) PFMG_DISPATCH_N(t, sdc_integrals_kernel, 3, t, nn, dt, S, F, I);
     PFMG_DISPATCH_N(t, sdc_integrals_kernel, 0, t, nn, dt, S, F, I);
+}
+
+hipError_t sdc_start(const Tiling &t, int nn, double dt, const double *S, double delta1, View<double> U,
+                     View<double> F, View<double> Usrc, View<double> Fsrc, View<double> I, View<double> tau,
+                     View<double> b, hipStream_t s)
+{
+    if (nn < 2 || nn > MAXN || (Usrc.p != nullptr) != (Fsrc.p != nullptr)) return hipErrorInvalidValue;
+    if (nn == 5) PFMG_DISPATCH_N(t, sdc_start_kernel, 5, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b);
+    if (nn == 3) PFMG_DISPATCH_N(t, sdc_start_kernel, 3, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b);
+    PFMG_DISPATCH_N(t, sdc_start_kernel, 0, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b);
+}
+
+bool apply_L_rhs_ok(const Tiling &t) { return t.dim == 3 && !stencil_z_ok(t); }
+
+hipError_t apply_L_rhs(const Tiling &t, double nu, View<double> u, View<double> F, double delta, View<double> Fn1,
+                       View<double> In, View<double> t1, View<double> t0, View<double> b, hipStream_t s)
+{
+    if (!apply_L_rhs_ok(t) || (t1.p != nullptr) != (t0.p != nullptr)) return hipErrorInvalidValue;
+    if (grid_blocks(t) == 0) return hipSuccess;
+    apply_L_rhs_kz_kernel<<<(unsigned)col_blocks<KZ>(t), BLOCK, 0, s>>>(t, nu, u, F, delta, Fn1, In, t1, t0, b);
+    return hipGetLastError();
 }
 
 hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> Fm1, View<double> Im,

@@ -93,7 +93,10 @@ struct Solver {
     hipError_t smooth(int n, int count, const int *mask, double alpha, View<T> u, View<T> b, View<T> tmp,
                       int sweeps, bool from_zero);
     hipError_t cycle_step(int lev, View<double> u, View<double> b, int count, const int *mask, double alpha);
-    hipError_t sweep(int lev, int p0, int p1);
+    // u0src / f0src (stride: one slice's node stack): node 0 of each swept
+    // slice is first copied from there, in the sweep's first kernel.
+    hipError_t sweep(int lev, int p0, int p1, const double *u0src = nullptr, const double *f0src = nullptr,
+                     long src_stride = 0);
     hipError_t fas_restrict(int p0, int p1);
     hipError_t interpolate(int p0, int p1);
     hipError_t predictor();
@@ -138,6 +141,7 @@ struct Solver {
     hipEvent_t evc[2] = {};           // coarse chain done through group G-2 / G-1
     int fine_streams = 1;             // streams the groups' fine sweeps alternate over
     bool late_interp = true;          // interpolation and residual of the early groups under the last chain
+    bool fused_sdc = true;            // sdc_start and apply_L_rhs in place of their separate kernels
     int mg_off = 0;                   // first multigrid scratch field of the current sweep
     template <typename T>
     View<T> scr(View<T> v) const { return View<T>{v.p ? v.p + (long)mg_off * v.stride : nullptr, v.stride}; }

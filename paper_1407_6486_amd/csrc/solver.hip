@@ -204,6 +204,10 @@ bool Solver::init_host(std::string &why)
     // its coarse chain on the chain stream (the earlier schedule).
     e = getenv("PFMG_LATE_INTERP");
     late_interp = !(e && atoi(e) == 0);
+    // PFMG_FUSED_SDC=0: the separate integral, right-hand-side, F and copy
+    // launches of a sweep.
+    e = getenv("PFMG_FUSED_SDC");
+    fused_sdc = !(e && atoi(e) == 0);
     e = getenv("PFMG_GROUPS");
     if (e && strchr(e, ',')) {
         for (const char *c = e; *c;) {
@@ -588,7 +592,7 @@ hipError_t Solver::learned_guess(View<double> u, View<double> b, int count, doub
 }
 
 // ------------------------------------------------------------------- SDC
-hipError_t Solver::sweep(int lev, int p0, int p1)
+hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const double *f0src, long src_stride)
 {
     PLevel &Lv = L[lev];
     const int count = p1 - p0;
@@ -597,29 +601,69 @@ hipError_t Solver::sweep(int lev, int p0, int p1)
     const long fs = Lv.fs, sst = (long)nn * fs, ist = (long)(nn - 1) * fs;
     const Tiling t = tl(Lv.n, count);
     const long pts = interior_points(Lv.n, dim) * count;
-    tstart("sdc_integrals", Lv.n, 8.0 * (2 * nn - 1), pts);
-    HC(k::sdc_integrals(t, nn, p.dt, Lv.dS, View<double>{Lv.slot(Lv.F, p0, 0), sst},
-                        View<double>{Lv.I + (long)p0 * ist, ist}, s));
-    tstop();
     View<double> Bv{Lv.B + (long)p0 * fs, fs};
-    for (int m = 0; m + 1 < nn; ++m) {
-        const double delta = p.dt * Lv.d[m + 1];
-        View<double> Um{Lv.slot(Lv.U, p0, m), sst}, Fm1{Lv.slot(Lv.F, p0, m + 1), sst};
-        View<double> Im{Lv.I + (long)p0 * ist + (long)m * fs, ist};
-        View<double> t1{nullptr, 0}, t0{nullptr, 0};
+    // views of the right-hand side of node m+1: U[m], F[m+1], I[m], tau
+    View<double> Um, Fm1, Im, t1, t0;
+    auto rhs_views = [&](int m) {
+        Um = {Lv.slot(Lv.U, p0, m), sst};
+        Fm1 = {Lv.slot(Lv.F, p0, m + 1), sst};
+        Im = {Lv.I + (long)p0 * ist + (long)m * fs, ist};
+        t1 = t0 = View<double>{nullptr, 0};
         if (lev == 1) {
             t1 = {Lv.slot(Lv.Tau, p0, m + 1), sst};
             t0 = {Lv.slot(Lv.Tau, p0, m), sst};
         }
-        tstart("sdc_rhs", Lv.n, lev == 1 ? 48 : 32, pts);
-        HC(k::sdc_rhs(t, delta, Um, Fm1, Im, t1, t0, Bv, s));
+    };
+    if (fused_sdc) {
+        // node 0 from the source, the integrals and the first right-hand side
+        const View<double> us{const_cast<double *>(u0src), src_stride};
+        const View<double> fsrc{const_cast<double *>(f0src), src_stride};
+        tstart("sdc_start", Lv.n, 8.0 * (2 * nn - 1) + 16 + (lev == 1 ? 16 : 0) + (u0src ? 16 : 0), pts);
+        HC(k::sdc_start(t, nn, p.dt, Lv.dS, p.dt * Lv.d[1], View<double>{Lv.slot(Lv.U, p0, 0), sst},
+                        View<double>{Lv.slot(Lv.F, p0, 0), sst}, us, fsrc, View<double>{Lv.I + (long)p0 * ist, ist},
+                        lev == 1 ? View<double>{Lv.slot(Lv.Tau, p0, 0), sst} : View<double>{nullptr, 0}, Bv, s));
         tstop();
-        View<double> Uv{Lv.slot(Lv.U, p0, m + 1), sst};
+    } else {
+        if (u0src) {
+            HC(k::copy(t, View<double>{const_cast<double *>(u0src), src_stride},
+                       View<double>{Lv.slot(Lv.U, p0, 0), sst}, s));
+            HC(k::copy(t, View<double>{const_cast<double *>(f0src), src_stride},
+                       View<double>{Lv.slot(Lv.F, p0, 0), sst}, s));
+        }
+        tstart("sdc_integrals", Lv.n, 8.0 * (2 * nn - 1), pts);
+        HC(k::sdc_integrals(t, nn, p.dt, Lv.dS, View<double>{Lv.slot(Lv.F, p0, 0), sst},
+                            View<double>{Lv.I + (long)p0 * ist, ist}, s));
+        tstop();
+        rhs_views(0);
+        tstart("sdc_rhs", Lv.n, lev == 1 ? 48 : 32, pts);
+        HC(k::sdc_rhs(t, p.dt * Lv.d[1], Um, Fm1, Im, t1, t0, Bv, s));
+        tstop();
+    }
+    const bool fuse_rhs = fused_sdc && k::apply_L_rhs_ok(t);
+    for (int m = 0; m + 1 < nn; ++m) {
+        // Bv holds the right-hand side of node m+1
+        const double delta = p.dt * Lv.d[m + 1];
+        View<double> Uv{Lv.slot(Lv.U, p0, m + 1), sst}, Fv{Lv.slot(Lv.F, p0, m + 1), sst};
         HC(solve(lev, Uv, Bv, count, p.nu * delta, p.vcycles_per_solve, nullptr));
         if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+        const bool more = m + 2 < nn;
+        if (more) rhs_views(m + 1);
+        if (more && fuse_rhs) {
+            // F of node m+1 and the right-hand side of node m+2, which reads
+            // the old F of node m+2, not the new F of node m+1
+            tstart("apply_L", Lv.n, 16, pts);
+            HC(k::apply_L_rhs(t, p.nu, Uv, Fv, p.dt * Lv.d[m + 2], Fm1, Im, t1, t0, Bv, s));
+            tstop();
+            continue;
+        }
         tstart("apply_L", Lv.n, 16, pts);
-        HC(k::apply_L(t, p.nu, Uv, Fm1, s));
+        HC(k::apply_L(t, p.nu, Uv, Fv, s));
         tstop();
+        if (more) {
+            tstart("sdc_rhs", Lv.n, lev == 1 ? 48 : 32, pts);
+            HC(k::sdc_rhs(t, p.dt * Lv.d[m + 2], Um, Fm1, Im, t1, t0, Bv, s));
+            tstop();
+        }
     }
     return hipSuccess;
 }
@@ -699,12 +743,10 @@ hipError_t Solver::predictor()
     const long cst = (long)Cs.nn * Cs.fs;
     HC(fas_restrict(0, P));
     for (int j = 0; j < P; ++j) {
-        if (j >= 1) {
-            const int cnt = P - j;
-            HC(k::copy(tl(Cs.n, cnt), View<double>{Cs.slot(Cs.U, j - 1, Mc), cst}, View<double>{Cs.slot(Cs.U, j, 0), cst}, s));
-            HC(k::copy(tl(Cs.n, cnt), View<double>{Cs.slot(Cs.F, j - 1, Mc), cst}, View<double>{Cs.slot(Cs.F, j, 0), cst}, s));
-        }
-        HC(sweep(1, j, P));
+        // round j >= 1: slices j .. P-1 first take node 0 from the previous
+        // slice's last node (in the sweep's first kernel)
+        if (j >= 1) HC(sweep(1, j, P, Cs.slot(Cs.U, j - 1, Mc), Cs.slot(Cs.F, j - 1, Mc), cst));
+        else HC(sweep(1, j, P));
         if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
     }
     return interpolate(0, P);
@@ -796,9 +838,7 @@ hipError_t Solver::chain_step(int q)
     const int Mc = Cs.nn - 1;
     const double *us = q == 0 ? ublock_c : Cs.slot(Cs.U, q - 1, Mc);
     const double *fsrc = q == 0 ? fublock_c : Cs.slot(Cs.F, q - 1, Mc);
-    HC(k::copy(tl(Cs.n, 1), View<double>{const_cast<double *>(us), 0}, View<double>{Cs.slot(Cs.U, q, 0), 0}, s));
-    HC(k::copy(tl(Cs.n, 1), View<double>{const_cast<double *>(fsrc), 0}, View<double>{Cs.slot(Cs.F, q, 0), 0}, s));
-    return sweep(1, q, q + 1);
+    return sweep(1, q, q + 1, us, fsrc, 0);
 }
 
 // The same iteration with the slices in groups: the fine sweep and FAS

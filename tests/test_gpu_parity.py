@@ -407,6 +407,33 @@ def test_nan_input_reports_err_nan(pf):
     assert ei.value.status == pf.ERR_NAN
 
 
+@pytest.mark.parametrize("n,P,nf,nc,fam", [(31, 4, 5, 3, 0), (63, 3, 3, 2, 1), (15, 8, 5, 3, 0)])
+def test_fused_sweep_launches_match_separate(pf, n, P, nf, nc, fam):
+    """The fused sweep kernels (node-0 copies + integrals + first right-hand
+    side; F + next right-hand side) give the separate launches' state."""
+    import os
+
+    say(f"fused vs separate sweep launches n={n} P={P} nodes {nf}/{nc} family {fam}")
+    u0, _ = inputs.random_fourier(n, 515) if n >= 7 else (inputs.random_field((n,) * 3, 5), None)
+    states = {}
+    for fused in ("1", "0"):
+        os.environ["PFMG_FUSED_SDC"] = fused
+        try:
+            c = make(pf, n=n, n_slices=P, nodes_fine=nf, nodes_coarse=nc, node_family=fam, dt=2e-3)
+        finally:
+            del os.environ["PFMG_FUSED_SDC"]
+        c.set_initial(u0)
+        res = [c.pfasst_iter() for _ in range(3)]
+        states[fused] = (res, [c.get(O.UF, p, nf - 1) for p in range(P)], [c.get(O.UC, p, nc - 1) for p in range(P)],
+                         [c.get(O.FC, p, 1) for p in range(P)])
+        c.close()
+    (r1, f1, c1, g1), (r0, f0, c0, g0) = states["1"], states["0"]
+    assert all(abs(a - b) <= 1e-13 * a for a, b in zip(r1, r0)), (r1, r0)
+    for p in range(P):
+        assert pins.rel_err(f1[p], f0[p]) <= 1e-14 and pins.rel_err(c1[p], c0[p]) <= 1e-14, p
+        assert pins.rel_err(g1[p], g0[p]) <= 1e-13, p
+
+
 @pytest.mark.parametrize("n,groups,streams,late", [(31, 2, 2, 1), (31, 4, 2, 1), (31, 5, 2, 1), (31, 4, 1, 1),
                                                    (63, 4, 2, 1), (31, 3, 1, 0), (63, 4, 1, 0)])
 def test_pipelined_iteration_matches_sequential(pf, n, groups, streams, late):

@@ -38,7 +38,8 @@ class MGPolicy(C.Structure):
 class Params(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int), ("nu", C.c_double), ("dt", C.c_double),
                 ("n_slices", C.c_int), ("nodes_fine", C.c_int), ("nodes_coarse", C.c_int),
-                ("mg", MGPolicy), ("interp_order", C.c_int), ("node_family", C.c_int)]
+                ("mg", MGPolicy), ("interp_order", C.c_int), ("node_family", C.c_int),
+                ("stencil_order", C.c_int)]
 
 
 def lib():
@@ -63,6 +64,12 @@ def lib():
         L.or_prolong_add.argtypes = [C.c_int, C.c_int, _dp, _dp]
         L.or_prolong4_add.argtypes = [C.c_int, C.c_int, _dp, _dp]
         L.or_coarsest.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _dp]
+        L.or_lap4.argtypes = [C.c_int, C.c_int, _dp, _dp]
+        L.or_resid4.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _dp, _dp]
+        L.or_smooth4.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, _dp, _dp]
+        L.or_vcycle4.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, _dp, _dp]
+        L.or_mg_solve4.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(MGPolicy), _dp, _dp, _dp]
+        L.or_mg_solve4.restype = C.c_int
         L.or_vcycle.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double,
                                 C.c_int, C.c_int, _dp, _dp]
         L.orf_vcycle.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double,
@@ -188,6 +195,34 @@ def vcycle32(dim, alpha, b, u, smoother=RBGS, omega=1.0, nu1=2, nu2=2):
     lib().orf_vcycle(dim, u.shape[0], alpha, smoother, omega, nu1, nu2, _p(b), _p(u)); return u
 
 
+def lap4(dim, u):
+    u = np.ascontiguousarray(u, dtype=np.float64); o = _out(u)
+    lib().or_lap4(dim, u.shape[0], _p(u), _p(o)); return o
+
+
+def resid4(dim, alpha, b, u):
+    b = np.ascontiguousarray(b, dtype=np.float64); u = np.ascontiguousarray(u, dtype=np.float64)
+    o = _out(u); lib().or_resid4(dim, u.shape[0], alpha, _p(b), _p(u), _p(o)); return o
+
+
+def smooth4(dim, alpha, smoother, omega, b, u):
+    u = np.array(u, dtype=np.float64, order="C"); b = np.ascontiguousarray(b, dtype=np.float64)
+    lib().or_smooth4(dim, u.shape[0], alpha, smoother, omega, _p(b), _p(u)); return u
+
+
+def vcycle4(dim, alpha, b, u, smoother=RBGS, omega=1.0, nu1=2, nu2=2):
+    u = np.array(u, dtype=np.float64, order="C"); b = np.ascontiguousarray(b, dtype=np.float64)
+    lib().or_vcycle4(dim, u.shape[0], alpha, smoother, omega, nu1, nu2, _p(b), _p(u)); return u
+
+
+def mg_solve4(dim, alpha, b, u, pol):
+    """Returns (u, cycles, relres) for (I - alpha L4) u = b."""
+    u = np.array(u, dtype=np.float64, order="C"); b = np.ascontiguousarray(b, dtype=np.float64)
+    rr = C.c_double(0.0)
+    nc = lib().or_mg_solve4(dim, u.shape[0], alpha, C.byref(pol), _p(b), _p(u), C.byref(rr))
+    return u, nc, rr.value
+
+
 def policy(smoother=RBGS, nu1=2, nu2=2, omega=1.0, cycles=1, tol=1e-12, stall=0.75,
            max_cycles=50, mixed=0) -> MGPolicy:
     return MGPolicy(smoother, nu1, nu2, omega, cycles, tol, stall, max_cycles, mixed)
@@ -207,9 +242,10 @@ class Pfasst:
     ``nodes_coarse == 0``)."""
 
     def __init__(self, dim, n, nu, dt, n_slices, nodes_fine=5, nodes_coarse=3,
-                 mg: MGPolicy | None = None, interp_order: int = 2, node_family: int = LOBATTO):
+                 mg: MGPolicy | None = None, interp_order: int = 2, node_family: int = LOBATTO,
+                 stencil_order: int = 2):
         self.prm = Params(dim, n, nu, dt, n_slices, nodes_fine, nodes_coarse,
-                          mg if mg is not None else policy(), interp_order, node_family)
+                          mg if mg is not None else policy(), interp_order, node_family, stencil_order)
         self.dim, self.n, self.P = dim, n, n_slices
         self.nn = [nodes_fine, nodes_coarse]
         self.nc = (n + 1) // 2 - 1

@@ -84,6 +84,15 @@ void or_prolong_add(int dim, int nc, const double *ec, double *u);
  * inwards next to the boundary (the boundary value 0 is one of the four
  * points).  Needs nc >= 3. */
 void or_prolong4_add(int dim, int nc, const double *ec, double *u);
+/* Fourth-order discretisation (Sec. 4.3): L4 with odd reflection beyond
+ * the boundary, its residual, smoother (weighted Jacobi or red-black JOR,
+ * each colour from the values before its pass), a V-cycle whose finest
+ * level uses L4 above the second-order V-cycle, and the solve policy. */
+void or_lap4(int dim, int n, const double *u, double *out);
+void or_resid4(int dim, int n, double alpha, const double *b, const double *u, double *r);
+void or_smooth4(int dim, int n, double alpha, int smoother, double omega, const double *b, double *u);
+void or_vcycle4(int dim, int n, double alpha, int smoother, double omega, int nu1, int nu2,
+                const double *b, double *u);
 /* Exact solve of (I - alpha L_h) u = b for n in {1,2}. */
 void or_coarsest(int dim, int n, double alpha, const double *b, double *u);
 /* One V(nu1,nu2)-cycle on (I - alpha L_h) u = b, in place on u. */
@@ -120,6 +129,9 @@ typedef struct or_mg_policy {
  * after the last cycle (computed only when relres != NULL). */
 int or_mg_solve(int dim, int n, double alpha, const or_mg_policy *pol,
                 const double *b, double *u, double *relres);
+/* The same for (I - alpha L4) (FP64 only). */
+int or_mg_solve4(int dim, int n, double alpha, const or_mg_policy *pol,
+                 const double *b, double *u, double *relres);
 
 /* ---------------------------------------------------------------- PFASST */
 typedef struct or_params {
@@ -131,6 +143,7 @@ typedef struct or_params {
     or_mg_policy mg;         /* policy for every node solve (both levels) */
     int interp_order;        /* PFASST spatial interpolation: 2 d-linear, 4 cubic */
     int node_family;         /* OR_NODES_LOBATTO / OR_NODES_UNIFORM */
+    int stencil_order;       /* fine-level Laplacian: 2, or 4 (coarse level stays 2) */
 } or_params;
 
 typedef struct or_pfasst or_pfasst;

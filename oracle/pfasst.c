@@ -78,6 +78,8 @@ or_pfasst *or_pfasst_create(const or_params *prm)
     if (prm->dim < 1 || prm->dim > 3 || prm->n < 1 || prm->n_slices < 1) return NULL;
     if (prm->nodes_fine < 2 || prm->nodes_fine > 16) return NULL;
     if (prm->node_family != OR_NODES_LOBATTO && prm->node_family != OR_NODES_UNIFORM) return NULL;
+    if (prm->stencil_order != 2 && prm->stencil_order != 4) return NULL;
+    if (prm->stencil_order == 4 && prm->mg.mixed) return NULL;
     or_pfasst *c = (or_pfasst *)calloc(1, sizeof(or_pfasst));
     c->p = *prm;
     c->nl = prm->nodes_coarse > 0 ? 2 : 1;
@@ -125,10 +127,12 @@ void or_pfasst_destroy(or_pfasst *c)
     free(c);
 }
 
-/* F = nu L_h u on level lev. */
+/* F = nu L_h u on level lev (the fine level's L is fourth order when
+ * stencil_order is 4). */
 static void feval(or_pfasst *c, int lev, const double *u, double *f)
 {
-    or_lap(c->p.dim, c->n[lev], u, f);
+    if (lev == 0 && c->p.stencil_order == 4) or_lap4(c->p.dim, c->n[lev], u, f);
+    else or_lap(c->p.dim, c->n[lev], u, f);
     const size_t len = c->len[lev];
     for (size_t x = 0; x < len; ++x) f[x] = c->p.nu * f[x];
 }
@@ -179,7 +183,10 @@ void or_sdc_sweep(or_pfasst *c, int lev, int p)
             for (size_t x = 0; x < len; ++x) b[x] = b[x] + (t1[x] - t0[x]);
         }
         double *u = fld(c, c->U[lev], lev, p, m + 1);
-        c->vcyc[lev] += or_mg_solve(c->p.dim, c->n[lev], c->p.nu * dtm, &c->p.mg, b, u, NULL);
+        if (lev == 0 && c->p.stencil_order == 4)
+            c->vcyc[lev] += or_mg_solve4(c->p.dim, c->n[lev], c->p.nu * dtm, &c->p.mg, b, u, NULL);
+        else
+            c->vcyc[lev] += or_mg_solve(c->p.dim, c->n[lev], c->p.nu * dtm, &c->p.mg, b, u, NULL);
         feval(c, lev, u, fld(c, c->F[lev], lev, p, m + 1));
     }
     free(I);

@@ -105,6 +105,20 @@ enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
  *   guess_min_relres with PFMG_GUESS_LEARNED: a node solve is offered the
  *                    network's guess only while its plain guess has
  *                    |b - H U|_inf > guess_min_relres |b|_inf (0: always).
+ *   stencil_order    2, or 4: the fine level's Laplacian is fourth order
+ *                    (per axis (-u_{i-2} + 16u_{i-1} - 30u_i + 16u_{i+1}
+ *                    - u_{i+2}) / 12h^2, the value two steps beyond the
+ *                    boundary the odd reflection of the interior one) as in
+ *                    the fourth-order runs of Sec. 4.3.  F, the node solves
+ *                    (a V-cycle whose finest level smooths with L4 --
+ *                    weighted Jacobi, or red-black JOR with each colour from
+ *                    the values before its pass -- above the second-order
+ *                    cycle) and the residual use it; the coarse PFASST level
+ *                    stays second order.  FP64, plain guesses, single
+ *                    contexts only.
+ *   interp_order     PFASST spatial interpolation of the coarse correction:
+ *                    2 d-linear, 4 tensor-product cubic (Sec. 4.3; needs a
+ *                    coarse grid of n >= 3).  Single contexts only.
  */
 typedef struct pfmg_params {
     int32_t dim;
@@ -129,6 +143,8 @@ typedef struct pfmg_params {
     double pfasst_tol;
     int32_t pfasst_max_iter;
     double guess_min_relres;
+    int32_t stencil_order;
+    int32_t interp_order;
 } pfmg_params;
 
 /* Fills *p with the defaults: 3D, n = 127, nu = 1, dt = 1e-3, 16 slices,

@@ -87,6 +87,8 @@ pfmg_status pfmg_default_params(pfmg_params *p)
     p->pfasst_tol = 1e-10;
     p->pfasst_max_iter = 200;
     p->guess_min_relres = 0.0;
+    p->stencil_order = 2;
+    p->interp_order = 2;
     return PFMG_OK;
 }
 

@@ -119,6 +119,16 @@ hipError_t sdc_start(const Tiling &t, int nn, double dt, const double *S, double
 // (Fn1, In, t1, t0 as sdc_rhs's Fm1, Im, tau1, tau0); for launches that
 // apply_L would run column-blocked (3D, below the z-marching size).
 bool apply_L_rhs_ok(const Tiling &t);
+// Fourth-order fine level (stencil4.hip): F = nu L4 u; r = b - (u - alpha
+// L4 u); one smoothing pass for (I - alpha L4), out of place (colour -1:
+// weighted Jacobi on every point; 0 / 1: that colour of the red-black JOR
+// from src, the other points copied); u += cubic interpolation of e_c
+// (coarse grids (n+1)/2 - 1 >= 3).
+hipError_t apply_L4(const Tiling &t, double nu, View<double> u, View<double> F, hipStream_t s);
+hipError_t resid4(const Tiling &t, double alpha, View<double> b, View<double> u, View<double> r, hipStream_t s);
+hipError_t smooth4(const Tiling &t, double alpha, double omega, int colour, View<double> b, View<double> src,
+                   View<double> dst, hipStream_t s);
+hipError_t prolong4_add(const Tiling &t, View<double> ec, View<double> u, hipStream_t s);
 hipError_t apply_L_rhs(const Tiling &t, double nu, View<double> u, View<double> F, double delta, View<double> Fn1,
                        View<double> In, View<double> t1, View<double> t0, View<double> b, hipStream_t s);
 // FAS injection (t on the coarse grids): Uc[mc] = Uold[mc] = Uf[cmap[mc]] at

@@ -93,6 +93,13 @@ struct Solver {
     hipError_t smooth(int n, int count, const int *mask, double alpha, View<T> u, View<T> b, View<T> tmp,
                       int sweeps, bool from_zero);
     hipError_t cycle_step(int lev, View<double> u, View<double> b, int count, const int *mask, double alpha);
+    // Fourth-order fine level: the top of the V-cycle with L4, smoothing
+    // passes, the residual max-norm and F of a level's operator.
+    hipError_t vcycle4(int lev, View<double> u, View<double> b, int count, const int *mask, double alpha);
+    hipError_t smooth4(const Tiling &t, double alpha, View<double> u, View<double> b, View<double> tmp, int sweeps);
+    hipError_t resid_norm_lev(int lev, const Tiling &t, double alpha, View<double> b, View<double> u,
+                              unsigned long long *out);
+    hipError_t apply_F(int lev, const Tiling &t, View<double> u, View<double> F);
     // u0src / f0src (stride: one slice's node stack): node 0 of each swept
     // slice is first copied from there, in the sweep's first kernel.
     hipError_t sweep(int lev, int p0, int p1, const double *u0src = nullptr, const double *f0src = nullptr,

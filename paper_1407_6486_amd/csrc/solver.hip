@@ -62,6 +62,15 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
         }
     }
     if (p.smoother != PFMG_SMOOTH_JACOBI && p.smoother != PFMG_SMOOTH_RBGS) { why = "bad smoother"; return false; }
+    if (p.stencil_order != 2 && p.stencil_order != 4) { why = "stencil_order must be 2 or 4"; return false; }
+    if (p.interp_order != 2 && p.interp_order != 4) { why = "interp_order must be 2 or 4"; return false; }
+    if (p.stencil_order == 4 && (p.precision != PFMG_FP64 || p.guess != PFMG_GUESS_PREV)) {
+        why = "stencil_order 4 needs FP64 and plain guesses"; return false;
+    }
+    if (p.stencil_order == 4 && p.n < 3) { why = "stencil_order 4 needs n >= 3"; return false; }
+    if (p.interp_order == 4 && p.nodes_coarse > 0 && coarser(p.n) < 3) {
+        why = "cubic interpolation needs a coarse grid of n >= 3"; return false;
+    }
     if (p.nu_pre < 0 || p.nu_post < 0 || p.nu_pre + p.nu_post == 0 || p.nu_pre > 16 || p.nu_post > 16) {
         why = "smoothing sweeps must be in 0..16 and not both 0"; return false;
     }
@@ -135,8 +144,10 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
                 G.e = {f64(nl_, P), G.fs64};
                 G.b = {f64(nl_, P), G.fs64};
             }
-            // second buffer for out-of-place sweeps (Jacobi, fused red-black)
-            const bool pingpong = jac || (dim == 3 && nl_ >= 31);
+            // second buffer for out-of-place sweeps (Jacobi, fused red-black,
+            // the fourth-order smoother and residual on the fine level's
+            // finest grid)
+            const bool pingpong = jac || (dim == 3 && nl_ >= 31) || (lev == 0 && l == 0 && p.stencil_order == 4);
             if (pingpong) G.t = {f64(nl_, P), G.fs64};
             if (mixed) {
                 G.e32 = {f32(nl_, P), G.fs32};
@@ -399,8 +410,62 @@ hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> 
     return hipSuccess;
 }
 
+// The fine PFASST level's operator with stencil_order 4: smoothing and the
+// residual use L4 on the finest multigrid level, and the correction
+// equation below it is the second-order cycle.
+hipError_t Solver::vcycle4(int lev, View<double> u, View<double> b, int count, const int *m, double alpha)
+{
+    if (L[lev].mg.size() < 2) return hipErrorInvalidValue;
+    MGLevel &G = L[lev].mg[0];
+    MGLevel &C = L[lev].mg[1];
+    const Tiling t = tl(G.n, count, m);
+    const View<double> gt = scr(G.t), ce = scr(C.e), cb = scr(C.b);
+    if (!gt.p || !ce.p || !cb.p) return hipErrorInvalidValue;
+    HC(smooth4(t, alpha, u, b, gt, p.nu_pre));
+    HC(k::resid4(t, alpha, b, u, gt, s));
+    HC(k::restrict_fw(t, gt, cb, s));
+    HC(vcycle64(lev, 1, ce, cb, count, m, alpha));
+    HC(k::prolong_add(t, ce, u, s));
+    return smooth4(t, alpha, u, b, gt, p.nu_post);
+}
+
+// Sweeps of weighted Jacobi (every point, then copied back) or red-black
+// JOR (red from u into tmp, black from tmp back into u).
+hipError_t Solver::smooth4(const Tiling &t, double alpha, View<double> u, View<double> b, View<double> tmp, int sweeps)
+{
+    for (int q = 0; q < sweeps; ++q) {
+        if (p.smoother == PFMG_SMOOTH_RBGS) {
+            HC(k::smooth4(t, alpha, p.omega, 0, b, u, tmp, s));
+            HC(k::smooth4(t, alpha, p.omega, 1, b, tmp, u, s));
+        } else {
+            HC(k::smooth4(t, alpha, p.omega, -1, b, u, tmp, s));
+            HC(k::copy(t, tmp, u, s));
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t Solver::resid_norm_lev(int lev, const Tiling &t, double alpha, View<double> b, View<double> u,
+                                  unsigned long long *out)
+{
+    if (lev == 0 && p.stencil_order == 4) {
+        const View<double> r = scr(L[0].mg[0].t);
+        if (!r.p) return hipErrorInvalidValue;
+        HC(k::resid4(t, alpha, b, u, r, s));
+        return k::norm_inf(t, r, out, s);
+    }
+    return k::resid_norm(t, alpha, b, u, out, s);
+}
+
+hipError_t Solver::apply_F(int lev, const Tiling &t, View<double> u, View<double> F)
+{
+    if (lev == 0 && p.stencil_order == 4) return k::apply_L4(t, p.nu, u, F, s);
+    return k::apply_L(t, p.nu, u, F, s);
+}
+
 hipError_t Solver::vcycle64(int lev, int l, View<double> u, View<double> b, int count, const int *m, double alpha)
 {
+    if (lev == 0 && l == 0 && p.stencil_order == 4) return vcycle4(lev, u, b, count, m, alpha);
     MGLevel &G = L[lev].mg[l];
     const Tiling t = tl(G.n, count, m);
     if (use_bottom && k::vcycle_bottom_lds(G.n, dim, p.smoother, sizeof(double)) <= k::bottom_lds_max())
@@ -467,7 +532,7 @@ hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, dou
         if (relres_host) {
             HC(k::fill_u64(bits, 0, 2 * count, s));
             HC(k::norm_inf(tl(n, count), b, bits, s));
-            HC(k::resid_norm(tl(n, count), alpha, b, u, bits + count, s));
+            HC(resid_norm_lev(lev, tl(n, count), alpha, b, u, bits + count));
             HC(hipMemcpyAsync(hbits, bits, sizeof(unsigned long long) * 2 * count, hipMemcpyDeviceToHost, s));
             HC(hipStreamSynchronize(s));
             for (int q = 0; q < count; ++q) {
@@ -481,7 +546,7 @@ hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, dou
     // the residual below stall * the previous one, at most mg_max_cycles.
     HC(k::fill_u64(bits, 0, 2 * count, s));
     HC(k::norm_inf(tl(n, count), b, bits, s));
-    HC(k::resid_norm(tl(n, count), alpha, b, u, bits + count, s));
+    HC(resid_norm_lev(lev, tl(n, count), alpha, b, u, bits + count));
     HC(hipMemcpyAsync(hbits, bits, sizeof(unsigned long long) * 2 * count, hipMemcpyDeviceToHost, s));
     HC(hipStreamSynchronize(s));
     std::vector<double> nb(count), rold(count);
@@ -491,7 +556,7 @@ hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, dou
         if (!std::isfinite(nb[q]) || !std::isfinite(rold[q])) { last_solve_status = PFMG_ERR_NAN; return hipSuccess; }
     }
     // fine-level node solves: record the training pair, try the learned guess
-    const bool rec = lev == 0 && rec_pairs && rec_count + count <= rec_cap && dim == 3;
+    const bool rec = lev == 0 && rec_pairs && rec_count + count <= rec_cap && dim == 3 && p.stencil_order == 2;
     const bool learned = lev == 0 && unet && p.guess == PFMG_GUESS_LEARNED;
     if (rec || learned) HC(learned_guess(u, b, count, alpha, nb, rold, rec));
     int active = 0;
@@ -509,7 +574,7 @@ hipError_t Solver::solve(int lev, View<double> u, View<double> b, int count, dou
         ++c;
         vcount[lev] += active;
         HC(k::fill_u64(bits + count, 0, count, s));
-        HC(k::resid_norm(tl(n, count, mask), alpha, b, u, bits + count, s));
+        HC(resid_norm_lev(lev, tl(n, count, mask), alpha, b, u, bits + count));
         HC(hipMemcpyAsync(hbits + count, bits + count, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, s));
         HC(hipStreamSynchronize(s));
         active = 0;
@@ -639,7 +704,7 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
         HC(k::sdc_rhs(t, p.dt * Lv.d[1], Um, Fm1, Im, t1, t0, Bv, s));
         tstop();
     }
-    const bool fuse_rhs = fused_sdc && k::apply_L_rhs_ok(t);
+    const bool fuse_rhs = fused_sdc && k::apply_L_rhs_ok(t) && !(lev == 0 && p.stencil_order == 4);
     for (int m = 0; m + 1 < nn; ++m) {
         // Bv holds the right-hand side of node m+1
         const double delta = p.dt * Lv.d[m + 1];
@@ -657,7 +722,7 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
             continue;
         }
         tstart("apply_L", Lv.n, 16, pts);
-        HC(k::apply_L(t, p.nu, Uv, Fv, s));
+        HC(apply_F(lev, t, Uv, Fv));
         tstop();
         if (more) {
             tstart("sdc_rhs", Lv.n, lev == 1 ? 48 : 32, pts);
@@ -693,11 +758,14 @@ hipError_t Solver::interpolate(int p0, int p1)
                         View<double>{Cs.slot(Cs.Uold, p0, 0), cst}, View<double>{dc, dst}, s));
     const long pts = interior_points(Fn.n, dim) * count * Fn.nn;
     tstart("prolong", Fn.n, 16 + 8.0 / (dim == 3 ? 8 : 2), pts);
-    HC(k::prolong_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs}, s));
+    if (p.interp_order == 4)
+        HC(k::prolong4_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs}, s));
+    else
+        HC(k::prolong_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs}, s));
     tstop();
     tstart("apply_L", Fn.n, 16, pts);
-    HC(k::apply_L(tl(Fn.n, count * Fn.nn), p.nu, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs},
-                  View<double>{Fn.slot(Fn.F, p0, 0), Fn.fs}, s));
+    HC(apply_F(0, tl(Fn.n, count * Fn.nn), View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs},
+               View<double>{Fn.slot(Fn.F, p0, 0), Fn.fs}));
     tstop();
     return hipSuccess;
 }
@@ -724,7 +792,7 @@ hipError_t Solver::spread_body()
 {
     PLevel &Fn = L[0];
     HC(k::copy(tl(Fn.n, P * Fn.nn), View<double>{ublock, 0}, View<double>{Fn.U, Fn.fs}, s));
-    HC(k::apply_L(tl(Fn.n, P * Fn.nn), p.nu, View<double>{ublock, 0}, View<double>{Fn.F, Fn.fs}, s));
+    HC(apply_F(0, tl(Fn.n, P * Fn.nn), View<double>{ublock, 0}, View<double>{Fn.F, Fn.fs}));
     if (nl > 1) {
         HC(k::inject(tl(L[1].n, 1), View<double>{ublock, 0}, View<double>{ublock_c, 0}, s));
         HC(k::apply_L(tl(L[1].n, 1), p.nu, View<double>{ublock_c, 0}, View<double>{fublock_c, 0}, s));

@@ -86,6 +86,30 @@ def test_node_families_on_the_host(pf):
         assert ei.value.status == pf.ERR_ARG
 
 
+def test_stencil_and_interpolation_orders_on_the_host(pf):
+    for kw in ({"stencil_order": 4}, {"interp_order": 4}, {"stencil_order": 4, "interp_order": 4, "n": 31},
+               {"stencil_order": 4, "nodes_coarse": 0, "n": 3, "dim": 1}):
+        assert pf.pfmg_workspace_bytes(pf.pfmg_default_params(**kw)) > 0, kw
+    for kw in ({"stencil_order": 3}, {"interp_order": 1}, {"stencil_order": 4, "precision": pf.MIXED},
+               {"stencil_order": 4, "guess": pf.GUESS_LEARNED, "vcycles_per_solve": 0},
+               {"interp_order": 4, "n": 5}):
+        with pytest.raises(pf.PfmgError) as ei:
+            pf.pfmg_workspace_bytes(pf.pfmg_default_params(**kw))
+        assert ei.value.status == pf.ERR_ARG, kw
+    with pytest.raises(pf.PfmgError) as ei:
+        pf.pfmg_batch_workspace_bytes([pf.pfmg_default_params(n=31, stencil_order=4)])
+    assert ei.value.status == pf.ERR_ARG
+    # the fourth-order smoother and residual need an out-of-place buffer on
+    # the finest grid, which red-black smoothing of a small grid otherwise
+    # does not reserve: one more field per slice
+    for n, dim in ((15, 3), (7, 3), (63, 1)):
+        kw = dict(n=n, dim=dim, n_slices=3, nodes_coarse=0)
+        extra = pf.pfmg_workspace_bytes(pf.pfmg_default_params(stencil_order=4, **kw)) - \
+            pf.pfmg_workspace_bytes(pf.pfmg_default_params(**kw))
+        elems = (n + 1) * (n + 2) ** 2 + 1 if dim == 3 else n + 2
+        assert extra >= 3 * elems * 8, (n, dim, extra)
+
+
 def test_valid_degenerate_sizes_accepted(pf):
     for n, nc in ((1, 0), (3, 3), (5, 0), (95, 3)):
         p = pf.pfmg_default_params(n=n, nodes_coarse=nc, n_slices=1)

@@ -67,7 +67,7 @@ def parse():
                          "the node-solve policies at 127^3 x 16 (solve-policies), the 1D latency and error report "
                          "(heat1d) or the paper's 3D strong-scaling problem with its uniform nodes, ISDC / IMLSDC / "
                          "IPFASST (table1)")
-    ap.add_argument("--table1-config", choices=["2nd/2nd", "2nd/4th"], default=None,
+    ap.add_argument("--table1-config", choices=["2nd/2nd", "2nd/4th", "4th/4th"], default=None,
                     help="with --form table1: only this temporal-order configuration")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain copy of known size three times (reference for HBM counters)")
@@ -378,17 +378,21 @@ def form_heat1d(pfmg, a):
 PAPER_TABLE1 = {
     "2nd/2nd": {1: 0.8, 2: 1.2, 4: 2.1, 8: 3.5, 16: 5.6, 32: 8.6},
     "2nd/4th": {1: 0.9, 2: 1.4, 4: 2.6, 8: 4.6, 12: 5.9, 24: 7.2},
+    "4th/4th": {1: 0.7, 2: 1.0, 4: 1.9, 8: 3.2, 12: 4.6, 24: 6.6},
 }
 
 
 def form_table1(pfmg, a):
     """The 3D strong-scaling problem of Sec. 4.3 (nu = 1/3, T = 1,
-    u0 = sin(pi x) sin(pi y) sin(pi z), zero Dirichlet data; h = 1/128, i.e.
-    127^3 interior points), with the paper's uniform nodes whose quadrature
-    leaves out the left end point: second order in time (3 fine nodes over
-    backward Euler, 128 steps) and fourth order (5 fine nodes over 3, 24
-    steps).  Each solve is two V(2,2) red-black cycles; each step or block
-    iterates to a relative residual of 1e-9.  On one GPU the paper's time
+    u0 = sin(pi x) sin(pi y) sin(pi z), zero Dirichlet data), with the
+    paper's uniform nodes whose quadrature leaves out the left end point:
+    second order in space and time (127^3, 3 fine nodes over backward
+    Euler, 128 steps), second order in space and fourth in time (127^3, 5
+    fine nodes over 3, 24 steps), fourth order in both (31^3 with the
+    fourth-order fine stencil over a second-order 15^3 coarse level, 24
+    steps).  The two-level methods interpolate in space with cubics, as the
+    paper's runs do.  Each solve is two V(2,2) red-black cycles; each step
+    or block iterates to a relative residual of 1e-9.  On one GPU the paper's time
     ranks become slices of one block, advanced together: serial ISDC (one
     level, one slice a block), serial IMLSDC (two levels, one slice) and
     IPFASST with N_p slices a block are timed over the whole interval, and
@@ -400,19 +404,25 @@ def form_table1(pfmg, a):
 
     import inputs
 
-    n, nu, T = 127, 1.0 / 3.0, 1.0
-    h = 1.0 / (n + 1)
-    u0 = torch.from_numpy(inputs.sine_mode(n, (1, 1, 1), 3)).to("cuda")
-    shape0 = inputs.sine_mode(n, (1, 1, 1), 3)
-    pde = np.exp(-np.pi ** 2 * T) * shape0
-    mu = 3 * (-4.0 * np.sin(np.pi * h / 2) ** 2 / h ** 2)
-    ode = np.exp(nu * mu * T) * shape0
-    configs = {"2nd/2nd": dict(nf=3, nc=2, steps=128, nps=(2, 4, 8, 16, 32)),
-               "2nd/4th": dict(nf=5, nc=3, steps=24, nps=(2, 4, 8, 12, 24))}
+    nu, T = 1.0 / 3.0, 1.0
+    configs = {"2nd/2nd": dict(n=127, so=2, nf=3, nc=2, steps=128, nps=(2, 4, 8, 16, 32)),
+               "2nd/4th": dict(n=127, so=2, nf=5, nc=3, steps=24, nps=(2, 4, 8, 12, 24)),
+               "4th/4th": dict(n=31, so=4, nf=5, nc=3, steps=24, nps=(2, 4, 8, 12, 24))}
     if a.table1_config:
         configs = {k: v for k, v in configs.items() if k == a.table1_config}
     out = {}
     for name, cf in configs.items():
+        n = cf["n"]
+        h = 1.0 / (n + 1)
+        u0 = torch.from_numpy(inputs.sine_mode(n, (1, 1, 1), 3)).to("cuda")
+        shape0 = inputs.sine_mode(n, (1, 1, 1), 3)
+        pde = np.exp(-np.pi ** 2 * T) * shape0
+        # the semi-discrete solution: the sine mode decays with the stencil's eigenvalue
+        if cf["so"] == 4:
+            mu = 3 * (-2 * np.cos(2 * np.pi * h) + 32 * np.cos(np.pi * h) - 30) / (12 * h * h)
+        else:
+            mu = 3 * (-4.0 * np.sin(np.pi * h / 2) ** 2 / h ** 2)
+        ode = np.exp(nu * mu * T) * shape0
         dt = T / cf["steps"]
         rows = []
         runs = [("ISDC", 1, 0)] + [("IMLSDC", 1, cf["nc"])] + [("IPFASST", npr, cf["nc"]) for npr in cf["nps"]]
@@ -420,7 +430,7 @@ def form_table1(pfmg, a):
             c = pfmg.Context(pfmg.pfmg_default_params(
                 dim=3, n=n, nu=nu, dt=dt, n_slices=P, nodes_fine=cf["nf"], nodes_coarse=nc,
                 node_family=pfmg.NODES_UNIFORM, smoother=pfmg.SMOOTH_RBGS, omega=1.0, vcycles_per_solve=2,
-                pfasst_tol=1e-9, pfasst_max_iter=50))
+                pfasst_tol=1e-9, pfasst_max_iter=50, stencil_order=cf["so"], interp_order=4 if nc else 2))
             nblocks = cf["steps"] // P
 
             def interval():
@@ -455,8 +465,9 @@ def form_table1(pfmg, a):
             "best": {"config": best[1], "method": best[2], "n_p": best[3]}, "configs": out,
             "higher_is_better": False,
             "dtype": "f64", "data": "synthetic", "n_gpus": 1,
-            "config": {"workload": "3D heat, 127^3, nu=1/3, T=1, sin sin sin, uniform nodes 3/2 (128 steps) and "
-                                   "5/3 (24 steps), rbgs V(2,2), 2 V-cycles/solve, residual 1e-9"}}
+            "config": {"workload": "3D heat, nu=1/3, T=1, sin sin sin, uniform nodes: 127^3 3/2 (128 steps), "
+                                   "127^3 5/3 (24 steps), 31^3 fourth-order stencil 5/3 (24 steps); rbgs V(2,2), "
+                                   "2 V-cycles/solve, cubic interpolation between levels, residual 1e-9"}}
 
 
 def main():

@@ -164,7 +164,7 @@ RbPlan rb_plan(const Tiling &t, double alpha, double omega, View<T> b, View<T> u
     int nmax = 0;
     for (int sg = 0; sg < t.nseg; ++sg) nmax = std::max(nmax, t.seg_n(sg));
     for (int nt : {256, 512})
-    for (int ty : {2, 4, 6, 8, 10, 16})
+    for (int ty : {2, 4, 6, 8, 10, 12, 16, 22})
         for (int zc : {2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128, 256}) {
             k::FusedShape f = k::rbgs_fused_shape(t, sizeof(T), ty, 1, nt);
             if (f.ty != ty || zc > nmax) continue;

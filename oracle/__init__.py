@@ -23,7 +23,7 @@ _lib = None
 
 JACOBI, RBGS = 0, 1
 LOBATTO, UNIFORM = 0, 1          # node families
-UF, FF, UC, FC, TAU, UCOLD = range(6)
+UF, FF, UC, FC, TAU, UCOLD, FCOLD = range(7)
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -39,7 +39,7 @@ class Params(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int), ("nu", C.c_double), ("dt", C.c_double),
                 ("n_slices", C.c_int), ("nodes_fine", C.c_int), ("nodes_coarse", C.c_int),
                 ("mg", MGPolicy), ("interp_order", C.c_int), ("node_family", C.c_int),
-                ("stencil_order", C.c_int)]
+                ("stencil_order", C.c_int), ("f_solve", C.c_int), ("f_interp", C.c_int)]
 
 
 def lib():
@@ -243,9 +243,10 @@ class Pfasst:
 
     def __init__(self, dim, n, nu, dt, n_slices, nodes_fine=5, nodes_coarse=3,
                  mg: MGPolicy | None = None, interp_order: int = 2, node_family: int = LOBATTO,
-                 stencil_order: int = 2):
+                 stencil_order: int = 2, f_solve: int = 0, f_interp: int = 0):
         self.prm = Params(dim, n, nu, dt, n_slices, nodes_fine, nodes_coarse,
-                          mg if mg is not None else policy(), interp_order, node_family, stencil_order)
+                          mg if mg is not None else policy(), interp_order, node_family, stencil_order,
+                          f_solve, f_interp)
         self.dim, self.n, self.P = dim, n, n_slices
         self.nn = [nodes_fine, nodes_coarse]
         self.nc = (n + 1) // 2 - 1
@@ -291,7 +292,7 @@ class Pfasst:
         return lib().or_pfasst_vcycles(self._h, level)
 
     def field(self, which, p, m) -> np.ndarray:
-        """A copy of the field (U_f, F_f, U_c, F_c, tau, U_c_old) at slice p, node m."""
+        """A copy of the field (U_f, F_f, U_c, F_c, tau, U_c_old, F_c_old) at slice p, node m."""
         n = self.n if which in (UF, FF) else self.nc
         ptr = lib().or_pfasst_field(self._h, which, p, m)
         if not ptr:

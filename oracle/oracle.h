@@ -144,6 +144,10 @@ typedef struct or_params {
     int interp_order;        /* PFASST spatial interpolation: 2 d-linear, 4 cubic */
     int node_family;         /* OR_NODES_LOBATTO / OR_NODES_UNIFORM */
     int stencil_order;       /* fine-level Laplacian: 2, or 4 (coarse level stays 2) */
+    int f_solve;             /* F at a node after its solve: 0 nu L U; 1 (U - b) / (dt d_m),
+                              * the value the implicit-Euler substep implies (both levels) */
+    int f_interp;            /* after the coarse correction: 0 F_f re-evaluated; 1 the
+                              * coarse F correction interpolated like U's */
 } or_params;
 
 typedef struct or_pfasst or_pfasst;
@@ -164,8 +168,9 @@ void or_sdc_sweep(or_pfasst *c, int level, int p);
 void or_fas_restrict(or_pfasst *c, int p);
 void or_interpolate(or_pfasst *c, int p);
 
-/* Field access.  which: 0 U_f, 1 F_f, 2 U_c, 3 F_c, 4 tau, 5 U_c_old. */
-enum { OR_UF = 0, OR_FF = 1, OR_UC = 2, OR_FC = 3, OR_TAU = 4, OR_UCOLD = 5 };
+/* Field access.  which: 0 U_f, 1 F_f, 2 U_c, 3 F_c, 4 tau, 5 U_c_old,
+ * 6 F_c_old (f_interp only). */
+enum { OR_UF = 0, OR_FF = 1, OR_UC = 2, OR_FC = 3, OR_TAU = 4, OR_UCOLD = 5, OR_FCOLD = 6 };
 double *or_pfasst_field(or_pfasst *c, int which, int p, int m);
 /* Node solve counters (V-cycles run so far at each level). */
 long long or_pfasst_vcycles(or_pfasst *c, int level);

@@ -18,7 +18,14 @@
  *    nodes are a subset of the fine nodes); interpolation is d-linear in
  *    space and Lagrange in time over the coarse nodes;
  *  - F at node 0 is recomputed whenever node 0 changes;
- *  - the V-cycle initial guess is the previous iterate at the same node.
+ *  - the V-cycle initial guess is the previous iterate at the same node;
+ *  - options (the paper leaves both open): with f_solve, F at a node after
+ *    its solve is (U - b) / (dt d_m), what the implicit-Euler substep
+ *    implies, equal to nu L U when the solve is exact; with f_interp, the
+ *    fine F values take the interpolated coarse F correction instead of
+ *    being re-evaluated on the corrected U.  With either, the stored F is
+ *    no longer F(U) until the iteration converges, so the collocation
+ *    residual re-evaluates F(U).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -35,6 +42,7 @@ struct or_pfasst {
     int cmap[16];            /* coarse node -> coarse-coinciding fine node */
     double *U[2], *F[2];     /* [P][nn][len] */
     double *tau, *Uold;      /* coarse: [P][nn_c][len_c] */
+    double *Fold;            /* coarse F at restriction (f_interp) */
     double *ublock, *ublock_c;
     long long vcyc[2];
 };
@@ -60,6 +68,7 @@ double *or_pfasst_field(or_pfasst *c, int which, int p, int m)
     case OR_FC: return c->nl > 1 ? fld(c, c->F[1], 1, p, m) : NULL;
     case OR_TAU: return c->nl > 1 ? fld(c, c->tau, 1, p, m) : NULL;
     case OR_UCOLD: return c->nl > 1 ? fld(c, c->Uold, 1, p, m) : NULL;
+    case OR_FCOLD: return c->nl > 1 && c->Fold ? fld(c, c->Fold, 1, p, m) : NULL;
     }
     return NULL;
 }
@@ -80,6 +89,7 @@ or_pfasst *or_pfasst_create(const or_params *prm)
     if (prm->node_family != OR_NODES_LOBATTO && prm->node_family != OR_NODES_UNIFORM) return NULL;
     if (prm->stencil_order != 2 && prm->stencil_order != 4) return NULL;
     if (prm->stencil_order == 4 && prm->mg.mixed) return NULL;
+    if ((prm->f_solve != 0 && prm->f_solve != 1) || (prm->f_interp != 0 && prm->f_interp != 1)) return NULL;
     or_pfasst *c = (or_pfasst *)calloc(1, sizeof(or_pfasst));
     c->p = *prm;
     c->nl = prm->nodes_coarse > 0 ? 2 : 1;
@@ -104,6 +114,7 @@ or_pfasst *or_pfasst_create(const or_params *prm)
         size_t tot = (size_t)prm->n_slices * c->nn[1] * c->len[1];
         c->tau = (double *)calloc(tot, sizeof(double));
         c->Uold = (double *)calloc(tot, sizeof(double));
+        if (prm->f_interp) c->Fold = (double *)calloc(tot, sizeof(double));
         c->ublock_c = (double *)calloc(c->len[1], sizeof(double));
         or_interp_matrix(c->nn[0], c->s[0], c->nn[1], c->s[1], c->Lt);
         for (int mc = 0; mc < c->nn[1]; ++mc) {
@@ -122,6 +133,7 @@ void or_pfasst_destroy(or_pfasst *c)
     for (int l = 0; l < 2; ++l) { free(c->U[l]); free(c->F[l]); }
     free(c->tau);
     free(c->Uold);
+    free(c->Fold);
     free(c->ublock);
     free(c->ublock_c);
     free(c);
@@ -154,7 +166,8 @@ static void inject(int dim, int nf, const double *uf, double *uc)
  * integrals of the old function values, written for the linear problem as
  * in eq. SDCcompactLIII): for m = 0..M-1
  *   b = U[m] - dt_{m+1} F^k[m+1] + I_m (+ tau[m+1] - tau[m] on level 1),
- *   solve (I - nu dt_{m+1} L) U[m+1] = b from U^k[m+1], F[m+1] = nu L U[m+1]. */
+ *   solve (I - nu dt_{m+1} L) U[m+1] = b from U^k[m+1], F[m+1] = nu L U[m+1]
+ *   (f_solve: F[m+1] = (U[m+1] - b) / dt_{m+1}). */
 void or_sdc_sweep(or_pfasst *c, int lev, int p)
 {
     const int nn = c->nn[lev], M = nn - 1;
@@ -187,7 +200,10 @@ void or_sdc_sweep(or_pfasst *c, int lev, int p)
             c->vcyc[lev] += or_mg_solve4(c->p.dim, c->n[lev], c->p.nu * dtm, &c->p.mg, b, u, NULL);
         else
             c->vcyc[lev] += or_mg_solve(c->p.dim, c->n[lev], c->p.nu * dtm, &c->p.mg, b, u, NULL);
-        feval(c, lev, u, fld(c, c->F[lev], lev, p, m + 1));
+        double *fm = fld(c, c->F[lev], lev, p, m + 1);
+        if (c->p.f_solve)
+            for (size_t x = 0; x < len; ++x) fm[x] = (u[x] - b[x]) / dtm;
+        else feval(c, lev, u, fm);
     }
     free(I);
     free(b);
@@ -224,12 +240,15 @@ void or_fas_restrict(or_pfasst *c, int p)
         }
     }
     memcpy(fld(c, c->Uold, 1, p, 0), fld(c, c->U[1], 1, p, 0), (size_t)nnc * lc * sizeof(double));
+    if (c->Fold) memcpy(fld(c, c->Fold, 1, p, 0), fld(c, c->F[1], 1, p, 0), (size_t)nnc * lc * sizeof(double));
     free(qf);
     free(qfc);
 }
 
 /* Interpolation of slice p: U_f[m] += P_s sum_mc L_t[m][mc] (U_c - U_c^old)[mc]
- * for every fine node, then F_f recomputed. */
+ * for every fine node, then F_f recomputed (f_interp: F_f[m] += P_s sum_mc
+ * L_t[m][mc] (F_c - F_c^old)[mc], the same interpolation of the coarse F
+ * change). */
 void or_interpolate(or_pfasst *c, int p)
 {
     const int dim = c->p.dim, nc = c->n[1], nnf = c->nn[0], nnc = c->nn[1];
@@ -246,7 +265,19 @@ void or_interpolate(or_pfasst *c, int p)
         double *uf = fld(c, c->U[0], 0, p, m);
         if (c->p.interp_order == 4 && nc >= 3) or_prolong4_add(dim, nc, dc, uf);
         else or_prolong_add(dim, nc, dc, uf);
-        feval(c, 0, uf, fld(c, c->F[0], 0, p, m));
+        double *ff = fld(c, c->F[0], 0, p, m);
+        if (!c->p.f_interp) {
+            feval(c, 0, uf, ff);
+            continue;
+        }
+        for (size_t x = 0; x < lc; ++x) {
+            double acc = 0.0;
+            for (int mc = 0; mc < nnc; ++mc)
+                acc += c->Lt[m * nnc + mc] * (fld(c, c->F[1], 1, p, mc)[x] - fld(c, c->Fold, 1, p, mc)[x]);
+            dc[x] = acc;
+        }
+        if (c->p.interp_order == 4 && nc >= 3) or_prolong4_add(dim, nc, dc, ff);
+        else or_prolong_add(dim, nc, dc, ff);
     }
     free(dc);
 }
@@ -289,23 +320,31 @@ void or_pfasst_predictor(or_pfasst *c)
 }
 
 /* Collocation residual (eq. resid) per slice:
- *   r[m] = U0_p - U[m] + dt sum_i Q[m][i] F[i],  m = 0..M,
+ *   r[m] = U0_p - U[m] + dt sum_i Q[m][i] F(U[i]),  m = 0..M,
  * with U0_p the previous slice's end value (u_block for p = 0), normalised
- * by |U0_p|_inf; the block residual is the maximum over slices. */
+ * by |U0_p|_inf; the block residual is the maximum over slices.  The stored
+ * F are F(U) unless f_solve or f_interp is set; then F(U) is re-evaluated. */
 double or_pfasst_residual(or_pfasst *c, double *res)
 {
     const int P = c->p.n_slices, nn = c->nn[0], M = nn - 1;
     const size_t len = c->len[0];
     const double dt = c->p.dt;
+    const int reeval = c->p.f_solve || c->p.f_interp;
+    double *Fe = reeval ? (double *)malloc((size_t)nn * len * sizeof(double)) : NULL;
     double blk = 0.0;
     for (int p = 0; p < P; ++p) {
+        const double *Fp = fld(c, c->F[0], 0, p, 0);
+        if (reeval) {
+            for (int i = 0; i < nn; ++i) feval(c, 0, fld(c, c->U[0], 0, p, i), Fe + (size_t)i * len);
+            Fp = Fe;
+        }
         const double *u0 = p == 0 ? c->ublock : fld(c, c->U[0], 0, p - 1, M);
         double rmax = 0.0;
         for (int m = 0; m <= M; ++m) {
             const double *um = fld(c, c->U[0], 0, p, m);
             for (size_t x = 0; x < len; ++x) {
                 double acc = 0.0;
-                for (int i = 0; i < nn; ++i) acc += c->Q[0][m * nn + i] * fld(c, c->F[0], 0, p, i)[x];
+                for (int i = 0; i < nn; ++i) acc += c->Q[0][m * nn + i] * Fp[(size_t)i * len + x];
                 double r = fabs(u0[x] - um[x] + dt * acc);
                 if (r > rmax || r != r) rmax = r;
             }
@@ -315,6 +354,7 @@ double or_pfasst_residual(or_pfasst *c, double *res)
         if (res) res[p] = rp;
         if (rp > blk || rp != rp) blk = rp;
     }
+    free(Fe);
     return blk;
 }
 

@@ -119,6 +119,18 @@ enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
  *   interp_order     PFASST spatial interpolation of the coarse correction:
  *                    2 d-linear, 4 tensor-product cubic (Sec. 4.3; needs a
  *                    coarse grid of n >= 3).  Single contexts only.
+ *   f_solve          F at a node after its implicit-Euler solve (both
+ *                    levels): 0 nu L_h U; 1 (U - b) / (dt d_m), the value
+ *                    the substep implies (equal to nu L_h U when the solve
+ *                    is exact; Sec. 2.2 leaves the choice open).  F at
+ *                    node 0 is nu L_h of its value either way.
+ *   f_interp         after the coarse correction: 0 the fine F values are
+ *                    re-evaluated on the corrected U; 1 they take the coarse
+ *                    F change interpolated like U's (time and space).  With
+ *                    either option the stored F differs from F(U) until the
+ *                    iteration converges, so the collocation residual
+ *                    (pfmg_residual, the block residual) evaluates F(U)
+ *                    itself.  Single contexts only; both default to 0.
  */
 typedef struct pfmg_params {
     int32_t dim;
@@ -145,6 +157,8 @@ typedef struct pfmg_params {
     double guess_min_relres;
     int32_t stencil_order;
     int32_t interp_order;
+    int32_t f_solve;
+    int32_t f_interp;
 } pfmg_params;
 
 /* Fills *p with the defaults: 3D, n = 127, nu = 1, dt = 1e-3, 16 slices,

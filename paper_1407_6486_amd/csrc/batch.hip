@@ -132,6 +132,9 @@ bool BatchSolver::validate(const pfmg_params *pp, int np, std::string &why)
     if (a.stencil_order != 2 || a.interp_order != 2) {
         why = "a batch runs the second-order stencil and d-linear interpolation"; return false;
     }
+    if (a.f_solve != 0 || a.f_interp != 0) {
+        why = "a batch re-evaluates F (f_solve = f_interp = 0)"; return false;
+    }
     return true;
 }
 

@@ -89,6 +89,8 @@ pfmg_status pfmg_default_params(pfmg_params *p)
     p->guess_min_relres = 0.0;
     p->stencil_order = 2;
     p->interp_order = 2;
+    p->f_solve = 0;
+    p->f_interp = 0;
     return PFMG_OK;
 }
 

@@ -110,11 +110,18 @@ hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> 
                    View<double> Im, View<double> tau1, View<double> tau0, View<double> b,
                    hipStream_t s);
 // sdc_integrals and the first node's sdc_rhs in one pass (node 0 of U and F
-// first copied from Usrc / Fsrc when they are set; tau: all coarse nodes,
-// or null on the fine level).
+// first copied from Usrc / Fsrc when they are set -- with nu0 > 0, F of
+// node 0 is instead nu0 L_h of Usrc, the second-order stencil; tau: all
+// coarse nodes, or null on the fine level).
 hipError_t sdc_start(const Tiling &t, int nn, double dt, const double *S, double delta1, View<double> U,
                      View<double> F, View<double> Usrc, View<double> Fsrc, View<double> I, View<double> tau,
-                     View<double> b, hipStream_t s);
+                     View<double> b, hipStream_t s, double nu0 = 0.0);
+// F = (U - B) / delta at the node just solved (B: its right-hand side);
+// then, when Fn1 is set, B = U - delta_next Fn1 + In (+ t1 - t0), the next
+// node's right-hand side.
+hipError_t solve_F_rhs(const Tiling &t, double delta, View<double> U, View<double> B, View<double> F,
+                       double delta_next, View<double> Fn1, View<double> In, View<double> t1, View<double> t0,
+                       hipStream_t s);
 // apply_L into F and, from the same loads of u, sdc_rhs of the next node
 // (Fn1, In, t1, t0 as sdc_rhs's Fm1, Im, tau1, tau0); for launches that
 // apply_L would run column-blocked (3D, below the z-marching size).

@@ -11,6 +11,8 @@
 //                integrals, and the first node solve's right-hand side.
 //  apply_L_rhs   F at one node and the next node solve's right-hand side
 //                from the same loads (column-blocked small launches).
+//  solve_F_rhs   F at one node from its solve, (u - b) / delta, and the
+//                next node solve's right-hand side in the same pass.
 //  fas_inject /  FAS coarsening (Sec. 2.3): point-wise injection of U and
 //  fas_tau       of the fine node integrals dt Q_f F_f, minus the coarse
 //                integrals dt Q_c F_c of the injected state.
@@ -106,6 +108,25 @@ __global__ __launch_bounds__(BLOCK) void sdc_rhs_kernel(Tiling t, double delta, 
     fp(b, q)[o] = v;
 }
 
+// F = (u - b) / delta at the node just solved (b still holds its
+// right-hand side), then, with Fn1 set, b = u - delta_next Fn1 + In
+// (+ t1 - t0): the next node's right-hand side, as in sdc_rhs.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void solve_F_rhs_kernel(Tiling t, double delta, View<double> U, View<double> B,
+                                                            View<double> F, double delta_next, View<double> Fn1,
+                                                            View<double> In, View<double> t1, View<double> t0)
+{
+    Pt q; int i, j, k; long o;
+    if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    const double u = fp(U, q)[o];
+    double *bb = fp(B, q);
+    fp(F, q)[o] = (u - bb[o]) / q.par(delta);
+    if (!Fn1.p) return;
+    double v = u - q.par(delta_next) * fp(Fn1, q)[o] + fp(In, q)[o];
+    if (t1.p) v = v + (fp(t1, q)[o] - fp(t0, q)[o]);
+    bb[o] = v;
+}
+
 // sdc_integrals followed by sdc_rhs for the first node, with the same
 // arithmetic; with Usrc / Fsrc set, node 0 of U and F is first copied from
 // them (the send-forward of the coarse chain and of the predictor rounds).
@@ -113,7 +134,7 @@ template <int DIM, int NN>
 __global__ __launch_bounds__(BLOCK) void sdc_start_kernel(Tiling t, int nn_rt, double dt, const double *__restrict__ S,
                                                           double delta1, View<double> U, View<double> F,
                                                           View<double> Usrc, View<double> Fsrc, View<double> I,
-                                                          View<double> tau, View<double> b)
+                                                          View<double> tau, View<double> b, double nu0)
 {
     const int nn = NN > 0 ? NN : nn_rt;
     Pt q; int i, j, k; long o;
@@ -125,8 +146,15 @@ __global__ __launch_bounds__(BLOCK) void sdc_start_kernel(Tiling t, int nn_rt, d
     double fv[MAXN];
     double u0;
     if (Usrc.p) {
-        u0 = fp(Usrc, q)[o];
-        fv[0] = fp(Fsrc, q)[o];
+        const double *us = fp(Usrc, q);
+        u0 = us[o];
+        if (nu0 > 0.0) {
+            // F of the new node 0 evaluated from its value (apply_L's arithmetic)
+            const double ih2 = (double)(q.n + 1) * (double)(q.n + 1);
+            fv[0] = q.par(nu0) * (ih2 * d2sum<DIM>(us, o, row_stride(q.n), plane_stride(q.n)));
+        } else {
+            fv[0] = fp(Fsrc, q)[o];
+        }
     } else {
         u0 = u[0];
         fv[0] = f[0];
@@ -422,12 +450,20 @@ hipError_t sdc_integrals(const Tiling &t, int nn, double dt, const double *S, Vi
 
 hipError_t sdc_start(const Tiling &t, int nn, double dt, const double *S, double delta1, View<double> U,
                      View<double> F, View<double> Usrc, View<double> Fsrc, View<double> I, View<double> tau,
-                     View<double> b, hipStream_t s)
+                     View<double> b, hipStream_t s, double nu0)
 {
     if (nn < 2 || nn > MAXN || (Usrc.p != nullptr) != (Fsrc.p != nullptr)) return hipErrorInvalidValue;
-    if (nn == 5) PFMG_DISPATCH_N(t, sdc_start_kernel, 5, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b);
-    if (nn == 3) PFMG_DISPATCH_N(t, sdc_start_kernel, 3, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b);
-    PFMG_DISPATCH_N(t, sdc_start_kernel, 0, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b);
+    if (nn == 5) PFMG_DISPATCH_N(t, sdc_start_kernel, 5, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b, nu0);
+    if (nn == 3) PFMG_DISPATCH_N(t, sdc_start_kernel, 3, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b, nu0);
+    PFMG_DISPATCH_N(t, sdc_start_kernel, 0, t, nn, dt, S, delta1, U, F, Usrc, Fsrc, I, tau, b, nu0);
+}
+
+hipError_t solve_F_rhs(const Tiling &t, double delta, View<double> U, View<double> B, View<double> F,
+                       double delta_next, View<double> Fn1, View<double> In, View<double> t1, View<double> t0,
+                       hipStream_t s)
+{
+    if ((Fn1.p != nullptr) != (In.p != nullptr) || (t1.p != nullptr) != (t0.p != nullptr)) return hipErrorInvalidValue;
+    PFMG_DISPATCH(t, solve_F_rhs_kernel, t, delta, U, B, F, delta_next, Fn1, In, t1, t0);
 }
 
 bool apply_L_rhs_ok(const Tiling &t) { return t.dim == 3 && !stencil_z_ok(t); }

@@ -25,6 +25,8 @@ struct PLevel {
     long fs = 0;                      // FP64 slot stride
     double *U = nullptr, *F = nullptr, *I = nullptr, *B = nullptr;
     double *Tau = nullptr, *Uold = nullptr, *DC = nullptr;   // coarse level only
+    double *Fold = nullptr;           // coarse F at restriction (f_interp)
+    double *Ft = nullptr;             // fine F(U) for the residual (f_solve or f_interp)
     std::vector<MGLevel> mg;          // mg[0].n == n
     long double s_ld[16];
     double s[16], Q[256], S[256], d[16];

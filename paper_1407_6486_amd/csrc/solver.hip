@@ -64,6 +64,9 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
     if (p.smoother != PFMG_SMOOTH_JACOBI && p.smoother != PFMG_SMOOTH_RBGS) { why = "bad smoother"; return false; }
     if (p.stencil_order != 2 && p.stencil_order != 4) { why = "stencil_order must be 2 or 4"; return false; }
     if (p.interp_order != 2 && p.interp_order != 4) { why = "interp_order must be 2 or 4"; return false; }
+    if ((p.f_solve != 0 && p.f_solve != 1) || (p.f_interp != 0 && p.f_interp != 1)) {
+        why = "f_solve and f_interp must be 0 or 1"; return false;
+    }
     if (p.stencil_order == 4 && (p.precision != PFMG_FP64 || p.guess != PFMG_GUESS_PREV)) {
         why = "stencil_order 4 needs FP64 and plain guesses"; return false;
     }
@@ -133,7 +136,11 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
             L.Tau = f64(n, (long)P * nn);
             L.Uold = f64(n, (long)P * nn);
             L.DC = f64(n, (long)P * p.nodes_fine);
+            L.Fold = p.f_interp ? f64(n, (long)P * nn) : nullptr;
         }
+        // F(U) of every fine node for the collocation residual when the
+        // stored F is not F(U)
+        L.Ft = lev == 0 && (p.f_solve || p.f_interp) ? f64(n, (long)P * nn) : nullptr;
         L.mg.clear();
         for (int l = 0, nl_ = n;; ++l, nl_ = coarser(nl_)) {
             MGLevel G;
@@ -679,6 +686,10 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
             t0 = {Lv.slot(Lv.Tau, p0, m), sst};
         }
     };
+    // A new node 0 taken from a source gets F = nu L_h of its value when
+    // the source's F came from a solve (f_solve); sources are coarse nodes.
+    const bool eval0 = u0src && p.f_solve;
+    if (eval0 && lev != 1) return hipErrorInvalidValue;
     if (fused_sdc) {
         // node 0 from the source, the integrals and the first right-hand side
         const View<double> us{const_cast<double *>(u0src), src_stride};
@@ -686,14 +697,18 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
         tstart("sdc_start", Lv.n, 8.0 * (2 * nn - 1) + 16 + (lev == 1 ? 16 : 0) + (u0src ? 16 : 0), pts);
         HC(k::sdc_start(t, nn, p.dt, Lv.dS, p.dt * Lv.d[1], View<double>{Lv.slot(Lv.U, p0, 0), sst},
                         View<double>{Lv.slot(Lv.F, p0, 0), sst}, us, fsrc, View<double>{Lv.I + (long)p0 * ist, ist},
-                        lev == 1 ? View<double>{Lv.slot(Lv.Tau, p0, 0), sst} : View<double>{nullptr, 0}, Bv, s));
+                        lev == 1 ? View<double>{Lv.slot(Lv.Tau, p0, 0), sst} : View<double>{nullptr, 0}, Bv, s,
+                        eval0 ? p.nu : 0.0));
         tstop();
     } else {
         if (u0src) {
             HC(k::copy(t, View<double>{const_cast<double *>(u0src), src_stride},
                        View<double>{Lv.slot(Lv.U, p0, 0), sst}, s));
-            HC(k::copy(t, View<double>{const_cast<double *>(f0src), src_stride},
-                       View<double>{Lv.slot(Lv.F, p0, 0), sst}, s));
+            if (eval0)
+                HC(apply_F(lev, t, View<double>{Lv.slot(Lv.U, p0, 0), sst}, View<double>{Lv.slot(Lv.F, p0, 0), sst}));
+            else
+                HC(k::copy(t, View<double>{const_cast<double *>(f0src), src_stride},
+                           View<double>{Lv.slot(Lv.F, p0, 0), sst}, s));
         }
         tstart("sdc_integrals", Lv.n, 8.0 * (2 * nn - 1), pts);
         HC(k::sdc_integrals(t, nn, p.dt, Lv.dS, View<double>{Lv.slot(Lv.F, p0, 0), sst},
@@ -713,6 +728,15 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
         if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
         const bool more = m + 2 < nn;
         if (more) rhs_views(m + 1);
+        if (p.f_solve) {
+            // F from the solve, then the next right-hand side (Um is node m+1)
+            tstart("solve_F", Lv.n, more ? (lev == 1 ? 72 : 56) : 24, pts);
+            HC(k::solve_F_rhs(t, delta, Uv, Bv, Fv, more ? p.dt * Lv.d[m + 2] : 0.0,
+                              more ? Fm1 : View<double>{nullptr, 0}, more ? Im : View<double>{nullptr, 0},
+                              more ? t1 : View<double>{nullptr, 0}, more ? t0 : View<double>{nullptr, 0}, s));
+            tstop();
+            continue;
+        }
         if (more && fuse_rhs) {
             // F of node m+1 and the right-hand side of node m+2, which reads
             // the old F of node m+2, not the new F of node m+1
@@ -744,6 +768,9 @@ hipError_t Solver::fas_restrict(int p0, int p1)
                      View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, s));
     HC(k::apply_L(tl(Cs.n, count * Cs.nn), p.nu, View<double>{Cs.slot(Cs.U, p0, 0), Cs.fs},
                   View<double>{Cs.slot(Cs.F, p0, 0), Cs.fs}, s));
+    if (Cs.Fold)
+        HC(k::copy(tl(Cs.n, count * Cs.nn), View<double>{Cs.slot(Cs.F, p0, 0), Cs.fs},
+                   View<double>{Cs.slot(Cs.Fold, p0, 0), Cs.fs}, s));
     return k::fas_tau(tl(Cs.n, count), Cs.nn, p.dt, Cs.dQ, View<double>{Cs.slot(Cs.F, p0, 0), cst},
                       View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, s);
 }
@@ -763,6 +790,18 @@ hipError_t Solver::interpolate(int p0, int p1)
     else
         HC(k::prolong_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs}, s));
     tstop();
+    if (p.f_interp) {
+        // the coarse F change, interpolated in time and space like U's
+        HC(k::interp_coarse(tl(Cs.n, count), Fn.nn, Cs.nn, dLt, View<double>{Cs.slot(Cs.F, p0, 0), cst},
+                            View<double>{Cs.slot(Cs.Fold, p0, 0), cst}, View<double>{dc, dst}, s));
+        tstart("prolong", Fn.n, 16 + 8.0 / (dim == 3 ? 8 : 2), pts);
+        if (p.interp_order == 4)
+            HC(k::prolong4_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.F, p0, 0), Fn.fs}, s));
+        else
+            HC(k::prolong_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.F, p0, 0), Fn.fs}, s));
+        tstop();
+        return hipSuccess;
+    }
     tstart("apply_L", Fn.n, 16, pts);
     HC(apply_F(0, tl(Fn.n, count * Fn.nn), View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs},
                View<double>{Fn.slot(Fn.F, p0, 0), Fn.fs}));
@@ -835,9 +874,18 @@ hipError_t Solver::residual_slices(int p0, int p1)
     PLevel &Fn = L[0];
     const long fst = (long)Fn.nn * Fn.fs;
     const int count = p1 - p0;
+    double *Fr = Fn.F;
+    if (Fn.Ft) {
+        // the stored F is not F(U) mid-iteration: evaluate F(U) for eq. resid
+        tstart("apply_L", Fn.n, 16, interior_points(Fn.n, dim) * count * Fn.nn);
+        HC(apply_F(0, tl(Fn.n, count * Fn.nn), View<double>{Fn.U + (long)p0 * fst, Fn.fs},
+                   View<double>{Fn.Ft + (long)p0 * fst, Fn.fs}));
+        tstop();
+        Fr = Fn.Ft;
+    }
     tstart("colloc_resid", Fn.n, 8.0 * (2 * Fn.nn + 1), interior_points(Fn.n, dim) * count);
     HC(k::colloc_resid(tl(Fn.n, count), Fn.nn, P, p.dt, Fn.dQ, View<double>{Fn.U + (long)p0 * fst, fst},
-                       View<double>{Fn.F + (long)p0 * fst, fst}, View<double>{ublock, 0},
+                       View<double>{Fr + (long)p0 * fst, fst}, View<double>{ublock, 0},
                        bits + (long)p0 * k::RSLOTS, bits + (long)(P + p0) * k::RSLOTS, s, p0));
     tstop();
     return hipSuccess;
@@ -882,7 +930,12 @@ hipError_t Solver::iterate_body()
     // slices at once, before any sweep changes them
     if (P > 1) {
         HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.U, 0, M), fst}, View<double>{Fn.slot(Fn.U, 1, 0), fst}, s));
-        HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.F, 0, M), fst}, View<double>{Fn.slot(Fn.F, 1, 0), fst}, s));
+        // F of the new node 0: the sent F is F(U) unless it came from a
+        // solve or an interpolation
+        if (p.f_solve || p.f_interp)
+            HC(apply_F(0, tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.U, 1, 0), fst}, View<double>{Fn.slot(Fn.F, 1, 0), fst}));
+        else
+            HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.F, 0, M), fst}, View<double>{Fn.slot(Fn.F, 1, 0), fst}, s));
     }
     if (nl > 1 && groups > 1 && p.vcycles_per_solve > 0) return iterate_pipelined();
     HC(sweep(0, 0, P));

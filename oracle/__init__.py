@@ -39,7 +39,8 @@ class Params(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int), ("nu", C.c_double), ("dt", C.c_double),
                 ("n_slices", C.c_int), ("nodes_fine", C.c_int), ("nodes_coarse", C.c_int),
                 ("mg", MGPolicy), ("interp_order", C.c_int), ("node_family", C.c_int),
-                ("stencil_order", C.c_int), ("f_solve", C.c_int), ("f_interp", C.c_int)]
+                ("stencil_order", C.c_int), ("f_solve", C.c_int), ("f_interp", C.c_int),
+                ("residual_abs", C.c_int)]
 
 
 def lib():
@@ -243,10 +244,10 @@ class Pfasst:
 
     def __init__(self, dim, n, nu, dt, n_slices, nodes_fine=5, nodes_coarse=3,
                  mg: MGPolicy | None = None, interp_order: int = 2, node_family: int = LOBATTO,
-                 stencil_order: int = 2, f_solve: int = 0, f_interp: int = 0):
+                 stencil_order: int = 2, f_solve: int = 0, f_interp: int = 0, residual_abs: int = 0):
         self.prm = Params(dim, n, nu, dt, n_slices, nodes_fine, nodes_coarse,
                           mg if mg is not None else policy(), interp_order, node_family, stencil_order,
-                          f_solve, f_interp)
+                          f_solve, f_interp, residual_abs)
         self.dim, self.n, self.P = dim, n, n_slices
         self.nn = [nodes_fine, nodes_coarse]
         self.nc = (n + 1) // 2 - 1

@@ -148,6 +148,7 @@ typedef struct or_params {
                               * the value the implicit-Euler substep implies (both levels) */
     int f_interp;            /* after the coarse correction: 0 F_f re-evaluated; 1 the
                               * coarse F correction interpolated like U's */
+    int residual_abs;        /* collocation residual: 0 relative to |U0_p|_inf, 1 absolute */
 } or_params;
 
 typedef struct or_pfasst or_pfasst;

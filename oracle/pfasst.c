@@ -90,6 +90,7 @@ or_pfasst *or_pfasst_create(const or_params *prm)
     if (prm->stencil_order != 2 && prm->stencil_order != 4) return NULL;
     if (prm->stencil_order == 4 && prm->mg.mixed) return NULL;
     if ((prm->f_solve != 0 && prm->f_solve != 1) || (prm->f_interp != 0 && prm->f_interp != 1)) return NULL;
+    if (prm->residual_abs != 0 && prm->residual_abs != 1) return NULL;
     or_pfasst *c = (or_pfasst *)calloc(1, sizeof(or_pfasst));
     c->p = *prm;
     c->nl = prm->nodes_coarse > 0 ? 2 : 1;
@@ -322,7 +323,8 @@ void or_pfasst_predictor(or_pfasst *c)
 /* Collocation residual (eq. resid) per slice:
  *   r[m] = U0_p - U[m] + dt sum_i Q[m][i] F(U[i]),  m = 0..M,
  * with U0_p the previous slice's end value (u_block for p = 0), normalised
- * by |U0_p|_inf; the block residual is the maximum over slices.  The stored
+ * by |U0_p|_inf (residual_abs: not normalised); the block residual is the
+ * maximum over slices.  The stored
  * F are F(U) unless f_solve or f_interp is set; then F(U) is re-evaluated. */
 double or_pfasst_residual(or_pfasst *c, double *res)
 {
@@ -350,7 +352,7 @@ double or_pfasst_residual(or_pfasst *c, double *res)
             }
         }
         double n0 = or_norm_inf(len, u0);
-        double rp = n0 > 0 ? rmax / n0 : rmax;
+        double rp = c->p.residual_abs ? rmax : (n0 > 0 ? rmax / n0 : rmax);
         if (res) res[p] = rp;
         if (rp > blk || rp != rp) blk = rp;
     }

@@ -133,3 +133,23 @@ def test_options_rejected_outside_0_1():
         O.Pfasst(3, 15, 1.0, 1e-3, 2, 5, 3, O.policy(cycles=1), f_solve=2)
     with pytest.raises(ValueError):
         O.Pfasst(3, 15, 1.0, 1e-3, 2, 5, 3, O.policy(cycles=1), f_interp=-1)
+
+
+def test_absolute_residual_is_relative_times_initial_norm():
+    """residual_abs: each slice's residual is the plain max-norm of eq.
+    resid, i.e. the relative one times |U0_p|_inf (U0_p from the fields)."""
+    n, P = 15, 4
+    u0 = inputs.random_fourier(n, 31)[0]
+    runs = []
+    for ra in (0, 1):
+        pf = O.Pfasst(3, n, 1.0, 2e-3, P, 5, 3, O.policy(cycles=1), residual_abs=ra)
+        pf.set_initial(u0)
+        pf.iterate()
+        runs.append(pf)
+    _, rel = runs[0].residual()
+    blk, ab = runs[1].residual()
+    norms = [np.max(np.abs(u0))] + [np.max(np.abs(runs[0].field(O.UF, p - 1, 4))) for p in range(1, P)]
+    assert np.allclose(ab, rel * np.array(norms), rtol=1e-13, atol=0)
+    assert blk == max(ab) and not np.allclose(ab, rel)
+    with pytest.raises(ValueError):
+        O.Pfasst(3, 15, 1.0, 1e-3, 2, 5, 3, O.policy(cycles=1), residual_abs=2)

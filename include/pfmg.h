@@ -131,6 +131,10 @@ enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
  *                    iteration converges, so the collocation residual
  *                    (pfmg_residual, the block residual) evaluates F(U)
  *                    itself.  Single contexts only; both default to 0.
+ *   residual_abs     0: each slice's collocation residual is relative to
+ *                    its initial value's max-norm (the default); 1: the
+ *                    plain max-norm, for an absolute pfasst_tol.  Single
+ *                    contexts only.
  */
 typedef struct pfmg_params {
     int32_t dim;
@@ -159,6 +163,7 @@ typedef struct pfmg_params {
     int32_t interp_order;
     int32_t f_solve;
     int32_t f_interp;
+    int32_t residual_abs;
 } pfmg_params;
 
 /* Fills *p with the defaults: 3D, n = 127, nu = 1, dt = 1e-3, 16 slices,

@@ -135,6 +135,7 @@ bool BatchSolver::validate(const pfmg_params *pp, int np, std::string &why)
     if (a.f_solve != 0 || a.f_interp != 0) {
         why = "a batch re-evaluates F (f_solve = f_interp = 0)"; return false;
     }
+    if (a.residual_abs != 0) { why = "a batch uses the relative residual (residual_abs = 0)"; return false; }
     return true;
 }
 

@@ -91,6 +91,7 @@ pfmg_status pfmg_default_params(pfmg_params *p)
     p->interp_order = 2;
     p->f_solve = 0;
     p->f_interp = 0;
+    p->residual_abs = 0;
     return PFMG_OK;
 }
 

@@ -67,6 +67,7 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
     if ((p.f_solve != 0 && p.f_solve != 1) || (p.f_interp != 0 && p.f_interp != 1)) {
         why = "f_solve and f_interp must be 0 or 1"; return false;
     }
+    if (p.residual_abs != 0 && p.residual_abs != 1) { why = "residual_abs must be 0 or 1"; return false; }
     if (p.stencil_order == 4 && (p.precision != PFMG_FP64 || p.guess != PFMG_GUESS_PREV)) {
         why = "stencil_order 4 needs FP64 and plain guesses"; return false;
     }
@@ -905,7 +906,7 @@ hipError_t Solver::residual_read(double *per_slice, double *block)
             ub = std::max(ub, hbits[(long)(P + q) * k::RSLOTS + w]);
         }
         const double r = bits_to_double(rb), u0 = bits_to_double(ub);
-        const double v = u0 > 0 ? r / u0 : r;
+        const double v = p.residual_abs || !(u0 > 0) ? r : r / u0;
         if (!std::isfinite(v)) bad = true;
         if (per_slice) per_slice[q] = v;
         if (v > blk || v != v) blk = v;

@@ -51,7 +51,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("guess", C.c_int32), ("fine_send", C.c_int32),
                 ("pfasst_tol", C.c_double), ("pfasst_max_iter", C.c_int32), ("guess_min_relres", C.c_double),
                 ("stencil_order", C.c_int32), ("interp_order", C.c_int32),
-                ("f_solve", C.c_int32), ("f_interp", C.c_int32)]
+                ("f_solve", C.c_int32), ("f_interp", C.c_int32), ("residual_abs", C.c_int32)]
 
 
 _vp, _dp = C.c_void_p, C.POINTER(C.c_double)

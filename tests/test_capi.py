@@ -111,7 +111,7 @@ def test_stencil_and_interpolation_orders_on_the_host(pf):
 
 
 def test_f_options_on_the_host(pf):
-    """f_solve / f_interp: 0 or 1, single contexts only; the workspace grows
+    """f_solve / f_interp / residual_abs: 0 or 1, single contexts only; the workspace grows
     by the F(U) fields of the residual (P nn fine fields) and, with f_interp,
     the coarse F at restriction (P nn_c coarse fields)."""
     kw = dict(n=31, n_slices=3)
@@ -121,13 +121,14 @@ def test_f_options_on_the_host(pf):
     fine, coarse = 32 * 33 ** 2 + 1, 16 * 17 ** 2 + 1
     assert fs - base >= 3 * 5 * fine * 8
     assert both - fs >= 3 * 3 * coarse * 8
-    for bad in ({"f_solve": 2}, {"f_interp": -1}):
+    for bad in ({"f_solve": 2}, {"f_interp": -1}, {"residual_abs": 3}):
         with pytest.raises(pf.PfmgError) as ei:
             pf.pfmg_workspace_bytes(pf.pfmg_default_params(**bad))
         assert ei.value.status == pf.ERR_ARG
-    with pytest.raises(pf.PfmgError) as ei:
-        pf.pfmg_batch_workspace_bytes([pf.pfmg_default_params(n=31, f_interp=1)])
-    assert ei.value.status == pf.ERR_ARG
+    for kw in ({"f_interp": 1}, {"residual_abs": 1}):
+        with pytest.raises(pf.PfmgError) as ei:
+            pf.pfmg_batch_workspace_bytes([pf.pfmg_default_params(n=31, **kw)])
+        assert ei.value.status == pf.ERR_ARG
 
 
 def test_valid_degenerate_sizes_accepted(pf):

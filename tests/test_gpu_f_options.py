@@ -144,3 +144,73 @@ def test_table1_second_order_two_level_converges_like_single_level(pf):
         c.close()
     say(f"ISDC {its[0]} iterations, IMLSDC with both options {its[2]}")
     assert its[2] <= its[0] + 1, its
+
+
+def test_absolute_residual_matches_oracle(pf):
+    """residual_abs = 1: per-slice and block residuals without the
+    normalisation, and run_block stopping on the absolute bound."""
+    n, P = 31, 4
+    say(f"absolute residual n={n} P={P}")
+    u0, _ = inputs.random_fourier(n, 1409)
+    c = make(pf, n=n, n_slices=P, residual_abs=1, f_solve=1, f_interp=1, pfasst_tol=1e-7, pfasst_max_iter=60)
+    orc = O.Pfasst(3, n, 1.0, 1e-3, P, 5, 3, O.policy(cycles=1), f_solve=1, f_interp=1, residual_abs=1)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    for k in range(2):
+        r_gpu, r_or = c.pfasst_iter(), orc.iterate()
+        assert abs(r_gpu - r_or) <= 1e-9 * r_or, (k, r_gpu, r_or)
+        np.testing.assert_allclose(c.residual(), orc.residual()[1], rtol=1e-9)
+    st, it, res = c.run_block(u0)
+    assert st == pf.OK and res <= 1e-7
+    orc.set_initial(u0)
+    k = 0
+    while k < 60:
+        k += 1
+        if orc.iterate() <= 1e-7:
+            break
+    assert it == k, (it, k)
+
+
+def resid_bar(c, orc, P, lnorm):
+    """Absolute bar for the (absolute) collocation residual
+    u0 - U[m] + dt sum_i q_{m,i} nu L_h U[i]: both sides evaluate it from
+    their own U, so the max-norm difference du of U (measured, at least 4
+    ulps of U) reaches it amplified by 2 + dt max_m sum_i |q_{m,i}| |nu L_h|;
+    four times that, plus a few ulps of the summed terms."""
+    eps = np.finfo(np.float64).eps
+    du = umax = 0.0
+    for p in range(P):
+        for m in range(orc.nn[0]):
+            u_or = orc.field(O.UF, p, m)
+            du = max(du, float(np.max(np.abs(c.get(O.UF, p, m) - u_or))))
+            umax = max(umax, float(np.max(np.abs(u_or))))
+    du = max(du, 4 * eps * umax)
+    _, Q = orc.matrices(0)
+    Lh = lnorm * orc.dim * orc.prm.nu * (orc.n + 1) ** 2
+    amp = 2.0 + orc.prm.dt * np.abs(Q).sum(axis=1).max() * Lh
+    return 4 * du * amp + 16 * eps * umax * amp
+
+
+def test_table1_127_second_order_matches_oracle(pf):
+    """The Table 1 form's launch configuration at its full size: 127^3,
+    uniform 3/2 nodes, nu = 1/3, dt = 1/128, two V-cycles per solve, cubic
+    interpolation, both F options, absolute residual; two slices, the
+    predictor and two iterations."""
+    n, P = 127, 2
+    say(f"Table 1 configuration at n={n}, P={P}: predictor + 2 iterations")
+    nu, dt = 1.0 / 3.0, 1.0 / 128
+    c = make(pf, n=n, n_slices=P, nu=nu, dt=dt, nodes_fine=3, nodes_coarse=2, node_family=pf.NODES_UNIFORM,
+             interp_order=4, vcycles_per_solve=2, f_solve=1, f_interp=1, residual_abs=1)
+    orc = O.Pfasst(3, n, nu, dt, P, 3, 2, O.policy(cycles=2), interp_order=4, node_family=O.UNIFORM,
+                   f_solve=1, f_interp=1, residual_abs=1)
+    u0 = inputs.sine_mode(n, (1, 1, 1), 3)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    ln = lnorm_eff(orc, 2)
+    compare_state(c, orc, P, lnorm_f=ln)
+    for k in range(2):
+        r_gpu, r_or = c.pfasst_iter(), orc.iterate()
+        bar = resid_bar(c, orc, P, ln)
+        assert abs(r_gpu - r_or) <= bar, (k, r_gpu, r_or, bar)
+        np.testing.assert_allclose(c.residual(), orc.residual()[1], rtol=0, atol=bar)
+        compare_state(c, orc, P, lnorm_f=ln)

@@ -24,6 +24,7 @@ _lib = None
 JACOBI, RBGS = 0, 1
 LOBATTO, UNIFORM = 0, 1          # node families
 UF, FF, UC, FC, TAU, UCOLD, FCOLD = range(7)
+K_U, K_F, K_TAU, K_UOLD = range(4)
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -40,7 +41,7 @@ class Params(C.Structure):
                 ("n_slices", C.c_int), ("nodes_fine", C.c_int), ("nodes_coarse", C.c_int),
                 ("mg", MGPolicy), ("interp_order", C.c_int), ("node_family", C.c_int),
                 ("stencil_order", C.c_int), ("f_solve", C.c_int), ("f_interp", C.c_int),
-                ("residual_abs", C.c_int)]
+                ("residual_abs", C.c_int), ("nodes_middle", C.c_int)]
 
 
 def lib():
@@ -92,6 +93,10 @@ def lib():
         L.or_interpolate.argtypes = [C.c_void_p, C.c_int]
         L.or_pfasst_field.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
         L.or_pfasst_field.restype = _dp
+        L.or_fas_restrict_level.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.or_interpolate_level.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.or_pfasst_level_field.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.or_pfasst_level_field.restype = _dp
         L.or_pfasst_vcycles.argtypes = [C.c_void_p, C.c_int]
         L.or_pfasst_vcycles.restype = C.c_longlong
         L.or_pfasst_matrices.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
@@ -244,13 +249,17 @@ class Pfasst:
 
     def __init__(self, dim, n, nu, dt, n_slices, nodes_fine=5, nodes_coarse=3,
                  mg: MGPolicy | None = None, interp_order: int = 2, node_family: int = LOBATTO,
-                 stencil_order: int = 2, f_solve: int = 0, f_interp: int = 0, residual_abs: int = 0):
+                 stencil_order: int = 2, f_solve: int = 0, f_interp: int = 0, residual_abs: int = 0,
+                 nodes_middle: int = 0):
         self.prm = Params(dim, n, nu, dt, n_slices, nodes_fine, nodes_coarse,
                           mg if mg is not None else policy(), interp_order, node_family, stencil_order,
-                          f_solve, f_interp, residual_abs)
+                          f_solve, f_interp, residual_abs, nodes_middle)
         self.dim, self.n, self.P = dim, n, n_slices
-        self.nn = [nodes_fine, nodes_coarse]
+        self.nn = [nodes_fine, nodes_coarse] if nodes_middle == 0 else [nodes_fine, nodes_middle, nodes_coarse]
         self.nc = (n + 1) // 2 - 1
+        self.ns = [n]
+        for _ in range(len(self.nn) - 1 if nodes_coarse else 0):
+            self.ns.append((self.ns[-1] + 1) // 2 - 1)
         h = lib().or_pfasst_create(C.byref(self.prm))
         if not h:
             raise ValueError("oracle rejected the parameters")
@@ -288,6 +297,21 @@ class Pfasst:
 
     def interpolate(self, p):
         lib().or_interpolate(self._h, p)
+
+    def fas_restrict_level(self, level, p):
+        lib().or_fas_restrict_level(self._h, level, p)
+
+    def interpolate_level(self, level, p):
+        lib().or_interpolate_level(self._h, level, p)
+
+    def level_field(self, level, kind, p, m) -> np.ndarray:
+        """A copy of level `level`'s field (kind: K_U, K_F, K_TAU, K_UOLD)."""
+        ptr = lib().or_pfasst_level_field(self._h, level, kind, p, m)
+        if not ptr:
+            raise ValueError("no such field")
+        n = self.ns[level]
+        a = np.ctypeslib.as_array(ptr, shape=(n ** self.dim,))
+        return a.reshape(shape(self.dim, n)).copy()
 
     def vcycles(self, level=0) -> int:
         return lib().or_pfasst_vcycles(self._h, level)

@@ -149,6 +149,8 @@ typedef struct or_params {
     int f_interp;            /* after the coarse correction: 0 F_f re-evaluated; 1 the
                               * coarse F correction interpolated like U's */
     int residual_abs;        /* collocation residual: 0 relative to |U0_p|_inf, 1 absolute */
+    int nodes_middle;        /* > 0: three levels, this many nodes on the middle one
+                              * (needs nodes_coarse > 0) */
 } or_params;
 
 typedef struct or_pfasst or_pfasst;
@@ -165,9 +167,15 @@ double or_pfasst_iter(or_pfasst *c);
 double or_pfasst_residual(or_pfasst *c, double *res);
 /* One SDC sweep on slice p at level 0 (fine) or 1 (coarse, with tau). */
 void or_sdc_sweep(or_pfasst *c, int level, int p);
-/* FAS restriction of slice p and interpolation of slice p. */
+/* FAS restriction of slice p and interpolation of slice p (levels 0 and
+ * 1), and the same between levels l and l+1. */
 void or_fas_restrict(or_pfasst *c, int p);
 void or_interpolate(or_pfasst *c, int p);
+void or_fas_restrict_level(or_pfasst *c, int l, int p);
+void or_interpolate_level(or_pfasst *c, int l, int p);
+/* Any level's field: kind 0 U, 1 F, 2 tau, 3 U^old (levels >= 1). */
+enum { OR_K_U = 0, OR_K_F = 1, OR_K_TAU = 2, OR_K_UOLD = 3 };
+double *or_pfasst_level_field(or_pfasst *c, int lev, int kind, int p, int m);
 
 /* Field access.  which: 0 U_f, 1 F_f, 2 U_c, 3 F_c, 4 tau, 5 U_c_old,
  * 6 F_c_old (f_interp only). */

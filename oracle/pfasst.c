@@ -19,6 +19,16 @@
  *    space and Lagrange in time over the coarse nodes;
  *  - F at node 0 is recomputed whenever node 0 changes;
  *  - the V-cycle initial guess is the previous iterate at the same node;
+ *  - three levels (nodes_middle > 0; Sec. 4.2's weak-scaling runs): the
+ *    FAS term of a level below the middle one carries the finer level's
+ *    own term through the restriction, tau_c = R(dt Q_f F_f + tau_f) -
+ *    dt Q_c F_c(R U_f); an iteration sweeps the fine level, restricts,
+ *    sweeps the middle level, restricts, runs the coarse chain, interpolates
+ *    to the middle level, sweeps it again and interpolates to the fine
+ *    level; the middle level's node 0 is what the restriction and the
+ *    interpolation of the coarse correction leave there (no separate
+ *    send-forward); the predictor interpolates straight up without
+ *    middle-level sweeps;
  *  - options (the paper leaves both open): with f_solve, F at a node after
  *    its solve is (U - b) / (dt d_m), what the implicit-Euler substep
  *    implies, equal to nu L U when the solve is exact; with f_interp, the
@@ -34,17 +44,18 @@
 
 struct or_pfasst {
     or_params p;
-    int nl;                  /* levels: 1 (single) or 2 */
-    int n[2], nn[2];         /* grid size, number of nodes */
-    size_t len[2];           /* points per field */
-    double s[2][16], Q[2][256], S[2][256], d[2][16];
-    double Lt[16 * 16];      /* fine node x coarse node */
-    int cmap[16];            /* coarse node -> coarse-coinciding fine node */
-    double *U[2], *F[2];     /* [P][nn][len] */
-    double *tau, *Uold;      /* coarse: [P][nn_c][len_c] */
-    double *Fold;            /* coarse F at restriction (f_interp) */
-    double *ublock, *ublock_c;
-    long long vcyc[2];
+    int nl;                  /* levels: 1 (single), 2 or 3 */
+    int n[3], nn[3];         /* grid size, number of nodes */
+    size_t len[3];           /* points per field */
+    double s[3][16], Q[3][256], S[3][256], d[3][16];
+    double Lt[2][16 * 16];   /* level l node x level l+1 node */
+    int cmap[2][16];         /* level l+1 node -> coinciding level l node */
+    double *U[3], *F[3];     /* [P][nn][len] */
+    double *tau[3], *Uold[3];/* levels >= 1: [P][nn][len] */
+    double *Fold[3];         /* levels >= 1: F at restriction (f_interp) */
+    double *ub[3];           /* the block's initial value on each level */
+    double *ublock;          /* = ub[0] */
+    long long vcyc[3];
 };
 
 static size_t glen(int dim, int n)
@@ -66,9 +77,21 @@ double *or_pfasst_field(or_pfasst *c, int which, int p, int m)
     case OR_FF: return fld(c, c->F[0], 0, p, m);
     case OR_UC: return c->nl > 1 ? fld(c, c->U[1], 1, p, m) : NULL;
     case OR_FC: return c->nl > 1 ? fld(c, c->F[1], 1, p, m) : NULL;
-    case OR_TAU: return c->nl > 1 ? fld(c, c->tau, 1, p, m) : NULL;
-    case OR_UCOLD: return c->nl > 1 ? fld(c, c->Uold, 1, p, m) : NULL;
-    case OR_FCOLD: return c->nl > 1 && c->Fold ? fld(c, c->Fold, 1, p, m) : NULL;
+    case OR_TAU: return c->nl > 1 ? fld(c, c->tau[1], 1, p, m) : NULL;
+    case OR_UCOLD: return c->nl > 1 ? fld(c, c->Uold[1], 1, p, m) : NULL;
+    case OR_FCOLD: return c->nl > 1 && c->Fold[1] ? fld(c, c->Fold[1], 1, p, m) : NULL;
+    }
+    return NULL;
+}
+
+double *or_pfasst_level_field(or_pfasst *c, int lev, int kind, int p, int m)
+{
+    if (lev < 0 || lev >= c->nl || p < 0 || p >= c->p.n_slices || m < 0 || m >= c->nn[lev]) return NULL;
+    switch (kind) {
+    case OR_K_U: return fld(c, c->U[lev], lev, p, m);
+    case OR_K_F: return fld(c, c->F[lev], lev, p, m);
+    case OR_K_TAU: return lev > 0 ? fld(c, c->tau[lev], lev, p, m) : NULL;
+    case OR_K_UOLD: return lev > 0 ? fld(c, c->Uold[lev], lev, p, m) : NULL;
     }
     return NULL;
 }
@@ -91,15 +114,21 @@ or_pfasst *or_pfasst_create(const or_params *prm)
     if (prm->stencil_order == 4 && prm->mg.mixed) return NULL;
     if ((prm->f_solve != 0 && prm->f_solve != 1) || (prm->f_interp != 0 && prm->f_interp != 1)) return NULL;
     if (prm->residual_abs != 0 && prm->residual_abs != 1) return NULL;
+    if (prm->nodes_middle != 0 && (prm->nodes_coarse == 0 || prm->nodes_middle < 2 || prm->nodes_middle > 16))
+        return NULL;
     or_pfasst *c = (or_pfasst *)calloc(1, sizeof(or_pfasst));
     c->p = *prm;
-    c->nl = prm->nodes_coarse > 0 ? 2 : 1;
+    c->nl = prm->nodes_coarse == 0 ? 1 : prm->nodes_middle > 0 ? 3 : 2;
     c->n[0] = prm->n;
     c->nn[0] = prm->nodes_fine;
-    if (c->nl > 1) {
-        if ((prm->n & 1) == 0 || prm->n < 3) { free(c); return NULL; }
-        c->n[1] = (prm->n + 1) / 2 - 1;
-        c->nn[1] = prm->nodes_coarse;
+    if (c->nl == 2) c->nn[1] = prm->nodes_coarse;
+    if (c->nl == 3) {
+        c->nn[1] = prm->nodes_middle;
+        c->nn[2] = prm->nodes_coarse;
+    }
+    for (int l = 1; l < c->nl; ++l) {
+        if ((c->n[l - 1] & 1) == 0 || c->n[l - 1] < 3) { free(c); return NULL; }
+        c->n[l] = (c->n[l - 1] + 1) / 2 - 1;
     }
     for (int l = 0; l < c->nl; ++l) {
         c->len[l] = glen(prm->dim, c->n[l]);
@@ -110,19 +139,19 @@ or_pfasst *or_pfasst_create(const or_params *prm)
         c->U[l] = (double *)calloc(tot, sizeof(double));
         c->F[l] = (double *)calloc(tot, sizeof(double));
     }
-    c->ublock = (double *)calloc(c->len[0], sizeof(double));
-    if (c->nl > 1) {
-        size_t tot = (size_t)prm->n_slices * c->nn[1] * c->len[1];
-        c->tau = (double *)calloc(tot, sizeof(double));
-        c->Uold = (double *)calloc(tot, sizeof(double));
-        if (prm->f_interp) c->Fold = (double *)calloc(tot, sizeof(double));
-        c->ublock_c = (double *)calloc(c->len[1], sizeof(double));
-        or_interp_matrix(c->nn[0], c->s[0], c->nn[1], c->s[1], c->Lt);
-        for (int mc = 0; mc < c->nn[1]; ++mc) {
-            c->cmap[mc] = -1;
-            for (int mf = 0; mf < c->nn[0]; ++mf)
-                if (fabs(c->s[0][mf] - c->s[1][mc]) < 1e-14) c->cmap[mc] = mf;
-            if (c->cmap[mc] < 0) { or_pfasst_destroy(c); return NULL; }
+    for (int l = 0; l < c->nl; ++l) c->ub[l] = (double *)calloc(c->len[l], sizeof(double));
+    c->ublock = c->ub[0];
+    for (int l = 1; l < c->nl; ++l) {
+        size_t tot = (size_t)prm->n_slices * c->nn[l] * c->len[l];
+        c->tau[l] = (double *)calloc(tot, sizeof(double));
+        c->Uold[l] = (double *)calloc(tot, sizeof(double));
+        if (prm->f_interp) c->Fold[l] = (double *)calloc(tot, sizeof(double));
+        or_interp_matrix(c->nn[l - 1], c->s[l - 1], c->nn[l], c->s[l], c->Lt[l - 1]);
+        for (int mc = 0; mc < c->nn[l]; ++mc) {
+            c->cmap[l - 1][mc] = -1;
+            for (int mf = 0; mf < c->nn[l - 1]; ++mf)
+                if (fabs(c->s[l - 1][mf] - c->s[l][mc]) < 1e-14) c->cmap[l - 1][mc] = mf;
+            if (c->cmap[l - 1][mc] < 0) { or_pfasst_destroy(c); return NULL; }
         }
     }
     return c;
@@ -131,12 +160,14 @@ or_pfasst *or_pfasst_create(const or_params *prm)
 void or_pfasst_destroy(or_pfasst *c)
 {
     if (!c) return;
-    for (int l = 0; l < 2; ++l) { free(c->U[l]); free(c->F[l]); }
-    free(c->tau);
-    free(c->Uold);
-    free(c->Fold);
-    free(c->ublock);
-    free(c->ublock_c);
+    for (int l = 0; l < 3; ++l) {
+        free(c->U[l]);
+        free(c->F[l]);
+        free(c->tau[l]);
+        free(c->Uold[l]);
+        free(c->Fold[l]);
+        free(c->ub[l]);
+    }
     free(c);
 }
 
@@ -192,8 +223,8 @@ void or_sdc_sweep(or_pfasst *c, int lev, int p)
         const double *Im = I + (size_t)m * len;
 #pragma omp parallel for schedule(static) if (len > 65536)
         for (size_t x = 0; x < len; ++x) b[x] = Um[x] - dtm * Fm1[x] + Im[x];
-        if (lev == 1) {
-            const double *t1 = fld(c, c->tau, 1, p, m + 1), *t0 = fld(c, c->tau, 1, p, m);
+        if (lev >= 1) {
+            const double *t1 = fld(c, c->tau[lev], lev, p, m + 1), *t0 = fld(c, c->tau[lev], lev, p, m);
             for (size_t x = 0; x < len; ++x) b[x] = b[x] + (t1[x] - t0[x]);
         }
         double *u = fld(c, c->U[lev], lev, p, m + 1);
@@ -210,71 +241,79 @@ void or_sdc_sweep(or_pfasst *c, int lev, int p)
     free(b);
 }
 
-/* FAS restriction of slice p (Sec. 2.3): U_c = R U_f, F_c = nu L_2h U_c,
- * tau = R(dt Q_f F_f) - dt Q_c F_c; the restricted state is kept as U_c^old. */
-void or_fas_restrict(or_pfasst *c, int p)
+/* FAS restriction of slice p from level l to level l+1 (Sec. 2.3):
+ * U_c = R U_f, F_c = nu L U_c, tau_c = R(dt Q_f F_f + tau_f) - dt Q_c F_c
+ * (tau_f = 0 on the fine level); the restricted state is kept as U_c^old
+ * (and F_c as F_c^old with f_interp). */
+void or_fas_restrict_level(or_pfasst *c, int l, int p)
 {
-    const int dim = c->p.dim, nf = c->n[0], nnf = c->nn[0], nnc = c->nn[1];
-    const size_t lf = c->len[0], lc = c->len[1];
+    const int L = l + 1;
+    const int dim = c->p.dim, nf = c->n[l], nnf = c->nn[l], nnc = c->nn[L];
+    const size_t lf = c->len[l], lc = c->len[L];
     const double dt = c->p.dt;
     for (int mc = 0; mc < nnc; ++mc) {
-        double *uc = fld(c, c->U[1], 1, p, mc);
-        inject(dim, nf, fld(c, c->U[0], 0, p, c->cmap[mc]), uc);
-        feval(c, 1, uc, fld(c, c->F[1], 1, p, mc));
+        double *uc = fld(c, c->U[L], L, p, mc);
+        inject(dim, nf, fld(c, c->U[l], l, p, c->cmap[l][mc]), uc);
+        feval(c, L, uc, fld(c, c->F[L], L, p, mc));
     }
     double *qf = (double *)malloc(lf * sizeof(double));
     double *qfc = (double *)malloc(lc * sizeof(double));
     for (int mc = 0; mc < nnc; ++mc) {
-        const int mf = c->cmap[mc];
+        const int mf = c->cmap[l][mc];
+        const double *tf = l > 0 ? fld(c, c->tau[l], l, p, mf) : NULL;
 #pragma omp parallel for schedule(static) if (lf > 65536)
         for (size_t x = 0; x < lf; ++x) {
             double acc = 0.0;
-            for (int i = 0; i < nnf; ++i) acc += c->Q[0][mf * nnf + i] * fld(c, c->F[0], 0, p, i)[x];
-            qf[x] = dt * acc;
+            for (int i = 0; i < nnf; ++i) acc += c->Q[l][mf * nnf + i] * fld(c, c->F[l], l, p, i)[x];
+            qf[x] = tf ? dt * acc + tf[x] : dt * acc;
         }
         inject(dim, nf, qf, qfc);
-        double *t = fld(c, c->tau, 1, p, mc);
+        double *t = fld(c, c->tau[L], L, p, mc);
         for (size_t x = 0; x < lc; ++x) {
             double acc = 0.0;
-            for (int j = 0; j < nnc; ++j) acc += c->Q[1][mc * nnc + j] * fld(c, c->F[1], 1, p, j)[x];
+            for (int j = 0; j < nnc; ++j) acc += c->Q[L][mc * nnc + j] * fld(c, c->F[L], L, p, j)[x];
             t[x] = qfc[x] - dt * acc;
         }
     }
-    memcpy(fld(c, c->Uold, 1, p, 0), fld(c, c->U[1], 1, p, 0), (size_t)nnc * lc * sizeof(double));
-    if (c->Fold) memcpy(fld(c, c->Fold, 1, p, 0), fld(c, c->F[1], 1, p, 0), (size_t)nnc * lc * sizeof(double));
+    memcpy(fld(c, c->Uold[L], L, p, 0), fld(c, c->U[L], L, p, 0), (size_t)nnc * lc * sizeof(double));
+    if (c->Fold[L]) memcpy(fld(c, c->Fold[L], L, p, 0), fld(c, c->F[L], L, p, 0), (size_t)nnc * lc * sizeof(double));
     free(qf);
     free(qfc);
 }
 
-/* Interpolation of slice p: U_f[m] += P_s sum_mc L_t[m][mc] (U_c - U_c^old)[mc]
- * for every fine node, then F_f recomputed (f_interp: F_f[m] += P_s sum_mc
- * L_t[m][mc] (F_c - F_c^old)[mc], the same interpolation of the coarse F
- * change). */
-void or_interpolate(or_pfasst *c, int p)
+void or_fas_restrict(or_pfasst *c, int p) { or_fas_restrict_level(c, 0, p); }
+
+/* Interpolation of slice p from level l+1 to level l: U_l[m] += P_s sum_mc
+ * L_t[m][mc] (U_{l+1} - U_{l+1}^old)[mc] for every node m of level l, then
+ * F_l recomputed (f_interp: F_l[m] += P_s sum_mc L_t[m][mc] (F_{l+1} -
+ * F_{l+1}^old)[mc], the same interpolation of the coarse F change). */
+void or_interpolate_level(or_pfasst *c, int l, int p)
 {
-    const int dim = c->p.dim, nc = c->n[1], nnf = c->nn[0], nnc = c->nn[1];
-    const size_t lc = c->len[1];
+    const int L = l + 1;
+    const int dim = c->p.dim, nc = c->n[L], nnf = c->nn[l], nnc = c->nn[L];
+    const size_t lc = c->len[L];
+    const double *Lt = c->Lt[l];
     double *dc = (double *)malloc(lc * sizeof(double));
     for (int m = 0; m < nnf; ++m) {
 #pragma omp parallel for schedule(static) if (lc > 65536)
         for (size_t x = 0; x < lc; ++x) {
             double acc = 0.0;
             for (int mc = 0; mc < nnc; ++mc)
-                acc += c->Lt[m * nnc + mc] * (fld(c, c->U[1], 1, p, mc)[x] - fld(c, c->Uold, 1, p, mc)[x]);
+                acc += Lt[m * nnc + mc] * (fld(c, c->U[L], L, p, mc)[x] - fld(c, c->Uold[L], L, p, mc)[x]);
             dc[x] = acc;
         }
-        double *uf = fld(c, c->U[0], 0, p, m);
+        double *uf = fld(c, c->U[l], l, p, m);
         if (c->p.interp_order == 4 && nc >= 3) or_prolong4_add(dim, nc, dc, uf);
         else or_prolong_add(dim, nc, dc, uf);
-        double *ff = fld(c, c->F[0], 0, p, m);
+        double *ff = fld(c, c->F[l], l, p, m);
         if (!c->p.f_interp) {
-            feval(c, 0, uf, ff);
+            feval(c, l, uf, ff);
             continue;
         }
         for (size_t x = 0; x < lc; ++x) {
             double acc = 0.0;
             for (int mc = 0; mc < nnc; ++mc)
-                acc += c->Lt[m * nnc + mc] * (fld(c, c->F[1], 1, p, mc)[x] - fld(c, c->Fold, 1, p, mc)[x]);
+                acc += Lt[m * nnc + mc] * (fld(c, c->F[L], L, p, mc)[x] - fld(c, c->Fold[L], L, p, mc)[x]);
             dc[x] = acc;
         }
         if (c->p.interp_order == 4 && nc >= 3) or_prolong4_add(dim, nc, dc, ff);
@@ -282,6 +321,8 @@ void or_interpolate(or_pfasst *c, int p)
     }
     free(dc);
 }
+
+void or_interpolate(or_pfasst *c, int p) { or_interpolate_level(c, 0, p); }
 
 void or_pfasst_spread(or_pfasst *c, const double *u_block)
 {
@@ -292,7 +333,7 @@ void or_pfasst_spread(or_pfasst *c, const double *u_block)
             memcpy(fld(c, c->U[0], 0, p, m), u_block, c->len[0] * sizeof(double));
             feval(c, 0, u_block, fld(c, c->F[0], 0, p, m));
         }
-    if (c->nl > 1) inject(c->p.dim, c->n[0], u_block, c->ublock_c);
+    for (int l = 1; l < c->nl; ++l) inject(c->p.dim, c->n[l - 1], c->ub[l - 1], c->ub[l]);
 }
 
 /* Predictor (Sec. 2.4): rounds j = 0..P-1; in round j every slice p >= j
@@ -301,23 +342,26 @@ void or_pfasst_spread(or_pfasst *c, const double *u_block)
 void or_pfasst_predictor(or_pfasst *c)
 {
     if (c->nl < 2) return;
-    const int P = c->p.n_slices, Mc = c->nn[1] - 1;
-    const size_t lc = c->len[1];
-    for (int p = 0; p < P; ++p) or_fas_restrict(c, p);
+    const int L = c->nl - 1;
+    const int P = c->p.n_slices, Mc = c->nn[L] - 1;
+    const size_t lc = c->len[L];
+    for (int l = 0; l < L; ++l)
+        for (int p = 0; p < P; ++p) or_fas_restrict_level(c, l, p);
     double *E = (double *)malloc((size_t)P * lc * sizeof(double));
     for (int j = 0; j < P; ++j) {
-        for (int p = 0; p < P; ++p) memcpy(E + p * lc, fld(c, c->U[1], 1, p, Mc), lc * sizeof(double));
+        for (int p = 0; p < P; ++p) memcpy(E + p * lc, fld(c, c->U[L], L, p, Mc), lc * sizeof(double));
         for (int p = j; p < P; ++p) {
             if (j >= 1 && p >= 1) {
-                double *u0 = fld(c, c->U[1], 1, p, 0);
+                double *u0 = fld(c, c->U[L], L, p, 0);
                 memcpy(u0, E + (size_t)(p - 1) * lc, lc * sizeof(double));
-                feval(c, 1, u0, fld(c, c->F[1], 1, p, 0));
+                feval(c, L, u0, fld(c, c->F[L], L, p, 0));
             }
-            or_sdc_sweep(c, 1, p);
+            or_sdc_sweep(c, L, p);
         }
     }
     free(E);
-    for (int p = 0; p < P; ++p) or_interpolate(c, p);
+    for (int l = L - 1; l >= 0; --l)
+        for (int p = 0; p < P; ++p) or_interpolate_level(c, l, p);
 }
 
 /* Collocation residual (eq. resid) per slice:
@@ -377,16 +421,26 @@ double or_pfasst_iter(or_pfasst *c)
     free(E);
     for (int p = 0; p < P; ++p) or_sdc_sweep(c, 0, p);
     if (c->nl > 1) {
-        const int Mc = c->nn[1] - 1;
-        const size_t lc = c->len[1];
-        for (int p = 0; p < P; ++p) or_fas_restrict(c, p);
-        for (int p = 0; p < P; ++p) {
-            double *u0 = fld(c, c->U[1], 1, p, 0);
-            memcpy(u0, p == 0 ? c->ublock_c : fld(c, c->U[1], 1, p - 1, Mc), lc * sizeof(double));
-            feval(c, 1, u0, fld(c, c->F[1], 1, p, 0));
-            or_sdc_sweep(c, 1, p);
+        const int L = c->nl - 1, Mc = c->nn[L] - 1;
+        const size_t lc = c->len[L];
+        for (int l = 0; l < L; ++l) {
+            for (int p = 0; p < P; ++p) or_fas_restrict_level(c, l, p);
+            /* middle levels sweep on the way down */
+            if (l + 1 < L)
+                for (int p = 0; p < P; ++p) or_sdc_sweep(c, l + 1, p);
         }
-        for (int p = 0; p < P; ++p) or_interpolate(c, p);
+        for (int p = 0; p < P; ++p) {
+            double *u0 = fld(c, c->U[L], L, p, 0);
+            memcpy(u0, p == 0 ? c->ub[L] : fld(c, c->U[L], L, p - 1, Mc), lc * sizeof(double));
+            feval(c, L, u0, fld(c, c->F[L], L, p, 0));
+            or_sdc_sweep(c, L, p);
+        }
+        for (int l = L - 1; l >= 0; --l) {
+            for (int p = 0; p < P; ++p) or_interpolate_level(c, l, p);
+            /* and on the way up */
+            if (l > 0)
+                for (int p = 0; p < P; ++p) or_sdc_sweep(c, l, p);
+        }
     }
     return or_pfasst_residual(c, NULL);
 }

@@ -58,7 +58,9 @@ enum { PFMG_GUESS_PREV = 0, PFMG_GUESS_LEARNED = 1 };
 enum { PFMG_SEND_AFTER_ITER = 0 };
 /* Fields readable / writable with pfmg_get / pfmg_set. */
 enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
-       PFMG_TAU = 4, PFMG_U_COARSE_OLD = 5 };
+       PFMG_TAU = 4, PFMG_U_COARSE_OLD = 5,
+       /* level 2 of a three-level context (fields 2..5 are its level 1) */
+       PFMG_U_L2 = 6, PFMG_F_L2 = 7, PFMG_TAU_L2 = 8, PFMG_U_L2_OLD = 9 };
 
 /*
  * Problem and method parameters.
@@ -135,6 +137,17 @@ enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
  *                    its initial value's max-norm (the default); 1: the
  *                    plain max-norm, for an absolute pfasst_tol.  Single
  *                    contexts only.
+ *   nodes_middle     0: one or two PFASST levels; > 0 (with nodes_coarse >
+ *                    0): three levels, fine (n, nodes_fine), middle
+ *                    ((n+1)/2 - 1, nodes_middle) and coarse (one more
+ *                    halving, nodes_coarse), each level's nodes a subset of
+ *                    the finer one's (Sec. 4.2's weak-scaling runs).  The
+ *                    FAS term of the coarse level carries the middle
+ *                    level's through the restriction; an iteration sweeps
+ *                    the middle level after the restriction and again after
+ *                    the coarse correction; the predictor interpolates
+ *                    straight up.  Single contexts only; the iteration runs
+ *                    the slices in one group (no pipelined schedule).
  */
 typedef struct pfmg_params {
     int32_t dim;
@@ -164,6 +177,7 @@ typedef struct pfmg_params {
     int32_t f_solve;
     int32_t f_interp;
     int32_t residual_abs;
+    int32_t nodes_middle;
 } pfmg_params;
 
 /* Fills *p with the defaults: 3D, n = 127, nu = 1, dt = 1e-3, 16 slices,
@@ -231,9 +245,10 @@ pfmg_status pfmg_residual(pfmg_ctx *ctx, int32_t level, double *per_slice_out);
 pfmg_status pfmg_run_block(pfmg_ctx *ctx, const double *u0, int32_t on_device,
                            int32_t *iters_out, double *res_out);
 
-/* Copy a field (PFMG_U_FINE .. PFMG_U_COARSE_OLD) of slice `slice`, node
- * `node` into / from a dense n^dim (fine) or nc^dim (coarse) float64 array
- * on the host (on_device == 0) or device. */
+/* Copy a field (PFMG_U_FINE .. PFMG_U_L2_OLD) of slice `slice`, node
+ * `node` into / from a dense float64 array of its level's grid (n^dim on
+ * the fine level, nc^dim on level 1, one more halving on level 2) on the
+ * host (on_device == 0) or device. */
 pfmg_status pfmg_get(pfmg_ctx *ctx, int32_t field, int32_t slice, int32_t node,
                      double *dst, int32_t on_device);
 pfmg_status pfmg_set(pfmg_ctx *ctx, int32_t field, int32_t slice, int32_t node,

@@ -136,6 +136,7 @@ bool BatchSolver::validate(const pfmg_params *pp, int np, std::string &why)
         why = "a batch re-evaluates F (f_solve = f_interp = 0)"; return false;
     }
     if (a.residual_abs != 0) { why = "a batch uses the relative residual (residual_abs = 0)"; return false; }
+    if (a.nodes_middle != 0) { why = "a batch runs one or two levels (nodes_middle = 0)"; return false; }
     return true;
 }
 

@@ -92,6 +92,7 @@ pfmg_status pfmg_default_params(pfmg_params *p)
     p->f_solve = 0;
     p->f_interp = 0;
     p->residual_abs = 0;
+    p->nodes_middle = 0;
     return PFMG_OK;
 }
 
@@ -245,16 +246,16 @@ pfmg_status pfmg_run_block(pfmg_ctx *ctx, const double *u0, int32_t on_device, i
 
 static pfmg_status field_ptr(pfmg::Solver &sv, int32_t field, int32_t slice, int32_t node, double **out, int *n)
 {
-    const bool coarse = field >= PFMG_U_COARSE;
-    if (field < PFMG_U_FINE || field > PFMG_U_COARSE_OLD) return fail(PFMG_ERR_ARG, "bad field");
-    if (coarse && sv.nl < 2) return fail(PFMG_ERR_ARG, "no coarse level");
-    const pfmg::PLevel &Lv = sv.L[coarse ? 1 : 0];
+    if (field < PFMG_U_FINE || field > PFMG_U_L2_OLD) return fail(PFMG_ERR_ARG, "bad field");
+    const int lev = field >= PFMG_U_L2 ? 2 : field >= PFMG_U_COARSE ? 1 : 0;
+    if (lev >= sv.nl) return fail(PFMG_ERR_ARG, "no such level");
+    const pfmg::PLevel &Lv = sv.L[lev];
     if (slice < 0 || slice >= sv.P || node < 0 || node >= Lv.nn) return fail(PFMG_ERR_ARG, "bad slice or node");
     double *base = nullptr;
     switch (field) {
-    case PFMG_U_FINE: case PFMG_U_COARSE: base = Lv.U; break;
-    case PFMG_F_FINE: case PFMG_F_COARSE: base = Lv.F; break;
-    case PFMG_TAU: base = Lv.Tau; break;
+    case PFMG_U_FINE: case PFMG_U_COARSE: case PFMG_U_L2: base = Lv.U; break;
+    case PFMG_F_FINE: case PFMG_F_COARSE: case PFMG_F_L2: base = Lv.F; break;
+    case PFMG_TAU: case PFMG_TAU_L2: base = Lv.Tau; break;
     default: base = Lv.Uold; break;
     }
     *out = Lv.slot(base, slice, node);
@@ -300,7 +301,7 @@ pfmg_status pfmg_set(pfmg_ctx *ctx, int32_t field, int32_t slice, int32_t node, 
 
 pfmg_status pfmg_vcycle_count(pfmg_ctx *ctx, int32_t level, int64_t *count_out)
 {
-    if (!ctx || !count_out || level < 0 || level > 1) return fail(PFMG_ERR_ARG, "bad argument");
+    if (!ctx || !count_out || level < 0 || level > 2) return fail(PFMG_ERR_ARG, "bad argument");
     *count_out = ctx->sv.vcount[level];
     return PFMG_OK;
 }

@@ -139,10 +139,12 @@ hipError_t prolong4_add(const Tiling &t, View<double> ec, View<double> u, hipStr
 hipError_t apply_L_rhs(const Tiling &t, double nu, View<double> u, View<double> F, double delta, View<double> Fn1,
                        View<double> In, View<double> t1, View<double> t0, View<double> b, hipStream_t s);
 // FAS injection (t on the coarse grids): Uc[mc] = Uold[mc] = Uf[cmap[mc]] at
-// 2J, Tau[mc] = dt sum_i Qf[cmap[mc]][i] Ff[i] at 2J.
+// 2J, Tau[mc] = dt sum_i Qf[cmap[mc]][i] Ff[i] (+ Tauf[cmap[mc]], the finer
+// level's own FAS term, when Tauf is set) at 2J.
 hipError_t fas_inject(const Tiling &t, int nnf, int nnc, const int *cmap, double dt,
                       const double *Qf, View<double> Uf, View<double> Ff,
-                      View<double> Uc, View<double> Uold, View<double> Tau, hipStream_t s);
+                      View<double> Uc, View<double> Uold, View<double> Tau, hipStream_t s,
+                      View<double> Tauf = View<double>{nullptr, 0});
 // Tau[mc] -= dt sum_j Qc[mc][j] Fc[j]   (t.n = coarse n)
 hipError_t fas_tau(const Tiling &t, int nnc, double dt, const double *Qc, View<double> Fc,
                    View<double> Tau, hipStream_t s);

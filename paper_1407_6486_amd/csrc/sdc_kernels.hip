@@ -230,7 +230,7 @@ template <int DIM, int NNF, int NNC>
 __global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nnf_rt, int nnc_rt, IntMap cmap, double dt,
                                                            const double *__restrict__ Qf, View<double> Uf,
                                                            View<double> Ff, View<double> Uc,
-                                                           View<double> Uold, View<double> Tau)
+                                                           View<double> Uold, View<double> Tau, View<double> Tauf)
 {
     const int nnf = NNF > 0 ? NNF : nnf_rt, nnc = NNC > 0 ? NNC : nnc_rt;
     Pt q; int I, J, K; long o;
@@ -244,6 +244,7 @@ __global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nnf_rt,
     double fv[MAXN];
     for (int w = 0; w < nnf; ++w) fv[w] = ff[w * f_node];
     double *uc = fp(Uc, q) + o, *uo = fp(Uold, q) + o, *ta = fp(Tau, q) + o;
+    const double *tf = Tauf.p ? fp(Tauf, q) + fo : nullptr;
     for (int mc = 0; mc < nnc; ++mc) {
         const int mf = cmap.v[mc];
         const double v = uf[mf * f_node];
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nnf_rt,
         uo[mc * c_node] = v;
         double acc = 0.0;
         for (int w = 0; w < nnf; ++w) acc += Qf[mf * nnf + w] * fv[w];
-        ta[mc * c_node] = h * acc;
+        ta[mc * c_node] = tf ? h * acc + tf[mf * f_node] : h * acc;
     }
 }
 
@@ -485,14 +486,14 @@ hipError_t sdc_rhs(const Tiling &t, double delta, View<double> Um, View<double> 
 
 hipError_t fas_inject(const Tiling &t, int nnf, int nnc, const int *cmap, double dt, const double *Qf,
                       View<double> Uf, View<double> Ff, View<double> Uc, View<double> Uold, View<double> Tau,
-                      hipStream_t s)
+                      hipStream_t s, View<double> Tauf)
 {
     if (nnf > MAXN || nnc > MAXN) return hipErrorInvalidValue;
     IntMap m{};
     for (int w = 0; w < nnc; ++w) m.v[w] = cmap[w];
     if (nnf == 5 && nnc == 3)
-        PFMG_DISPATCH_N2(t, fas_inject_kernel, 5, 3, t, nnf, nnc, m, dt, Qf, Uf, Ff, Uc, Uold, Tau);
-    PFMG_DISPATCH_N2(t, fas_inject_kernel, 0, 0, t, nnf, nnc, m, dt, Qf, Uf, Ff, Uc, Uold, Tau);
+        PFMG_DISPATCH_N2(t, fas_inject_kernel, 5, 3, t, nnf, nnc, m, dt, Qf, Uf, Ff, Uc, Uold, Tau, Tauf);
+    PFMG_DISPATCH_N2(t, fas_inject_kernel, 0, 0, t, nnf, nnc, m, dt, Qf, Uf, Ff, Uc, Uold, Tau, Tauf);
 }
 
 hipError_t fas_tau(const Tiling &t, int nnc, double dt, const double *Qc, View<double> Fc, View<double> Tau,

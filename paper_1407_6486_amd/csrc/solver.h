@@ -64,22 +64,29 @@ struct Solver {
     pfmg_params p{};
     hipStream_t s = nullptr;
     int dim = 3, P = 1, nl = 1;
-    PLevel L[2];
-    double *ublock = nullptr, *ublock_c = nullptr, *fublock_c = nullptr;
+    PLevel L[3];                      // fine, (middle,) coarse
+    double *ublock = nullptr, *ublock_c = nullptr, *fublock_c = nullptr;   // fine; coarsest level
+    double *ublock_m = nullptr;               // middle level (three levels)
     double *vb = nullptr, *vu = nullptr;      // pfmg_vcycle staging slots (fine)
-    double *dLt = nullptr;
-    int cmap[16] = {0};
+    double *dLt[2] = {nullptr, nullptr};      // level l node x level l+1 node
+    int cmap[2][16] = {};
     unsigned long long *bits = nullptr;       // reduction scratch [4 * P]
     int *mask = nullptr;                      // [P]
     unsigned long long *hbits = nullptr;      // pinned host mirror [4 * P]
     int *hmask = nullptr;                     // pinned host mask [P]
     bool has_state = false;
-    long long vcount[2] = {0, 0};
+    long long vcount[3] = {0, 0, 0};
     int last_solve_status = 0;
     Timer timer;
 
     // --- setup
     static bool validate(const pfmg_params &p, std::string &why);
+    // levels of a context (1, 2 or 3) and the node count of level lev
+    static int levels(const pfmg_params &p) { return p.nodes_coarse == 0 ? 1 : p.nodes_middle > 0 ? 3 : 2; }
+    static int level_nodes(const pfmg_params &p, int lev)
+    {
+        return lev == 0 ? p.nodes_fine : (levels(p) == 3 && lev == 1) ? p.nodes_middle : p.nodes_coarse;
+    }
     static size_t carve(const pfmg_params &p, char *base, Solver *sv);   // returns bytes
     bool init_host(std::string &why);
     hipError_t upload_constants();
@@ -106,8 +113,9 @@ struct Solver {
     // slice is first copied from there, in the sweep's first kernel.
     hipError_t sweep(int lev, int p0, int p1, const double *u0src = nullptr, const double *f0src = nullptr,
                      long src_stride = 0);
-    hipError_t fas_restrict(int p0, int p1);
-    hipError_t interpolate(int p0, int p1);
+    // level l -> l+1 and l+1 -> l
+    hipError_t fas_restrict(int p0, int p1, int l = 0);
+    hipError_t interpolate(int p0, int p1, int l = 0);
     hipError_t predictor();
     hipError_t spread(const double *u0_dev);
     hipError_t residual(double *per_slice, double *block);
@@ -121,7 +129,7 @@ struct Solver {
     hipGraphExec_t g_iter = nullptr, g_start = nullptr;
     bool warm_iter = false, warm_start = false;   // first call ran eagerly
     bool use_graph() const { return graphs && p.vcycles_per_solve > 0 && !timer.on; }
-    long long vc_iter[2] = {0, 0}, vc_start[2] = {0, 0};   // V-cycles of one replay
+    long long vc_iter[3] = {0, 0, 0}, vc_start[3] = {0, 0, 0};   // V-cycles of one replay
     // learned initial guess and the recording of training pairs
     UNet *unet = nullptr;
     double *nnsc = nullptr, *hnnsc = nullptr;   // per-field scale factors [2P], device and pinned host

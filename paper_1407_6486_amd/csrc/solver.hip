@@ -48,17 +48,24 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
     if (p.node_family != PFMG_NODES_LOBATTO && p.node_family != PFMG_NODES_UNIFORM) {
         why = "node_family must be PFMG_NODES_LOBATTO or PFMG_NODES_UNIFORM"; return false;
     }
+    if (p.nodes_middle != 0 && (p.nodes_coarse == 0 || p.nodes_middle < 2 || p.nodes_middle > p.nodes_fine)) {
+        why = "nodes_middle needs a coarse level and must be in 2..nodes_fine"; return false;
+    }
     if (p.nodes_coarse != 0) {
-        if (p.nodes_coarse < 2 || p.nodes_coarse > p.nodes_fine) { why = "bad nodes_coarse"; return false; }
-        if (p.n < 3) { why = "two levels need n >= 3"; return false; }
-        long double sf[16], sc[16];
-        if (!family_nodes_ld(p.node_family, p.nodes_fine, sf) || !family_nodes_ld(p.node_family, p.nodes_coarse, sc)) {
-            why = "node construction failed"; return false;
-        }
-        for (int mc = 0; mc < p.nodes_coarse; ++mc) {
-            bool found = false;
-            for (int mf = 0; mf < p.nodes_fine; ++mf) found = found || std::fabs((double)(sf[mf] - sc[mc])) < 1e-14;
-            if (!found) { why = "coarse nodes must be a subset of the fine nodes (injection in time)"; return false; }
+        const int nlv = levels(p);
+        if (p.nodes_coarse < 2 || p.nodes_coarse > level_nodes(p, nlv - 2)) { why = "bad nodes_coarse"; return false; }
+        if (p.n < 3 || (nlv == 3 && coarser(p.n) < 3)) { why = "every coarser level needs n >= 3 above it"; return false; }
+        for (int l = 1; l < nlv; ++l) {
+            long double sf[16], sc[16];
+            const int nf = level_nodes(p, l - 1), nc = level_nodes(p, l);
+            if (!family_nodes_ld(p.node_family, nf, sf) || !family_nodes_ld(p.node_family, nc, sc)) {
+                why = "node construction failed"; return false;
+            }
+            for (int mc = 0; mc < nc; ++mc) {
+                bool found = false;
+                for (int mf = 0; mf < nf; ++mf) found = found || std::fabs((double)(sf[mf] - sc[mc])) < 1e-14;
+                if (!found) { why = "a level's nodes must be a subset of the finer level's (injection in time)"; return false; }
+            }
         }
     }
     if (p.smoother != PFMG_SMOOTH_JACOBI && p.smoother != PFMG_SMOOTH_RBGS) { why = "bad smoother"; return false; }
@@ -72,7 +79,8 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
         why = "stencil_order 4 needs FP64 and plain guesses"; return false;
     }
     if (p.stencil_order == 4 && p.n < 3) { why = "stencil_order 4 needs n >= 3"; return false; }
-    if (p.interp_order == 4 && p.nodes_coarse > 0 && coarser(p.n) < 3) {
+    if (p.interp_order == 4 && p.nodes_coarse > 0 &&
+        coarser(levels(p) == 3 ? coarser(p.n) : p.n) < 3) {
         why = "cubic interpolation needs a coarse grid of n >= 3"; return false;
     }
     if (p.nu_pre < 0 || p.nu_post < 0 || p.nu_pre + p.nu_post == 0 || p.nu_pre > 16 || p.nu_post > 16) {
@@ -108,7 +116,7 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
         return r;
     };
     const int dim = p.dim, P = p.n_slices;
-    const int nl = p.nodes_coarse > 0 ? 2 : 1;
+    const int nl = levels(p);
     const bool mixed = p.precision == PFMG_MIXED;
     const bool jac = p.smoother == PFMG_SMOOTH_JACOBI;
     auto f64 = [&](int n, long count) -> double * {
@@ -121,9 +129,8 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
         char *c = take((size_t)count * fs * 4);
         return c ? (float *)c + field_lead(4) : nullptr;
     };
-    for (int lev = 0; lev < nl; ++lev) {
-        const int n = lev == 0 ? p.n : coarser(p.n);
-        const int nn = lev == 0 ? p.nodes_fine : p.nodes_coarse;
+    for (int lev = 0, n = p.n; lev < nl; ++lev, n = coarser(n)) {
+        const int nn = level_nodes(p, lev);
         PLevel tmp;
         PLevel &L = sv ? sv->L[lev] : tmp;
         L.n = n;
@@ -133,10 +140,10 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
         L.F = f64(n, (long)P * nn);
         L.I = f64(n, (long)P * (nn - 1));
         L.B = f64(n, P);
-        if (lev == 1) {
+        if (lev >= 1) {
             L.Tau = f64(n, (long)P * nn);
             L.Uold = f64(n, (long)P * nn);
-            L.DC = f64(n, (long)P * p.nodes_fine);
+            L.DC = f64(n, (long)P * level_nodes(p, lev - 1));
             L.Fold = p.f_interp ? f64(n, (long)P * nn) : nullptr;
         }
         // F(U) of every fine node for the collocation residual when the
@@ -170,12 +177,14 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
         L.dS = dS;
     }
     double *ub = f64(p.n, 1), *vb = f64(p.n, 1), *vu = f64(p.n, 1);
-    double *ubc = nullptr, *fubc = nullptr;
+    double *ubc = nullptr, *fubc = nullptr, *ubm = nullptr;
     if (nl > 1) {
-        ubc = f64(coarser(p.n), 1);
-        fubc = f64(coarser(p.n), 1);
+        const int nc = nl == 3 ? coarser(coarser(p.n)) : coarser(p.n);
+        ubc = f64(nc, 1);
+        fubc = f64(nc, 1);
+        if (nl == 3) ubm = f64(coarser(p.n), 1);
     }
-    double *lt = (double *)take(256 * 8);
+    double *lt = (double *)take(256 * 8), *lt2 = (double *)take(256 * 8);
     auto *bits = (unsigned long long *)take((size_t)4 * P * k::RSLOTS * 8);
     int *mask = (int *)take((size_t)P * 4);
     double *nnsc = (double *)take((size_t)2 * P * 8);
@@ -185,7 +194,9 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
         sv->vu = vu;
         sv->ublock_c = ubc;
         sv->fublock_c = fubc;
-        sv->dLt = lt;
+        sv->ublock_m = ubm;
+        sv->dLt[0] = lt;
+        sv->dLt[1] = lt2;
         sv->bits = bits;
         sv->mask = mask;
         sv->nnsc = nnsc;
@@ -247,22 +258,27 @@ bool Solver::init_host(std::string &why)
     }
     if ((int)gbound.size() - 1 > MAXGROUPS) gbound = {0, P};
     groups = (int)gbound.size() - 1;
-    nl = p.nodes_coarse > 0 ? 2 : 1;
+    nl = levels(p);
+    // the pipelined schedule is built for two levels
+    if (nl == 3) {
+        gbound = {0, P};
+        groups = 1;
+    }
     for (int lev = 0; lev < nl; ++lev) {
         PLevel &Lv = L[lev];
-        const int nn = lev == 0 ? p.nodes_fine : p.nodes_coarse;
+        const int nn = level_nodes(p, lev);
         if (!family_nodes_ld(p.node_family, nn, Lv.s_ld)) { why = "node construction failed"; return false; }
         for (int q = 0; q < nn; ++q) Lv.s[q] = (double)Lv.s_ld[q];
         if (!collocation_matrices(nn, Lv.s_ld, Lv.Q, Lv.S, Lv.d, p.node_family == PFMG_NODES_UNIFORM ? 1 : 0)) {
             why = "Q construction failed"; return false;
         }
     }
-    if (nl > 1) {
-        for (int mc = 0; mc < p.nodes_coarse; ++mc) {
-            cmap[mc] = -1;
-            for (int mf = 0; mf < p.nodes_fine; ++mf)
-                if (std::fabs((double)(L[0].s_ld[mf] - L[1].s_ld[mc])) < 1e-14) cmap[mc] = mf;
-            if (cmap[mc] < 0) { why = "coarse nodes must be a subset of the fine nodes"; return false; }
+    for (int l = 0; l + 1 < nl; ++l) {
+        for (int mc = 0; mc < L[l + 1].nn; ++mc) {
+            cmap[l][mc] = -1;
+            for (int mf = 0; mf < L[l].nn; ++mf)
+                if (std::fabs((double)(L[l].s_ld[mf] - L[l + 1].s_ld[mc])) < 1e-14) cmap[l][mc] = mf;
+            if (cmap[l][mc] < 0) { why = "a level's nodes must be a subset of the finer level's"; return false; }
         }
     }
     return true;
@@ -275,9 +291,11 @@ hipError_t Solver::upload_constants()
         HC(hipMemcpyAsync(L[lev].dQ, L[lev].Q, sizeof(double) * L[lev].nn * L[lev].nn, hipMemcpyHostToDevice, s));
         HC(hipMemcpyAsync(L[lev].dS, L[lev].S, sizeof(double) * L[lev].nn * L[lev].nn, hipMemcpyHostToDevice, s));
     }
-    if (nl > 1) {
-        lagrange_interp(p.nodes_fine, L[0].s_ld, p.nodes_coarse, L[1].s_ld, Lt);
-        HC(hipMemcpyAsync(dLt, Lt, sizeof(double) * p.nodes_fine * p.nodes_coarse, hipMemcpyHostToDevice, s));
+    for (int l = 0; l + 1 < nl; ++l) {
+        lagrange_interp(L[l].nn, L[l].s_ld, L[l + 1].nn, L[l + 1].s_ld, Lt);
+        HC(hipMemcpyAsync(dLt[l], Lt, sizeof(double) * L[l].nn * L[l + 1].nn, hipMemcpyHostToDevice, s));
+        // the copy reads the host table when it runs
+        HC(hipStreamSynchronize(s));
     }
     return hipStreamSynchronize(s);
 }
@@ -682,7 +700,7 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
         Fm1 = {Lv.slot(Lv.F, p0, m + 1), sst};
         Im = {Lv.I + (long)p0 * ist + (long)m * fs, ist};
         t1 = t0 = View<double>{nullptr, 0};
-        if (lev == 1) {
+        if (lev >= 1) {
             t1 = {Lv.slot(Lv.Tau, p0, m + 1), sst};
             t0 = {Lv.slot(Lv.Tau, p0, m), sst};
         }
@@ -690,15 +708,15 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
     // A new node 0 taken from a source gets F = nu L_h of its value when
     // the source's F came from a solve (f_solve); sources are coarse nodes.
     const bool eval0 = u0src && p.f_solve;
-    if (eval0 && lev != 1) return hipErrorInvalidValue;
+    if (eval0 && lev == 0) return hipErrorInvalidValue;
     if (fused_sdc) {
         // node 0 from the source, the integrals and the first right-hand side
         const View<double> us{const_cast<double *>(u0src), src_stride};
         const View<double> fsrc{const_cast<double *>(f0src), src_stride};
-        tstart("sdc_start", Lv.n, 8.0 * (2 * nn - 1) + 16 + (lev == 1 ? 16 : 0) + (u0src ? 16 : 0), pts);
+        tstart("sdc_start", Lv.n, 8.0 * (2 * nn - 1) + 16 + (lev >= 1 ? 16 : 0) + (u0src ? 16 : 0), pts);
         HC(k::sdc_start(t, nn, p.dt, Lv.dS, p.dt * Lv.d[1], View<double>{Lv.slot(Lv.U, p0, 0), sst},
                         View<double>{Lv.slot(Lv.F, p0, 0), sst}, us, fsrc, View<double>{Lv.I + (long)p0 * ist, ist},
-                        lev == 1 ? View<double>{Lv.slot(Lv.Tau, p0, 0), sst} : View<double>{nullptr, 0}, Bv, s,
+                        lev >= 1 ? View<double>{Lv.slot(Lv.Tau, p0, 0), sst} : View<double>{nullptr, 0}, Bv, s,
                         eval0 ? p.nu : 0.0));
         tstop();
     } else {
@@ -716,7 +734,7 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
                             View<double>{Lv.I + (long)p0 * ist, ist}, s));
         tstop();
         rhs_views(0);
-        tstart("sdc_rhs", Lv.n, lev == 1 ? 48 : 32, pts);
+        tstart("sdc_rhs", Lv.n, lev >= 1 ? 48 : 32, pts);
         HC(k::sdc_rhs(t, p.dt * Lv.d[1], Um, Fm1, Im, t1, t0, Bv, s));
         tstop();
     }
@@ -731,7 +749,7 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
         if (more) rhs_views(m + 1);
         if (p.f_solve) {
             // F from the solve, then the next right-hand side (Um is node m+1)
-            tstart("solve_F", Lv.n, more ? (lev == 1 ? 72 : 56) : 24, pts);
+            tstart("solve_F", Lv.n, more ? (lev >= 1 ? 72 : 56) : 24, pts);
             HC(k::solve_F_rhs(t, delta, Uv, Bv, Fv, more ? p.dt * Lv.d[m + 2] : 0.0,
                               more ? Fm1 : View<double>{nullptr, 0}, more ? Im : View<double>{nullptr, 0},
                               more ? t1 : View<double>{nullptr, 0}, more ? t0 : View<double>{nullptr, 0}, s));
@@ -750,7 +768,7 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
         HC(apply_F(lev, t, Uv, Fv));
         tstop();
         if (more) {
-            tstart("sdc_rhs", Lv.n, lev == 1 ? 48 : 32, pts);
+            tstart("sdc_rhs", Lv.n, lev >= 1 ? 48 : 32, pts);
             HC(k::sdc_rhs(t, p.dt * Lv.d[m + 2], Um, Fm1, Im, t1, t0, Bv, s));
             tstop();
         }
@@ -758,15 +776,18 @@ hipError_t Solver::sweep(int lev, int p0, int p1, const double *u0src, const dou
     return hipSuccess;
 }
 
-hipError_t Solver::fas_restrict(int p0, int p1)
+// Level l to l+1; below the middle level the finer level's own FAS term
+// joins the restricted integrals (tau_c = R(dt Q_f F_f + tau_f) - dt Q_c F_c).
+hipError_t Solver::fas_restrict(int p0, int p1, int l)
 {
-    PLevel &Fn = L[0], &Cs = L[1];
+    PLevel &Fn = L[l], &Cs = L[l + 1];
     const int count = p1 - p0;
     const long fst = (long)Fn.nn * Fn.fs, cst = (long)Cs.nn * Cs.fs;
-    HC(k::fas_inject(tl(Cs.n, count), Fn.nn, Cs.nn, cmap, p.dt, Fn.dQ,
+    HC(k::fas_inject(tl(Cs.n, count), Fn.nn, Cs.nn, cmap[l], p.dt, Fn.dQ,
                      View<double>{Fn.slot(Fn.U, p0, 0), fst}, View<double>{Fn.slot(Fn.F, p0, 0), fst},
                      View<double>{Cs.slot(Cs.U, p0, 0), cst}, View<double>{Cs.slot(Cs.Uold, p0, 0), cst},
-                     View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, s));
+                     View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, s,
+                     l > 0 ? View<double>{Fn.slot(Fn.Tau, p0, 0), fst} : View<double>{nullptr, 0}));
     HC(k::apply_L(tl(Cs.n, count * Cs.nn), p.nu, View<double>{Cs.slot(Cs.U, p0, 0), Cs.fs},
                   View<double>{Cs.slot(Cs.F, p0, 0), Cs.fs}, s));
     if (Cs.Fold)
@@ -776,9 +797,10 @@ hipError_t Solver::fas_restrict(int p0, int p1)
                       View<double>{Cs.slot(Cs.Tau, p0, 0), cst}, s);
 }
 
-hipError_t Solver::interpolate(int p0, int p1)
+hipError_t Solver::interpolate(int p0, int p1, int l)
 {
-    PLevel &Fn = L[0], &Cs = L[1];
+    PLevel &Fn = L[l], &Cs = L[l + 1];
+    const double *dLt = this->dLt[l];
     const int count = p1 - p0;
     const long cst = (long)Cs.nn * Cs.fs, dst = (long)Fn.nn * Cs.fs;
     double *dc = Cs.DC + (long)p0 * dst;
@@ -804,7 +826,7 @@ hipError_t Solver::interpolate(int p0, int p1)
         return hipSuccess;
     }
     tstart("apply_L", Fn.n, 16, pts);
-    HC(apply_F(0, tl(Fn.n, count * Fn.nn), View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs},
+    HC(apply_F(l, tl(Fn.n, count * Fn.nn), View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs},
                View<double>{Fn.slot(Fn.F, p0, 0), Fn.fs}));
     tstop();
     return hipSuccess;
@@ -816,8 +838,7 @@ hipError_t Solver::spread(const double *u0_dev)
     HC(k::unpack(tl(Fn.n, 1), u0_dev, View<double>{ublock, 0}, s));
     if (use_graph() && warm_start) {
         if (!g_start) HC(capture([this] { return spread_body(); }, &g_start, vc_start));
-        vcount[0] += vc_start[0];
-        vcount[1] += vc_start[1];
+        for (int l = 0; l < 3; ++l) vcount[l] += vc_start[l];
         return hipGraphLaunch(g_start, s);
     }
     // the first block start runs eagerly: launch shapes are tuned outside
@@ -833,10 +854,13 @@ hipError_t Solver::spread_body()
     PLevel &Fn = L[0];
     HC(k::copy(tl(Fn.n, P * Fn.nn), View<double>{ublock, 0}, View<double>{Fn.U, Fn.fs}, s));
     HC(apply_F(0, tl(Fn.n, P * Fn.nn), View<double>{ublock, 0}, View<double>{Fn.F, Fn.fs}));
-    if (nl > 1) {
-        HC(k::inject(tl(L[1].n, 1), View<double>{ublock, 0}, View<double>{ublock_c, 0}, s));
-        HC(k::apply_L(tl(L[1].n, 1), p.nu, View<double>{ublock_c, 0}, View<double>{fublock_c, 0}, s));
+    if (nl == 2) HC(k::inject(tl(L[1].n, 1), View<double>{ublock, 0}, View<double>{ublock_c, 0}, s));
+    if (nl == 3) {
+        HC(k::inject(tl(L[1].n, 1), View<double>{ublock, 0}, View<double>{ublock_m, 0}, s));
+        HC(k::inject(tl(L[2].n, 1), View<double>{ublock_m, 0}, View<double>{ublock_c, 0}, s));
     }
+    if (nl > 1)
+        HC(k::apply_L(tl(L[nl - 1].n, 1), p.nu, View<double>{ublock_c, 0}, View<double>{fublock_c, 0}, s));
     return predictor();
 }
 
@@ -846,18 +870,21 @@ hipError_t Solver::spread_body()
 hipError_t Solver::predictor()
 {
     if (nl < 2) return hipSuccess;
-    PLevel &Cs = L[1];
+    const int Lc = nl - 1;
+    PLevel &Cs = L[Lc];
     const int Mc = Cs.nn - 1;
     const long cst = (long)Cs.nn * Cs.fs;
-    HC(fas_restrict(0, P));
+    for (int l = 0; l < Lc; ++l) HC(fas_restrict(0, P, l));
     for (int j = 0; j < P; ++j) {
         // round j >= 1: slices j .. P-1 first take node 0 from the previous
         // slice's last node (in the sweep's first kernel)
-        if (j >= 1) HC(sweep(1, j, P, Cs.slot(Cs.U, j - 1, Mc), Cs.slot(Cs.F, j - 1, Mc), cst));
-        else HC(sweep(1, j, P));
+        if (j >= 1) HC(sweep(Lc, j, P, Cs.slot(Cs.U, j - 1, Mc), Cs.slot(Cs.F, j - 1, Mc), cst));
+        else HC(sweep(Lc, j, P));
         if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
     }
-    return interpolate(0, P);
+    // straight up, without middle-level sweeps
+    for (int l = Lc - 1; l >= 0; --l) HC(interpolate(0, P, l));
+    return hipSuccess;
 }
 
 // Per-slice maxima land in RSLOTS partial slots per slice (spreading the
@@ -938,16 +965,31 @@ hipError_t Solver::iterate_body()
         else
             HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.F, 0, M), fst}, View<double>{Fn.slot(Fn.F, 1, 0), fst}, s));
     }
-    if (nl > 1 && groups > 1 && p.vcycles_per_solve > 0) return iterate_pipelined();
+    if (nl == 2 && groups > 1 && p.vcycles_per_solve > 0) return iterate_pipelined();
     HC(sweep(0, 0, P));
     if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
     if (nl > 1) {
-        HC(fas_restrict(0, P));
+        const int Lc = nl - 1;
+        for (int l = 0; l < Lc; ++l) {
+            HC(fas_restrict(0, P, l));
+            // a middle level sweeps on the way down
+            if (l + 1 < Lc) {
+                HC(sweep(l + 1, 0, P));
+                if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+            }
+        }
         for (int q = 0; q < P; ++q) {
             HC(chain_step(q));
             if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
         }
-        HC(interpolate(0, P));
+        for (int l = Lc - 1; l >= 0; --l) {
+            HC(interpolate(0, P, l));
+            // and on the way up
+            if (l > 0) {
+                HC(sweep(l, 0, P));
+                if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+            }
+        }
     }
     return residual_enqueue();
 }
@@ -956,11 +998,12 @@ hipError_t Solver::iterate_body()
 // initial value for q = 0, else slice q-1's end value of this iteration.
 hipError_t Solver::chain_step(int q)
 {
-    PLevel &Cs = L[1];
+    const int Lc = nl - 1;
+    PLevel &Cs = L[Lc];
     const int Mc = Cs.nn - 1;
     const double *us = q == 0 ? ublock_c : Cs.slot(Cs.U, q - 1, Mc);
     const double *fsrc = q == 0 ? fublock_c : Cs.slot(Cs.F, q - 1, Mc);
-    return sweep(1, q, q + 1, us, fsrc, 0);
+    return sweep(Lc, q, q + 1, us, fsrc, 0);
 }
 
 // The same iteration with the slices in groups: the fine sweep and FAS
@@ -1045,8 +1088,7 @@ hipError_t Solver::iterate(double *block)
 {
     if (use_graph() && warm_iter) {
         if (!g_iter) HC(capture([this] { return iterate_body(); }, &g_iter, vc_iter));
-        vcount[0] += vc_iter[0];
-        vcount[1] += vc_iter[1];
+        for (int l = 0; l < 3; ++l) vcount[l] += vc_iter[l];
         HC(hipGraphLaunch(g_iter, s));
     } else {
         warm_iter = true;
@@ -1064,7 +1106,7 @@ hipError_t Solver::capture(const std::function<hipError_t()> &fn, hipGraphExec_t
     if (!cap) HC(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     // V-cycles are counted on the host as they are enqueued: keep the count
     // of one replay and restore the counters (nothing ran during capture)
-    const long long v0 = vcount[0], v1 = vcount[1];
+    const long long v0 = vcount[0], v1 = vcount[1], v2 = vcount[2];
     hipStream_t saved = s;
     s = cap;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
@@ -1074,8 +1116,10 @@ hipError_t Solver::capture(const std::function<hipError_t()> &fn, hipGraphExec_t
     s = saved;
     vc[0] = vcount[0] - v0;
     vc[1] = vcount[1] - v1;
+    vc[2] = vcount[2] - v2;
     vcount[0] = v0;
     vcount[1] = v1;
+    vcount[2] = v2;
     if (e1 != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return e1 != hipSuccess ? e1 : e2;

@@ -34,6 +34,7 @@ FP64, MIXED = 0, 1
 GUESS_PREV, GUESS_LEARNED = 0, 1
 SEND_AFTER_ITER = 0
 U_FINE, F_FINE, U_COARSE, F_COARSE, TAU, U_COARSE_OLD = range(6)
+U_L2, F_L2, TAU_L2, U_L2_OLD = range(6, 10)    # level 2 of a three-level context
 
 
 class PfmgError(RuntimeError):
@@ -51,7 +52,8 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("guess", C.c_int32), ("fine_send", C.c_int32),
                 ("pfasst_tol", C.c_double), ("pfasst_max_iter", C.c_int32), ("guess_min_relres", C.c_double),
                 ("stencil_order", C.c_int32), ("interp_order", C.c_int32),
-                ("f_solve", C.c_int32), ("f_interp", C.c_int32), ("residual_abs", C.c_int32)]
+                ("f_solve", C.c_int32), ("f_interp", C.c_int32), ("residual_abs", C.c_int32),
+                ("nodes_middle", C.c_int32)]
 
 
 _vp, _dp = C.c_void_p, C.POINTER(C.c_double)
@@ -402,6 +404,8 @@ class Context:
     # arrays are float64 torch tensors on the device (or numpy on the host)
     def _shape(self, coarse=False):
         n = self.nc if coarse else self.n
+        if coarse == 2:
+            n = (self.nc + 1) // 2 - 1
         return (n,) * self.dim
 
     def _dev(self, a):
@@ -435,7 +439,7 @@ class Context:
         return pfmg_run_block(self.h, u.data_ptr(), True)
 
     def get(self, field: int, slice_: int, node: int, host: bool = True):
-        coarse = field >= U_COARSE
+        coarse = 2 if field >= U_L2 else field >= U_COARSE
         out = self.torch.empty(self._shape(coarse), dtype=self.torch.float64, device=self.device)
         pfmg_get(self.h, field, slice_, node, out.data_ptr(), True)
         return out.cpu().numpy() if host else out

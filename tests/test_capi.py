@@ -131,6 +131,27 @@ def test_f_options_on_the_host(pf):
         assert ei.value.status == pf.ERR_ARG
 
 
+def test_three_levels_on_the_host(pf):
+    """nodes_middle: a third level's state, FAS terms and multigrid grow the
+    workspace; subsets, grid sizes and the batch are checked."""
+    kw = dict(n=31, n_slices=3, nodes_fine=5, nodes_coarse=2)
+    # the same fine and 15^3 level (3 nodes) as a two-level context, plus a
+    # 7^3 level: U, F, tau and U^old of its 2 nodes per slice at least
+    two = pf.pfmg_workspace_bytes(pf.pfmg_default_params(**{**kw, "nodes_coarse": 3}))
+    three = pf.pfmg_workspace_bytes(pf.pfmg_default_params(nodes_middle=3, **kw))
+    assert three - two >= 4 * 3 * 2 * (8 * 9 ** 2) * 8, (three, two)
+    for bad in ({"nodes_middle": 3, "nodes_coarse": 0}, {"nodes_middle": 4},            # 4 Lobatto nodes: no subset
+                {"nodes_middle": 3, "n": 5}, {"nodes_middle": 3, "nodes_coarse": 4},
+                {"nodes_middle": 3, "n": 7, "interp_order": 4}):
+        with pytest.raises(pf.PfmgError) as ei:
+            pf.pfmg_workspace_bytes(pf.pfmg_default_params(**{**kw, **bad}))
+        assert ei.value.status == pf.ERR_ARG, bad
+    assert pf.pfmg_workspace_bytes(pf.pfmg_default_params(**{**kw, "nodes_middle": 3, "n": 7})) > 0
+    with pytest.raises(pf.PfmgError) as ei:
+        pf.pfmg_batch_workspace_bytes([pf.pfmg_default_params(nodes_middle=3, **kw)])
+    assert ei.value.status == pf.ERR_ARG
+
+
 def test_valid_degenerate_sizes_accepted(pf):
     for n, nc in ((1, 0), (3, 3), (5, 0), (95, 3)):
         p = pf.pfmg_default_params(n=n, nodes_coarse=nc, n_slices=1)

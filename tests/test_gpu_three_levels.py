@@ -1,0 +1,97 @@
+"""Parity of the three-level hierarchy (nodes_middle; Sec. 4.2's
+weak-scaling runs) with the FP64 oracle through the C-ABI: the fine state
+and the middle level's U and tau with the bars of test_gpu_parity, the
+coarsest level's U within 1e-12, residuals and V-cycle counts on every
+level, over the predictor and three iterations."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle as O
+from tests import pins
+from tests.test_gpu_parity import TOL, compare_state, make, say
+from tests.test_gpu_f_options import lnorm_eff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible ROCm device"
+    from paper_1407_6486_amd import pfmg
+    return pfmg
+
+
+#         dim  n   P  family        nf nm nc fs io cycles
+CASES = [(3, 31, 4, O.UNIFORM, 3, 3, 2, 1, 4, 2),
+         (3, 31, 3, O.LOBATTO, 5, 3, 2, 0, 2, 1),
+         (1, 63, 8, O.UNIFORM, 3, 3, 2, 1, 4, 2),
+         (1, 127, 16, O.UNIFORM, 3, 3, 2, 0, 2, 2),
+         (3, 15, 2, O.LOBATTO, 5, 3, 2, 1, 2, 0),
+         (3, 63, 2, O.LOBATTO, 5, 5, 3, 0, 2, 1)]
+
+
+@pytest.mark.parametrize("dim,n,P,fam,nf,nm,nc,fs,io,cycles", CASES)
+def test_three_levels_match_oracle(pf, dim, n, P, fam, nf, nm, nc, fs, io, cycles):
+    say(f"three levels: dim={dim} n={n} P={P} family={fam} nodes {nf}/{nm}/{nc} F options {fs} interp {io} "
+        f"cycles {cycles}")
+    nu, dt = (1.0, 1.0 / P) if dim == 1 else (1.0, 2e-3)
+    kw = dict(vcycles_per_solve=cycles)
+    pol = O.policy(cycles=cycles)
+    if cycles == 0:
+        kw.update(mg_tol=1e-12, mg_stall=0.75, mg_max_cycles=50)
+        pol = O.policy(cycles=0, tol=1e-12, stall=0.75, max_cycles=50)
+    c = make(pf, dim=dim, n=n, n_slices=P, nu=nu, dt=dt, nodes_fine=nf, nodes_middle=nm, nodes_coarse=nc,
+             node_family=fam, interp_order=io, f_solve=fs, f_interp=fs, **kw)
+    orc = O.Pfasst(dim, n, nu, dt, P, nf, nc, pol, interp_order=io, node_family=fam, f_solve=fs, f_interp=fs,
+                   nodes_middle=nm)
+    if dim == 3:
+        u0 = inputs.random_fourier(n, 321)[0]
+    else:
+        x = np.arange(1, n + 1) / (n + 1)
+        u0 = np.sin(np.pi * x)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    ln = lnorm_eff(orc, 2)
+
+    def compare():
+        compare_state(c, orc, P, lnorm_f=ln)
+        for p in range(P):
+            for m in range(nc):
+                assert pins.rel_err(c.get(pf.U_L2, p, m), orc.level_field(2, O.K_U, p, m)) <= TOL, ("U_2", p, m)
+
+    compare()
+    for k in range(3):
+        r_gpu, r_or = c.pfasst_iter(), orc.iterate()
+        assert abs(r_gpu - r_or) <= 1e-9 * r_or, (k, r_gpu, r_or)
+        compare()
+    for lev in range(3):
+        assert c.vcycle_count(lev) == orc.vcycles(lev), lev
+
+
+def test_three_levels_converge_like_the_oracle_1d_weak_scaling(pf):
+    """Sec. 4.2's weak-scaling configuration at N_x = N_t = 64 (1D, nu = 1,
+    T = 1, sin(pi x), 64 slices, uniform 3/3/2 nodes, two red-black V-cycles
+    per solve), with both F options and cubic interpolation: the last
+    slice's error against exp(-pi^2) sin(pi x) per iteration matches the
+    oracle's, and reaches the discretisation level."""
+    N = 64
+    n = N - 1
+    say(f"three-level weak-scaling configuration N={N}")
+    x = np.arange(1, n + 1) / (n + 1)
+    u0 = np.sin(np.pi * x)
+    c = make(pf, dim=1, n=n, n_slices=N, nu=1.0, dt=1.0 / N, nodes_fine=3, nodes_middle=3, nodes_coarse=2,
+             node_family=pf.NODES_UNIFORM, interp_order=4, f_solve=1, f_interp=1, vcycles_per_solve=2)
+    orc = O.Pfasst(1, n, 1.0, 1.0 / N, N, 3, 2, O.policy(cycles=2), interp_order=4, node_family=O.UNIFORM,
+                   f_solve=1, f_interp=1, nodes_middle=3)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    pde = np.exp(-np.pi ** 2) * u0
+    for k in range(8):
+        c.pfasst_iter()
+        orc.iterate()
+        e_gpu = np.max(np.abs(c.get(pf.U_FINE, N - 1, 2) - pde))
+        e_or = np.max(np.abs(orc.field(O.UF, N - 1, 2) - pde))
+        assert abs(e_gpu - e_or) <= 1e-9 * e_or + 1e-13, (k, e_gpu, e_or)
+    assert e_gpu < 6e-7

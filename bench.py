@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--max-iter", type=int, default=400,
                     help="iteration cap per block (profiling runs cap it to keep traces small)")
-    ap.add_argument("--form", choices=["mixed", "batched", "learned", "solve-policies", "heat1d", "table1"],
+    ap.add_argument("--form", choices=["mixed", "batched", "learned", "solve-policies", "heat1d", "table1", "weak3"],
                     default=None,
                     help="instead: one of the method's forms against the plain FP64 path (mixed, batched, learned), "
                          "the node-solve policies at 127^3 x 16 (solve-policies), the 1D latency and error report "
@@ -388,6 +388,61 @@ PAPER_TABLE1 = {
 }
 
 
+def form_weak3(pfmg, a):
+    """Sec. 4.2's weak-scaling runs: 1D heat, nu = L = T = 1, u0 = sin(pi x),
+    N_x = N_t = 32, 64, 128 (n = N - 1 interior points, N slices of one
+    block), three levels coarsened by two in space, uniform nodes (3 on the
+    fine and middle levels, backward Euler on the coarsest), two red-black
+    V(2,2) cycles per solve, both F options and cubic interpolation; the
+    two-level hierarchy beside it.  Per iteration: the last slice's error
+    against exp(-pi^2) sin(pi x) (PDE) and against the semi-discrete
+    solution (ODE), and the block residual; the wall time of the iterations
+    to the error level (the first iteration within 10 % of the converged
+    error, which 30 iterations give)."""
+    import numpy as np
+
+    out = {}
+    for N in (32, 64, 128):
+        n = N - 1
+        h = 1.0 / N
+        x = np.arange(1, n + 1) * h
+        u0 = np.sin(np.pi * x)
+        pde = np.exp(-np.pi ** 2) * u0
+        ode = np.exp(-4.0 * np.sin(np.pi * h / 2) ** 2 / h ** 2) * u0
+        for levels in (3, 2):
+            c = pfmg.Context(pfmg.pfmg_default_params(
+                dim=1, n=n, nu=1.0, dt=1.0 / N, n_slices=N, nodes_fine=3, nodes_coarse=2,
+                nodes_middle=3 if levels == 3 else 0, node_family=pfmg.NODES_UNIFORM, smoother=pfmg.SMOOTH_RBGS,
+                omega=1.0, vcycles_per_solve=2, interp_order=4, f_solve=1, f_interp=1))
+            c.set_initial(u0)
+            rows = []
+            for k in range(30):
+                r = c.pfasst_iter()
+                ue = c.get(pfmg.U_FINE, N - 1, 2)
+                rows.append((float(np.max(np.abs(ue - pde))), float(np.max(np.abs(ue - ode))), r))
+            level = rows[-1][0]
+            reach = next(k + 1 for k, (e, _, _) in enumerate(rows) if abs(e - level) <= 0.1 * level)
+            c.set_initial(u0)
+            import torch
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reach):
+                c.pfasst_iter()
+            torch.cuda.synchronize()
+            out[f"N={N}, {levels} levels"] = {
+                "iteration_reaching_error_level": reach, "s_to_level": round(time.perf_counter() - t0, 5),
+                "pde_error": [float(f"{e:.3e}") for e, _, _ in rows[:8]],
+                "ode_error": [float(f"{o:.3e}") for _, o, _ in rows[:8]],
+                "residual": [float(f"{q:.3e}") for _, _, q in rows[:8]], "converged_pde_error": float(f"{level:.4e}")}
+            c.close()
+    return {"metric": "iterations to the error level (Sec. 4.2 weak scaling, N=128, three levels)",
+            "value": out["N=128, 3 levels"]["iteration_reaching_error_level"], "unit": "iterations",
+            "form": "three-level IPFASST, N_x = N_t", "runs": out, "paper": "error level at iteration 5 (N=32), 3 (N=64, 128)",
+            "higher_is_better": False, "dtype": "f64", "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": "1D heat, nu=1, T=1, sin(pi x), N_x=N_t=32/64/128 (N slices), uniform nodes 3/3/2, "
+                                   "rbgs V(2,2), 2 V-cycles/solve, cubic interpolation, F options"}}
+
+
 def form_table1(pfmg, a):
     """The 3D strong-scaling problem of Sec. 4.3 (nu = 1/3, T = 1,
     u0 = sin(pi x) sin(pi y) sin(pi z), zero Dirichlet data), with the
@@ -499,7 +554,8 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     if a.form:
         fn = {"mixed": form_mixed, "batched": form_batched, "learned": form_learned,
-              "solve-policies": form_solve_policies, "heat1d": form_heat1d, "table1": form_table1}[a.form]
+              "solve-policies": form_solve_policies, "heat1d": form_heat1d, "table1": form_table1,
+              "weak3": form_weak3}[a.form]
         print(json.dumps(fn(pfmg, a), default=float), flush=True)
         return
     if a.calibrate_copy:

@@ -273,10 +273,11 @@ bool Solver::init_host(std::string &why)
             why = "Q construction failed"; return false;
         }
     }
+    // (the workspace is carved after this, so node counts come from p)
     for (int l = 0; l + 1 < nl; ++l) {
-        for (int mc = 0; mc < L[l + 1].nn; ++mc) {
+        for (int mc = 0; mc < level_nodes(p, l + 1); ++mc) {
             cmap[l][mc] = -1;
-            for (int mf = 0; mf < L[l].nn; ++mf)
+            for (int mf = 0; mf < level_nodes(p, l); ++mf)
                 if (std::fabs((double)(L[l].s_ld[mf] - L[l + 1].s_ld[mc])) < 1e-14) cmap[l][mc] = mf;
             if (cmap[l][mc] < 0) { why = "a level's nodes must be a subset of the finer level's"; return false; }
         }
@@ -292,8 +293,9 @@ hipError_t Solver::upload_constants()
         HC(hipMemcpyAsync(L[lev].dS, L[lev].S, sizeof(double) * L[lev].nn * L[lev].nn, hipMemcpyHostToDevice, s));
     }
     for (int l = 0; l + 1 < nl; ++l) {
-        lagrange_interp(L[l].nn, L[l].s_ld, L[l + 1].nn, L[l + 1].s_ld, Lt);
-        HC(hipMemcpyAsync(dLt[l], Lt, sizeof(double) * L[l].nn * L[l + 1].nn, hipMemcpyHostToDevice, s));
+        const int nf = level_nodes(p, l), nc = level_nodes(p, l + 1);
+        lagrange_interp(nf, L[l].s_ld, nc, L[l + 1].s_ld, Lt);
+        HC(hipMemcpyAsync(dLt[l], Lt, sizeof(double) * nf * nc, hipMemcpyHostToDevice, s));
         // the copy reads the host table when it runs
         HC(hipStreamSynchronize(s));
     }

@@ -222,7 +222,7 @@ def tau_bar(orc, p, mc, cmap, du_f, du_c, lnorm_f=4.0):
 
 
 def compare_state(c, orc, P, two_levels=True, tol=TOL, lnorm_f=4.0):
-    nnf, nnc = orc.nn
+    nnf, nnc = orc.nn[0], orc.nn[1]   # level 1: the coarse level, or the middle one of three
     if two_levels:
         sf, _ = orc.matrices(0)
         sc, _ = orc.matrices(1)

@@ -210,9 +210,11 @@ const char *pfmg_last_error(void);
 pfmg_status pfmg_set_initial(pfmg_ctx *ctx, const double *u0, int32_t on_device);
 
 /* One SDC sweep (eq. sdc-be / SDCcompactLIII) on slices [p_begin, p_end) of
- * level 0 (fine) or level 1 (coarse, right-hand side corrected by the FAS
- * term tau[m+1] - tau[m]).  Slices are swept independently (their node-0
- * values are used as they are).  Each node solve follows the solve policy. */
+ * level 0 (fine) or a coarser level 1 or 2 (right-hand side corrected by
+ * that level's FAS term tau[m+1] - tau[m]; level 2 only in a three-level
+ * context).  Slices are swept independently (their node-0 values are used
+ * as they are).  Each node solve follows the solve policy.  PFMG_ERR_ARG
+ * for a level the context does not have. */
 pfmg_status pfmg_sdc_sweep(pfmg_ctx *ctx, int32_t level, int32_t p_begin, int32_t p_end);
 
 /* Solve (I - alpha L_h) u = b on the fine grid with V-cycles (Sec. 4.1.1).
@@ -227,8 +229,10 @@ pfmg_status pfmg_vcycle(pfmg_ctx *ctx, double alpha, const double *b, double *u,
 
 /* One IPFASST iteration (Sec. 2.4): new fine initial values from the
  * previous slices, fine sweeps on all slices, FAS restriction, coarse sweeps
- * in slice order, interpolation, collocation residual.  *block_res_out
- * (may be NULL) receives max over slices of the relative residual. */
+ * in slice order, interpolation, collocation residual (three levels: with
+ * middle-level sweeps after the restriction and after the coarse
+ * correction).  *block_res_out (may be NULL) receives max over slices of
+ * the residual (relative, or absolute with residual_abs). */
 pfmg_status pfmg_pfasst_iter(pfmg_ctx *ctx, double *block_res_out);
 
 /* Collocation residual (eq. resid) of every slice on level 0:
@@ -254,7 +258,8 @@ pfmg_status pfmg_get(pfmg_ctx *ctx, int32_t field, int32_t slice, int32_t node,
 pfmg_status pfmg_set(pfmg_ctx *ctx, int32_t field, int32_t slice, int32_t node,
                      const double *src, int32_t on_device);
 
-/* V-cycles run so far by node solves on level 0 / 1 (counted per slice). */
+/* V-cycles run so far by node solves on level 0, 1 or 2 (counted per
+ * slice; zero for a level the context does not have). */
 pfmg_status pfmg_vcycle_count(pfmg_ctx *ctx, int32_t level, int64_t *count_out);
 
 /* Kernel timing for measurement: while enabled, every launch of the named

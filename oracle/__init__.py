@@ -331,6 +331,13 @@ class Pfasst:
         a = np.ctypeslib.as_array(ptr, shape=(n ** self.dim,))
         a[:] = np.asarray(v, dtype=np.float64).reshape(-1)
 
+    def set_level_field(self, level, kind, p, m, v):
+        ptr = lib().or_pfasst_level_field(self._h, level, kind, p, m)
+        if not ptr:
+            raise ValueError("no such field")
+        a = np.ctypeslib.as_array(ptr, shape=(self.ns[level] ** self.dim,))
+        a[:] = np.asarray(v, dtype=np.float64).reshape(-1)
+
     def matrices(self, level):
         nn = self.nn[level]
         s = np.zeros(nn); Q = np.zeros((nn, nn))

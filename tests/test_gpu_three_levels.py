@@ -11,7 +11,7 @@ import pytest
 import inputs
 import oracle as O
 from tests import pins
-from tests.test_gpu_parity import TOL, compare_state, make, say
+from tests.test_gpu_parity import TOL, compare_state, f_tol, make, say
 from tests.test_gpu_f_options import lnorm_eff, resid_bar
 
 pytestmark = pytest.mark.gpu
@@ -103,3 +103,31 @@ def test_three_levels_converge_like_the_oracle_1d_weak_scaling(pf):
         e_or = np.max(np.abs(orc.field(O.UF, N - 1, 2) - pde))
         assert abs(e_gpu - e_or) <= 1e-9 * e_or + 1e-13, (k, e_gpu, e_or)
     assert e_gpu < 6e-7
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_sweep_on_a_coarser_level_matches_oracle(pf, level):
+    """pfmg_sdc_sweep on the middle and the coarsest level of a three-level
+    context (3D, n = 31: grids 15^3 and 7^3, Lobatto 5/3/2), from random U,
+    F and tau set through pfmg_set on both sides."""
+    n, P, nu, dt = 31, 3, 1.0, 2e-3
+    say(f"three levels: sweep on level {level}")
+    c = make(pf, n=n, n_slices=P, nu=nu, dt=dt, nodes_fine=5, nodes_middle=3, nodes_coarse=2, vcycles_per_solve=1)
+    orc = O.Pfasst(3, n, nu, dt, P, 5, 2, O.policy(cycles=1), nodes_middle=3)
+    ids = {1: (pf.U_COARSE, pf.F_COARSE, pf.TAU), 2: (pf.U_L2, pf.F_L2, pf.TAU_L2)}[level]
+    ng, nn = orc.ns[level], orc.nn[level]
+    rng = np.random.default_rng(40 + level)
+    for p in range(P):
+        for m in range(nn):
+            for fid, kind, scale in zip(ids, (O.K_U, O.K_F, O.K_TAU), (1.0, 1.0, 1e-3)):
+                v = rng.standard_normal((ng,) * 3) * scale
+                c.set(fid, p, m, v)
+                orc.set_level_field(level, kind, p, m, v)
+    c.sdc_sweep(level, 0, P)
+    for p in range(P):
+        orc.sweep(level, p)
+    for p in range(P):
+        for m in range(nn):
+            u_or, f_or = orc.level_field(level, O.K_U, p, m), orc.level_field(level, O.K_F, p, m)
+            assert pins.rel_err(c.get(ids[0], p, m), u_or) <= TOL, (p, m)
+            assert pins.rel_err(c.get(ids[1], p, m), f_or) <= f_tol(u_or, f_or, ng, 3, nu), (p, m)

@@ -99,6 +99,10 @@ __global__ __launch_bounds__(BLOCK) void smooth4_kernel(Tiling t, double alpha, 
 
 // Cubic Lagrange weights of fine 1-based index x on coarse 1-based
 // indices idx (0 and nc+1 are the boundary).  Returns the count (1 or 4).
+// A fine point between coarse points sits at their midpoint, so the
+// weights are constants: (-1, 9, 9, -1)/16 on J-1 .. J+2, and next to a
+// boundary the shifted stencils (5, 15, -5, 1)/16 and (1, -5, 15, 5)/16
+// (exact dyadic values of the Lagrange basis at the midpoint).
 __device__ inline int cubic_w(int x, int nc, int *idx, double *w)
 {
     if ((x & 1) == 0) {
@@ -107,16 +111,18 @@ __device__ inline int cubic_w(int x, int nc, int *idx, double *w)
         return 1;
     }
     const int J = (x - 1) / 2;
-    int lo = J - 1 < 0 ? 0 : J - 1;
-    if (lo + 3 > nc + 1) lo = nc + 1 - 3;
-    const double xf = J + 0.5;
-    for (int a = 0; a < 4; ++a) {
-        double v = 1.0;
-        for (int r = 0; r < 4; ++r)
-            if (r != a) v *= (xf - (lo + r)) / (double)((lo + a) - (lo + r));
-        idx[a] = lo + a;
-        w[a] = v;
+    int lo;
+    if (J == 0) {
+        lo = 0;
+        w[0] = 5.0 / 16; w[1] = 15.0 / 16; w[2] = -5.0 / 16; w[3] = 1.0 / 16;
+    } else if (J == nc) {
+        lo = nc - 2;
+        w[0] = 1.0 / 16; w[1] = -5.0 / 16; w[2] = 15.0 / 16; w[3] = 5.0 / 16;
+    } else {
+        lo = J - 1;
+        w[0] = -1.0 / 16; w[1] = 9.0 / 16; w[2] = 9.0 / 16; w[3] = -1.0 / 16;
     }
+    for (int a = 0; a < 4; ++a) idx[a] = lo + a;
     return 4;
 }
 

@@ -136,6 +136,8 @@ hipError_t resid4(const Tiling &t, double alpha, View<double> b, View<double> u,
 hipError_t smooth4(const Tiling &t, double alpha, double omega, int colour, View<double> b, View<double> src,
                    View<double> dst, hipStream_t s);
 hipError_t prolong4_add(const Tiling &t, View<double> ec, View<double> u, hipStream_t s);
+hipError_t prolong4_add2(const Tiling &t, View<double> ec, View<double> u, View<double> ec2, View<double> u2,
+                         hipStream_t s);
 hipError_t apply_L_rhs(const Tiling &t, double nu, View<double> u, View<double> F, double delta, View<double> Fn1,
                        View<double> In, View<double> t1, View<double> t0, View<double> b, hipStream_t s);
 // FAS injection (t on the coarse grids): Uc[mc] = Uold[mc] = Uf[cmap[mc]] at

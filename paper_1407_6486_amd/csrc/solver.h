@@ -26,6 +26,7 @@ struct PLevel {
     double *U = nullptr, *F = nullptr, *I = nullptr, *B = nullptr;
     double *Tau = nullptr, *Uold = nullptr, *DC = nullptr;   // coarse level only
     double *Fold = nullptr;           // coarse F at restriction (f_interp)
+    double *DCF = nullptr;            // interpolated coarse F change (f_interp)
     double *Ft = nullptr;             // fine F(U) for the residual (f_solve or f_interp)
     std::vector<MGLevel> mg;          // mg[0].n == n
     long double s_ld[16];

@@ -144,6 +144,7 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
             L.Tau = f64(n, (long)P * nn);
             L.Uold = f64(n, (long)P * nn);
             L.DC = f64(n, (long)P * level_nodes(p, lev - 1));
+            L.DCF = p.f_interp ? f64(n, (long)P * level_nodes(p, lev - 1)) : nullptr;
             L.Fold = p.f_interp ? f64(n, (long)P * nn) : nullptr;
         }
         // F(U) of every fine node for the collocation residual when the
@@ -809,6 +810,18 @@ hipError_t Solver::interpolate(int p0, int p1, int l)
     HC(k::interp_coarse(tl(Cs.n, count), Fn.nn, Cs.nn, dLt, View<double>{Cs.slot(Cs.U, p0, 0), cst},
                         View<double>{Cs.slot(Cs.Uold, p0, 0), cst}, View<double>{dc, dst}, s));
     const long pts = interior_points(Fn.n, dim) * count * Fn.nn;
+    if (p.f_interp && p.interp_order == 4) {
+        // the coarse F change beside U's, and both cubic interpolations in
+        // one launch (shared indices and weights)
+        double *dcf = Cs.DCF + (long)p0 * dst;
+        HC(k::interp_coarse(tl(Cs.n, count), Fn.nn, Cs.nn, dLt, View<double>{Cs.slot(Cs.F, p0, 0), cst},
+                            View<double>{Cs.slot(Cs.Fold, p0, 0), cst}, View<double>{dcf, dst}, s));
+        tstart("prolong", Fn.n, 32 + 16.0 / (dim == 3 ? 8 : 2), pts);
+        HC(k::prolong4_add2(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs},
+                            View<double>{dcf, Cs.fs}, View<double>{Fn.slot(Fn.F, p0, 0), Fn.fs}, s));
+        tstop();
+        return hipSuccess;
+    }
     tstart("prolong", Fn.n, 16 + 8.0 / (dim == 3 ? 8 : 2), pts);
     if (p.interp_order == 4)
         HC(k::prolong4_add(tl(Fn.n, count * Fn.nn), View<double>{dc, Cs.fs}, View<double>{Fn.slot(Fn.U, p0, 0), Fn.fs}, s));

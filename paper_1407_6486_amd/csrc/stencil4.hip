@@ -14,7 +14,8 @@
 //               of the red-black JOR: points of the colour are updated from
 //               the input field (the stencil reaches same-colour points two
 //               steps away), the others copied; out of place.
-//  prolong4_add u += P4 e_c: tensor-product cubic Lagrange interpolation.
+//  prolong4_add u += P4 e_c: tensor-product cubic Lagrange interpolation
+//               (prolong4_add2: two corrections into two fields at once).
 //               A fine point on a coarse point takes its value; between
 //               coarse points J and J+1 the cubic through J-1 .. J+2,
 //               shifted inwards next to the boundary (whose zero value is
@@ -150,6 +151,36 @@ __global__ __launch_bounds__(BLOCK) void prolong4_add_kernel(Tiling t, View<doub
     fp(u, q)[o] += acc;
 }
 
+// prolong4_add of two corrections at once (U's and F's in PFASST
+// interpolation): the same indices and weights, each sum accumulated as in
+// prolong4_add_kernel.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void prolong4_add2_kernel(Tiling t, View<double> ec, View<double> u,
+                                                              View<double> ec2, View<double> u2)
+{
+    Pt q; int i, j, k; long o;
+    if (!tile_point<DIM>(t, q, i, j, k, o)) return;
+    const int nc = coarser(q.n);
+    const long syc = row_stride(nc), szc = plane_stride(nc);
+    const double *e = fp(ec, q), *e2 = fp(ec2, q);
+    int ix[4], iy[4] = {0, 0, 0, 0}, iz[4] = {0, 0, 0, 0};
+    double wx[4], wy[4] = {1.0, 0, 0, 0}, wz[4] = {1.0, 0, 0, 0};
+    const int cx = cubic_w(i, nc, ix, wx);
+    const int cy = DIM == 3 ? cubic_w(j, nc, iy, wy) : 1;
+    const int cz = DIM == 3 ? cubic_w(k, nc, iz, wz) : 1;
+    double acc = 0.0, acc2 = 0.0;
+    for (int c = 0; c < cz; ++c)
+        for (int b = 0; b < cy; ++b)
+            for (int a = 0; a < cx; ++a) {
+                const long oc = DIM == 3 ? (long)ix[a] + (long)iy[b] * syc + (long)iz[c] * szc : (long)ix[a];
+                const double w = wz[c] * wy[b] * wx[a];
+                acc += w * e[oc];
+                acc2 += w * e2[oc];
+            }
+    fp(u, q)[o] += acc;
+    fp(u2, q)[o] += acc2;
+}
+
 inline dim3 grid4(const Tiling &t) { return dim3((unsigned)grid_blocks(t)); }
 
 #define PFMG_DISPATCH4(t, KER, ...)                                                         \
@@ -186,6 +217,14 @@ hipError_t prolong4_add(const Tiling &t, View<double> ec, View<double> u, hipStr
     for (int sg = 0; sg < t.nseg; ++sg)
         if (t.seg_count(sg) > 0 && coarser(t.seg_n(sg)) < 3) return hipErrorInvalidValue;
     PFMG_DISPATCH4(t, prolong4_add_kernel, t, ec, u);
+}
+
+hipError_t prolong4_add2(const Tiling &t, View<double> ec, View<double> u, View<double> ec2, View<double> u2,
+                         hipStream_t s)
+{
+    for (int sg = 0; sg < t.nseg; ++sg)
+        if (t.seg_count(sg) > 0 && coarser(t.seg_n(sg)) < 3) return hipErrorInvalidValue;
+    PFMG_DISPATCH4(t, prolong4_add2_kernel, t, ec, u, ec2, u2);
 }
 
 }  // namespace k

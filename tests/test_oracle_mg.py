@@ -233,3 +233,17 @@ def test_cubic_interpolation_is_fourth_order():
         assert 14.0 < a / b < 18.0
     for a, b in zip(errs2, errs2[1:]):
         assert 3.6 < a / b < 4.4
+
+
+@pytest.mark.parametrize("dim,n,sm,om", [(1, 7, O.RBGS, 1.0), (1, 15, O.JACOBI, 2.0 / 3.0), (3, 7, O.RBGS, 1.0),
+                                         (3, 7, O.JACOBI, 2.0 / 3.0)])
+def test_vcycle_equals_dense_two_grid_recursion(dim, n, sm, om):
+    """The second-order V(2,2) cycle equals its recursion written with dense
+    matrices (red-black Gauss-Seidel is the red-black JOR pass with weight 1
+    for the 7-point stencil, whose same-colour points do not couple)."""
+    a = 3.0 / (n + 1) ** 2
+    b = inputs.random_field((n,) * dim, 47)
+    u = inputs.random_field((n,) * dim, 48)
+    want = pins.dense_vcycle(dim, n, a, b.ravel(), u.ravel(), sm == O.RBGS, om)
+    got = O.vcycle(dim, a, b, u, smoother=sm, omega=om).ravel()
+    assert pins.rel_err(got, want) <= 1e-13

@@ -118,3 +118,76 @@ def test_fourth_order_rejects_mixed_precision():
         O.Pfasst(3, 15, 1.0, 1e-3, 2, 5, 3, O.policy(cycles=1, mixed=1), stencil_order=4)
     with pytest.raises(ValueError):
         O.Pfasst(3, 15, 1.0, 1e-3, 2, 5, 3, O.policy(cycles=1), stencil_order=3)
+
+
+# ---- dense pins of the fourth-order smoother and V-cycle (Sec. 4.3's
+# red-black JOR on the fine level): the operator, the colour order, the
+# in-pass data dependence and the two-grid recursion are each rebuilt from
+# dense matrices assembled independently of the stencil code.
+
+@pytest.mark.parametrize("n", [5, 9, 15])
+def test_dense_l4_has_the_sine_eigenpairs(n):
+    """The dense 1D matrix (boundary rows by odd reflection) has the sine
+    modes as eigenvectors with the closed-form eigenvalue."""
+    L1 = pins.lap4_1d(n)
+    for k in range(1, n + 1):
+        phi = inputs.sine_mode(n, (k,), 1)
+        assert pins.rel_err(L1 @ phi, lam4(n, (k,)) * phi) <= 1e-13
+
+
+@pytest.mark.parametrize("dim,n", [(1, 5), (1, 9), (3, 3), (3, 5)])
+def test_l4_and_residual_match_dense_matrix(dim, n):
+    u = inputs.random_field((n,) * dim, 41)
+    b = inputs.random_field((n,) * dim, 42)
+    L = pins.lap4_dense(dim, n)
+    assert pins.rel_err(O.lap4(dim, u).ravel(), L @ u.ravel()) <= 1e-14
+    a = 0.03
+    A = np.eye(n ** dim) - a * L
+    assert pins.rel_err(O.resid4(dim, a, b, u).ravel(), b.ravel() - A @ u.ravel()) <= 1e-14
+
+
+@pytest.mark.parametrize("dim,n,k", [(1, 15, (5,)), (1, 31, (29,)), (3, 7, (1, 6, 3)), (3, 15, (2, 9, 4))])
+def test_jacobi4_damps_each_mode_by_closed_form(dim, n, k):
+    """omega-Jacobi on L4 with b = 0 scales the sine mode k by
+    1 - omega (1 - alpha lambda4_k)/(1 + 2.5 dim alpha/h^2)."""
+    phi = inputs.sine_mode(n, k, dim)
+    alpha, omega = 2e-3, 2.0 / 3.0
+    g = 1 - omega * (1 - alpha * lam4(n, k)) / (1 + 2.5 * dim * alpha * (n + 1) ** 2)
+    out = O.smooth4(dim, alpha, O.JACOBI, omega, np.zeros_like(phi), phi)
+    assert pins.rel_err(out, g * phi) <= 1e-13
+
+
+@pytest.mark.parametrize("dim,n,omega", [(1, 5, 1.0), (1, 7, 0.8), (3, 3, 1.0), (3, 5, 1.0), (3, 5, 0.7)])
+def test_red_black_jor4_equals_dense_passes(dim, n, omega):
+    """One red-black JOR pass on (I - alpha L4): the points with an even
+    1-based index sum relax together from the values before the pass, then
+    the odd points from the red-updated field."""
+    a = 0.05 / (n + 1) ** 2 * 40
+    A = np.eye(n ** dim) - a * pins.lap4_dense(dim, n)
+    diag = 1.0 + 2.5 * dim * a * (n + 1) ** 2
+    b = inputs.random_field((n,) * dim, 43).ravel()
+    u = inputs.random_field((n,) * dim, 44).ravel()
+    want = pins.dense_smooth(A, diag, dim, n, True, omega, b, u)
+    got = O.smooth4(dim, a, O.RBGS, omega, b.reshape((n,) * dim), u.reshape((n,) * dim)).ravel()
+    assert pins.rel_err(got, want) <= 1e-14
+    # the pin separates the readings it rules out: black first, or black
+    # from the pre-red values
+    red = pins.red_mask(dim, n)
+    swapped = pins.jor_pass(A, diag, red, omega, b, pins.jor_pass(A, diag, ~red, omega, b, u))
+    simultaneous = u + omega * (b - A @ u) / diag
+    assert pins.rel_err(got, swapped) > 1e-3 and pins.rel_err(got, simultaneous) > 1e-3
+
+
+@pytest.mark.parametrize("dim,n,sm,om", [(1, 5, O.RBGS, 1.0), (1, 7, O.RBGS, 1.0), (1, 15, O.JACOBI, 2.0 / 3.0),
+                                         (3, 3, O.RBGS, 1.0), (3, 7, O.RBGS, 1.0), (3, 7, O.JACOBI, 2.0 / 3.0)])
+def test_vcycle4_equals_dense_two_grid_recursion(dim, n, sm, om):
+    """V(2,2) with L4 on the finest level and the second-order rediscretised
+    operator below it equals the same recursion written with dense matrices
+    (dense L4 and L, interpolation matrix P, full weighting P^T/2^dim, exact
+    solve on grids of at most two points)."""
+    a = 3.0 / (n + 1) ** 2
+    b = inputs.random_field((n,) * dim, 45)
+    u = inputs.random_field((n,) * dim, 46)
+    want = pins.dense_vcycle(dim, n, a, b.ravel(), u.ravel(), sm == O.RBGS, om, fourth=True)
+    got = O.vcycle4(dim, a, b, u, smoother=sm, omega=om).ravel()
+    assert pins.rel_err(got, want) <= 1e-13

@@ -267,7 +267,10 @@ class Pfasst:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().or_pfasst_destroy(self._h)
+            try:
+                lib().or_pfasst_destroy(self._h)
+            except (TypeError, AttributeError):    # interpreter shutdown: the module is gone
+                pass
             self._h = None
 
     def spread(self, u0):

@@ -227,6 +227,36 @@ pfmg_status pfmg_sdc_sweep(pfmg_ctx *ctx, int32_t level, int32_t p_begin, int32_
 pfmg_status pfmg_vcycle(pfmg_ctx *ctx, double alpha, const double *b, double *u,
                         int32_t n_cycles, double *relres_out, int32_t *cycles_out);
 
+/* Static device scratch of pfmg_vcycle_noalloc, per GPU (64 MiB): enough
+ * for a 3D FP64 solve up to n = 127 (the mixed form up to n = 63). */
+#define PFMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * solve of pfmg_vcycle without a context or workspace.  It calls no
+ * hipMalloc, hipFree, hipHostMalloc or other device-allocating routine;
+ * its multigrid hierarchy and b / u staging live in a static device array
+ * of PFMG_NOALLOC_SCRATCH_BYTES per GPU, held from the library's load until
+ * the process ends.
+ *   p: the grid and solve policy (dim, n, smoother, omega, nu_pre,
+ *      nu_post, precision, stencil_order, mg_tol, mg_stall, mg_max_cycles;
+ *      guess must be PFMG_GUESS_PREV; the time-stepping fields only need to
+ *      pass pfmg_create's checks for a one-slice, one-level context).
+ *   b, u: device pointers to n^dim float64 (C order, x fastest); u is the
+ *      initial guess and is overwritten.  Borrowed for the call.
+ *   n_cycles, relres_out, cycles_out: as pfmg_vcycle.
+ *   hip_stream: the stream every launch goes to (NULL: the null stream).
+ * With n_cycles > 0 and relres_out NULL the call only enqueues kernels on
+ * the stream (stream-ordered, no synchronisation); otherwise it
+ * synchronises the stream before returning.  PFMG_ERR_WORKSPACE (and
+ * nothing launched) when the grid needs more scratch than the array holds;
+ * PFMG_ERR_ARG for invalid parameters.  Every call on one GPU shares that
+ * GPU's array and leaves its contents there: calls that overlap on one GPU
+ * (other streams or threads) race and must be serialised by the caller. */
+pfmg_status pfmg_vcycle_noalloc(const pfmg_params *p, double alpha, const double *b, double *u,
+                                int32_t n_cycles, void *hip_stream, double *relres_out,
+                                int32_t *cycles_out);
+
 /* One IPFASST iteration (Sec. 2.4): new fine initial values from the
  * previous slices, fine sweeps on all slices, FAS restriction, coarse sweeps
  * in slice order, interpolation, collocation residual (three levels: with

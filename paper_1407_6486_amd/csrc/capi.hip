@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -201,6 +202,113 @@ pfmg_status pfmg_vcycle(pfmg_ctx *ctx, double alpha, const double *b, double *u,
     if (relres_out) *relres_out = rr;
     if (cycles_out) *cycles_out = (int32_t)(sv.vcount[0] - before);
     sv.vcount[0] = before;
+    if (st == PFMG_ERR_NAN) return fail(PFMG_ERR_NAN, "a norm evaluated to NaN or Inf");
+    return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- solve without allocation
+// Device scratch of pfmg_vcycle_noalloc: one static array per GPU (each
+// device that loads the library holds its own copy until the process
+// ends).  Host code never passes `scratch` itself to a kernel or copy: the
+// name is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+namespace pfmg {
+namespace noalloc {
+
+__device__ __align__(256) unsigned char scratch[PFMG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAXDEV = 64;
+std::mutex g_mu;
+void *g_ptr[MAXDEV] = {};
+// Layout of the last call per device: the scratch is cleared (halo words
+// carry the Dirichlet zeros) whenever it changes.
+struct Key {
+    int dim = 0, n = 0, precision = -1, smoother = -1, stencil_order = 0;
+    bool operator==(const Key &o) const
+    {
+        return dim == o.dim && n == o.n && precision == o.precision && smoother == o.smoother &&
+               stencil_order == o.stencil_order;
+    }
+};
+Key g_key[MAXDEV];
+
+// Device address of this device's scratch (nullptr and the error on failure).
+hipError_t scratch_ptr(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_ptr[dev] = ptr;
+    }
+    *out = g_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace noalloc
+}  // namespace pfmg
+
+extern "C" {
+
+pfmg_status pfmg_vcycle_noalloc(const pfmg_params *p, double alpha, const double *b, double *u, int32_t n_cycles,
+                                void *hip_stream, double *relres_out, int32_t *cycles_out)
+{
+    namespace na = pfmg::noalloc;
+    if (!p || !b || !u) return fail(PFMG_ERR_ARG, "null argument");
+    if (!(alpha >= 0) || !std::isfinite(alpha)) return fail(PFMG_ERR_ARG, "alpha must be finite and >= 0");
+    if (n_cycles < 0 || n_cycles > 1000) return fail(PFMG_ERR_ARG, "n_cycles must be in 0..1000");
+    if (p->guess != PFMG_GUESS_PREV) return fail(PFMG_ERR_ARG, "pfmg_vcycle_noalloc takes guess = PFMG_GUESS_PREV");
+    // the fine grid's solve only: one slice, one level
+    pfmg_params q = *p;
+    q.n_slices = 1;
+    q.nodes_coarse = 0;
+    q.nodes_middle = 0;
+    std::string why;
+    if (!pfmg::Solver::validate(q, why)) return fail(PFMG_ERR_ARG, why);
+    const size_t need = pfmg::Solver::carve_vcycle(q, nullptr, nullptr);
+    if (need > PFMG_NOALLOC_SCRATCH_BYTES)
+        return fail(PFMG_ERR_WORKSPACE, "pfmg_vcycle_noalloc: this grid needs " + std::to_string(need) +
+                                            " bytes of scratch, the static scratch holds " +
+                                            std::to_string((size_t)PFMG_NOALLOC_SCRATCH_BYTES));
+    int dev = 0;
+    HIPCALL(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= na::MAXDEV) return fail(PFMG_ERR_ARG, "device index beyond the scratch table");
+    void *base = nullptr;
+    HIPCALL(na::scratch_ptr(dev, &base), "hipGetSymbolAddress(scratch)");
+    pfmg::Solver sv;
+    sv.p = q;
+    sv.s = (hipStream_t)hip_stream;
+    if (!sv.init_host(why)) return fail(PFMG_ERR_ARG, why);
+    sv.tune = false;
+    pfmg::Solver::carve_vcycle(q, (char *)base, &sv);
+    // host mirrors of the reduction scratch: pageable, read after a synchronisation
+    unsigned long long hbits[4 * pfmg::k::RSLOTS] = {};
+    int hmask[1] = {0};
+    sv.hbits = hbits;
+    sv.hmask = hmask;
+    const na::Key key{q.dim, q.n, q.precision, q.smoother, q.stencil_order};
+    {
+        std::lock_guard<std::mutex> lk(na::g_mu);
+        if (!(na::g_key[dev] == key)) {
+            HIPCALL(pfmg::k::fill_u64((unsigned long long *)base, 0, (int)(need / 8), sv.s), "clear scratch");
+            na::g_key[dev] = key;
+        }
+    }
+    const int n = q.n;
+    pfmg::View<double> vb{sv.vb, 0}, vu{sv.vu, 0};
+    HIPCALL(pfmg::k::unpack(sv.tl(n, 1), b, vb, sv.s), "unpack b");
+    HIPCALL(pfmg::k::unpack(sv.tl(n, 1), u, vu, sv.s), "unpack u");
+    double rr = 0;
+    HIPCALL(sv.solve(0, vu, vb, 1, alpha, n_cycles, relres_out ? &rr : nullptr), "vcycle");
+    const pfmg_status st = sv.last_solve_status;
+    HIPCALL(pfmg::k::pack(sv.tl(n, 1), vu, u, sv.s), "pack u");
+    if (n_cycles == 0 || relres_out) HIPCALL(hipStreamSynchronize(sv.s), "vcycle");
+    if (relres_out) *relres_out = rr;
+    if (cycles_out) *cycles_out = (int32_t)sv.vcount[0];
     if (st == PFMG_ERR_NAN) return fail(PFMG_ERR_NAN, "a norm evaluated to NaN or Inf");
     return st;
 }

@@ -89,6 +89,10 @@ struct Solver {
         return lev == 0 ? p.nodes_fine : (levels(p) == 3 && lev == 1) ? p.nodes_middle : p.nodes_coarse;
     }
     static size_t carve(const pfmg_params &p, char *base, Solver *sv);   // returns bytes
+    // Only what a fine-grid solve needs (one field): the multigrid
+    // hierarchy of level 0, the b / u staging slots and the reduction
+    // scratch.  Returns bytes (a multiple of 256).
+    static size_t carve_vcycle(const pfmg_params &p, char *base, Solver *sv);
     bool init_host(std::string &why);
     hipError_t upload_constants();
 
@@ -123,6 +127,7 @@ struct Solver {
     hipError_t iterate(double *block);
 
     int noremap = 0;
+    bool tune = true;                 // false: fixed launch shapes, no tuner timing runs
     bool use_bottom = true;           // small grids: whole V-cycle in one LDS kernel
     bool graphs = true;               // replay captured graphs of block start / iteration
     long fused_min_points = 2000000;  // one-pass red-black sweep from this batch size up

@@ -205,6 +205,62 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
     return ((off + 255) & ~(size_t)255) + 256;
 }
 
+size_t Solver::carve_vcycle(const pfmg_params &p, char *base, Solver *sv)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        off = (off + 255) & ~(size_t)255;
+        char *r = base ? base + off : nullptr;
+        off += bytes;
+        return r;
+    };
+    const int dim = p.dim;
+    const bool mixed = p.precision == PFMG_MIXED;
+    const bool jac = p.smoother == PFMG_SMOOTH_JACOBI;
+    auto f64 = [&](int n) -> double * {
+        char *c = take((size_t)field_stride(n, dim, 8) * 8);
+        return c ? (double *)c + field_lead(8) : nullptr;
+    };
+    auto f32 = [&](int n) -> float * {
+        char *c = take((size_t)field_stride(n, dim, 4) * 4);
+        return c ? (float *)c + field_lead(4) : nullptr;
+    };
+    PLevel tmp;
+    PLevel &L0 = sv ? sv->L[0] : tmp;
+    L0.n = p.n;
+    L0.fs = field_stride(p.n, dim, 8);
+    L0.mg.clear();
+    for (int l = 0, n = p.n;; ++l, n = coarser(n)) {
+        MGLevel G;
+        G.n = n;
+        G.fs64 = field_stride(n, dim, 8);
+        G.fs32 = field_stride(n, dim, 4);
+        if (l > 0) {
+            G.e = {f64(n), G.fs64};
+            G.b = {f64(n), G.fs64};
+        }
+        const bool pingpong = jac || (dim == 3 && n >= 31) || (l == 0 && p.stencil_order == 4);
+        if (pingpong) G.t = {f64(n), G.fs64};
+        if (mixed) {
+            G.e32 = {f32(n), G.fs32};
+            G.b32 = {f32(n), G.fs32};
+            if (pingpong) G.t32 = {f32(n), G.fs32};
+        }
+        if (sv) L0.mg.push_back(G);
+        if (n <= 2) break;
+    }
+    double *vb = f64(p.n), *vu = f64(p.n);
+    auto *bits = (unsigned long long *)take((size_t)4 * k::RSLOTS * 8);
+    int *mask = (int *)take(sizeof(int));
+    if (sv) {
+        sv->vb = vb;
+        sv->vu = vu;
+        sv->bits = bits;
+        sv->mask = mask;
+    }
+    return (off + 255) & ~(size_t)255;
+}
+
 bool Solver::init_host(std::string &why)
 {
     const char *e = getenv("PFMG_NO_XCD_REMAP");
@@ -401,8 +457,15 @@ hipError_t Solver::smooth(int n, int count, const int *m, double alpha, View<T> 
     // the one-pass shapes) on first use; without timing, big batches take
     // the one-pass kernel.
     RbPlan plan;
-    if (p.smoother == PFMG_SMOOTH_RBGS && dim == 3 && n >= 31 && n <= 255 && tmp.p)
-        plan = rb_plan<T>(t, alpha, om, b, u, tmp, s, (long)count * interior_points(n, dim) >= fused_min_points);
+    if (p.smoother == PFMG_SMOOTH_RBGS && dim == 3 && n >= 31 && n <= 255 && tmp.p) {
+        const bool big = (long)count * interior_points(n, dim) >= fused_min_points;
+        if (tune) {
+            plan = rb_plan<T>(t, alpha, om, b, u, tmp, s, big);
+        } else {
+            plan.fused = big;
+            if (big) plan.shape = k::rbgs_fused_shape(t, sizeof(T));
+        }
+    }
     if (plan.fused) {
         // whole sweeps in one pass each, ping-pong between u and tmp
         View<T> src = u, dst = tmp;

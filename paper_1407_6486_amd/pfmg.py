@@ -66,6 +66,8 @@ _sigs = {
     "pfmg_set_initial": ([_vp, _vp, C.c_int32], C.c_int32),
     "pfmg_sdc_sweep": ([_vp, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
     "pfmg_vcycle": ([_vp, C.c_double, _vp, _vp, C.c_int32, _dp, C.POINTER(C.c_int32)], C.c_int32),
+    "pfmg_vcycle_noalloc": ([C.POINTER(Params), C.c_double, _vp, _vp, C.c_int32, _vp, _dp, C.POINTER(C.c_int32)],
+                            C.c_int32),
     "pfmg_pfasst_iter": ([_vp, _dp], C.c_int32),
     "pfmg_residual": ([_vp, C.c_int32, _dp], C.c_int32),
     "pfmg_run_block": ([_vp, _vp, C.c_int32, C.POINTER(C.c_int32), _dp], C.c_int32),
@@ -161,6 +163,17 @@ def pfmg_vcycle(h, alpha: float, b_ptr: int, u_ptr: int, n_cycles: int):
     nc = C.c_int32(0)
     st = _check(_lib.pfmg_vcycle(h, alpha, _vp(b_ptr), _vp(u_ptr), n_cycles, C.byref(rr), C.byref(nc)))
     return st, rr.value, nc.value
+
+
+def pfmg_vcycle_noalloc(p: Params, alpha: float, b_ptr: int, u_ptr: int, n_cycles: int, stream_ptr: int,
+                        want_relres: bool = True):
+    """The context-free solve in the library's static scratch; returns
+    (status, relres or None, cycles)."""
+    rr = C.c_double(0.0)
+    nc = C.c_int32(0)
+    st = _check(_lib.pfmg_vcycle_noalloc(C.byref(p), alpha, _vp(b_ptr), _vp(u_ptr), n_cycles, _vp(stream_ptr),
+                                         C.byref(rr) if want_relres else None, C.byref(nc)))
+    return st, (rr.value if want_relres else None), nc.value
 
 
 def pfmg_pfasst_iter(h):

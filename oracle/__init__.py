@@ -41,7 +41,7 @@ class Params(C.Structure):
                 ("n_slices", C.c_int), ("nodes_fine", C.c_int), ("nodes_coarse", C.c_int),
                 ("mg", MGPolicy), ("interp_order", C.c_int), ("node_family", C.c_int),
                 ("stencil_order", C.c_int), ("f_solve", C.c_int), ("f_interp", C.c_int),
-                ("residual_abs", C.c_int), ("nodes_middle", C.c_int)]
+                ("residual_abs", C.c_int), ("nodes_middle", C.c_int), ("fine_send", C.c_int)]
 
 
 def lib():
@@ -250,10 +250,10 @@ class Pfasst:
     def __init__(self, dim, n, nu, dt, n_slices, nodes_fine=5, nodes_coarse=3,
                  mg: MGPolicy | None = None, interp_order: int = 2, node_family: int = LOBATTO,
                  stencil_order: int = 2, f_solve: int = 0, f_interp: int = 0, residual_abs: int = 0,
-                 nodes_middle: int = 0):
+                 nodes_middle: int = 0, fine_send: int = 0):
         self.prm = Params(dim, n, nu, dt, n_slices, nodes_fine, nodes_coarse,
                           mg if mg is not None else policy(), interp_order, node_family, stencil_order,
-                          f_solve, f_interp, residual_abs, nodes_middle)
+                          f_solve, f_interp, residual_abs, nodes_middle, fine_send)
         self.dim, self.n, self.P = dim, n, n_slices
         self.nn = [nodes_fine, nodes_coarse] if nodes_middle == 0 else [nodes_fine, nodes_middle, nodes_coarse]
         self.nc = (n + 1) // 2 - 1

@@ -151,6 +151,10 @@ typedef struct or_params {
     int residual_abs;        /* collocation residual: 0 relative to |U0_p|_inf, 1 absolute */
     int nodes_middle;        /* > 0: three levels, this many nodes on the middle one
                               * (needs nodes_coarse > 0) */
+    int fine_send;           /* new fine initial value of slice p at iteration k+1: 0 slice
+                              * p-1's end value after iteration k (after the coarse
+                              * correction); 1 its end value right after its fine sweep of
+                              * iteration k (Sec. 2.4, sent after the sweep) */
 } or_params;
 
 typedef struct or_pfasst or_pfasst;

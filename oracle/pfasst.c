@@ -18,6 +18,10 @@
  *    nodes are a subset of the fine nodes); interpolation is d-linear in
  *    space and Lagrange in time over the coarse nodes;
  *  - F at node 0 is recomputed whenever node 0 changes;
+ *  - fine_send = 1: the fine end value a slice sends is the one right after
+ *    its fine sweep (before the coarse correction reaches it), taken up by
+ *    the next slice at its next iteration; before the first iteration it is
+ *    the end value the predictor leaves;
  *  - the V-cycle initial guess is the previous iterate at the same node;
  *  - three levels (nodes_middle > 0; Sec. 4.2's weak-scaling runs): the
  *    FAS term of a level below the middle one carries the finer level's
@@ -54,6 +58,7 @@ struct or_pfasst {
     double *tau[3], *Uold[3];/* levels >= 1: [P][nn][len] */
     double *Fold[3];         /* levels >= 1: F at restriction (f_interp) */
     double *ub[3];           /* the block's initial value on each level */
+    double *Esnap;           /* fine_send = 1: [P][len0] end values after the fine sweep */
     double *ublock;          /* = ub[0] */
     long long vcyc[3];
 };
@@ -116,6 +121,7 @@ or_pfasst *or_pfasst_create(const or_params *prm)
     if (prm->residual_abs != 0 && prm->residual_abs != 1) return NULL;
     if (prm->nodes_middle != 0 && (prm->nodes_coarse == 0 || prm->nodes_middle < 2 || prm->nodes_middle > 16))
         return NULL;
+    if (prm->fine_send != 0 && prm->fine_send != 1) return NULL;
     or_pfasst *c = (or_pfasst *)calloc(1, sizeof(or_pfasst));
     c->p = *prm;
     c->nl = prm->nodes_coarse == 0 ? 1 : prm->nodes_middle > 0 ? 3 : 2;
@@ -141,6 +147,7 @@ or_pfasst *or_pfasst_create(const or_params *prm)
     }
     for (int l = 0; l < c->nl; ++l) c->ub[l] = (double *)calloc(c->len[l], sizeof(double));
     c->ublock = c->ub[0];
+    if (prm->fine_send) c->Esnap = (double *)calloc((size_t)prm->n_slices * c->len[0], sizeof(double));
     for (int l = 1; l < c->nl; ++l) {
         size_t tot = (size_t)prm->n_slices * c->nn[l] * c->len[l];
         c->tau[l] = (double *)calloc(tot, sizeof(double));
@@ -168,6 +175,7 @@ void or_pfasst_destroy(or_pfasst *c)
         free(c->Fold[l]);
         free(c->ub[l]);
     }
+    free(c->Esnap);
     free(c);
 }
 
@@ -336,12 +344,24 @@ void or_pfasst_spread(or_pfasst *c, const double *u_block)
     for (int l = 1; l < c->nl; ++l) inject(c->p.dim, c->n[l - 1], c->ub[l - 1], c->ub[l]);
 }
 
+/* fine_send = 1: keep every slice's fine end value as the one it sends. */
+static void snapshot_ends(or_pfasst *c)
+{
+    if (!c->p.fine_send) return;
+    const int Mf = c->nn[0] - 1;
+    for (int p = 0; p < c->p.n_slices; ++p)
+        memcpy(c->Esnap + (size_t)p * c->len[0], fld(c, c->U[0], 0, p, Mf), c->len[0] * sizeof(double));
+}
+
 /* Predictor (Sec. 2.4): rounds j = 0..P-1; in round j every slice p >= j
  * (for j >= 1) takes the coarse end value slice p-1 had after round j-1
  * and does one coarse sweep, so slice p sweeps p+1 times. */
 void or_pfasst_predictor(or_pfasst *c)
 {
-    if (c->nl < 2) return;
+    if (c->nl < 2) {
+        snapshot_ends(c);
+        return;
+    }
     const int L = c->nl - 1;
     const int P = c->p.n_slices, Mc = c->nn[L] - 1;
     const size_t lc = c->len[L];
@@ -362,6 +382,7 @@ void or_pfasst_predictor(or_pfasst *c)
     free(E);
     for (int l = L - 1; l >= 0; --l)
         for (int p = 0; p < P; ++p) or_interpolate_level(c, l, p);
+    snapshot_ends(c);
 }
 
 /* Collocation residual (eq. resid) per slice:
@@ -411,8 +432,12 @@ double or_pfasst_iter(or_pfasst *c)
 {
     const int P = c->p.n_slices, Mf = c->nn[0] - 1;
     const size_t lf = c->len[0];
+    /* the value each slice sends: its end value now (after the previous
+     * iteration), or the one kept right after its last fine sweep */
     double *E = (double *)malloc((size_t)P * lf * sizeof(double));
-    for (int p = 0; p < P; ++p) memcpy(E + p * lf, fld(c, c->U[0], 0, p, Mf), lf * sizeof(double));
+    for (int p = 0; p < P; ++p)
+        memcpy(E + p * lf, c->p.fine_send ? c->Esnap + (size_t)p * lf : fld(c, c->U[0], 0, p, Mf),
+               lf * sizeof(double));
     for (int p = 1; p < P; ++p) {
         double *u0 = fld(c, c->U[0], 0, p, 0);
         memcpy(u0, E + (size_t)(p - 1) * lf, lf * sizeof(double));
@@ -420,6 +445,7 @@ double or_pfasst_iter(or_pfasst *c)
     }
     free(E);
     for (int p = 0; p < P; ++p) or_sdc_sweep(c, 0, p);
+    snapshot_ends(c);
     if (c->nl > 1) {
         const int L = c->nl - 1, Mc = c->nn[L] - 1;
         const size_t lc = c->len[L];

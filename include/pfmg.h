@@ -55,7 +55,7 @@ enum { PFMG_NODES_LOBATTO = 0, PFMG_NODES_UNIFORM = 1 };
 enum { PFMG_SMOOTH_JACOBI = 0, PFMG_SMOOTH_RBGS = 1 };
 enum { PFMG_FP64 = 0, PFMG_MIXED = 1 };
 enum { PFMG_GUESS_PREV = 0, PFMG_GUESS_LEARNED = 1 };
-enum { PFMG_SEND_AFTER_ITER = 0 };
+enum { PFMG_SEND_AFTER_ITER = 0, PFMG_SEND_AFTER_SWEEP = 1 };
 /* Fields readable / writable with pfmg_get / pfmg_set. */
 enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
        PFMG_TAU = 4, PFMG_U_COARSE_OLD = 5,
@@ -101,7 +101,14 @@ enum { PFMG_U_FINE = 0, PFMG_F_FINE = 1, PFMG_U_COARSE = 2, PFMG_F_COARSE = 3,
  *                    PFMG_GUESS_LEARNED (the judged network guess below; 3D
  *                    full solves only).
  *   fine_send        PFMG_SEND_AFTER_ITER: slice p takes slice p-1's end
- *                    value after p-1's previous iteration.
+ *                    value after p-1's previous iteration (after its coarse
+ *                    correction).  PFMG_SEND_AFTER_SWEEP (Sec. 2.4: a level
+ *                    sends after its sweep): slice p takes slice p-1's end
+ *                    value right after p-1's fine sweep of the previous
+ *                    iteration (the predictor's end value before the first
+ *                    iteration); costs one fine field per slice of
+ *                    workspace.  Single contexts only (batches take
+ *                    AFTER_ITER).
  *   pfasst_tol       block relative residual tolerance for pfmg_run_block.
  *   pfasst_max_iter  iteration cap for pfmg_run_block.
  *   guess_min_relres with PFMG_GUESS_LEARNED: a node solve is offered the

@@ -128,6 +128,7 @@ bool BatchSolver::validate(const pfmg_params *pp, int np, std::string &why)
         }
     }
     if (a.vcycles_per_solve < 1) { why = "batched node solves take a fixed number of V-cycles (vcycles_per_solve >= 1)"; return false; }
+    if (a.fine_send != PFMG_SEND_AFTER_ITER) { why = "a batch sends the fine end value after the iteration (PFMG_SEND_AFTER_ITER)"; return false; }
     if (a.n_slices > 64) { why = "a batch takes at most 64 slices per problem"; return false; }
     if (a.stencil_order != 2 || a.interp_order != 2) {
         why = "a batch runs the second-order stencil and d-linear interpolation"; return false;

@@ -69,6 +69,7 @@ struct Solver {
     double *ublock = nullptr, *ublock_c = nullptr, *fublock_c = nullptr;   // fine; coarsest level
     double *ublock_m = nullptr;               // middle level (three levels)
     double *vb = nullptr, *vu = nullptr;      // pfmg_vcycle staging slots (fine)
+    double *esnap = nullptr;                  // AFTER_SWEEP: fine end values after the fine sweep [P]
     double *dLt[2] = {nullptr, nullptr};      // level l node x level l+1 node
     int cmap[2][16] = {};
     unsigned long long *bits = nullptr;       // reduction scratch [4 * P]
@@ -151,6 +152,7 @@ struct Solver {
     hipError_t spread_body();
     hipError_t iterate_body();
     hipError_t residual_enqueue();
+    hipError_t snapshot_ends(int p0, int p1);
     hipError_t residual_slices(int p0, int p1);
     hipError_t chain_step(int q);
     hipError_t iterate_pipelined();

@@ -99,7 +99,9 @@ bool Solver::validate(const pfmg_params &p, std::string &why)
               "levels, n >= 31 with red-black smoothing";
         return false;
     }
-    if (p.fine_send != PFMG_SEND_AFTER_ITER) { why = "fine_send must be PFMG_SEND_AFTER_ITER"; return false; }
+    if (p.fine_send != PFMG_SEND_AFTER_ITER && p.fine_send != PFMG_SEND_AFTER_SWEEP) {
+        why = "fine_send must be PFMG_SEND_AFTER_ITER or PFMG_SEND_AFTER_SWEEP"; return false;
+    }
     if (p.pfasst_max_iter < 1) { why = "pfasst_max_iter must be >= 1"; return false; }
     if (!(p.guess_min_relres >= 0)) { why = "guess_min_relres must be >= 0"; return false; }
     return true;
@@ -178,6 +180,8 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
         L.dS = dS;
     }
     double *ub = f64(p.n, 1), *vb = f64(p.n, 1), *vu = f64(p.n, 1);
+    // the fine end values kept right after the fine sweeps (AFTER_SWEEP)
+    double *esnap = p.fine_send == PFMG_SEND_AFTER_SWEEP ? f64(p.n, P) : nullptr;
     double *ubc = nullptr, *fubc = nullptr, *ubm = nullptr;
     if (nl > 1) {
         const int nc = nl == 3 ? coarser(coarser(p.n)) : coarser(p.n);
@@ -191,6 +195,7 @@ size_t Solver::carve(const pfmg_params &p, char *base, Solver *sv)
     double *nnsc = (double *)take((size_t)2 * P * 8);
     if (sv) {
         sv->ublock = ub;
+        sv->esnap = esnap;
         sv->vb = vb;
         sv->vu = vu;
         sv->ublock_c = ubc;
@@ -939,7 +944,18 @@ hipError_t Solver::spread_body()
     }
     if (nl > 1)
         HC(k::apply_L(tl(L[nl - 1].n, 1), p.nu, View<double>{ublock_c, 0}, View<double>{fublock_c, 0}, s));
-    return predictor();
+    HC(predictor());
+    return snapshot_ends(0, P);
+}
+
+// AFTER_SWEEP: keep the fine end values of slices p0 .. p1-1 as the values
+// they send at the next iteration.
+hipError_t Solver::snapshot_ends(int p0, int p1)
+{
+    if (!esnap || p1 <= p0) return hipSuccess;
+    PLevel &Fn = L[0];
+    return k::copy(tl(Fn.n, p1 - p0), View<double>{Fn.slot(Fn.U, p0, Fn.nn - 1), (long)Fn.nn * Fn.fs},
+                   View<double>{esnap + (long)p0 * Fn.fs, Fn.fs}, s);
 }
 
 // Predictor (Sec. 2.4): round j sweeps every slice p >= j on the coarse
@@ -1035,10 +1051,13 @@ hipError_t Solver::iterate_body()
     // new fine initial values from the previous iteration's end values, all
     // slices at once, before any sweep changes them
     if (P > 1) {
-        HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.U, 0, M), fst}, View<double>{Fn.slot(Fn.U, 1, 0), fst}, s));
+        // the sent values: the end values now, or those kept after the last
+        // fine sweeps (AFTER_SWEEP)
+        const View<double> sent = esnap ? View<double>{esnap, Fn.fs} : View<double>{Fn.slot(Fn.U, 0, M), fst};
+        HC(k::copy(tl(Fn.n, P - 1), sent, View<double>{Fn.slot(Fn.U, 1, 0), fst}, s));
         // F of the new node 0: the sent F is F(U) unless it came from a
-        // solve or an interpolation
-        if (p.f_solve || p.f_interp)
+        // solve or an interpolation, or was kept before the correction
+        if (p.f_solve || p.f_interp || esnap)
             HC(apply_F(0, tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.U, 1, 0), fst}, View<double>{Fn.slot(Fn.F, 1, 0), fst}));
         else
             HC(k::copy(tl(Fn.n, P - 1), View<double>{Fn.slot(Fn.F, 0, M), fst}, View<double>{Fn.slot(Fn.F, 1, 0), fst}, s));
@@ -1046,6 +1065,7 @@ hipError_t Solver::iterate_body()
     if (nl == 2 && groups > 1 && p.vcycles_per_solve > 0) return iterate_pipelined();
     HC(sweep(0, 0, P));
     if (last_solve_status == PFMG_ERR_NAN) return hipSuccess;
+    HC(snapshot_ends(0, P));
     if (nl > 1) {
         const int Lc = nl - 1;
         for (int l = 0; l < Lc; ++l) {
@@ -1114,6 +1134,7 @@ hipError_t Solver::iterate_pipelined()
         s = (nfs > 1 && (g & 1)) ? s3 : main;
         mg_off = first(g);
         hipError_t e = sweep(0, first(g), first(g + 1));
+        if (e == hipSuccess) e = snapshot_ends(first(g), first(g + 1));
         if (e == hipSuccess) e = fas_restrict(first(g), first(g + 1));
         if (e == hipSuccess) e = hipEventRecord(ev[g], s);
         s = main;

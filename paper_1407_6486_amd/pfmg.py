@@ -32,7 +32,7 @@ NODES_LOBATTO, NODES_UNIFORM = 0, 1
 SMOOTH_JACOBI, SMOOTH_RBGS = 0, 1
 FP64, MIXED = 0, 1
 GUESS_PREV, GUESS_LEARNED = 0, 1
-SEND_AFTER_ITER = 0
+SEND_AFTER_ITER, SEND_AFTER_SWEEP = 0, 1
 U_FINE, F_FINE, U_COARSE, F_COARSE, TAU, U_COARSE_OLD = range(6)
 U_L2, F_L2, TAU_L2, U_L2_OLD = range(6, 10)    # level 2 of a three-level context
 

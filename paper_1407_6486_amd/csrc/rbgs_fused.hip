@@ -18,13 +18,6 @@
 // red-updated field at k-2, k-1, k and b at k-1, k.  Only the current plane
 // of uin and of the red-updated field pass through LDS, for the x and y
 // neighbours.  Every global load of a step is issued before its barrier.
-// The uin plane in LDS alternates between two buffers, as the red planes
-// do, so one barrier per step orders every LDS write before its reads and
-// after the last reads of the buffer it overwrites: phase B reads only the
-// red plane k-1, written before this step's barrier, and its own red
-// values of plane k from registers.  The output goes out with nontemporal
-// stores (no later read in this launch; the stream does not evict the
-// halo rows the neighbouring workgroups still read from L2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,9 +55,8 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
     constexpr int rowlanes = RLN;
     constexpr int RL = rowlanes + 2;
     const int rows = ty + 2;                 // rows of the red update (owned rows)
-    const int ub_len = (ty + 4) * RL;        // one uin plane: rows j0-2 .. j0+ty+1
-    T *up = reinterpret_cast<T *>(smem_raw); // two uin planes (k even / odd)
-    T *wp = up + 2 * ub_len;                 // two planes of the red-updated field
+    T *up = reinterpret_cast<T *>(smem_raw);             // uin plane k: rows j0-2 .. j0+ty+1
+    T *wp = up + (ty + 4) * RL;                  // 2 planes of the red-updated field
     const int ytiles = (n + ty - 1) / ty, zch = (n + zchunk - 1) / zchunk;
     const int item = (int)(bid / (unsigned)(ytiles * zch));
     const int rem = (int)(bid - (unsigned)item * (unsigned)(ytiles * zch));
@@ -86,14 +78,13 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
     const bool xin = i <= n;
 
     // x index 0 is the boundary: zero once in every LDS row
-    for (int r = threadIdx.x; r < 2 * (ty + 4) + 2 * rows; r += NT) up[r * RL] = (T)0;
+    for (int r = threadIdx.x; r < (ty + 4) + 2 * rows; r += NT) up[r * RL] = (T)0;
 
     auto inside = [&](int j, int k) { return xin && j >= 1 && j <= n && k >= 1 && k <= n; };
     auto ld = [&](const T *__restrict__ a, int j, int k) -> T {
         return inside(j, k) ? a[i + j * sy + k * sz] : (T)0;
     };
-    // the global loads of step k: uin plane k+1 and b plane k on the owned
-    // rows, uin plane k on the two outer halo rows
+    // the global loads of step k
     auto load_step = [&](int k, T (&un)[Q], T (&bn)[Q], T (&ex)[2]) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -118,17 +109,26 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
         uc[q] = (own && !zero_in) ? ld(U, j, k0 - 1) : (T)0;
         wm2[q] = wm1[q] = bm1[q] = (T)0;
     }
+    T pun[Q], pbn[Q], pex[2];
+    load_step(k0 - 1, pun, pbn, pex);
 
-    // one step: un / bn / ex are the loads of load_step(k)
-    auto step = [&](int k, const T (&un)[Q], const T (&bn)[Q], const T (&ex)[2]) {
+    for (int k = k0 - 1; k <= k1; ++k) {
+        T un[Q], bn[Q], ex[2];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            un[q] = pun[q];
+            bn[q] = pbn[q];
+        }
+        ex[0] = pex[0];
+        ex[1] = pex[1];
+        if (k < k1) load_step(k + 1, pun, pbn, pex);
         // ---- uin plane k -> LDS (rows e = 0 .. ty+3 <-> j = j0-2+e)
-        T *uk = up + (k & 1) * ub_len;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int r = rsub + q * rpp;
-            if (r < rows) uk[(r + 1) * RL + i] = uc[q];
+            if (r < rows) up[(r + 1) * RL + i] = uc[q];
         }
-        for (int e = rsub, q = 0; e < 2; e += rpp, ++q) uk[(e == 0 ? 0 : ty + 3) * RL + i] = ex[q];
+        for (int e = rsub, q = 0; e < 2; e += rpp, ++q) up[(e == 0 ? 0 : ty + 3) * RL + i] = ex[q];
         __syncthreads();
         // ---- phase A: red update of plane k on the owned rows
         T *wk = wp + (k & 1) * rows * RL;
@@ -143,9 +143,9 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
                 if (zero_in) {
                     val = red ? winv * bn[q] : (T)0;
                 } else if (red) {
-                    const T *row = uk + (r + 1) * RL;
+                    const T *row = up + (r + 1) * RL;
                     T s = row[i - 1] + row[i + 1];
-                    s += (uk[r * RL + i] + uk[(r + 2) * RL + i]) + (um[q] + un[q]);
+                    s += (up[r * RL + i] + up[(r + 2) * RL + i]) + (um[q] + un[q]);
                     s -= (T)6 * uc[q];
                     val = uc[q] + winv * (bn[q] - (uc[q] - ah * s));
                 } else {
@@ -155,8 +155,8 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
             wn[q] = val;
             if (r < rows) wk[r * RL + i] = val;
         }
-        // ---- phase B: black update of plane k-1 on rows 1..ty (its red
-        // plane was written before this step's barrier)
+        __syncthreads();
+        // ---- phase B: black update of plane k-1 on rows 1..ty
         const int kb = k - 1;
         if (kb >= k0 && kb < k1) {
             const T *wb = wp + (kb & 1) * rows * RL;
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
                         s -= (T)6 * wc;
                         out = wc + winv * (bm1[q] - (wc - ah * s));
                     }
-                    __builtin_nontemporal_store(out, &O[i + j * sy + kb * sz]);
+                    O[i + j * sy + kb * sz] = out;
                 }
             }
         }
@@ -187,22 +187,6 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
             wm1[q] = wn[q];
             bm1[q] = bn[q];
         }
-    };
-
-    // the loads of step k+1 are issued before step k's work
-    T pun[Q], pbn[Q], pex[2];
-    load_step(k0 - 1, pun, pbn, pex);
-    for (int k = k0 - 1; k <= k1; ++k) {
-        T un[Q], bn[Q], ex[2];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            un[q] = pun[q];
-            bn[q] = pbn[q];
-        }
-        ex[0] = pex[0];
-        ex[1] = pex[1];
-        if (k < k1) load_step(k + 1, pun, pbn, pex);
-        step(k, un, bn, ex);
     }
 }
 
@@ -253,7 +237,7 @@ FusedShape rbgs_fused_shape(const Tiling &t, size_t elem, int ty, int target_blo
         const int n = t.seg_n(sg);
         f.blocks += (long)t.seg_count(sg) * ((n + f.ty - 1) / f.ty) * ((n + f.zchunk - 1) / f.zchunk);
     }
-    f.lds = (size_t)(2 * (f.ty + 4) + 2 * (f.ty + 2)) * (rowlanes + 2) * elem;
+    f.lds = (size_t)((f.ty + 4) + 2 * (f.ty + 2)) * (rowlanes + 2) * elem;
     return f;
 }
 

@@ -75,8 +75,14 @@ def parse():
     ap.add_argument("--table1-tol", choices=["absolute", "relative"], default="absolute",
                     help="with --form table1: the 1e-9 residual bound on the max-norm residual, or relative to "
                          "the slice's initial value")
+    ap.add_argument("--cpu-full-block", action="store_true",
+                    help="instead: run the oracle's whole block to 1e-10 on the host (minutes) and print its time")
+    ap.add_argument("--families", action="store_true",
+                    help="also report every kernel family's launches, event-stamped time and algorithmic bytes "
+                         "per launch on the fine (127) and coarse (63) grid, one more block per family")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain copy of known size three times (reference for HBM counters)")
+                    help="first run the library's streaming copy of 1 GiB three times (reference for the HBM "
+                         "counters)")
     return ap.parse_args()
 
 
@@ -102,61 +108,142 @@ def measured_traffic():
     return rec
 
 
-CALIB_N = 255
+CALIB_BYTES = 1 << 30
 
 
 def copy_calibration(pfmg):
-    """A plain copy of known size for the HBM counters: the library's pack
-    kernel (one load and one store per point) gathers one 255^3 field into a
-    dense array, three times.  Reads: 255^2 rows of 2048 bytes (each row's
-    255 values plus its halo word share 16 whole 128-byte lines); writes:
-    255^3 x 8 bytes."""
+    """A plain copy of known size for the HBM counters: the library's
+    streaming copy of 1 GiB, three times (per dispatch 1 GiB read, 1 GiB
+    written)."""
     import torch
 
-    c = pfmg.Context(pfmg.pfmg_default_params(dim=3, n=CALIB_N, n_slices=1, nodes_coarse=0))
-    out = torch.empty((CALIB_N,) * 3, dtype=torch.float64, device="cuda")
+    a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
     for _ in range(3):
-        pfmg.pfmg_get(c.h, pfmg.U_FINE, 0, 0, out.data_ptr(), True)
+        pfmg.pfmg_stream_copy(b.data_ptr(), a.data_ptr(), CALIB_BYTES, torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
-    c.close()
+    del a, b
+    torch.cuda.empty_cache()
+
+
+def host_info():
+    """The host the oracle runs on: CPU model, sockets x cores per socket
+    (physical cores) and logical CPUs from lscpu."""
+    import subprocess
+
+    info = {"model": None, "physical_cores": None, "logical_cpus": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {ln.split(":", 1)[0].strip(): ln.split(":", 1)[1].strip() for ln in out.splitlines() if ":" in ln}
+        info["model"] = kv.get("Model name")
+        if kv.get("Socket(s)", "").isdigit() and kv.get("Core(s) per socket", "").isdigit():
+            info["physical_cores"] = int(kv["Socket(s)"]) * int(kv["Core(s) per socket"])
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def host_triad_gbs(threads, nbytes=1 << 29, reps=5):
+    """STREAM-triad bandwidth of the host (a = b + s c over three arrays of
+    nbytes, one fused pass on `threads` threads; 3 nbytes moved per pass)."""
+    import torch
+
+    prev = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    b = torch.ones(nbytes // 8, dtype=torch.float64)
+    c = torch.ones_like(b)
+    a = torch.empty_like(b)
+    torch.add(b, c, alpha=3.0, out=a)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        torch.add(b, c, alpha=3.0, out=a)
+    dt = (time.perf_counter() - t0) / reps
+    torch.set_num_threads(prev)
+    return 3 * nbytes / dt / 1e9
+
+
+def _omp_threads(k):
+    """Set the OpenMP thread count of the oracle's runtime (libgomp)."""
+    import ctypes
+
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
 
 
 def cpu_baseline(n, P, iters_gpu, cpu_iters, u0):
-    """The oracle as it stands, on the host: predictor + cpu_iters iterations,
-    extrapolated to the iteration count of the block."""
+    """The oracle as it stands (gcc -O3, no fast-math, no contraction), on
+    the host: predictor + cpu_iters iterations on the threads of the box's
+    CPU share (OMP_NUM_THREADS), extrapolated to the iteration count of the
+    block; then the same on one thread (predictor + one iteration); the
+    host's CPU model, physical cores and STREAM-triad bandwidth."""
+    import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def sample(k, iters):
+        _omp_threads(k)
+        t0 = time.perf_counter()
+        orc = O.Pfasst(3, n, 1.0, 1e-3, P, 5, 3, O.policy(cycles=1))
+        orc.set_initial(u0)
+        t1 = time.perf_counter()
+        for _ in range(iters):
+            orc.iterate()
+        t2 = time.perf_counter()
+        return t1 - t0, (t2 - t1) / iters
+
+    pred, per_iter = sample(threads, cpu_iters)
+    pred1, per_iter1 = sample(1, 1)
+    _omp_threads(threads)
+    est = pred + per_iter * iters_gpu
+    est1 = pred1 + per_iter1 * iters_gpu
+    host = host_info()
+    host["threads_used"] = threads
+    host["triad_gbs"] = round(host_triad_gbs(threads), 1)
+    host["triad_gbs_one_thread"] = round(host_triad_gbs(1), 1)
+    return {"value": round(est, 3), "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"predictor ({pred:.2f} s) + {cpu_iters} iterations ({per_iter:.2f} s each) of the "
+                      f"same block on {threads} threads, extrapolated to the {iters_gpu} iterations the block needs",
+            "one_thread": {"value": round(est1, 3), "sample": f"predictor ({pred1:.2f} s) + 1 iteration "
+                                                               f"({per_iter1:.2f} s) on 1 thread, extrapolated"},
+            "host": host}
+
+
+def cpu_full_block(n, P, u0, tol=1e-10, max_iter=400):
+    """The oracle's whole block to the residual bound (validates the
+    extrapolation of cpu_baseline); prints a progress line every 10
+    iterations."""
     import oracle as O
 
     t0 = time.perf_counter()
     orc = O.Pfasst(3, n, 1.0, 1e-3, P, 5, 3, O.policy(cycles=1))
     orc.set_initial(u0)
-    t1 = time.perf_counter()
-    for _ in range(cpu_iters):
-        orc.iterate()
-    t2 = time.perf_counter()
-    per_iter = (t2 - t1) / cpu_iters
-    est = (t1 - t0) + per_iter * iters_gpu
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(est, 3), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"predictor ({t1 - t0:.2f} s) + {cpu_iters} iterations ({per_iter:.2f} s each) of the "
-                      f"same block on the host, extrapolated to the {iters_gpu} iterations the block needs"}
+    it, res = 0, float("inf")
+    while it < max_iter and res > tol:
+        res = orc.iterate()
+        it += 1
+        if it % 10 == 0:
+            print(f"oracle block: iteration {it} residual {res:.3e} at {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    return {"value": round(time.perf_counter() - t0, 3), "unit": "s", "iterations": it, "final_residual": res,
+            "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
 
 
-def copy_bandwidth_gbs(nbytes=1 << 30, reps=10):
-    """Read + write bytes per second of a plain device-to-device copy of
-    nbytes (torch's copy kernel): the bandwidth a streaming kernel can
-    expect on this GPU, next to the 8 TB/s spec peak."""
+def copy_bandwidth_gbs(pfmg, nbytes=1 << 30, reps=10):
+    """Read + write bytes per second of the library's streaming copy of
+    nbytes (one 16-byte nontemporal load and store per thread), timed with
+    HIP events on the stream it runs on: the bandwidth a plain stream gets
+    from HBM on this GPU, next to the 8 TB/s spec peak."""
     import torch
 
-    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    a.fill_(1.0)
+    st = torch.cuda.current_stream()
     for _ in range(3):
-        b.copy_(a)
+        pfmg.pfmg_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(st)
     for _ in range(reps):
-        b.copy_(a)
-    e1.record()
+        pfmg.pfmg_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
+    e1.record(st)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
     del a, b
@@ -558,6 +645,11 @@ def main():
               "weak3": form_weak3}[a.form]
         print(json.dumps(fn(pfmg, a), default=float), flush=True)
         return
+    if a.cpu_full_block:
+        u0_host, _ = inputs.random_fourier(a.n, 1407)
+        print(json.dumps({"cpu_full_block": cpu_full_block(a.n, a.slices, u0_host), "host": host_info()}),
+              flush=True)
+        return
     if a.calibrate_copy:
         copy_calibration(pfmg)
     n, P = a.n, a.slices
@@ -620,7 +712,7 @@ def main():
                 "traffic": traffic, "kernel": dominant, "launches": launches,
                 "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2), "bytes_per_launch": per_launch,
                 "eager_block_s": round(eager_block_s, 4),
-                "copy_gbs": round(copy_bandwidth_gbs(), 1)}
+                "copy_gbs": round(copy_bandwidth_gbs(pfmg), 1)}
 
     out = {
         "metric": "s to 1e-10 residual per PFASST block",
@@ -645,6 +737,15 @@ def main():
         "vcycle_gdofs": round(vcycle_gdofs, 2) if vcycle_gdofs else None,
         "roofline": roofline,
     }
+    if a.families:
+        fams = {}
+        for fam in ("rbgs", "resid_restrict", "prolong", "apply_L", "sdc_start", "sdc_rhs", "colloc_resid"):
+            for g in (n, (n + 1) // 2 - 1):
+                r = stamped_roofline(ctx, u0, fam, g)
+                if r:
+                    fams[r["kernel"]] = {k: r[k] for k in ("launches", "avg_launch_us", "bytes_per_launch",
+                                                           "achieved")}
+        out["families"] = fams
     if not a.no_cpu_baseline and iters:
         out["cpu_baseline"] = cpu_baseline(n, P, iters[-1], a.cpu_iters, u0_host)
     print(json.dumps(out), flush=True)

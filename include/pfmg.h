@@ -364,6 +364,16 @@ pfmg_status pfmg_batch_timing_enable(pfmg_batch *b, const char *kernel, int32_t 
 pfmg_status pfmg_batch_timing_read(pfmg_batch *b, int64_t *launches, double *ms_total,
                                    double *bytes_total);
 
+/* Streaming reference (measurement, not a step of the method): copy `bytes`
+ * from src to dst, device pointers, with one 16-byte nontemporal load and
+ * store per thread, the copy shape that streams fastest on gfx950.  The
+ * benchmark times it next to the stencil kernels as the bandwidth HBM
+ * delivers to a plain stream, and its hardware counters calibrate the
+ * counter readings of the other kernels.  bytes and both pointers must be
+ * multiples of 16 and the ranges must not overlap (PFMG_ERR_ARG).
+ * Stream-ordered on hip_stream; does not synchronise. */
+pfmg_status pfmg_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 /* Red-black launch-shape autotuner: the number of configurations in the
  * process-wide table, and the entry for a key ("<arch>/rbgs/<f64|f32>/"
  * followed by n x fields per segment joined by '+'), written to buf as

@@ -573,6 +573,18 @@ pfmg_status pfmg_batch_vcycle_count(pfmg_batch *b, int32_t level, int64_t *count
     return PFMG_OK;
 }
 
+pfmg_status pfmg_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    if (bytes == 0) return PFMG_OK;
+    if (!dst || !src) return fail(PFMG_ERR_ARG, "null pointer");
+    if ((bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+        return fail(PFMG_ERR_ARG, "bytes and both pointers must be multiples of 16");
+    const uintptr_t d = (uintptr_t)dst, sr = (uintptr_t)src;
+    if (d < sr + bytes && sr < d + bytes) return fail(PFMG_ERR_ARG, "source and destination overlap");
+    HIPCALL(pfmg::k::stream_copy(dst, src, bytes, (hipStream_t)hip_stream), "stream copy");
+    return PFMG_OK;
+}
+
 pfmg_status pfmg_tune_count(int32_t *count_out)
 {
     if (!count_out) return fail(PFMG_ERR_ARG, "null argument");

@@ -170,6 +170,9 @@ hipError_t inject(const Tiling &t, View<double> uf, View<double> uc, hipStream_t
 hipError_t pack(const Tiling &t, View<double> f, double *dense, hipStream_t s);
 hipError_t unpack(const Tiling &t, const double *dense, View<double> f, hipStream_t s);
 hipError_t fill_u64(unsigned long long *p, unsigned long long v, int count, hipStream_t s);
+// dst[0 .. bytes) = src[0 .. bytes) in 16-byte nontemporal loads / stores
+// (bytes a multiple of 16, both 16-byte aligned, not overlapping).
+hipError_t stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 }  // namespace k
 }  // namespace pfmg

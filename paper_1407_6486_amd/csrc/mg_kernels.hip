@@ -480,6 +480,18 @@ __global__ __launch_bounds__(BLOCK) void resid_norm_kernel(Tiling t, double alph
     block_max_bits(m, bits + flat_item(t, qb));
 }
 
+// Streaming reference: one 16-byte nontemporal load and store per thread
+// and no loop (the shape that copied fastest on gfx950 among unrolled,
+// grid-stride and temporal variants).
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void stream_copy_kernel(const dvec2 *__restrict__ a, dvec2 *__restrict__ b,
+                                                          size_t n16)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
+}
+
 __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v, int count)
 {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -643,6 +655,16 @@ hipError_t resid_norm(const Tiling &t, double alpha, View<double> b, View<double
                       hipStream_t s)
 {
     PFMG_DISPATCH(t, resid_norm_kernel, t, alpha, b, u, bits);
+}
+
+hipError_t stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    const size_t blocks = (n16 + 255) / 256;
+    if (blocks > 0xffffffffull) return hipErrorInvalidValue;
+    stream_copy_kernel<<<(unsigned)blocks, 256, 0, s>>>((const dvec2 *)src, (dvec2 *)dst, n16);
+    return hipGetLastError();
 }
 
 hipError_t fill_u64(unsigned long long *p, unsigned long long v, int count, hipStream_t s)

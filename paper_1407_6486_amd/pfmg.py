@@ -66,6 +66,7 @@ _sigs = {
     "pfmg_set_initial": ([_vp, _vp, C.c_int32], C.c_int32),
     "pfmg_sdc_sweep": ([_vp, C.c_int32, C.c_int32, C.c_int32], C.c_int32),
     "pfmg_vcycle": ([_vp, C.c_double, _vp, _vp, C.c_int32, _dp, C.POINTER(C.c_int32)], C.c_int32),
+    "pfmg_stream_copy": ([_vp, _vp, C.c_size_t, _vp], C.c_int32),
     "pfmg_vcycle_noalloc": ([C.POINTER(Params), C.c_double, _vp, _vp, C.c_int32, _vp, _dp, C.POINTER(C.c_int32)],
                             C.c_int32),
     "pfmg_pfasst_iter": ([_vp, _dp], C.c_int32),
@@ -111,6 +112,13 @@ for _name, (_args, _res) in _sigs.items():
     _f.restype = _res
 
 EXPORTED = tuple(_sigs)
+
+# Launch shapes of the red-black smoother measured on gfx950 by the
+# library's autotuner (lines "key fused ty zchunk blocks"), pinned at import
+# so that every run takes the same shapes without timing runs;
+# PFMG_TUNE_DEFAULTS=0 leaves the table empty (shapes are then timed on
+# first use, or read from PFMG_TUNE_CACHE).
+TUNE_TABLE = os.path.join(HERE, "tune_gfx950.txt")
 
 
 def _check(st: int) -> int:
@@ -174,6 +182,10 @@ def pfmg_vcycle_noalloc(p: Params, alpha: float, b_ptr: int, u_ptr: int, n_cycle
     st = _check(_lib.pfmg_vcycle_noalloc(C.byref(p), alpha, _vp(b_ptr), _vp(u_ptr), n_cycles, _vp(stream_ptr),
                                          C.byref(rr) if want_relres else None, C.byref(nc)))
     return st, (rr.value if want_relres else None), nc.value
+
+
+def pfmg_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int | None) -> int:
+    return _check(_lib.pfmg_stream_copy(_vp(dst_ptr), _vp(src_ptr), nbytes, _vp(stream_ptr or 0)))
 
 
 def pfmg_pfasst_iter(h):
@@ -629,3 +641,21 @@ class PairStore:
     def attach(self, ctx: "Context", offset: int = 0):
         pfmg_record(ctx.h, self.pairs[offset:].data_ptr(), self.ah2[offset:].data_ptr(), self.scratch.data_ptr(),
                     self.capacity - offset)
+
+
+def load_tune_table(path: str = TUNE_TABLE) -> int:
+    """Pin every entry of a tuner table file through pfmg_tune_set; returns
+    the number of entries pinned."""
+    count = 0
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) != 5:
+                continue
+            pfmg_tune_set(parts[0], int(parts[1]), int(parts[2]), int(parts[3]))
+            count += 1
+    return count
+
+
+if os.environ.get("PFMG_TUNE_DEFAULTS", "1") != "0" and os.path.exists(TUNE_TABLE):
+    load_tune_table()

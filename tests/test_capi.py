@@ -54,7 +54,7 @@ def test_default_params_and_workspace_size(pf):
 @pytest.mark.parametrize("field,value", [("n", 64), ("n", 9), ("dim", 2), ("nu", -1.0), ("dt", 0.0),
                                          ("n_slices", 0), ("nodes_fine", 1), ("nodes_coarse", 4),
                                          ("omega", 2.5), ("smoother", 7), ("precision", 3),
-                                         ("vcycles_per_solve", -1), ("fine_send", 1)])
+                                         ("vcycles_per_solve", -1), ("fine_send", 2)])
 def test_invalid_parameters_rejected(pf, field, value):
     p = pf.pfmg_default_params(**{field: value})
     with pytest.raises(pf.PfmgError) as ei:
@@ -225,3 +225,14 @@ def test_network_sizes_on_the_host(pf):
     with pytest.raises(pf.PfmgError):   # learned guess needs full solves
         pf.pfmg_workspace_bytes(pf.pfmg_default_params(n=63, guess=pf.GUESS_LEARNED))
     assert pf.pfmg_workspace_bytes(pf.pfmg_default_params(n=63, guess=pf.GUESS_LEARNED, vcycles_per_solve=0)) > 0
+
+
+def test_stream_copy_checks_arguments_on_the_host(pf):
+    """Sizes and pointers not multiples of 16, null and overlapping ranges
+    are refused before any launch (no GPU needed)."""
+    for dst, src, nb in ((1 << 20, 1 << 24, 24), (1 << 20 | 8, 1 << 24, 32), (0, 1 << 24, 32),
+                         (1 << 20, (1 << 20) + 16, 64)):
+        with pytest.raises(pf.PfmgError) as ei:
+            pf.pfmg_stream_copy(dst, src, nb, None)
+        assert ei.value.status == pf.ERR_ARG
+    assert pf.pfmg_stream_copy(1 << 20, 1 << 24, 0, None) == pf.OK

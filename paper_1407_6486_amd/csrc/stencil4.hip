@@ -423,7 +423,10 @@ hipError_t prolong4z(const Tiling &t, View<double> ec, View<double> u, View<doub
     }
     if (fields == 0) return hipSuccess;
     const int rln = nmax <= 64 ? 64 : nmax <= 128 ? 128 : 256;
-    constexpr int TYF = 8;   // fine rows per tile (Q * BLOCK / RLN for every instantiation)
+    // fine rows per tile, Q * BLOCK / RLN of the instantiation below (4 rows
+    // measured faster than 8 at 127^3: half the registers, twice the
+    // workgroups per CU)
+    const int TYF = rln == 64 ? 8 : 4;
     // fine planes per chunk: about 4096 workgroups in all, at least 8 planes
     long rows = 0;
     for (int sg = 0; sg < t.nseg; ++sg) rows += (long)t.seg_count(sg) * ((t.seg_n(sg) + TYF - 1) / TYF);
@@ -437,8 +440,8 @@ hipError_t prolong4z(const Tiling &t, View<double> ec, View<double> u, View<doub
     const size_t lds = (size_t)NA * (TYF / 2 + 5) * ((rln / 2 + 2) + rln) * sizeof(double);
     const dim3 g((unsigned)blocks), blk(BLOCK);
     if (rln == 64) prolong4z_kernel<64, 2, NA><<<g, blk, lds, s>>>(t, kch, ec, u, ec2, u2);
-    else if (rln == 128) prolong4z_kernel<128, 4, NA><<<g, blk, lds, s>>>(t, kch, ec, u, ec2, u2);
-    else prolong4z_kernel<256, 8, NA><<<g, blk, lds, s>>>(t, kch, ec, u, ec2, u2);
+    else if (rln == 128) prolong4z_kernel<128, 2, NA><<<g, blk, lds, s>>>(t, kch, ec, u, ec2, u2);
+    else prolong4z_kernel<256, 4, NA><<<g, blk, lds, s>>>(t, kch, ec, u, ec2, u2);
     return hipGetLastError();
 }
 

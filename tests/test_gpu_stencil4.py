@@ -80,3 +80,26 @@ def test_pfasst4_matches_oracle(pf, n, P, fam, so, io, cycles):
         assert abs(r_gpu - r_or) <= 1e-9 * r_or, (k, r_gpu, r_or)
         compare_state(c, orc, P, lnorm_f=ln)
     assert c.vcycle_count(0) == orc.vcycles(0) and c.vcycle_count(1) == orc.vcycles(1)
+
+
+@pytest.mark.parametrize("fi", [0, 1])
+def test_cubic_interpolation_255_matches_oracle(pf, fi):
+    """The widest cubic-interpolation launch (fine 255^3, 256-lane rows):
+    one slice, uniform 3/2 nodes, so that the predictor's interpolation
+    moves U (and, with f_interp, F in the same launch) of every fine node;
+    every field after the predictor and one iteration."""
+    from tests.test_gpu_f_options import lnorm_eff
+    say(f"cubic interpolation at 255^3, f_interp {fi}")
+    n, P, nu, dt = 255, 1, 1.0 / 3.0, 1.0 / 64
+    c = make(pf, dim=3, n=n, n_slices=P, nu=nu, dt=dt, nodes_fine=3, nodes_coarse=2, node_family=pf.NODES_UNIFORM,
+             interp_order=4, f_solve=fi, f_interp=fi, vcycles_per_solve=1)
+    orc = O.Pfasst(3, n, nu, dt, P, 3, 2, O.policy(cycles=1), interp_order=4, node_family=O.UNIFORM, f_solve=fi,
+                   f_interp=fi)
+    u0 = inputs.sine_mode(n, (1, 1, 1), 3) + 0.1 * inputs.sine_mode(n, (7, 3, 11), 3)
+    c.set_initial(u0)
+    orc.set_initial(u0)
+    ln = lnorm_eff(orc, 2)
+    compare_state(c, orc, P, lnorm_f=ln)
+    r_gpu, r_or = c.pfasst_iter(), orc.iterate()
+    assert abs(r_gpu - r_or) <= 1e-9 * r_or + 1e-15, (r_gpu, r_or)
+    compare_state(c, orc, P, lnorm_f=ln)

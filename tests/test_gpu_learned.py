@@ -271,6 +271,15 @@ def test_learned_guess_is_judged_and_converges(pf):
     assert tried > 0 and 0 <= taken <= tried
     for p in range(P):
         assert pins.rel_err(learned.get(O.UF, p, 4), plain.get(O.UF, p, 4)) <= 1e-9
+    # end to end against the closed form: at convergence every slice's end
+    # value is sum_j a_j R44(dt nu mu_j)^(p+1) phi_j (Lobatto IIIA)
+    g = pins.golden("lobatto_iiia.json")
+    _, modes = inputs.random_fourier(n, 99)
+    for p in range(P):
+        want = np.zeros((n,) * 3)
+        for a, k in zip(modes.amp, modes.k):
+            want += a * pins.pade(2e-3 * pins.mu(n, k), g["pade44_num"]) ** (p + 1) * inputs.sine_mode(n, k, 3)
+        assert pins.rel_err(learned.get(O.UF, p, 4), want) <= 1e-9, p
     plain.close()
     learned.close()
     net.close()

@@ -227,21 +227,30 @@ __device__ void resid_restrict(Grid<DIM, T> &f, Grid<DIM, T> &c, T ah)
 template <int DIM, typename T>
 __device__ void prolong_add(const Grid<DIM, T> &c, Grid<DIM, T> &f)
 {
+    // fine 1-based index x1: even sits on coarse x1/2, odd between
+    // (x1-1)/2 and (x1+1)/2 (1-based; 0 and nc+1 are the zero boundary).
+    // All eight coarse values are read unconditionally (the two indices
+    // coincide on an even axis) and combined with selects, so the LDS
+    // reads issue together: per axis 0.5 (lo + hi) when odd, lo when even.
     for_flat<DIM>(f.n, [&](int p, int i, int j, int k) {
-        // 1-based fine index i+1; coarse 1-based (i+1)>>1 and (i+2)>>1, 0-based minus one
         const int i1 = i + 1;
         const int a0 = (i1 >> 1) - 1, a1 = ((i1 + 1) >> 1) - 1;
+        const bool ox = (i1 & 1) != 0;
         auto rowv = [&](int jj, int kk) -> T {
-            return (i1 & 1) ? (T)0.5 * (c.at(c.u, a0, jj, kk) + c.at(c.u, a1, jj, kk)) : c.at(c.u, a0, jj, kk);
+            const T x0 = c.at(c.u, a0, jj, kk), x1 = c.at(c.u, a1, jj, kk);
+            const T h = (T)0.5 * (x0 + x1);
+            return ox ? h : x0;
         };
         T v;
         if (DIM == 3) {
             const int j1 = j + 1, k1 = k + 1;
             const int b0 = (j1 >> 1) - 1, b1 = ((j1 + 1) >> 1) - 1, c0 = (k1 >> 1) - 1, c1 = ((k1 + 1) >> 1) - 1;
-            auto planev = [&](int kk) -> T {
-                return (j1 & 1) ? (T)0.5 * (rowv(b0, kk) + rowv(b1, kk)) : rowv(b0, kk);
-            };
-            v = (k1 & 1) ? (T)0.5 * (planev(c0) + planev(c1)) : planev(c0);
+            const bool oy = (j1 & 1) != 0, oz = (k1 & 1) != 0;
+            const T r00 = rowv(b0, c0), r10 = rowv(b1, c0), r01 = rowv(b0, c1), r11 = rowv(b1, c1);
+            const T p0h = (T)0.5 * (r00 + r10), p1h = (T)0.5 * (r01 + r11);
+            const T p0 = oy ? p0h : r00, p1 = oy ? p1h : r01;
+            const T vh = (T)0.5 * (p0 + p1);
+            v = oz ? vh : p0;
         } else {
             v = rowv(0, 0);
         }

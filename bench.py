@@ -11,10 +11,11 @@ The initial data sits in HBM before the timed region, which runs whole
 blocks as the library does (captured graphs replayed per iteration).
 Printed: one JSON line with the block time, V-cycle GDOF/s, the roofline of
 the dominant kernel (the one-pass red-black sweep on the fine grid, its
-launches bracketed by HIP events on the stream they run on during one more
-block of the same workload; HBM traffic from the committed counter summary
-while the kernel source and launch shape are unchanged) and the oracle
-timed on the host.
+launches stamping HIP events on the stream they run on during one more
+block of the same workload in a context whose coarse chain shares the main
+stream, and again beside the chain in the benchmark's own context; HBM
+traffic from the committed counter summary while the kernel source and
+launch shape are unchanged) and the oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -695,17 +696,32 @@ def main():
     fine_vcycles = (ctx.vcycle_count(0) - v0) / max(a.steps, 1)
     s_per_block = (t1 - t0) / a.steps if a.steps > 0 else None
 
-    # dominant kernel: one more block with HIP events around each of its
-    # launches on the stream it runs on (event brackets run the block from
-    # the host, launch by launch)
+    # dominant kernel: one more block with HIP events that each launch
+    # stamps itself (hipExtLaunchKernel) on the stream it runs on (event
+    # brackets run the block from the host, launch by launch).  Measured
+    # twice: in a context whose coarse chain shares the main stream (the
+    # sweeps run without the chain's kernels beside them, as under
+    # rocprofv3, which serialises the two streams), and in the benchmark's
+    # own context (the chain beside the sweeps)
     dominant = f"{a.smoother}@{n}"
+    os.environ["PFMG_ONE_STREAM"] = "1"
+    try:
+        ctx1 = pfmg.Context(p)
+    finally:
+        del os.environ["PFMG_ONE_STREAM"]
+    ctx1.run_block(u0)
+    ctx1.timing_enable(dominant, True)
+    ctx1.run_block(u0)
+    launches, ms, nbytes = ctx1.timing_read()
+    ctx1.timing_enable(None, False)
+    ctx1.close()
     ctx.timing_enable(dominant, True)
     torch.cuda.synchronize()
     te0 = time.perf_counter()
     ctx.run_block(u0)
     torch.cuda.synchronize()
     eager_block_s = time.perf_counter() - te0
-    launches, ms, nbytes = ctx.timing_read()
+    launches_b, ms_b, nbytes_b = ctx.timing_read()
     ctx.timing_enable(None, False)
 
     # V-cycle throughput: one more block with every fine-grid V-cycle bracketed
@@ -725,6 +741,8 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                 "traffic": traffic, "kernel": dominant, "launches": launches,
                 "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2), "bytes_per_launch": per_launch,
+                "avg_launch_us_beside_chain": round(ms_b * 1e3 / max(launches_b, 1), 2),
+                "achieved_beside_chain": round(nbytes_b / (ms_b * 1e-3) / 1e9, 1) if ms_b > 0 else None,
                 "eager_block_s": round(eager_block_s, 4),
                 "copy_gbs": round(copy_bandwidth_gbs(pfmg), 1)}
 

@@ -166,6 +166,7 @@ struct Solver {
     hipEvent_t evc[2] = {};           // coarse chain done through group G-2 / G-1
     int fine_streams = 1;             // streams the groups' fine sweeps alternate over
     bool late_interp = true;          // interpolation and residual of the early groups under the last chain
+    bool one_stream = false;          // the chain on the main stream too (no overlap)
     bool fused_sdc = true;            // sdc_start and apply_L_rhs in place of their separate kernels
     int mg_off = 0;                   // first multigrid scratch field of the current sweep
     template <typename T>

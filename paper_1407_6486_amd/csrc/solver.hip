@@ -296,6 +296,10 @@ bool Solver::init_host(std::string &why)
     // its coarse chain on the chain stream (the earlier schedule).
     e = getenv("PFMG_LATE_INTERP");
     late_interp = !(e && atoi(e) == 0);
+    // PFMG_ONE_STREAM=1: the pipelined iteration's coarse chain runs on the
+    // main stream (for timing kernels without the chain beside them)
+    e = getenv("PFMG_ONE_STREAM");
+    one_stream = e && atoi(e) != 0;
     // PFMG_FUSED_SDC=0: the separate integral, right-hand-side, F and copy
     // launches of a sweep.
     e = getenv("PFMG_FUSED_SDC");
@@ -1117,6 +1121,9 @@ hipError_t Solver::iterate_pipelined()
     for (int g = 0; g <= groups; ++g)
         if (!ev[g]) HC(hipEventCreateWithFlags(&ev[g], hipEventDisableTiming));
     const int G = groups;
+    // one_stream: the chain goes to the main stream behind the fine sweeps
+    // (the same launches in the same per-slice order, without overlap)
+    hipStream_t const s2 = one_stream ? s : this->s2;
     auto first = [&](int g) { return gbound[g]; };
     // The fine sweeps of the groups touch disjoint slices and, with the
     // multigrid scratch offset to their first slice, disjoint scratch, so

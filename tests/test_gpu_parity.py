@@ -512,30 +512,35 @@ def test_fused_sweep_launches_match_separate(pf, n, P, nf, nc, fam):
         assert pins.rel_err(g1[p], g0[p]) <= 1e-13, p
 
 
-@pytest.mark.parametrize("n,groups,streams,late", [(31, 2, 2, 1), (31, 4, 2, 1), (31, 5, 2, 1), (31, 4, 1, 1),
-                                                   (63, 4, 2, 1), (31, 3, 1, 0), (63, 4, 1, 0)])
-def test_pipelined_iteration_matches_sequential(pf, n, groups, streams, late):
+@pytest.mark.parametrize("n,groups,streams,late,one", [(31, 2, 2, 1, 0), (31, 4, 2, 1, 0), (31, 5, 2, 1, 0),
+                                                       (31, 4, 1, 1, 0), (63, 4, 2, 1, 0), (31, 3, 1, 0, 0),
+                                                       (63, 4, 1, 0, 0), (63, 4, 1, 1, 1)])
+def test_pipelined_iteration_matches_sequential(pf, n, groups, streams, late, one):
     """Slice groups whose fine sweeps overlap the coarse chain of earlier
     groups (second stream), and each other (fine sweeps alternating over
     two streams), give the sequential schedule's results, with the early
     groups' interpolation and residual on the main stream under the last
-    chain (late = 1) or behind each group's chain (late = 0)."""
+    chain (late = 1) or behind each group's chain (late = 0); one = 1 puts
+    the chain on the main stream (the benchmark's timing context)."""
     import os
 
     P = 8
-    say(f"pipelined iteration, {groups} groups, {streams} fine stream(s), late interpolation {late}, n={n}, P={P}")
+    say(f"pipelined iteration, {groups} groups, {streams} fine stream(s), late interpolation {late}, "
+        f"one stream {one}, n={n}, P={P}")
     u0, _ = inputs.random_fourier(n, 4242)
     states = {}
     for g in (1, groups):
         os.environ["PFMG_GROUPS"] = str(g)
         os.environ["PFMG_FINE_STREAMS"] = str(streams)
         os.environ["PFMG_LATE_INTERP"] = str(late)
+        os.environ["PFMG_ONE_STREAM"] = str(one)
         try:
             c = make(pf, n=n, n_slices=P)
         finally:
             del os.environ["PFMG_GROUPS"]
             del os.environ["PFMG_FINE_STREAMS"]
             del os.environ["PFMG_LATE_INTERP"]
+            del os.environ["PFMG_ONE_STREAM"]
         c.set_initial(u0)
         res = [c.pfasst_iter() for _ in range(4)]
         states[g] = (res, [c.get(O.UF, p, 4) for p in range(P)], [c.get(O.UC, p, 2) for p in range(P)])

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -39,8 +40,17 @@ constexpr int QMAX = 6;   // owned rows per thread
 // occupancy.  The loads of step k + 1 are issued at the top of step k
 // (uin plane k + 2, b plane k + 1, the halo rows of uin plane k + 1) and
 // wait behind the whole step's arithmetic and barriers.
+//
+// The z-march is written without divergent branches: a thread's rows are
+// the same for the whole wavefront (RLN is a multiple of the wavefront
+// width), so row and plane conditions are scalar; loads read clamped
+// indices, whose values outside the interior are the zero halo words of
+// the layout; the colour and the interior test pick results with selects.
+// The register windows live in four slots indexed by the plane modulo 4
+// and the loop is unrolled four times, so no values are moved between
+// windows.
 template <typename T, int RLN, int Q, int NT>
-__global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
+__global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
                                                            double omega, View<T> b, View<T> uin, View<T> uout)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -52,8 +62,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
         }))
         return;
     const int n = qs.n;
-    constexpr int rowlanes = RLN;
-    constexpr int RL = rowlanes + 2;
+    constexpr int RL = RLN + 2;
     const int rows = ty + 2;                 // rows of the red update (owned rows)
     T *up = reinterpret_cast<T *>(smem_raw);             // uin plane k: rows j0-2 .. j0+ty+1
     T *wp = up + (ty + 4) * RL;                  // 2 planes of the red-updated field
@@ -67,127 +76,189 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 5 : 2) : 1)) void rbgs_f
     const T ah = (T)ahd, winv = (T)(omega / (1.0 + 2.0 * 3 * ahd));
     const int j0 = jt * ty + 1, k0 = zc * zchunk + 1;
     const int k1 = min(k0 + zchunk, n + 1);
-    constexpr int rpp = NT / rowlanes;
-    const int i = (int)(threadIdx.x % rowlanes) + 1;
-    const int rsub = (int)(threadIdx.x / rowlanes);
+    constexpr int rpp = NT / RLN;
+    const int i = (int)(threadIdx.x % RLN) + 1;
+    const int rsub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / RLN));
     // element offsets inside one field fit in 32 bits (n <= 255)
     const int sy = (int)row_stride(n), sz = (int)plane_stride(n);
     const T *__restrict__ U = fp(uin, qs);
     const T *__restrict__ Bv = fp(b, qs);
     T *__restrict__ O = fp(uout, qs);
     const bool xin = i <= n;
+    // lanes past the row read its right halo word (zero)
+    const unsigned ib = (unsigned)min(i, n + 1) * (unsigned)sizeof(T);
 
     // x index 0 is the boundary: zero once in every LDS row
     for (int r = threadIdx.x; r < (ty + 4) + 2 * rows; r += NT) up[r * RL] = (T)0;
 
-    auto inside = [&](int j, int k) { return xin && j >= 1 && j <= n && k >= 1 && k <= n; };
-    auto ld = [&](const T *__restrict__ a, int j, int k) -> T {
-        return inside(j, k) ? a[i + j * sy + k * sz] : (T)0;
-    };
-    // the global loads of step k
-    auto load_step = [&](int k, T (&un)[Q], T (&bn)[Q], T (&ex)[2]) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int r = rsub + q * rpp;
-            const int j = j0 - 1 + r;
-            const bool own = r < rows;
-            un[q] = (own && !zero_in) ? ld(U, j, k + 1) : (T)0;
-            bn[q] = own ? ld(Bv, j, k) : (T)0;
-        }
-        ex[0] = ex[1] = (T)0;
-        if (!zero_in)
-            for (int e = rsub, q = 0; e < 2; e += rpp, ++q) ex[q] = ld(U, e == 0 ? j0 - 2 : j0 + ty + 1, k);
-    };
-
-    T um[Q], uc[Q], wm2[Q], wm1[Q], bm1[Q];
+    // Per owned row (uniform): ownership, the byte offset of the row clamped
+    // to the halo (every point outside the interior is zero), and the lanes
+    // of the row that are red on even and on odd planes (interior only).
+    bool own[Q], eown[2];
+    unsigned roff[Q], eoff[2];
+    bool red_e[Q], red_o[Q];
+    auto rowb = [&](int j) { return (unsigned)(min(max(j, 0), n + 1) * sy) * (unsigned)sizeof(T); };
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int r = rsub + q * rpp;
-        const int j = j0 - 1 + r;
-        const bool own = r < rows;
-        um[q] = (own && !zero_in) ? ld(U, j, k0 - 2) : (T)0;
-        uc[q] = (own && !zero_in) ? ld(U, j, k0 - 1) : (T)0;
-        wm2[q] = wm1[q] = bm1[q] = (T)0;
+        const int r = rsub + q * rpp, j = j0 - 1 + r;
+        own[q] = r < rows;
+        roff[q] = rowb(j);
+        const bool in = xin && j >= 1 && j <= n;
+        const bool even = ((i + j) & 1) == 0;
+        red_e[q] = in && even;
+        red_o[q] = in && !even;
     }
-    T pun[Q], pbn[Q], pex[2];
-    load_step(k0 - 1, pun, pbn, pex);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = rsub + q * rpp;
+        eown[q] = e < 2;
+        eoff[q] = rowb(e == 0 ? j0 - 2 : j0 + ty + 1);
+    }
+    auto planeb = [&](int k) { return (unsigned)(min(max(k, 0), n + 1) * sz) * (unsigned)sizeof(T); };
+    auto ld = [&](const T *__restrict__ a, unsigned rb, unsigned pb) -> T {
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + (rb + pb) + ib);
+    };
 
-    for (int k = k0 - 1; k <= k1; ++k) {
-        T un[Q], bn[Q], ex[2];
+    // The z-march; ZI: the input is zero (uin is not read).
+    auto march = [&](auto zi) {
+        constexpr bool ZI = decltype(zi)::value;
+        // the global loads of step k: uin plane k + 1 and b plane k on the
+        // owned rows, uin plane k on the two outer halo rows
+        auto load_step = [&](int k, T (&un)[Q], T (&bn)[Q], T (&ex)[2]) {
+            const unsigned pu = planeb(k + 1), pb = planeb(k);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            un[q] = pun[q];
-            bn[q] = pbn[q];
-        }
-        ex[0] = pex[0];
-        ex[1] = pex[1];
-        if (k < k1) load_step(k + 1, pun, pbn, pex);
-        // ---- uin plane k -> LDS (rows e = 0 .. ty+3 <-> j = j0-2+e)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int r = rsub + q * rpp;
-            if (r < rows) up[(r + 1) * RL + i] = uc[q];
-        }
-        for (int e = rsub, q = 0; e < 2; e += rpp, ++q) up[(e == 0 ? 0 : ty + 3) * RL + i] = ex[q];
-        __syncthreads();
-        // ---- phase A: red update of plane k on the owned rows
-        T *wk = wp + (k & 1) * rows * RL;
-        T wn[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int r = rsub + q * rpp;
-            const int j = j0 - 1 + r;
-            T val = (T)0;
-            if (r < rows && inside(j, k)) {
-                const bool red = ((i + j + k) & 1) == 0;
-                if (zero_in) {
-                    val = red ? winv * bn[q] : (T)0;
-                } else if (red) {
-                    const T *row = up + (r + 1) * RL;
-                    T s = row[i - 1] + row[i + 1];
-                    s += (up[r * RL + i] + up[(r + 2) * RL + i]) + (um[q] + un[q]);
-                    s -= (T)6 * uc[q];
-                    val = uc[q] + winv * (bn[q] - (uc[q] - ah * s));
-                } else {
-                    val = uc[q];
+            for (int q = 0; q < Q; ++q) {
+                if (own[q]) {
+                    if (!ZI) un[q] = ld(U, roff[q], pu);
+                    bn[q] = ld(Bv, roff[q], pb);
                 }
             }
-            wn[q] = val;
-            if (r < rows) wk[r * RL + i] = val;
+            if (!ZI) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (eown[q]) ex[q] = ld(U, eoff[q], pb);
+            }
+        };
+
+        T us[4][Q], bs[4][Q], ws[4][Q], es[2][2];
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) us[sl][q] = bs[sl][q] = ws[sl][q] = (T)0;
+        es[0][0] = es[0][1] = es[1][0] = es[1][1] = (T)0;
+        // plane p lives in slot (p - (k0 - 1)) & 3 (uin, b, red field) and
+        // (p - (k0 - 1)) & 1 (outer halo rows)
+        if (!ZI) {
+            const unsigned pm = planeb(k0 - 2), pc = planeb(k0 - 1);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (own[q]) {
+                    us[3][q] = ld(U, roff[q], pm);
+                    us[0][q] = ld(U, roff[q], pc);
+                }
+            }
         }
-        __syncthreads();
-        // ---- phase B: black update of plane k-1 on rows 1..ty
-        const int kb = k - 1;
-        if (kb >= k0 && kb < k1) {
-            const T *wb = wp + (kb & 1) * rows * RL;
+        load_step(k0 - 1, us[1], bs[0], es[0]);
+
+        // one z-step on plane k, whose slot is S
+        auto step = [&](auto sc, int k) {
+            constexpr int S = decltype(sc)::value;
+            constexpr int S1 = (S + 1) & 3, S2 = (S + 2) & 3, S3 = (S + 3) & 3;
+            // Everything this step reads from memory was loaded during the
+            // previous step: wait for it here, before the next step's loads
+            // are issued (a wait placed at the first use would also wait for
+            // those, since how many are in flight depends on the row branches).
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+            __builtin_amdgcn_sched_barrier(0);
+            if (k < k1) load_step(k + 1, us[S2], bs[S1], es[(S + 1) & 1]);
+            // ---- uin plane k -> LDS (rows e = 0 .. ty+3 <-> j = j0-2+e)
+            if (!ZI) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int r = rsub + q * rpp;
+                    if (own[q]) up[(r + 1) * RL + i] = us[S][q];
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int e = rsub + q * rpp;
+                    if (eown[q]) up[(e == 0 ? 0 : ty + 3) * RL + i] = es[S & 1][q];
+                }
+            }
+            // also orders phase B of the previous step (reading the red
+            // plane buffer of k - 2) before this step's red writes into it
+            __syncthreads();
+            // ---- phase A: red update of plane k on the owned rows
+            T *wk = wp + (k & 1) * rows * RL;
+            const bool kin = k >= 1 && k <= n, kodd = (k & 1) != 0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int r = rsub + q * rpp;
-                const int j = j0 - 1 + r;
-                if (r >= 1 && r <= ty && j <= n && xin) {
-                    const T wc = wm1[q];
-                    T out = wc;
-                    if (((i + j + kb) & 1) == 1) {
-                        const T *row = wb + r * RL;
+                if (own[q]) {
+                    const bool red = kin && (kodd ? red_o[q] : red_e[q]);
+                    T val;
+                    if (ZI) {
+                        val = red ? winv * bs[S][q] : (T)0;
+                    } else {
+                        // outside the interior uc is a halo zero and stays
+                        const T uc = us[S][q];
+                        const T *row = up + (r + 1) * RL;
                         T s = row[i - 1] + row[i + 1];
-                        s += (wb[(r - 1) * RL + i] + wb[(r + 1) * RL + i]) + (wm2[q] + wn[q]);
-                        s -= (T)6 * wc;
-                        out = wc + winv * (bm1[q] - (wc - ah * s));
+                        s += (up[r * RL + i] + up[(r + 2) * RL + i]) + (us[S3][q] + us[S1][q]);
+                        s -= (T)6 * uc;
+                        const T upd = uc + winv * (bs[S][q] - (uc - ah * s));
+                        val = red ? upd : uc;
                     }
-                    O[i + j * sy + kb * sz] = out;
+                    ws[S][q] = val;
+                    wk[r * RL + i] = val;
                 }
             }
-        }
-        // ---- rotate the register windows
+            __syncthreads();
+            // ---- phase B: black update of plane k-1 on rows 1..ty
+            const int kb = k - 1;
+            if (kb >= k0 && kb < k1) {
+                const T *wb = wp + (kb & 1) * rows * RL;
+                const bool kbodd = (kb & 1) != 0;
+                T outv[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            um[q] = uc[q];
-            uc[q] = un[q];
-            wm2[q] = wm1[q];
-            wm1[q] = wn[q];
-            bm1[q] = bn[q];
+                for (int q = 0; q < Q; ++q) {
+                    const int r = rsub + q * rpp;
+                    outv[q] = (T)0;
+                    if (r >= 1 && r <= ty) {
+                        const bool black = kbodd ? red_e[q] : red_o[q];
+                        const T wc = ws[S3][q];
+                        const T *row = wb + r * RL;
+                        T s = row[i - 1] + row[i + 1];
+                        s += (wb[(r - 1) * RL + i] + wb[(r + 1) * RL + i]) + (ws[S2][q] + ws[S][q]);
+                        s -= (T)6 * wc;
+                        const T upd = wc + winv * (bs[S3][q] - (wc - ah * s));
+                        outv[q] = black ? upd : wc;
+                    }
+                }
+                if (xin) {
+                    const int ko = kb * sz;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const int r = rsub + q * rpp;
+                        const int j = j0 - 1 + r;
+                        if (r >= 1 && r <= ty && j <= n) O[i + j * sy + ko] = outv[q];
+                    }
+                }
+            }
+        };
+        for (int kk = k0 - 1; kk <= k1; kk += 4) {
+            step(std::integral_constant<int, 0>{}, kk);
+            if (kk + 1 > k1) break;
+            step(std::integral_constant<int, 1>{}, kk + 1);
+            if (kk + 2 > k1) break;
+            step(std::integral_constant<int, 2>{}, kk + 2);
+            if (kk + 3 > k1) break;
+            step(std::integral_constant<int, 3>{}, kk + 3);
         }
-    }
+    };
+    if (zero_in)
+        march(std::true_type{});
+    else
+        march(std::false_type{});
 }
 
 // Rows per thread for a launch of row width RLN and ty output rows.

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -28,6 +29,13 @@ namespace {
 // TJ coarse rows (at most 512 / RLN, so that the TJ x (RLN / 2) coarse
 // points of a plane are at most one per thread); the 2 TJ + 1 fine residual
 // rows are Q per thread.
+//
+// As in the one-pass sweep, the march has no divergent branches around its
+// loads: a thread's fine rows are wave-uniform, loads read clamped indices
+// (zero halo words outside the interior), the interior test is a select,
+// the register windows sit in slots indexed by the fine plane modulo 4 and
+// the loop is unrolled four times; every step first waits for the loads of
+// the previous step, then issues its own.
 template <typename T, int RLN, int TJ>
 __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int kch, double alpha, View<T> b,
                                                                  View<T> u, View<T> bc)
@@ -62,7 +70,7 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
     const int J0 = jt * TJ + 1, K0 = zc * kch + 1, K1 = min(K0 + kch, nc + 1);
     const int fy0 = 2 * J0 - 1;
     const int i = (int)(threadIdx.x % RLN) + 1;
-    const int rsub = (int)(threadIdx.x / RLN);
+    const int rsub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / RLN));
     const bool xin = i <= nf;
     // element offsets inside one field fit in 32 bits (n <= 255)
     const int sy = (int)row_stride(nf), sz = (int)plane_stride(nf);
@@ -73,74 +81,107 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
     // this thread's coarse point
     const int I = (int)(threadIdx.x % CX) + 1, Jl = (int)(threadIdx.x / CX), J = J0 + Jl;
     const bool cin = I <= nc && Jl < TJ && J <= nc;
+    // lanes past the row read its right halo word (zero)
+    const unsigned ib = (unsigned)min(i, nf + 1) * (unsigned)sizeof(T);
 
     // x index 0 is the boundary: zero once in every LDS row
     for (int r = threadIdx.x; r < UR + FR; r += BLOCK) up[r * RL] = (T)0;
 
-    auto inside = [&](int j, int k) { return xin && j >= 1 && j <= nf && k >= 1 && k <= nf; };
-    auto ld = [&](const T *__restrict__ a, int j, int k) -> T {
-        return inside(j, k) ? a[i + j * sy + k * sz] : (T)0;
+    // per fine row (uniform): ownership, clamped byte offset, interior lanes
+    bool own[Q], rin[Q], eown[2];
+    unsigned roff[Q], eoff[2];
+    auto rowb = [&](int j) { return (unsigned)(min(max(j, 0), nf + 1) * sy) * (unsigned)sizeof(T); };
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int r = rsub + q * RPP, j = fy0 + r;
+        own[q] = r < FR;
+        roff[q] = rowb(j);
+        rin[q] = xin && j >= 1 && j <= nf;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = rsub + q * RPP;
+        eown[q] = e < 2;
+        eoff[q] = rowb(e == 0 ? fy0 - 1 : fy0 + FR);
+    }
+    auto planeb = [&](int k) { return (unsigned)(min(max(k, 0), nf + 1) * sz) * (unsigned)sizeof(T); };
+    auto ld = [&](const T *__restrict__ a, unsigned rb, unsigned pb) -> T {
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + (rb + pb) + ib);
     };
     // loads of step kf: u plane kf + 1 and b plane kf on the residual rows,
     // u plane kf on the two halo rows
     auto load_step = [&](int kf, T (&un)[Q], T (&bn)[Q], T (&ex)[2]) {
+        const unsigned pu = planeb(kf + 1), pb = planeb(kf);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int r = rsub + q * RPP;
-            const bool own = r < FR;
-            un[q] = own ? ld(U, fy0 + r, kf + 1) : (T)0;
-            bn[q] = own ? ld(Bv, fy0 + r, kf) : (T)0;
-        }
-        ex[0] = ex[1] = (T)0;
-        for (int e = rsub, q = 0; e < 2; e += RPP, ++q) ex[q] = ld(U, e == 0 ? fy0 - 1 : fy0 + FR, kf);
+        for (int q = 0; q < Q; ++q)
+            if (own[q]) {
+                un[q] = ld(U, roff[q], pu);
+                bn[q] = ld(Bv, roff[q], pb);
+            }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (eown[q]) ex[q] = ld(U, eoff[q], pb);
     };
 
     const int kf0 = 2 * K0 - 1, kf1 = 2 * K1 - 1;
-    T um[Q], uc[Q];
+    // fine plane p lives in slot (p - kf0 + 1) & 3 (u), (p - kf0) & 1 (b,
+    // outer halo rows)
+    T us[4][Q], bs[2][Q], es[2][2];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int r = rsub + q * RPP;
-        const bool own = r < FR;
-        um[q] = own ? ld(U, fy0 + r, kf0 - 1) : (T)0;
-        uc[q] = own ? ld(U, fy0 + r, kf0) : (T)0;
+    for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) us[sl][q] = (T)0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) bs[0][q] = bs[1][q] = (T)0;
+    es[0][0] = es[0][1] = es[1][0] = es[1][1] = (T)0;
+    {
+        const unsigned pm = planeb(kf0 - 1), pc = planeb(kf0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (own[q]) {
+                us[0][q] = ld(U, roff[q], pm);
+                us[1][q] = ld(U, roff[q], pc);
+            }
     }
-    T pun[Q], pbn[Q], pex[2];
-    load_step(kf0, pun, pbn, pex);
+    load_step(kf0, us[2], bs[0], es[0]);
     const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
     T acc = (T)0;
 
-    for (int kf = kf0; kf <= kf1; ++kf) {
-        T un[Q], bn[Q], ex[2];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            un[q] = pun[q];
-            bn[q] = pbn[q];
-        }
-        ex[0] = pex[0];
-        ex[1] = pex[1];
-        if (kf < kf1) load_step(kf + 1, pun, pbn, pex);
+    // one step on fine plane kf = kf0 + 4 m + S (odd for even S)
+    auto step = [&](auto sc, int kf) {
+        constexpr int S = decltype(sc)::value;
+        constexpr int SU = (S + 1) & 3;              // slot of u plane kf
+        constexpr int SM = S & 3, SP = (S + 2) & 3, SN = (S + 3) & 3;
+        // everything this step reads from memory was loaded during the
+        // previous step: wait for it before issuing the next step's loads
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        __builtin_amdgcn_sched_barrier(0);
+        if (kf < kf1) load_step(kf + 1, us[SN], bs[(S + 1) & 1], es[(S + 1) & 1]);
         // ---- u plane kf -> LDS
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int r = rsub + q * RPP;
-            if (r < FR) up[(r + 1) * RL + i] = uc[q];
+            if (own[q]) up[(r + 1) * RL + i] = us[SU][q];
         }
-        for (int e = rsub, q = 0; e < 2; e += RPP, ++q) up[(e == 0 ? 0 : UR - 1) * RL + i] = ex[q];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = rsub + q * RPP;
+            if (eown[q]) up[(e == 0 ? 0 : UR - 1) * RL + i] = es[S & 1][q];
+        }
         __syncthreads();
         // ---- residual of the tile's fine rows -> LDS
+        const bool kin = kf >= 1 && kf <= nf;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int r = rsub + q * RPP;
-            if (r < FR) {
-                T res = (T)0;
-                if (inside(fy0 + r, kf)) {
-                    const T *row = up + (r + 1) * RL;
-                    T s = row[i - 1] + row[i + 1];
-                    s += (up[r * RL + i] + up[(r + 2) * RL + i]) + (um[q] + un[q]);
-                    s -= (T)6 * uc[q];
-                    res = bn[q] - (uc[q] - ah * s);
-                }
-                rp[r * RL + i] = res;
+            if (own[q]) {
+                const T uc = us[SU][q];
+                const T *row = up + (r + 1) * RL;
+                T s = row[i - 1] + row[i + 1];
+                s += (up[r * RL + i] + up[(r + 2) * RL + i]) + (us[SM][q] + us[SP][q]);
+                s -= (T)6 * uc;
+                const T res = bs[S & 1][q] - (uc - ah * s);
+                rp[r * RL + i] = (kin && rin[q]) ? res : (T)0;
             }
         }
         __syncthreads();
@@ -152,7 +193,7 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
                 const T *row = rp + (2 * Jl + 1 + bq) * RL + 2 * I;
                 s += w[bq + 1] * ((w[0] * row[-1] + w[1] * row[0]) + w[2] * row[1]);
             }
-            if (kf & 1) {
+            if ((S & 1) == 0) {
                 // fine plane 2K + 1 closes coarse plane K = (kf - 1) / 2 and
                 // opens K + 1
                 if (kf > kf0) C[(long)I + (long)J * syc + (long)((kf - 1) / 2) * szc] = acc + w[2] * s;
@@ -161,12 +202,15 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
                 acc += w[1] * s;
             }
         }
-        // ---- rotate the register windows
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            um[q] = uc[q];
-            uc[q] = un[q];
-        }
+    };
+    for (int kk = kf0; kk <= kf1; kk += 4) {
+        step(std::integral_constant<int, 0>{}, kk);
+        if (kk + 1 > kf1) break;
+        step(std::integral_constant<int, 1>{}, kk + 1);
+        if (kk + 2 > kf1) break;
+        step(std::integral_constant<int, 2>{}, kk + 2);
+        if (kk + 3 > kf1) break;
+        step(std::integral_constant<int, 3>{}, kk + 3);
     }
 }
 

@@ -7,7 +7,7 @@
 //
 // A workgroup owns full x-rows, TY output rows and a chunk of z planes and
 // marches upwards in z.  At step k the rows j0-1 .. j0+TY of plane k go into
-// one of three LDS buffers and the output is computed on plane k-1 from the
+// one of four LDS buffers and the output is computed on plane k-1 from the
 // x and y neighbours in LDS and the z neighbours in registers; u is read
 // once (plus the halo rows that neighbouring tiles also read) and the output
 // written once.  The loads of step k + 1 are issued before step k's
@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -26,6 +27,12 @@ constexpr int TY = 4;   // output rows per workgroup
 
 // RLN: x lanes per row; Q = ceil((TY + 2) / (BLOCK / RLN)) rows per thread.
 // JAC: Jacobi sweep (b read, c = alpha, omega given) instead of F = c L u.
+//
+// The march has no divergent branches around its loads: a thread's rows
+// are wave-uniform, loads read clamped indices (zero halo words outside the
+// interior), the u planes sit in register slots and LDS buffers indexed by
+// the plane modulo 4 and the loop is unrolled four times; every step first
+// waits for the loads of the previous step, then issues its own.
 template <typename T, int RLN, int Q, bool JAC>
 __global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, double c, double omega, View<T> b,
                                                           View<T> u, View<T> F)
@@ -35,7 +42,7 @@ __global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, 
     constexpr int ROWS = TY + 2;             // rows j0-1 .. j0+TY
     static_assert(Q * RPP >= ROWS, "rows per thread");
     extern __shared__ unsigned char smem_raw[];
-    T *lp = reinterpret_cast<T *>(smem_raw);             // 3 planes of ROWS rows
+    T *lp = reinterpret_cast<T *>(smem_raw);             // 4 planes of ROWS rows
 
     unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
     Pt qs;
@@ -57,82 +64,101 @@ __global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, 
     const int j0 = jt * TY + 1, k0 = zc * zchunk + 1;
     const int k1 = min(k0 + zchunk, n + 1);  // F on planes k0 .. k1-1
     const int i = (int)(threadIdx.x % RLN) + 1;
-    const int rsub = (int)(threadIdx.x / RLN);
+    const int rsub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / RLN));
     const bool xin = i <= n;
     // element offsets inside one field fit in 32 bits (n <= 255)
     const int sy = (int)row_stride(n), sz = (int)plane_stride(n);
     const T *__restrict__ U = fp(u, qs);
     const T *__restrict__ Bv = JAC ? fp(b, qs) : nullptr;
     T *__restrict__ Fo = fp(F, qs);
+    // lanes past the row read its right halo word (zero)
+    const unsigned ib = (unsigned)min(i, n + 1) * (unsigned)sizeof(T);
 
-    for (int r = threadIdx.x; r < 3 * ROWS; r += BLOCK) lp[r * RL] = (T)0;
+    for (int r = threadIdx.x; r < 4 * ROWS; r += BLOCK) lp[r * RL] = (T)0;
 
-    auto inside = [&](int j, int k) { return xin && j >= 1 && j <= n && k >= 1 && k <= n; };
-    // pu: u plane k + 1 (prefetched); pb: b plane k, used at step k + 1
-    T pu[Q], pb[Q], bk[Q];
+    // per row (uniform): ownership, clamped byte offset
+    bool own[Q];
+    unsigned roff[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int r = rsub + q * RPP, j = j0 - 1 + r;
-        pu[q] = (r < ROWS && inside(j, k0 - 1)) ? U[i + j * sy + (k0 - 1) * sz] : (T)0;
-        pb[q] = bk[q] = (T)0;
+        own[q] = r < ROWS;
+        roff[q] = (unsigned)(min(max(j, 0), n + 1) * sy) * (unsigned)sizeof(T);
     }
-    T wm2[Q], wm1[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) wm2[q] = wm1[q] = (T)0;
+    auto planeb = [&](int k) { return (unsigned)(min(max(k, 0), n + 1) * sz) * (unsigned)sizeof(T); };
+    auto ld = [&](const T *__restrict__ a, unsigned rb, unsigned pb) -> T {
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + (rb + pb) + ib);
+    };
 
-    for (int k = k0 - 1; k <= k1; ++k) {
-        T uk[Q];
+    // u plane p in slot (p - (k0 - 1)) & 3, b plane p in (p - (k0 - 1)) & 1
+    T us[4][Q], bs[2][Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            uk[q] = pu[q];
-            bk[q] = pb[q];   // b on plane k - 1
-        }
+    for (int q = 0; q < Q; ++q) {
+        us[0][q] = us[1][q] = us[2][q] = us[3][q] = (T)0;
+        bs[0][q] = bs[1][q] = (T)0;
+    }
+    {
+        const unsigned p0 = planeb(k0 - 1);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (own[q]) us[0][q] = ld(U, roff[q], p0);
+    }
+
+    // one step on plane k (slot S): u plane k to LDS, output on plane k - 1
+    auto step = [&](auto sc, int k) {
+        constexpr int S = decltype(sc)::value;
+        constexpr int S1 = (S + 1) & 3, S2 = (S + 2) & 3, S3 = (S + 3) & 3;
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the previous step's loads
+        __builtin_amdgcn_sched_barrier(0);
         if (k < k1) {
+            const unsigned pu = planeb(k + 1), pb = planeb(k);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const int r = rsub + q * RPP, j = j0 - 1 + r;
-                pu[q] = (r < ROWS && inside(j, k + 1)) ? U[i + j * sy + (k + 1) * sz] : (T)0;
-                if (JAC) pb[q] = (r >= 1 && r <= TY && inside(j, k)) ? Bv[i + j * sy + k * sz] : (T)0;
+                const int r = rsub + q * RPP;
+                if (own[q]) us[S1][q] = ld(U, roff[q], pu);
+                if (JAC && r >= 1 && r <= TY) bs[S & 1][q] = ld(Bv, roff[q], pb);
             }
         }
-        // ---- u plane k -> LDS
-        T wn[Q];
-        T *buf = lp + (k % 3 + 3) % 3 * ROWS * RL;
+        // ---- u plane k -> LDS (4 buffers: plane k-1's buffer is not
+        // rewritten before every thread has passed the next barrier)
+        T *buf = lp + S * ROWS * RL;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int r = rsub + q * RPP, j = j0 - 1 + r;
-            const T v = (r < ROWS && inside(j, k)) ? uk[q] : (T)0;
-            wn[q] = v;
-            if (r < ROWS) buf[r * RL + i] = v;
+            const int r = rsub + q * RPP;
+            if (own[q]) buf[r * RL + i] = us[S][q];
         }
         __syncthreads();
-        // ---- F on plane k-1 (three LDS buffers: plane k-1's buffer is not
-        // rewritten before every thread has passed the next barrier)
+        // ---- output on plane k-1
         const int kb = k - 1;
-        if (kb >= k0 && kb < k1) {
-            const T *bb = lp + (kb % 3 + 3) % 3 * ROWS * RL;
+        if (kb >= k0 && kb < k1 && xin) {
+            const T *bb = lp + S3 * ROWS * RL;
+            const int ko = kb * sz;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int r = rsub + q * RPP, j = j0 - 1 + r;
-                if (r >= 1 && r <= TY && j <= n && xin) {
+                if (r >= 1 && r <= TY && j <= n) {
                     const T *row = bb + r * RL;
                     T s = row[i - 1] + row[i + 1];
-                    s += (bb[(r - 1) * RL + i] + bb[(r + 1) * RL + i]) + (wm2[q] + wn[q]);
-                    s -= (T)6 * wm1[q];
+                    s += (bb[(r - 1) * RL + i] + bb[(r + 1) * RL + i]) + (us[S2][q] + us[S][q]);
+                    s -= (T)6 * us[S3][q];
                     if (JAC) {
-                        const T res = bk[q] - (wm1[q] - ah * s);
-                        Fo[i + j * sy + kb * sz] = wm1[q] + winv * res;
+                        const T res = bs[(S + 1) & 1][q] - (us[S3][q] - ah * s);
+                        Fo[i + j * sy + ko] = us[S3][q] + winv * res;
                     } else {
-                        Fo[i + j * sy + kb * sz] = (T)(cc * (ih2 * (double)s));
+                        Fo[i + j * sy + ko] = (T)(cc * (ih2 * (double)s));
                     }
                 }
             }
         }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            wm2[q] = wm1[q];
-            wm1[q] = wn[q];
-        }
+    };
+    for (int kk = k0 - 1; kk <= k1; kk += 4) {
+        step(std::integral_constant<int, 0>{}, kk);
+        if (kk + 1 > k1) break;
+        step(std::integral_constant<int, 1>{}, kk + 1);
+        if (kk + 2 > k1) break;
+        step(std::integral_constant<int, 2>{}, kk + 2);
+        if (kk + 3 > k1) break;
+        step(std::integral_constant<int, 3>{}, kk + 3);
     }
 }
 
@@ -173,7 +199,7 @@ hipError_t stencil_z(const Tiling &t, double c, double omega, View<T> b, View<T>
         blocks += (long)t.seg_count(sg) * ((n + TY - 1) / TY) * ((n + zchunk - 1) / zchunk);
     }
     const int rln = nmax <= 64 ? 64 : nmax <= 128 ? 128 : 256;
-    const size_t lds = (size_t)3 * (TY + 2) * (rln + 2) * sizeof(T);
+    const size_t lds = (size_t)4 * (TY + 2) * (rln + 2) * sizeof(T);
     const dim3 g((unsigned)blocks), blk(BLOCK);
     if (rln == 64) return launch(stencil_z_kernel<T, 64, 2, JAC>, g, blk, lds, s, t, zchunk, c, omega, b, u, F);
     if (rln == 128) return launch(stencil_z_kernel<T, 128, 3, JAC>, g, blk, lds, s, t, zchunk, c, omega, b, u, F);

@@ -135,10 +135,13 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_kernel(Tiling t, double 
     T acc = 0;
     if (DIM == 3) {
         const long f = 2L * I + 2L * J * sy + 2L * K * sz;
+        // one fine plane at a time: its nine residuals' loads issue together
         for (int c = -1; c <= 1; ++c)
+#pragma unroll
             for (int bq = -1; bq <= 1; ++bq) {
                 const T wzy = w[c + 1] * w[bq + 1];
                 T row = 0;
+#pragma unroll
                 for (int a = -1; a <= 1; ++a) {
                     const long o = f + a + bq * sy + c * sz;
                     const T res = bb[o] - (uu[o] - ah * d2sum<3>(uu, o, sy, sz));
@@ -241,6 +244,9 @@ __global__ void coarsest_kernel(Tiling t, double alpha, View<T> b, View<T> u)
 // Same arithmetic as the point kernels; a thread owns KZ planes of one
 // (i, j) column and issues every load before its stores (several KB in
 // flight per wavefront; one point per thread leaves HBM latency-bound).
+// Loads are not guarded by the column length: a short column (top chunk)
+// repeats its last plane, so every load issues at once without branches
+// and only the stores are guarded.
 constexpr int KZ = 4;
 
 // col[w] = u at plane k0-1+w, w = 0 .. nk+1 (planes 0 and n+1 are halo zeros)
@@ -248,7 +254,7 @@ template <typename T>
 __device__ inline void load_col(const T *__restrict__ u, long o, long sz, int nk, T (&col)[KZ + 2])
 {
 #pragma unroll
-    for (int w = 0; w < KZ + 2; ++w) col[w] = w <= nk + 1 ? u[o + (long)(w - 1) * sz] : (T)0;
+    for (int w = 0; w < KZ + 2; ++w) col[w] = u[o + (long)(min(w, nk + 1) - 1) * sz];
 }
 
 template <typename T>
@@ -256,11 +262,9 @@ __device__ inline void load_xy(const T *__restrict__ u, long o, long sy, long sz
 {
 #pragma unroll
     for (int w = 0; w < KZ; ++w) {
-        if (w < nk) {
-            const long c = o + (long)w * sz;
-            xs[w] = u[c - 1] + u[c + 1];
-            ys[w] = u[c - sy] + u[c + sy];
-        }
+        const long c = o + (long)min(w, nk - 1) * sz;
+        xs[w] = u[c - 1] + u[c + 1];
+        ys[w] = u[c - sy] + u[c + sy];
     }
 }
 
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(BLOCK) void resid_kz_kernel(Tiling t, double alpha,
     load_col(uu, o, sz, nk, col);
     load_xy(uu, o, sy, sz, nk, xs, ys);
 #pragma unroll
-    for (int w = 0; w < KZ; ++w) if (w < nk) bv[w] = bb[o + (long)w * sz];
+    for (int w = 0; w < KZ; ++w) bv[w] = bb[o + (long)min(w, nk - 1) * sz];
 #pragma unroll
     for (int w = 0; w < KZ; ++w)
         if (w < nk) rr[o + (long)w * sz] = (TO)(bv[w] - (col[w + 1] - ah * d2_of(col, xs, ys, w)));
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(BLOCK) void jacobi_kz_kernel(Tiling t, double alpha
     load_col(uu, o, sz, nk, col);
     load_xy(uu, o, sy, sz, nk, xs, ys);
 #pragma unroll
-    for (int w = 0; w < KZ; ++w) if (w < nk) bv[w] = bb[o + (long)w * sz];
+    for (int w = 0; w < KZ; ++w) bv[w] = bb[o + (long)min(w, nk - 1) * sz];
 #pragma unroll
     for (int w = 0; w < KZ; ++w) {
         if (w < nk) {
@@ -320,6 +324,11 @@ __global__ __launch_bounds__(BLOCK) void jacobi_kz_kernel(Tiling t, double alpha
 
 // u += P ec: the d-linear value at fine (i, j, k) is the z-average of the
 // bilinear values of coarse planes k>>1 and (k+1)>>1 (one plane when k even).
+// Every load is issued before any arithmetic, without branches around
+// them: the four coarse values of each touched plane (the two x and the
+// two y neighbours coincide on an even axis; planes past the top are
+// clamped to the zero halo plane) and the KZ fine values (repeated from
+// the last plane of a short column); the parities pick with selects.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void prolong_kz_kernel(Tiling t, View<T> ec, View<T> u)
 {
@@ -328,27 +337,29 @@ __global__ __launch_bounds__(BLOCK) void prolong_kz_kernel(Tiling t, View<T> ec,
     const int nc = coarser(q.n);
     const T *__restrict__ e = fp(ec, q);
     T *__restrict__ uu = fp(u, q);
-    const long csy = row_stride(nc), csz = plane_stride(nc), sz = plane_stride(q.n);
+    const int csy = (int)row_stride(nc), csz = (int)plane_stride(nc), sz = (int)plane_stride(q.n);
     const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1;
     const int c0 = k0 >> 1;                       // first coarse plane touched
     constexpr int NCP = KZ / 2 + 2;               // coarse planes touched by KZ fine planes
-    T pv[NCP], uv[KZ];
+    const bool ox = (i & 1) != 0, oy = (j & 1) != 0;
+    T c00[NCP], c01[NCP], c10[NCP], c11[NCP], uv[KZ];
 #pragma unroll
     for (int cq = 0; cq < NCP; ++cq) {
-        const int kk = c0 + cq;
-        T v = (T)0;
-        if (kk <= nc + 1) {
-            const long ob = (long)kk * csz;
-            auto rowv = [&](int jj) -> T {
-                const long orow = ob + (long)jj * csy;
-                return (i & 1) ? (T)0.5 * (e[orow + i0] + e[orow + i1]) : e[orow + i0];
-            };
-            v = (j & 1) ? (T)0.5 * (rowv(j0) + rowv(j1)) : rowv(j0);
-        }
-        pv[cq] = v;
+        const int ob = min(c0 + cq, nc + 1) * csz;
+        c00[cq] = e[ob + j0 * csy + i0];
+        c01[cq] = e[ob + j0 * csy + i1];
+        c10[cq] = e[ob + j1 * csy + i0];
+        c11[cq] = e[ob + j1 * csy + i1];
     }
 #pragma unroll
-    for (int w = 0; w < KZ; ++w) if (w < nk) uv[w] = uu[o + (long)w * sz];
+    for (int w = 0; w < KZ; ++w) uv[w] = uu[o + (long)min(w, nk - 1) * sz];
+    T pv[NCP];
+#pragma unroll
+    for (int cq = 0; cq < NCP; ++cq) {
+        const T r0 = ox ? (T)0.5 * (c00[cq] + c01[cq]) : c00[cq];
+        const T r1 = ox ? (T)0.5 * (c10[cq] + c11[cq]) : c10[cq];
+        pv[cq] = oy ? (T)0.5 * (r0 + r1) : r0;
+    }
 #pragma unroll
     for (int w = 0; w < KZ; ++w) {
         if (w < nk) {
@@ -370,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void copy_kz_kernel(Tiling t, View<T> src, V
     T *__restrict__ d = fp(dst, q);
     T v[KZ];
 #pragma unroll
-    for (int w = 0; w < KZ; ++w) if (w < nk) v[w] = a[o + (long)w * sz];
+    for (int w = 0; w < KZ; ++w) v[w] = a[o + (long)min(w, nk - 1) * sz];
 #pragma unroll
     for (int w = 0; w < KZ; ++w) if (w < nk) d[o + (long)w * sz] = v[w];
 }
@@ -386,10 +397,8 @@ __global__ __launch_bounds__(BLOCK) void add_f32_kz_kernel(Tiling t, View<float>
     float ev[KZ];
 #pragma unroll
     for (int w = 0; w < KZ; ++w) {
-        if (w < nk) {
-            uv[w] = uu[o + (long)w * sz];
-            ev[w] = ee[o + (long)w * sz];
-        }
+        uv[w] = uu[o + (long)min(w, nk - 1) * sz];
+        ev[w] = ee[o + (long)min(w, nk - 1) * sz];
     }
 #pragma unroll
     for (int w = 0; w < KZ; ++w) if (w < nk) uu[o + (long)w * sz] = uv[w] + (double)ev[w];

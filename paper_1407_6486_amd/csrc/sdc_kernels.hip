@@ -52,16 +52,15 @@ __global__ __launch_bounds__(BLOCK) void apply_L_kz_kernel(Tiling t, double c, V
     double *__restrict__ ff = fp(F, q);
     const double ih2 = (double)(q.n + 1) * (double)(q.n + 1);
     const double cc = q.par(c);
+    // every load unguarded (a short column repeats its last plane)
     double col[KZ + 2], xs[KZ], ys[KZ];
 #pragma unroll
-    for (int w = 0; w < KZ + 2; ++w) col[w] = w <= nk + 1 ? uu[o + (long)(w - 1) * sz] : 0.0;
+    for (int w = 0; w < KZ + 2; ++w) col[w] = uu[o + (long)(min(w, nk + 1) - 1) * sz];
 #pragma unroll
     for (int w = 0; w < KZ; ++w) {
-        if (w < nk) {
-            const long ow = o + (long)w * sz;
-            xs[w] = uu[ow - 1] + uu[ow + 1];
-            ys[w] = uu[ow - sy] + uu[ow + sy];
-        }
+        const long ow = o + (long)min(w, nk - 1) * sz;
+        xs[w] = uu[ow - 1] + uu[ow + 1];
+        ys[w] = uu[ow - sy] + uu[ow + sy];
     }
 #pragma unroll
     for (int w = 0; w < KZ; ++w) {
@@ -103,8 +102,13 @@ __global__ __launch_bounds__(BLOCK) void sdc_rhs_kernel(Tiling t, double delta, 
 {
     Pt q; int i, j, k; long o;
     if (!tile_point<DIM>(t, q, i, j, k, o)) return;
-    double v = fp(Um, q)[o] - q.par(delta) * fp(Fm1, q)[o] + fp(Im, q)[o];
-    if (t1.p) v = v + (fp(t1, q)[o] - fp(t0, q)[o]);
+    // every load first (without t1 the difference reads Um twice, unused)
+    const bool ht = t1.p != nullptr;
+    const double *um = fp(Um, q);
+    const double um_v = um[o], fm = fp(Fm1, q)[o], im = fp(Im, q)[o];
+    const double x1 = (ht ? fp(t1, q) : um)[o], x0 = (ht ? fp(t0, q) : um)[o];
+    double v = um_v - q.par(delta) * fm + im;
+    if (ht) v = v + (x1 - x0);
     fp(b, q)[o] = v;
 }
 
@@ -118,12 +122,17 @@ __global__ __launch_bounds__(BLOCK) void solve_F_rhs_kernel(Tiling t, double del
 {
     Pt q; int i, j, k; long o;
     if (!tile_point<DIM>(t, q, i, j, k, o)) return;
-    const double u = fp(U, q)[o];
+    // every load before the first store (absent arrays read U, unused)
+    const double *uu = fp(U, q);
     double *bb = fp(B, q);
-    fp(F, q)[o] = (u - bb[o]) / q.par(delta);
-    if (!Fn1.p) return;
-    double v = u - q.par(delta_next) * fp(Fn1, q)[o] + fp(In, q)[o];
-    if (t1.p) v = v + (fp(t1, q)[o] - fp(t0, q)[o]);
+    const bool hn = Fn1.p != nullptr, ht = t1.p != nullptr;
+    const double u = uu[o], bo = bb[o];
+    const double fn = (hn ? fp(Fn1, q) : uu)[o], in = (hn ? fp(In, q) : uu)[o];
+    const double x1 = (hn && ht ? fp(t1, q) : uu)[o], x0 = (hn && ht ? fp(t0, q) : uu)[o];
+    fp(F, q)[o] = (u - bo) / q.par(delta);
+    if (!hn) return;
+    double v = u - q.par(delta_next) * fn + in;
+    if (ht) v = v + (x1 - x0);
     bb[o] = v;
 }
 
@@ -143,7 +152,13 @@ __global__ __launch_bounds__(BLOCK) void sdc_start_kernel(Tiling t, int nn_rt, d
     const double h = q.par(dt);
     double *u = fp(U, q) + o;
     double *f = fp(F, q) + o;
+    // every load before the first store: the other nodes' F and tau (read
+    // from F when absent, unused) first, then node 0
+    const bool ht = tau.p != nullptr;
+    const double *tb = ht ? fp(tau, q) + o : f;
     double fv[MAXN];
+    for (int w = 1; w < nn; ++w) fv[w] = f[w * f_node];
+    const double t_hi = tb[f_node], t_lo = tb[0];
     double u0;
     if (Usrc.p) {
         const double *us = fp(Usrc, q);
@@ -159,7 +174,6 @@ __global__ __launch_bounds__(BLOCK) void sdc_start_kernel(Tiling t, int nn_rt, d
         u0 = u[0];
         fv[0] = f[0];
     }
-    for (int w = 1; w < nn; ++w) fv[w] = f[w * f_node];
     if (Usrc.p) {
         u[0] = u0;
         f[0] = fv[0];
@@ -174,7 +188,7 @@ __global__ __launch_bounds__(BLOCK) void sdc_start_kernel(Tiling t, int nn_rt, d
         if (m == 0) i0 = v;
     }
     double v = u0 - q.par(delta1) * fv[1] + i0;
-    if (tau.p) v = v + (fp(tau, q)[o + f_node] - fp(tau, q)[o]);
+    if (ht) v = v + (t_hi - t_lo);
     fp(b, q)[o] = v;
 }
 
@@ -195,19 +209,29 @@ __global__ __launch_bounds__(BLOCK) void apply_L_rhs_kz_kernel(Tiling t, double 
     double *__restrict__ bb = fp(b, q);
     const double ih2 = (double)(q.n + 1) * (double)(q.n + 1);
     const double cc = q.par(c), dl = q.par(delta);
-    double col[KZ + 2], xs[KZ], ys[KZ], rv[KZ];
+    // every load unguarded (a short column repeats its last plane; without
+    // t1 the difference reads u twice and is not added)
+    const bool ht = t1.p != nullptr;
+    const double *__restrict__ a1 = ht ? fp(t1, q) : uu;
+    const double *__restrict__ a0 = ht ? fp(t0, q) : uu;
+    double col[KZ + 2], xs[KZ], ys[KZ], rv[KZ], fv[KZ], iv[KZ], x1[KZ], x0[KZ];
 #pragma unroll
-    for (int w = 0; w < KZ + 2; ++w) col[w] = w <= nk + 1 ? uu[o + (long)(w - 1) * sz] : 0.0;
+    for (int w = 0; w < KZ + 2; ++w) col[w] = uu[o + (long)(min(w, nk + 1) - 1) * sz];
 #pragma unroll
     for (int w = 0; w < KZ; ++w) {
-        if (w < nk) {
-            const long ow = o + (long)w * sz;
-            xs[w] = uu[ow - 1] + uu[ow + 1];
-            ys[w] = uu[ow - sy] + uu[ow + sy];
-            double v = col[w + 1] - dl * fn[ow] + in[ow];
-            if (t1.p) v = v + (fp(t1, q)[ow] - fp(t0, q)[ow]);
-            rv[w] = v;
-        }
+        const long ow = o + (long)min(w, nk - 1) * sz;
+        xs[w] = uu[ow - 1] + uu[ow + 1];
+        ys[w] = uu[ow - sy] + uu[ow + sy];
+        fv[w] = fn[ow];
+        iv[w] = in[ow];
+        x1[w] = a1[ow];
+        x0[w] = a0[ow];
+    }
+#pragma unroll
+    for (int w = 0; w < KZ; ++w) {
+        double v = col[w + 1] - dl * fv[w] + iv[w];
+        if (ht) v = v + (x1[w] - x0[w]);
+        rv[w] = v;
     }
 #pragma unroll
     for (int w = 0; w < KZ; ++w) {
@@ -241,18 +265,25 @@ __global__ __launch_bounds__(BLOCK) void fas_inject_kernel(Tiling t, int nnf_rt,
     const long fo = DIM == 3 ? 2L * I + 2L * J * row_stride(nf) + 2L * K * plane_stride(nf) : 2L * I;
     const double *uf = fp(Uf, q) + fo;
     const double *ff = fp(Ff, q) + fo;
-    double fv[MAXN];
+    // every load before the first store (the finer tau read from F when
+    // absent, unused)
+    double fv[MAXN], uv[MAXN], tv[MAXN];
     for (int w = 0; w < nnf; ++w) fv[w] = ff[w * f_node];
     double *uc = fp(Uc, q) + o, *uo = fp(Uold, q) + o, *ta = fp(Tau, q) + o;
-    const double *tf = Tauf.p ? fp(Tauf, q) + fo : nullptr;
+    const bool htf = Tauf.p != nullptr;
+    const double *tf = htf ? fp(Tauf, q) + fo : ff;
     for (int mc = 0; mc < nnc; ++mc) {
         const int mf = cmap.v[mc];
-        const double v = uf[mf * f_node];
-        uc[mc * c_node] = v;
-        uo[mc * c_node] = v;
+        uv[mc] = uf[mf * f_node];
+        tv[mc] = tf[mf * f_node];
+    }
+    for (int mc = 0; mc < nnc; ++mc) {
+        const int mf = cmap.v[mc];
+        uc[mc * c_node] = uv[mc];
+        uo[mc * c_node] = uv[mc];
         double acc = 0.0;
         for (int w = 0; w < nnf; ++w) acc += Qf[mf * nnf + w] * fv[w];
-        ta[mc * c_node] = tf ? h * acc + tf[mf * f_node] : h * acc;
+        ta[mc * c_node] = htf ? h * acc + tv[mc] : h * acc;
     }
 }
 

@@ -59,32 +59,58 @@ __device__ inline Dom domain(int mode, int nin, int nout, int cls)
 
 constexpr int MB = 4;   // 16-voxel groups per wavefront
 
+// Quotient t / d (t < 2^31) from a double reciprocal of d: the product is
+// within one of the quotient, so one correction each way makes it exact.
+__device__ inline unsigned udiv(unsigned t, unsigned d, double inv)
+{
+    unsigned q = (unsigned)((double)t * inv);
+    q = q * d > t ? q - 1 : q;
+    q = (q + 1) * d <= t ? q + 1 : q;
+    return q;
+}
+
+// Flat index v of the M domain -> (sample, z, y, x).
+struct Dec {
+    unsigned cx, cy, cz;
+    double ix, iy, iz;
+    __device__ void operator()(unsigned v, int &s, int &z, int &y, int &x) const
+    {
+        const unsigned q1 = udiv(v, cx, ix), q2 = udiv(q1, cy, iy), q3 = udiv(q2, cz, iz);
+        x = (int)(v - q1 * cx);
+        y = (int)(q1 - q2 * cy);
+        z = (int)(q2 - q3 * cz);
+        s = (int)q3;
+    }
+};
+
+// cb_shift: log2 of the 8-channel blocks of the input (1, 2, 4 or 8 blocks).
+// Every load of a K step is issued unconditionally (a group past the end
+// reads tap 0 of block 0, an A row past the end its first voxel, and the
+// value is replaced by zero), and the loads of step ks + 1 are issued
+// before the MFMAs of step ks.
 template <int MODE, int NT>
-__global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_count, Act out, const bf16 *__restrict__ W,
+__global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_shift, Act out, const bf16 *__restrict__ W,
                                                    const float *__restrict__ bias, int relu, int batch)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nin = in.n, nout = out.n;
     constexpr int cout = NT * 16;
+    const int cb_count = 1 << cb_shift;
     const Dom D = domain(MODE, nin, nout, blockIdx.y);
-    const long total = (long)batch * D.cz * D.cy * D.cx;
-    const long vblk = (long)blockIdx.x * 64 * MB;
+    const unsigned total = (unsigned)batch * (unsigned)(D.cz * D.cy * D.cx);
+    const unsigned vblk = blockIdx.x * 64u * MB;
     if (vblk >= total) return;
+    const Dec dec{(unsigned)D.cx, (unsigned)D.cy, (unsigned)D.cz, 1.0 / D.cx, 1.0 / D.cy, 1.0 / D.cz};
     const long m = nin + 2;
     // this lane's A row (voxel) in each of the wavefront's MB groups
     const bf16 *xin[MB];
     bool a_ok[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-        const long va = vblk + (wave * MB + mb) * 16 + (lane & 15);
+        const unsigned va = vblk + (wave * MB + mb) * 16 + (lane & 15);
         a_ok[mb] = va < total;
-        long t = a_ok[mb] ? va : 0;
-        const int ix = (int)(t % D.cx);
-        t /= D.cx;
-        const int iy = (int)(t % D.cy);
-        t /= D.cy;
-        const int iz = (int)(t % D.cz);
-        const int s = (int)(t / D.cz);
+        int s, iz, iy, ix;
+        dec(a_ok[mb] ? va : 0u, s, iz, iy, ix);
         int bz, by, bx;   // input point (halo'd) of tap offset 0
         if (MODE == SAME) {
             bz = iz + 1; by = iy + 1; bx = ix + 1;
@@ -97,70 +123,85 @@ __global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_count, Act out
         xin[mb] = in.p + vox(nin, s, bz, by, bx) * in.cs;
     }
     const int ntap = MODE == UP ? (1 << (D.pz + D.py + D.px)) : 27;
-    const int groups = ntap * cb_count;
+    const int groups = ntap << cb_shift;
     const int ksteps = (groups + 3) >> 2;
     const int cin8 = cb_count * 8;
     const int kg = lane >> 4;
+    // the A and B fragments of K step ks
+    auto load = [&](int ks, bf16x8 (&a)[MB], bf16x8 (&bw)[NT], bool &gok) {
+        const int g = ks * 4 + kg;
+        gok = g < groups;
+        const int gg = gok ? g : 0;
+        const int t = gg >> cb_shift, cb = gg & (cb_count - 1);
+        int oz, oy, ox, tapw;
+        if (MODE == UP) {
+            int bit = 0, wz = 0, wy = 0, wx = 0;
+            oz = oy = ox = 0;
+            if (D.pz) { const int sel = (t >> bit++) & 1; wz = sel ? -1 : 1; oz = sel; }
+            if (D.py) { const int sel = (t >> bit++) & 1; wy = sel ? -1 : 1; oy = sel; }
+            if (D.px) { const int sel = (t >> bit++) & 1; wx = sel ? -1 : 1; ox = sel; }
+            tapw = (wz + 1) * 9 + (wy + 1) * 3 + (wx + 1);
+        } else {
+            oz = t / 9 - 1;
+            oy = (t / 3) % 3 - 1;
+            ox = t % 3 - 1;
+            tapw = t;
+        }
+        const long aoff = (((long)oz * m + oy) * m + ox) * in.cs + cb * 8;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) a[mb] = *reinterpret_cast<const bf16x8 *>(xin[mb] + aoff);
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+            bw[q] = *reinterpret_cast<const bf16x8 *>(W + ((long)tapw * cout + q * 16 + (lane & 15)) * cin8 + cb * 8);
+    };
     f4 acc[MB][NT];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[mb][q] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < ksteps; ++ks) {
-        const int g = ks * 4 + kg;
-        const bool gok = g < groups;
-        long aoff = 0;
-        int tapw = 0, cb = 0;
-        if (gok) {
-            const int t = g / cb_count;
-            cb = g - t * cb_count;
-            int oz, oy, ox;
-            if (MODE == UP) {
-                int bit = 0, wz = 0, wy = 0, wx = 0;
-                oz = oy = ox = 0;
-                if (D.pz) { const int sel = (t >> bit++) & 1; wz = sel ? -1 : 1; oz = sel; }
-                if (D.py) { const int sel = (t >> bit++) & 1; wy = sel ? -1 : 1; oy = sel; }
-                if (D.px) { const int sel = (t >> bit++) & 1; wx = sel ? -1 : 1; ox = sel; }
-                tapw = (wz + 1) * 9 + (wy + 1) * 3 + (wx + 1);
-            } else {
-                oz = t / 9 - 1;
-                oy = (t / 3) % 3 - 1;
-                ox = t % 3 - 1;
-                tapw = t;
-            }
-            aoff = (((long)oz * m + oy) * m + ox) * in.cs + cb * 8;
-        }
-        bf16x8 a[MB], bw[NT];
+    auto mma = [&](const bf16x8 (&a)[MB], const bf16x8 (&bw)[NT], bool gok) {
+        bf16x8 az[MB];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            a[mb] = bf16x8{};
-            if (gok && a_ok[mb]) a[mb] = *reinterpret_cast<const bf16x8 *>(xin[mb] + aoff);
-        }
-#pragma unroll
-        for (int q = 0; q < NT; ++q) {
-            bw[q] = bf16x8{};
-            if (gok)
-                bw[q] = *reinterpret_cast<const bf16x8 *>(W + ((long)tapw * cout + q * 16 + (lane & 15)) * cin8 + cb * 8);
-        }
+        for (int mb = 0; mb < MB; ++mb) az[mb] = (gok && a_ok[mb]) ? a[mb] : bf16x8{};
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-            for (int q = 0; q < NT; ++q) acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bw[q], acc[mb][q], 0, 0, 0);
+            for (int q = 0; q < NT; ++q)
+                acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(az[mb], gok ? bw[q] : bf16x8{}, acc[mb][q], 0, 0, 0);
+    };
+    bf16x8 a0[MB], b0[NT], a1[MB], b1[NT];
+    bool g0, g1;
+    load(0, a0, b0, g0);
+    for (int ks = 0; ks < ksteps; ks += 2) {
+        // the last step's prefetch reads a group past the end (clamped)
+        load(ks + 1, a1, b1, g1);
+        mma(a0, b0, g0);
+        if (ks + 1 >= ksteps) break;
+        load(ks + 2, a0, b0, g0);
+        mma(a1, b1, g1);
     }
+    float bq[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) bq[q] = bias ? bias[q * 16 + (lane & 15)] : 0.f;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-        const long v0 = vblk + (wave * MB + mb) * 16;
+        const unsigned v0 = vblk + (wave * MB + mb) * 16 + 4 * (lane >> 4);
+        if (v0 >= total) continue;
+        int os, oz, oy, ox;
+        dec(v0, os, oz, oy, ox);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const long v = v0 + 4 * (lane >> 4) + t;
-            if (v >= total) continue;
-            long u = v;
-            const int ox = (int)(u % D.cx);
-            u /= D.cx;
-            const int oy = (int)(u % D.cy);
-            u /= D.cy;
-            const int oz = (int)(u % D.cz);
-            const int os = (int)(u / D.cz);
+            if (t > 0) {
+                // the next voxel in the flat order
+                if (++ox == D.cx) {
+                    ox = 0;
+                    if (++oy == D.cy) {
+                        oy = 0;
+                        if (++oz == D.cz) { oz = 0; ++os; }
+                    }
+                }
+            }
+            if (v0 + t >= total) break;
             int z, y, x;
             if (MODE == UP) {
                 z = D.pz ? 2 * oz + 1 : 2 * (oz + 1);
@@ -173,7 +214,7 @@ __global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_count, Act out
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
                 const int co = q * 16 + (lane & 15);
-                float val = acc[mb][q][t] + (bias ? bias[co] : 0.f);
+                float val = acc[mb][q][t] + bq[q];
                 if (relu) val = fmaxf(val, 0.f);
                 o[co] = (bf16)val;
             }
@@ -551,6 +592,8 @@ hipError_t conv(Mode mode, const Act &in, int cin8, const Act &out, int cout, co
     if (mode == DOWN && out.n != (in.n + 1) / 2 - 1) return hipErrorInvalidValue;
     if (mode == UP && in.n != (out.n + 1) / 2 - 1) return hipErrorInvalidValue;
     const int cb = cin8 / 8;
+    if (cb & (cb - 1)) return hipErrorInvalidValue;   // 1, 2, 4 or 8 channel blocks
+    const int cb_shift = __builtin_ctz((unsigned)cb);
     long total;
     dim3 grid;
     if (mode == UP) {
@@ -561,7 +604,7 @@ hipError_t conv(Mode mode, const Act &in, int cin8, const Act &out, int cout, co
         grid = dim3(blocks_of(total, 64 * MB), 1);
     }
     const int r = relu ? 1 : 0;
-#define NN_CONV(MODE_, NT_) conv_kernel<MODE_, NT_><<<grid, 256, 0, s>>>(in, cb, out, W, bias, r, batch)
+#define NN_CONV(MODE_, NT_) conv_kernel<MODE_, NT_><<<grid, 256, 0, s>>>(in, cb_shift, out, W, bias, r, batch)
 #define NN_CONV_NT(MODE_)                     \
     switch (cout / 16) {                      \
     case 1: NN_CONV(MODE_, 1); break;         \

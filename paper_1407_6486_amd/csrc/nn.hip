@@ -222,6 +222,115 @@ __global__ __launch_bounds__(256) void conv_kernel(Act in, int cb_shift, Act out
     }
 }
 
+// SAME convolution on a tile staged in LDS: a workgroup owns a box of
+// TZB x TYB x TXB output voxels of one sample (wavefront w: plane z0 + w;
+// group mb: row y0 + mb; the 16 voxels of a row are the A rows).  The
+// (TZB + 2) x (TYB + 2) x (TXB + 2) input voxels the box reads are loaded
+// into LDS once (channels 0 .. 8 CB - 1, a voxel's channels contiguous,
+// padded at 64 channels so that the 16 rows of a fragment spread over the
+// banks), and every tap's A fragments are read from there; the weights
+// come through the caches.  The K order is that of conv_kernel.
+constexpr int TXB = 16, TYB = 4, TZB = 4;
+constexpr int BXB = TXB + 2, BYB = TYB + 2, BZB = TZB + 2;
+
+__host__ __device__ constexpr int tile_vstride(int cb) { return 8 * cb + (cb >= 8 ? 8 : 0); }
+
+template <int NT, int CB>
+__global__ __launch_bounds__(256) void conv_same_lds_kernel(Act in, Act out, const bf16 *__restrict__ W,
+                                                            const float *__restrict__ bias, int relu)
+{
+    static_assert(MB == TYB && TZB == 4, "one plane per wavefront, one row per group");
+    constexpr int C8 = 8 * CB, VS = tile_vstride(CB);
+    constexpr int cout = NT * 16;
+    extern __shared__ unsigned char smem_raw[];
+    bf16 *tile = reinterpret_cast<bf16 *>(smem_raw);   // [BZB][BYB][BXB] voxels of VS channels
+    const int n = in.n;
+    const int nbx = (n + TXB - 1) / TXB, nby = (n + TYB - 1) / TYB, nbz = (n + TZB - 1) / TZB;
+    unsigned b = blockIdx.x;
+    const int bx = (int)(b % (unsigned)nbx);
+    b /= (unsigned)nbx;
+    const int by = (int)(b % (unsigned)nby);
+    b /= (unsigned)nby;
+    const int bz = (int)(b % (unsigned)nbz);
+    const int s = (int)(b / (unsigned)nbz);
+    const int x0 = bx * TXB, y0 = by * TYB, z0 = bz * TZB;   // first output voxel (0-based interior)
+
+    // stage the box: halo'd input voxel (z0 + vz, y0 + vy, x0 + vx), clamped
+    // to the tensor (clamped voxels only feed outputs past the grid)
+    constexpr int CHUNKS = BZB * BYB * BXB * CB;
+    constexpr int PER = (CHUNKS + 255) / 256;
+    constexpr int BATCH = PER < 8 ? PER : 8;
+    for (int p0 = 0; p0 < PER; p0 += BATCH) {
+        bf16x8 v[BATCH];
+        int dst[BATCH];
+#pragma unroll
+        for (int e = 0; e < BATCH; ++e) {
+            const int c = (int)threadIdx.x + (p0 + e) * 256;
+            const int cc = c < CHUNKS ? c : CHUNKS - 1;
+            const int cb = cc % CB, vv = cc / CB;
+            const int vx = vv % BXB, vy = (vv / BXB) % BYB, vz = vv / (BXB * BYB);
+            const int gz = min(z0 + vz, n + 1), gy = min(y0 + vy, n + 1), gx = min(x0 + vx, n + 1);
+            v[e] = *reinterpret_cast<const bf16x8 *>(in.p + vox(n, s, gz, gy, gx) * in.cs + cb * 8);
+            dst[e] = c < CHUNKS && p0 + e < PER ? vv * VS + cb * 8 : -1;
+        }
+#pragma unroll
+        for (int e = 0; e < BATCH; ++e)
+            if (dst[e] >= 0) *reinterpret_cast<bf16x8 *>(tile + dst[e]) = v[e];
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kg = lane >> 4, v = lane & 15;
+    constexpr int groups = 27 * CB, ksteps = (groups + 3) / 4;
+    f4 acc[MB][NT];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[mb][q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < ksteps; ++ks) {
+        const int g = ks * 4 + kg;
+        const bool gok = g < groups;
+        const int gg = gok ? g : 0;
+        const int t = gg / CB, cb = gg % CB;
+        const int oz = t / 9, oy = (t / 3) % 3, ox = t % 3;   // box offsets 0..2 (tap offset + 1)
+        bf16x8 a[MB], bw[NT];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int vv = ((wave + oz) * BYB + (mb + oy)) * BXB + (v + ox);
+            a[mb] = *reinterpret_cast<const bf16x8 *>(tile + vv * VS + cb * 8);
+        }
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+            bw[q] = *reinterpret_cast<const bf16x8 *>(W + ((long)t * cout + q * 16 + v) * C8 + cb * 8);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+                acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gok ? a[mb] : bf16x8{}, gok ? bw[q] : bf16x8{},
+                                                                     acc[mb][q], 0, 0, 0);
+    }
+    float bq[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) bq[q] = bias ? bias[q * 16 + v] : 0.f;
+    const int z = z0 + wave;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const int y = y0 + mb;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int x = x0 + 4 * kg + t;
+            if (x >= n || y >= n || z >= n) continue;
+            bf16 *o = out.p + vox(n, s, z + 1, y + 1, x + 1) * out.cs;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                float val = acc[mb][q][t] + bq[q];
+                if (relu) val = fmaxf(val, 0.f);
+                o[q * 16 + v] = (bf16)val;
+            }
+        }
+    }
+}
+
 // Weight gradient of one tap over a chunk of the base domain: SAME and DOWN
 // iterate over the output grid (dz at the point, x at the tap's input
 // point); UP iterates over the coarse input grid (x at J, dz at 2J + d).
@@ -604,6 +713,35 @@ hipError_t conv(Mode mode, const Act &in, int cin8, const Act &out, int cout, co
         grid = dim3(blocks_of(total, 64 * MB), 1);
     }
     const int r = relu ? 1 : 0;
+    if (mode == SAME) {
+        // LDS-tiled kernel: (n/4)^2 (n/16) boxes per sample
+        const int nb = ((out.n + TXB - 1) / TXB) * ((out.n + TYB - 1) / TYB) * ((out.n + TZB - 1) / TZB);
+        const dim3 g2((unsigned)((long)nb * batch));
+        const size_t lds = (size_t)BZB * BYB * BXB * tile_vstride(cb) * sizeof(bf16);
+#define NN_SAME(NT_, CB_)                                                                                    \
+    do {                                                                                                     \
+        static const hipError_t ea = hipFuncSetAttribute((const void *)conv_same_lds_kernel<NT_, CB_>,      \
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024); \
+        if (ea != hipSuccess) return ea;                                                                     \
+        conv_same_lds_kernel<NT_, CB_><<<g2, 256, lds, s>>>(in, out, W, bias, r);                            \
+    } while (0)
+#define NN_SAME_CB(NT_)                          \
+    switch (cb) {                                \
+    case 1: NN_SAME(NT_, 1); break;              \
+    case 2: NN_SAME(NT_, 2); break;              \
+    case 4: NN_SAME(NT_, 4); break;              \
+    default: NN_SAME(NT_, 8); break;             \
+    }
+        switch (cout / 16) {
+        case 1: NN_SAME_CB(1); break;
+        case 2: NN_SAME_CB(2); break;
+        case 3: NN_SAME_CB(3); break;
+        default: NN_SAME_CB(4); break;
+        }
+#undef NN_SAME_CB
+#undef NN_SAME
+        return hipGetLastError();
+    }
 #define NN_CONV(MODE_, NT_) conv_kernel<MODE_, NT_><<<grid, 256, 0, s>>>(in, cb_shift, out, W, bias, r, batch)
 #define NN_CONV_NT(MODE_)                     \
     switch (cout / 16) {                      \

@@ -331,6 +331,110 @@ __global__ __launch_bounds__(256) void conv_same_lds_kernel(Act in, Act out, con
     }
 }
 
+// UP convolution (coarse -> fine) on a coarse box staged in LDS: a
+// workgroup of 8 wavefronts owns a fine box of 4 x 4 x 32 points starting
+// at fine (4 bz + 1, 4 by + 1, 32 bx + 1); wavefront w takes the parity
+// class (pz, py, px) = bits of w, i.e. 2 x 2 of the box's rows and 16 of
+// the 32 points of each (every other x), so the four groups of a
+// wavefront share their taps.  Per axis, fine 2J + 1 reads coarse J
+// (d = +1) and J + 1 (d = -1), fine 2J reads J (d = 0); the box reads
+// coarse 2 bz .. 2 bz + 2, 2 by .. 2 by + 2, 16 bx .. 16 bx + 16.
+constexpr int UXB = 32, UCX = UXB / 2 + 1;
+
+template <int NT, int CB>
+__global__ __launch_bounds__(512) void conv_up_lds_kernel(Act in, Act out, const bf16 *__restrict__ W,
+                                                          const float *__restrict__ bias, int relu)
+{
+    constexpr int C8 = 8 * CB, VS = tile_vstride(CB);
+    constexpr int cout = NT * 16;
+    constexpr int cb_shift = CB == 1 ? 0 : CB == 2 ? 1 : CB == 4 ? 2 : 3;
+    extern __shared__ unsigned char smem_raw[];
+    bf16 *tile = reinterpret_cast<bf16 *>(smem_raw);   // [3][3][UCX] coarse voxels of VS channels
+    const int nc = in.n, nf = out.n;
+    const int nbx = (nf + UXB - 1) / UXB, nby = (nf + 3) / 4, nbz = (nf + 3) / 4;
+    unsigned b = blockIdx.x;
+    const int bx = (int)(b % (unsigned)nbx);
+    b /= (unsigned)nbx;
+    const int by = (int)(b % (unsigned)nby);
+    b /= (unsigned)nby;
+    const int bz = (int)(b % (unsigned)nbz);
+    const int s = (int)(b / (unsigned)nbz);
+    const int cz0 = 2 * bz, cy0 = 2 * by, cx0 = 16 * bx;   // first coarse (halo'd) index of the box
+
+    constexpr int CHUNKS = 3 * 3 * UCX * CB;
+    for (int c = threadIdx.x; c < CHUNKS; c += 512) {
+        const int cb = c % CB, vv = c / CB;
+        const int vx = vv % UCX, vy = (vv / UCX) % 3, vz = vv / (UCX * 3);
+        const int gz = min(cz0 + vz, nc + 1), gy = min(cy0 + vy, nc + 1), gx = min(cx0 + vx, nc + 1);
+        *reinterpret_cast<bf16x8 *>(tile + vv * VS + cb * 8) =
+            *reinterpret_cast<const bf16x8 *>(in.p + vox(nc, s, gz, gy, gx) * in.cs + cb * 8);
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kg = lane >> 4, v = lane & 15;
+    const int pz = (wave >> 2) & 1, py = (wave >> 1) & 1, px = wave & 1;
+    const int ntap = 1 << (pz + py + px);
+    const int groups = ntap << cb_shift;
+    const int ksteps = (groups + 3) >> 2;
+    // group mb = (zr, yr): fine row 2 c + 1 + 2 r + (1 - p) on each axis,
+    // whose base coarse index in the box is r (odd) or 1 + r (even)
+    f4 acc[MB][NT];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[mb][q] = f4{0.f, 0.f, 0.f, 0.f};
+    const int xb = px ? v : v + 1;
+    for (int ks = 0; ks < ksteps; ++ks) {
+        const int g = ks * 4 + kg;
+        const bool gok = g < groups;
+        const int gg = gok ? g : 0;
+        const int t = gg >> cb_shift, cb = gg & (CB - 1);
+        int bit = 0, oz = 0, oy = 0, ox = 0, wz = 1, wy = 1, wx = 1;   // offsets; weight index per axis
+        if (pz) { const int sel = (t >> bit++) & 1; oz = sel; wz = sel ? 0 : 2; }
+        if (py) { const int sel = (t >> bit++) & 1; oy = sel; wy = sel ? 0 : 2; }
+        if (px) { const int sel = (t >> bit++) & 1; ox = sel; wx = sel ? 0 : 2; }
+        const int tapw = wz * 9 + wy * 3 + wx;
+        bf16x8 a[MB], bw[NT];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int zr = mb >> 1, yr = mb & 1;
+            const int zb = pz ? zr : 1 + zr, yb = py ? yr : 1 + yr;
+            const int vv = ((zb + oz) * 3 + (yb + oy)) * UCX + (xb + ox);
+            a[mb] = *reinterpret_cast<const bf16x8 *>(tile + vv * VS + cb * 8);
+        }
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+            bw[q] = *reinterpret_cast<const bf16x8 *>(W + ((long)tapw * cout + q * 16 + v) * C8 + cb * 8);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+                acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gok ? a[mb] : bf16x8{}, gok ? bw[q] : bf16x8{},
+                                                                     acc[mb][q], 0, 0, 0);
+    }
+    float bq[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) bq[q] = bias ? bias[q * 16 + v] : 0.f;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const int zr = mb >> 1, yr = mb & 1;
+        const int z = 4 * bz + 1 + 2 * zr + (1 - pz), y = 4 * by + 1 + 2 * yr + (1 - py);   // fine, 1-based
+        if (z > nf || y > nf) continue;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int x = UXB * bx + 1 + 2 * (4 * kg + t) + (1 - px);
+            if (x > nf) continue;
+            bf16 *o = out.p + vox(nf, s, z, y, x) * out.cs;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                float val = acc[mb][q][t] + bq[q];
+                if (relu) val = fmaxf(val, 0.f);
+                o[q * 16 + v] = (bf16)val;
+            }
+        }
+    }
+}
+
 // Weight gradient of one tap over a chunk of the base domain: SAME and DOWN
 // iterate over the output grid (dz at the point, x at the tap's input
 // point); UP iterates over the coarse input grid (x at J, dz at 2J + d).
@@ -740,6 +844,30 @@ hipError_t conv(Mode mode, const Act &in, int cin8, const Act &out, int cout, co
         }
 #undef NN_SAME_CB
 #undef NN_SAME
+        return hipGetLastError();
+    }
+    if (mode == UP) {
+        // coarse-box kernel: fine boxes of 4 x 4 x 32 points
+        const int nf = out.n;
+        const long nb = (long)((nf + UXB - 1) / UXB) * ((nf + 3) / 4) * ((nf + 3) / 4);
+        const dim3 g2((unsigned)(nb * batch));
+        const size_t lds = (size_t)3 * 3 * UCX * tile_vstride(cb) * sizeof(bf16);
+#define NN_UP(NT_, CB_) conv_up_lds_kernel<NT_, CB_><<<g2, 512, lds, s>>>(in, out, W, bias, r)
+#define NN_UP_CB(NT_)                            \
+    switch (cb) {                                \
+    case 1: NN_UP(NT_, 1); break;                \
+    case 2: NN_UP(NT_, 2); break;                \
+    case 4: NN_UP(NT_, 4); break;                \
+    default: NN_UP(NT_, 8); break;               \
+    }
+        switch (cout / 16) {
+        case 1: NN_UP_CB(1); break;
+        case 2: NN_UP_CB(2); break;
+        case 3: NN_UP_CB(3); break;
+        default: NN_UP_CB(4); break;
+        }
+#undef NN_UP_CB
+#undef NN_UP
         return hipGetLastError();
     }
 #define NN_CONV(MODE_, NT_) conv_kernel<MODE_, NT_><<<grid, 256, 0, s>>>(in, cb_shift, out, W, bias, r, batch)

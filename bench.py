@@ -62,9 +62,11 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--max-iter", type=int, default=400,
                     help="iteration cap per block (profiling runs cap it to keep traces small)")
-    ap.add_argument("--form", choices=["mixed", "batched", "learned", "solve-policies", "heat1d", "table1", "weak3"],
+    ap.add_argument("--form", choices=["mixed", "batched", "learned", "nn-forward", "solve-policies", "heat1d", "table1",
+                                       "weak3"],
                     default=None,
                     help="instead: one of the method's forms against the plain FP64 path (mixed, batched, learned), "
+                         "the network's forward pass alone (nn-forward), "
                          "the node-solve policies at 127^3 x 16 (solve-policies), the 1D latency and error report "
                          "(heat1d) or the paper's 3D strong-scaling problem with its uniform nodes, ISDC / IMLSDC / "
                          "IPFASST (table1)")
@@ -398,6 +400,42 @@ def form_learned(pfmg, a):
                                    "dt=1e-3, seed 1407, full solves to 1e-12"}}
 
 
+def form_nn_forward(pfmg, a):
+    """The learned guess's network alone: forward passes of 16 x 127^3 with
+    randomly initialised weights on a seeded random input (the timing does
+    not depend on the values)."""
+    import torch
+
+    from paper_1407_6486_amd import learned as L
+
+    if a.calibrate_copy:
+        copy_calibration(pfmg)
+    n, batch = 127, 16
+    net = pfmg.Net(n, batch, training=False)
+    net.init(1407)
+    g = torch.Generator(device="cuda").manual_seed(1407)
+    x = torch.randn((batch, 3, n ** 3), dtype=torch.float32, device="cuda", generator=g)
+    y = torch.empty((batch, n ** 3), dtype=torch.float32, device="cuda")
+    for _ in range(max(a.warmup, 1)):
+        pfmg.pfmg_nn_forward(net.h, x.data_ptr(), batch, y.data_ptr())
+    torch.cuda.synchronize()
+    reps = max(a.steps, 1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pfmg.pfmg_nn_forward(net.h, x.data_ptr(), batch, y.data_ptr())
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    net.close()
+    tf = L.flops_per_voxel() * n ** 3 * batch / t / 1e12
+    return {"metric": "ms per network forward pass", "value": round(t * 1e3, 3), "unit": "ms",
+            "form": "learned guess network forward", "steps": reps, "warmup": max(a.warmup, 1),
+            "roofline": {"bound": "mfma", "kernel": "network forward, 16 x 127^3 (BF16 MFMA, FP32 accumulate)",
+                         "achieved": round(tf, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 4), "traffic": None},
+            "higher_is_better": False, "dtype": "bf16", "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": "U-Net 16/32/64, 16 x 127^3, random weights (seed 1407), random input"}}
+
+
 def form_solve_policies(pfmg, a):
     """The 127^3 x 16 block (seed 1407) with the node-solve policies the
     paper weighs against each other: one and two V-cycles per solve and
@@ -655,7 +693,7 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     if a.form:
-        fn = {"mixed": form_mixed, "batched": form_batched, "learned": form_learned,
+        fn = {"mixed": form_mixed, "batched": form_batched, "learned": form_learned, "nn-forward": form_nn_forward,
               "solve-policies": form_solve_policies, "heat1d": form_heat1d, "table1": form_table1,
               "weak3": form_weak3}[a.form]
         print(json.dumps(fn(pfmg, a), default=float), flush=True)

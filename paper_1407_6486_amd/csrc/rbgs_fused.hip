@@ -49,15 +49,19 @@ constexpr int QMAX = 6;   // owned rows per thread
 // The register windows live in four slots indexed by the plane modulo 4
 // and the loop is unrolled four times, so no values are moved between
 // windows.
-template <typename T, int RLN, int Q, int NT>
-__global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_fused_kernel(Tiling t, int ty, int zchunk, int zero_in, double alpha,
+// TYC > 0 fixes the rows per workgroup at compile time (the shapes the
+// shipped tuner table picks), which turns the row ownership tests into
+// constants; TYC = 0 takes ty_rt.
+template <typename T, int RLN, int Q, int NT, int TYC>
+__global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_fused_kernel(Tiling t, int ty_rt, int zchunk, int zero_in, double alpha,
                                                            double omega, View<T> b, View<T> uin, View<T> uout)
 {
     extern __shared__ unsigned char smem_raw[];
+    const int ty = TYC > 0 ? TYC : ty_rt;
     unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
     Pt qs;
     const int *mask;
-    if (!find_seg(t, bid, qs, mask, [ty, zchunk](int nn) {
+    if (!find_seg(t, bid, qs, mask, [&](int nn) {
             return (long)((nn + ty - 1) / ty) * ((nn + zchunk - 1) / zchunk);
         }))
         return;
@@ -79,6 +83,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
     constexpr int rpp = NT / RLN;
     const int i = (int)(threadIdx.x % RLN) + 1;
     const int rsub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / RLN));
+    __builtin_assume(rsub >= 0 && rsub < rpp);
     // element offsets inside one field fit in 32 bits (n <= 255)
     const int sy = (int)row_stride(n), sz = (int)plane_stride(n);
     const T *__restrict__ U = fp(uin, qs);
@@ -337,9 +342,19 @@ hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in,
     const int rln = nmax <= 64 ? 64 : nmax <= 128 ? 128 : 256;
     const int q = rows_per_thread(rln, f.ty, f.nt);
     const dim3 g((unsigned)f.blocks), blk(f.nt);
-#define PFMG_FUSED(RL_, Q_, NT_)                                                                                \
-    return launch(rbgs_fused_kernel<T, RL_, Q_, NT_>, g, blk, f.lds, s, t, f.ty, f.zchunk, zi, alpha, omega, b, uin, \
-                  uout)
+#define PFMG_FUSED_TY(RL_, Q_, NT_, TY_)                                                                         \
+    return launch(rbgs_fused_kernel<T, RL_, Q_, NT_, TY_>, g, blk, f.lds, s, t, f.ty, f.zchunk, zi, alpha, omega, b, \
+                  uin, uout)
+#define PFMG_FUSED(RL_, Q_, NT_) PFMG_FUSED_TY(RL_, Q_, NT_, 0)
+    // compile-time rows for the shapes of the 127^3 / 63^3 / 31^3 V-cycle
+    // levels in the shipped FP64 tuner table
+    if constexpr (sizeof(T) == 8) {
+        if (f.nt == 512 && rln == 128 && q == 3 && f.ty == 8) PFMG_FUSED_TY(128, 3, 512, 8);
+        if (f.nt == 512 && rln == 64 && q == 2 && f.ty == 8) PFMG_FUSED_TY(64, 2, 512, 8);
+        if (f.nt == 512 && rln == 64 && q == 3 && f.ty == 16) PFMG_FUSED_TY(64, 3, 512, 16);
+        if (f.nt == 512 && rln == 64 && q == 1 && f.ty == 6) PFMG_FUSED_TY(64, 1, 512, 6);
+        if (f.nt == 256 && rln == 64 && q == 1 && f.ty == 2) PFMG_FUSED_TY(64, 1, 256, 2);
+    }
     // instantiated row counts: those of ty = 1, 2, 4, 8, 16 that fit QMAX,
     // and QMAX for any other ty; 512-thread workgroups for up to 3 rows
     if (f.nt == 512) {
@@ -372,6 +387,7 @@ hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in,
         if (q <= QMAX) PFMG_FUSED(256, 6, 256);
     }
 #undef PFMG_FUSED
+#undef PFMG_FUSED_TY
     return hipErrorInvalidValue;
 }
 

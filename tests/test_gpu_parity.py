@@ -67,8 +67,10 @@ def test_vcycle_matches_oracle(pf, dim, n, sm, cycles):
 # (threads / lanes)) gives 1, 2, 3, 5, 6 (64 lanes), 2, 3, 5, 6 (128) and 3,
 # 4, 6 (256) with 256 threads, 1, 2, 3 / 2, 3 / 3 with 512 (a row count
 # below a compiled one runs the next one up).
+# (8 at 128 lanes and 8, 16 at 64 lanes with 512 threads, 2 at 64 lanes
+# with 256: the shapes with compile-time row counts)
 SWEEP_TY = {256: {64: [2, 4, 8, 14, 22], 128: [2, 4, 8, 10], 256: [1, 2, 4]},
-            512: {64: [6, 14, 22], 128: [2, 10], 256: [4]}}
+            512: {64: [6, 8, 14, 16, 22], 128: [2, 8, 10], 256: [4]}}
 SWEEP_ZC = [5, 7, 3, 16, 9, 64, 2, 31]
 
 

@@ -1,5 +1,5 @@
 // Residual plus full-weighting restriction in one pass over the fine grid
-// (3D, fine n >= 63): bc = FW(b - (u - ah L u)), the coarse right-hand side
+// (3D, odd fine n >= 31): bc = FW(b - (u - ah L u)), the coarse right-hand side
 // of the V-cycle (Sec. 4.2.1; full weighting is the tensor product of the
 // weights 1/4, 1/2, 1/4 around the fine point 2J of coarse point J).
 //
@@ -222,7 +222,7 @@ bool resid_restrict_z_ok(const Tiling &t)
 {
     if (t.dim != 3) return false;
     for (int sg = 0; sg < t.nseg; ++sg)
-        if (t.seg_count(sg) > 0 && (t.seg_n(sg) < 63 || t.seg_n(sg) > 255 || (t.seg_n(sg) & 1) == 0)) return false;
+        if (t.seg_count(sg) > 0 && (t.seg_n(sg) < 31 || t.seg_n(sg) > 255 || (t.seg_n(sg) & 1) == 0)) return false;
     return true;
 }
 

@@ -37,8 +37,9 @@ constexpr int QMAX = 6;   // owned rows per thread
 // at the same register footprint, so fewer halo rows are re-read).
 // Q: rows per thread, ceil((ty + 2) / (NT / RLN)) rounded up to an
 // instantiated value; the register windows hold Q rows, so a small ty buys
-// occupancy.  The loads of step k + 1 are issued at the top of step k
-// (uin plane k + 2, b plane k + 1, the halo rows of uin plane k + 1) and
+// occupancy.  The loads of the next step are issued at the top of the
+// current one (uin two planes ahead, b and the halo rows of uin one plane
+// ahead) and
 // wait behind the whole step's arithmetic and barriers.
 //
 // The z-march is written without divergent branches: a thread's rows are
@@ -80,6 +81,13 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
     const T ah = (T)ahd, winv = (T)(omega / (1.0 + 2.0 * 3 * ahd));
     const int j0 = jt * ty + 1, k0 = zc * zchunk + 1;
     const int k1 = min(k0 + zchunk, n + 1);
+    // odd z-chunks march downwards, so that two neighbouring chunks read
+    // their shared border planes at the same time (both at their start or
+    // both at their end) and the second read hits the XCD's L2.  Step v of
+    // the march (v = -1 .. L) works on plane kv(v); the arithmetic is the
+    // same in both directions (the z-neighbour sums commute).
+    const int dk = (zc & 1) ? -1 : 1, L = k1 - k0;
+    auto kv = [&](int v) { return dk > 0 ? k0 + v : k1 - 1 - v; };
     constexpr int rpp = NT / RLN;
     const int i = (int)(threadIdx.x % RLN) + 1;
     const int rsub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / RLN));
@@ -127,10 +135,10 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
     // The z-march; ZI: the input is zero (uin is not read).
     auto march = [&](auto zi) {
         constexpr bool ZI = decltype(zi)::value;
-        // the global loads of step k: uin plane k + 1 and b plane k on the
-        // owned rows, uin plane k on the two outer halo rows
+        // the global loads of the step on plane k: uin plane k + dk and b
+        // plane k on the owned rows, uin plane k on the two outer halo rows
         auto load_step = [&](int k, T (&un)[Q], T (&bn)[Q], T (&ex)[2]) {
-            const unsigned pu = planeb(k + 1), pb = planeb(k);
+            const unsigned pu = planeb(k + dk), pb = planeb(k);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 if (own[q]) {
@@ -151,10 +159,10 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
 #pragma unroll
             for (int q = 0; q < Q; ++q) us[sl][q] = bs[sl][q] = ws[sl][q] = (T)0;
         es[0][0] = es[0][1] = es[1][0] = es[1][1] = (T)0;
-        // plane p lives in slot (p - (k0 - 1)) & 3 (uin, b, red field) and
-        // (p - (k0 - 1)) & 1 (outer halo rows)
+        // the plane of step v lives in slot (v + 1) & 3 (uin, b, red field)
+        // and (v + 1) & 1 (outer halo rows)
         if (!ZI) {
-            const unsigned pm = planeb(k0 - 2), pc = planeb(k0 - 1);
+            const unsigned pm = planeb(kv(-2)), pc = planeb(kv(-1));
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 if (own[q]) {
@@ -163,11 +171,12 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
                 }
             }
         }
-        load_step(k0 - 1, us[1], bs[0], es[0]);
+        load_step(kv(-1), us[1], bs[0], es[0]);
 
-        // one z-step on plane k, whose slot is S
-        auto step = [&](auto sc, int k) {
+        // step v of the march, on plane k = kv(v), whose slot is S
+        auto step = [&](auto sc, int v) {
             constexpr int S = decltype(sc)::value;
+            const int k = kv(v);
             constexpr int S1 = (S + 1) & 3, S2 = (S + 2) & 3, S3 = (S + 3) & 3;
             // Everything this step reads from memory was loaded during the
             // previous step: wait for it here, before the next step's loads
@@ -175,7 +184,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
             // those, since how many are in flight depends on the row branches).
             __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             __builtin_amdgcn_sched_barrier(0);
-            if (k < k1) load_step(k + 1, us[S2], bs[S1], es[(S + 1) & 1]);
+            if (v < L) load_step(k + dk, us[S2], bs[S1], es[(S + 1) & 1]);
             // ---- uin plane k -> LDS (rows e = 0 .. ty+3 <-> j = j0-2+e)
             if (!ZI) {
 #pragma unroll
@@ -190,7 +199,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
                 }
             }
             // also orders phase B of the previous step (reading the red
-            // plane buffer of k - 2) before this step's red writes into it
+            // plane buffer of k - 2 dk) before this step's red writes into it
             __syncthreads();
             // ---- phase A: red update of plane k on the owned rows
             T *wk = wp + (k & 1) * rows * RL;
@@ -218,8 +227,8 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
                 }
             }
             __syncthreads();
-            // ---- phase B: black update of plane k-1 on rows 1..ty
-            const int kb = k - 1;
+            // ---- phase B: black update of plane k - dk on rows 1..ty
+            const int kb = k - dk;
             if (kb >= k0 && kb < k1) {
                 const T *wb = wp + (kb & 1) * rows * RL;
                 const bool kbodd = (kb & 1) != 0;
@@ -250,14 +259,14 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
                 }
             }
         };
-        for (int kk = k0 - 1; kk <= k1; kk += 4) {
-            step(std::integral_constant<int, 0>{}, kk);
-            if (kk + 1 > k1) break;
-            step(std::integral_constant<int, 1>{}, kk + 1);
-            if (kk + 2 > k1) break;
-            step(std::integral_constant<int, 2>{}, kk + 2);
-            if (kk + 3 > k1) break;
-            step(std::integral_constant<int, 3>{}, kk + 3);
+        for (int vv = -1; vv <= L; vv += 4) {
+            step(std::integral_constant<int, 0>{}, vv);
+            if (vv + 1 > L) break;
+            step(std::integral_constant<int, 1>{}, vv + 1);
+            if (vv + 2 > L) break;
+            step(std::integral_constant<int, 2>{}, vv + 2);
+            if (vv + 3 > L) break;
+            step(std::integral_constant<int, 3>{}, vv + 3);
         }
     };
     if (zero_in)

@@ -70,7 +70,7 @@ def test_vcycle_matches_oracle(pf, dim, n, sm, cycles):
 # (8 at 128 lanes and 8, 16 at 64 lanes with 512 threads, 2 at 64 lanes
 # with 256: the shapes with compile-time row counts)
 SWEEP_TY = {256: {64: [2, 4, 8, 14, 22], 128: [2, 4, 8, 10], 256: [1, 2, 4]},
-            512: {64: [6, 8, 14, 16, 22], 128: [2, 8, 10], 256: [4]}}
+            512: {64: [6, 8, 14, 16, 22], 128: [2, 6, 8, 10], 256: [4]}}
 SWEEP_ZC = [5, 7, 3, 16, 9, 64, 2, 31]
 
 

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "../../include/pfmg.h"
 #include "kernels.h"
@@ -387,6 +388,304 @@ __global__ __launch_bounds__(1024) void vcycle_bottom_kernel(Tiling t, double al
     });
 }
 
+
+// ---------------------------------------------------------------------------
+// The same V-cycle for the case the big-grid V-cycles hand down (3D, top grid
+// 15^3, red-black smoother): levels 15, 7, 3, 1 with compile-time sizes, so
+// every loop over points is unrolled and its index arithmetic folded.  A pass
+// first reads everything it needs (its points' neighbours have the other
+// colour, or live in another array), then writes, so the LDS reads of all
+// its points are in flight together; the level constants live in registers.
+// The arithmetic is that of the generic kernel above, term for term.
+namespace b15 {
+
+constexpr int N0 = 15, N1 = 7, N2 = 3;
+// dense level arrays u, b, t of each level, one after the other in LDS
+constexpr int OFF1 = 3 * N0 * N0 * N0, OFF2 = OFF1 + 3 * N1 * N1 * N1, OFF3 = OFF2 + 3 * N2 * N2 * N2;
+constexpr int LDS_ELEMS = OFF3 + 3;
+
+// One point of an N^3 grid per slot; rounds of 16 x 16 x 4 slots for
+// 8 < N <= 16, of 8 x 16 x 8 for N <= 8 (as the generic kernel visits them).
+template <int N>
+struct All {
+    static constexpr int R = N > 8 ? (N + 3) / 4 : 1;
+    __device__ static void at(int r, int &i, int &j, int &k, bool &ok)
+    {
+        if (N > 8) {
+            i = threadIdx.x; j = threadIdx.y; k = threadIdx.z + 4 * r;
+        } else {
+            i = threadIdx.x & 7; j = threadIdx.y; k = 2 * threadIdx.z + (threadIdx.x >> 3);
+        }
+        ok = i < N && j < N && k < N;
+    }
+};
+
+// One point of colour c (1-based parity (i + j + k + 3) & 1 == c) per slot:
+// i / 2 from the low x lanes, rounds of 8 x 16 x 8 slots.
+template <int N>
+struct Colour {
+    static constexpr int H = (N + 1) / 2, R = (N + 7) / 8;
+    __device__ static void at(int r, int c, int &i, int &j, int &k, bool &ok)
+    {
+        const int i2 = threadIdx.x & 7;
+        j = threadIdx.y;
+        k = 2 * threadIdx.z + (threadIdx.x >> 3) + 8 * r;
+        i = 2 * i2 + ((c + j + k + 1) & 1);
+        ok = i2 < H && j < N && k < N && i < N;
+    }
+};
+
+template <int N>
+__device__ inline int idx(int i, int j, int k) { return i + N * (j + N * k); }
+
+// Laplacian numerator of point (i, j, k) (inside the grid): neighbours
+// outside read the point itself and are replaced by the zero boundary.
+template <int N, typename T>
+__device__ inline T d2(const T *a, int i, int j, int k)
+{
+    const int p = idx<N>(i, j, k);
+    auto nb = [&](int off, bool in) { const T v = a[in ? p + off : p]; return in ? v : (T)0; };
+    const T c = a[p];
+    T s = nb(-1, i > 0) + nb(1, i < N - 1);
+    s += (nb(-N, j > 0) + nb(N, j < N - 1)) + (nb(-N * N, k > 0) + nb(N * N, k < N - 1));
+    return s - (T)6 * c;
+}
+
+// Gauss-Seidel update of colour c in place.
+template <int N, typename T>
+__device__ inline void rb_pass(T *u, const T *b, T ah, T winv, int c)
+{
+    constexpr int R = Colour<N>::R;
+    T v[R];
+    int pp[R];
+    bool okr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int i, j, k;
+        bool ok;
+        Colour<N>::at(r, c, i, j, k, ok);
+        if (!ok) i = j = k = 0;
+        const int p = idx<N>(i, j, k);
+        const T uc = u[p];
+        v[r] = uc + winv * (b[p] - (uc - ah * d2<N>(u, i, j, k)));
+        pp[r] = p;
+        okr[r] = ok;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (okr[r]) u[pp[r]] = v[r];
+    __syncthreads();
+}
+
+// RB-GS sweeps; from zero the first red pass is winv b on red points, 0 on
+// black ones.
+template <int N, typename T>
+__device__ inline void smooth(T *u, const T *b, T ah, T winv, int sweeps, bool from_zero)
+{
+    if (sweeps == 0 && from_zero) {
+#pragma unroll
+        for (int r = 0; r < All<N>::R; ++r) {
+            int i, j, k;
+            bool ok;
+            All<N>::at(r, i, j, k, ok);
+            if (ok) u[idx<N>(i, j, k)] = (T)0;
+        }
+        __syncthreads();
+        return;
+    }
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const bool z = sw == 0 && from_zero;
+        if (z) {
+            constexpr int R = All<N>::R;
+            T v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int i, j, k;
+                bool ok;
+                All<N>::at(r, i, j, k, ok);
+                const T bv = b[ok ? idx<N>(i, j, k) : 0];
+                v[r] = ((i + j + k + 3) & 1) == 0 ? winv * bv : (T)0;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int i, j, k;
+                bool ok;
+                All<N>::at(r, i, j, k, ok);
+                if (ok) u[idx<N>(i, j, k)] = v[r];
+            }
+            __syncthreads();
+        } else {
+            rb_pass<N>(u, b, ah, winv, 0);
+        }
+        rb_pass<N>(u, b, ah, winv, 1);
+    }
+}
+
+// Fine residual into t, then coarse b = its full weighting.
+template <int NF, int NC, typename T>
+__device__ inline void resid_restrict(const T *u, const T *b, T *t, T *bc, T ah)
+{
+    constexpr int R = All<NF>::R;
+    T v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int i, j, k;
+        bool ok;
+        All<NF>::at(r, i, j, k, ok);
+        if (!ok) i = j = k = 0;
+        const int p = idx<NF>(i, j, k);
+        v[r] = b[p] - (u[p] - ah * d2<NF>(u, i, j, k));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int i, j, k;
+        bool ok;
+        All<NF>::at(r, i, j, k, ok);
+        if (ok) t[idx<NF>(i, j, k)] = v[r];
+    }
+    __syncthreads();
+    const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
+#pragma unroll
+    for (int r = 0; r < All<NC>::R; ++r) {
+        int I, J, K;
+        bool ok;
+        All<NC>::at(r, I, J, K, ok);
+        if (!ok) I = J = K = 0;
+        const int fi = 2 * I + 1, fj = 2 * J + 1, fk = 2 * K + 1;
+        T acc = 0;
+#pragma unroll
+        for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+            for (int oy = -1; oy <= 1; ++oy) {
+                T row = 0;
+#pragma unroll
+                for (int ox = -1; ox <= 1; ++ox) row += w[ox + 1] * t[idx<NF>(fi + ox, fj + oy, fk + oz)];
+                acc += w[oz + 1] * w[oy + 1] * row;
+            }
+        if (ok) bc[idx<NC>(I, J, K)] = acc;
+    }
+    __syncthreads();
+}
+
+// Fine u += d-linear interpolation of the coarse u (as prolong_add above).
+template <int NC, int NF, typename T>
+__device__ inline void prolong_add(const T *uc, T *uf)
+{
+    auto at = [&](int i, int j, int k) -> T {
+        const bool ok = (unsigned)i < (unsigned)NC && (unsigned)j < (unsigned)NC && (unsigned)k < (unsigned)NC;
+        const T v = uc[ok ? idx<NC>(i, j, k) : 0];
+        return ok ? v : (T)0;
+    };
+    constexpr int R = All<NF>::R;
+    T v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int i, j, k;
+        bool ok;
+        All<NF>::at(r, i, j, k, ok);
+        if (!ok) i = j = k = 0;
+        const int i1 = i + 1, j1 = j + 1, k1 = k + 1;
+        const int a0 = (i1 >> 1) - 1, a1 = ((i1 + 1) >> 1) - 1;
+        const int b0 = (j1 >> 1) - 1, b1 = ((j1 + 1) >> 1) - 1, c0 = (k1 >> 1) - 1, c1 = ((k1 + 1) >> 1) - 1;
+        const bool ox = (i1 & 1) != 0, oy = (j1 & 1) != 0, oz = (k1 & 1) != 0;
+        auto rowv = [&](int jj, int kk) -> T {
+            const T x0 = at(a0, jj, kk), x1 = at(a1, jj, kk);
+            const T h = (T)0.5 * (x0 + x1);
+            return ox ? h : x0;
+        };
+        const T r00 = rowv(b0, c0), r10 = rowv(b1, c0), r01 = rowv(b0, c1), r11 = rowv(b1, c1);
+        const T p0h = (T)0.5 * (r00 + r10), p1h = (T)0.5 * (r01 + r11);
+        const T p0 = oy ? p0h : r00, p1 = oy ? p1h : r01;
+        const T vh = (T)0.5 * (p0 + p1);
+        v[r] = uf[idx<NF>(i, j, k)] + (oz ? vh : p0);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int i, j, k;
+        bool ok;
+        All<NF>::at(r, i, j, k, ok);
+        if (ok) uf[idx<NF>(i, j, k)] = v[r];
+    }
+    __syncthreads();
+}
+
+}  // namespace b15
+
+template <typename T>
+__global__ __launch_bounds__(1024) void vcycle_bottom15_kernel(Tiling t, double alpha_s, double omega, int nu1, int nu2,
+                                                               int zero_init, View<T> bg, View<T> ug)
+{
+    using namespace b15;
+    extern __shared__ unsigned char smem_raw[];
+    unsigned bid = blockIdx.x;
+    Pt qs;
+    const int *mask;
+    if (!find_seg(t, bid, qs, mask, [](int) { return 1L; })) return;
+    qs.item = (int)bid;
+    if (mask && !mask[qs.item]) return;
+    const double alpha = qs.par(alpha_s);
+    // per level: ah = alpha (n + 1)^2, winv = omega / (1 + 6 ah)
+    const double a0 = alpha * 256.0, a1 = alpha * 64.0, a2 = alpha * 16.0, a3 = alpha * 4.0;
+    const T ah0 = (T)a0, ah1 = (T)a1, ah2 = (T)a2, ah3 = (T)a3;
+    const T wi0 = (T)(omega / (1.0 + 6.0 * a0)), wi1 = (T)(omega / (1.0 + 6.0 * a1)),
+            wi2 = (T)(omega / (1.0 + 6.0 * a2));
+    T *base = reinterpret_cast<T *>(smem_raw);
+    T *u0 = base, *b0 = u0 + N0 * N0 * N0, *t0 = b0 + N0 * N0 * N0;
+    T *u1 = base + OFF1, *b1 = u1 + N1 * N1 * N1, *t1 = b1 + N1 * N1 * N1;
+    T *u2 = base + OFF2, *b2 = u2 + N2 * N2 * N2, *t2 = b2 + N2 * N2 * N2;
+    T *u3 = base + OFF3, *b3 = u3 + 1;
+    const T *bsrc = fp(bg, qs);
+    T *udst = fp(ug, qs);
+    constexpr int sy = N0 + 1, sz = (N0 + 1) * (N0 + 2);
+    // the top grid: every global load issued before the first LDS store
+    // (slots outside the grid read element 0, a halo word)
+    {
+        constexpr int R = All<N0>::R;
+        T bv[R], uv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int i, j, k;
+            bool ok;
+            All<N0>::at(r, i, j, k, ok);
+            const int o = ok ? (i + 1) + (j + 1) * sy + (k + 1) * sz : 0;
+            bv[r] = bsrc[o];
+            uv[r] = zero_init ? (T)0 : udst[o];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int i, j, k;
+            bool ok;
+            All<N0>::at(r, i, j, k, ok);
+            if (ok) {
+                b0[idx<N0>(i, j, k)] = bv[r];
+                u0[idx<N0>(i, j, k)] = uv[r];
+            }
+        }
+    }
+    __syncthreads();
+    smooth<N0>(u0, b0, ah0, wi0, nu1, zero_init != 0);
+    resid_restrict<N0, N1>(u0, b0, t0, b1, ah0);
+    smooth<N1>(u1, b1, ah1, wi1, nu1, true);
+    resid_restrict<N1, N2>(u1, b1, t1, b2, ah1);
+    smooth<N2>(u2, b2, ah2, wi2, nu1, true);
+    resid_restrict<N2, 1>(u2, b2, t2, b3, ah2);
+    if (threadIdx.x + threadIdx.y + threadIdx.z == 0) u3[0] = b3[0] / ((T)1 + (T)6 * ah3);
+    __syncthreads();
+    prolong_add<1, N2>(u3, u2);
+    smooth<N2>(u2, b2, ah2, wi2, nu2, false);
+    prolong_add<N2, N1>(u2, u1);
+    smooth<N1>(u1, b1, ah1, wi1, nu2, false);
+    prolong_add<N1, N0>(u1, u0);
+    smooth<N0>(u0, b0, ah0, wi0, nu2, false);
+#pragma unroll
+    for (int r = 0; r < All<N0>::R; ++r) {
+        int i, j, k;
+        bool ok;
+        All<N0>::at(r, i, j, k, ok);
+        if (ok) udst[(i + 1) + (j + 1) * sy + (k + 1) * sz] = u0[idx<N0>(i, j, k)];
+    }
+}
+
 }  // namespace
 
 namespace k {
@@ -425,6 +724,26 @@ hipError_t vcycle_bottom(const Tiling &t, double alpha, int smoother, double ome
     }
     if (items == 0) return hipSuccess;
     if (lds > bottom_lds_max()) return hipErrorInvalidValue;
+    // 3D red-black from a 15^3 top: the kernel with compile-time levels
+    // (PFMG_BOTTOM15=0 keeps the generic one)
+    static const bool use15 = [] {
+        const char *e = getenv("PFMG_BOTTOM15");
+        return !(e && atoi(e) == 0);
+    }();
+    bool all15 = t.dim == 3 && smoother == PFMG_SMOOTH_RBGS && use15;
+    for (int sg = 0; sg < t.nseg; ++sg) all15 = all15 && t.seg_n(sg) == b15::N0;
+    if (all15) {
+        const size_t l15 = (size_t)b15::LDS_ELEMS * sizeof(T);
+        if (l15 > 64 * 1024) {
+            static const hipError_t e15 = hipFuncSetAttribute((const void *)vcycle_bottom15_kernel<T>,
+                                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                              (int)bottom_lds_max());
+            if (e15 != hipSuccess) return e15;
+        }
+        vcycle_bottom15_kernel<T><<<(unsigned)items, dim3(16, 16, 4), l15, s>>>(t, alpha, omega, nu1, nu2,
+                                                                                zero_init ? 1 : 0, b, u);
+        return hipGetLastError();
+    }
     if (lds > 64 * 1024) {
         // above the default dynamic-LDS limit: raise it once per kernel
         static const hipError_t e3 = hipFuncSetAttribute((const void *)vcycle_bottom_kernel<3, T>,

@@ -477,10 +477,10 @@ __device__ inline void rb_pass(T *u, const T *b, T ah, T winv, int c)
     __syncthreads();
 }
 
-// RB-GS sweeps; from zero the first red pass is winv b on red points, 0 on
-// black ones.
+// RB-GS sweeps on a small grid (N <= 8: one slot round per colour); from
+// zero the first red pass is winv b on red points, 0 on black ones.
 template <int N, typename T>
-__device__ inline void smooth(T *u, const T *b, T ah, T winv, int sweeps, bool from_zero)
+__device__ inline void smooth_pt(T *u, const T *b, T ah, T winv, int sweeps, bool from_zero)
 {
     if (sweeps == 0 && from_zero) {
 #pragma unroll
@@ -518,6 +518,84 @@ __device__ inline void smooth(T *u, const T *b, T ah, T winv, int sweeps, bool f
             rb_pass<N>(u, b, ah, winv, 0);
         }
         rb_pass<N>(u, b, ah, winv, 1);
+    }
+}
+
+// RB-GS sweeps; from zero the first red pass is winv b on red points, 0 on
+// black ones.  A thread visits the same points (slot r of colour c) in every
+// pass, so it keeps their b and their current u in registers: a pass reads
+// only the six neighbours from LDS.  The arithmetic is that of the generic
+// kernel (the centre value is the same number, held in a register).
+template <int N, typename T>
+__device__ inline void smooth(T *u, const T *b, T ah, T winv, int sweeps, bool from_zero)
+{
+    if constexpr (N <= 8) {
+        // small grids: the registers would cost more than the LDS reads
+        smooth_pt<N>(u, b, ah, winv, sweeps, from_zero);
+        return;
+    }
+    constexpr int R = Colour<N>::R;
+    int ci[2][R], cj[2][R], ck[2][R], pp[2][R];
+    bool okr[2][R];
+    T bb[2][R], uu[2][R];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int i, j, k;
+            bool ok;
+            Colour<N>::at(r, c, i, j, k, ok);
+            if (!ok) i = j = k = 0;
+            ci[c][r] = i; cj[c][r] = j; ck[c][r] = k;
+            pp[c][r] = idx<N>(i, j, k);
+            okr[c][r] = ok;
+            bb[c][r] = b[pp[c][r]];
+            uu[c][r] = from_zero ? (T)0 : u[pp[c][r]];
+        }
+    if (sweeps == 0) {
+        if (from_zero) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (okr[c][r]) u[pp[c][r]] = (T)0;
+        }
+        __syncthreads();
+        return;
+    }
+    auto pass = [&](int c) {
+        T v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = ci[c][r], j = cj[c][r], k = ck[c][r], p = pp[c][r];
+            auto nb = [&](int off, bool in) { const T x = u[in ? p + off : p]; return in ? x : (T)0; };
+            T sn = nb(-1, i > 0) + nb(1, i < N - 1);
+            sn += (nb(-N, j > 0) + nb(N, j < N - 1)) + (nb(-N * N, k > 0) + nb(N * N, k < N - 1));
+            const T uc = uu[c][r];
+            const T d2 = sn - (T)6 * uc;
+            v[r] = uc + winv * (bb[c][r] - (uc - ah * d2));
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uu[c][r] = v[r];
+            if (okr[c][r]) u[pp[c][r]] = v[r];
+        }
+        __syncthreads();
+    };
+    for (int sw = 0; sw < sweeps; ++sw) {
+        if (sw == 0 && from_zero) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    uu[c][r] = c == 0 ? winv * bb[c][r] : (T)0;
+                    if (okr[c][r]) u[pp[c][r]] = uu[c][r];
+                }
+            __syncthreads();
+        } else {
+            pass(0);
+        }
+        pass(1);
     }
 }
 
@@ -567,9 +645,10 @@ __device__ inline void resid_restrict(const T *u, const T *b, T *t, T *bc, T ah)
     __syncthreads();
 }
 
-// Fine u += d-linear interpolation of the coarse u (as prolong_add above).
+// Fine u += d-linear interpolation of the coarse u (as prolong_add above),
+// point by point (the small levels).
 template <int NC, int NF, typename T>
-__device__ inline void prolong_add(const T *uc, T *uf)
+__device__ inline void prolong_pt(const T *uc, T *uf)
 {
     auto at = [&](int i, int j, int k) -> T {
         const bool ok = (unsigned)i < (unsigned)NC && (unsigned)j < (unsigned)NC && (unsigned)k < (unsigned)NC;
@@ -606,6 +685,70 @@ __device__ inline void prolong_add(const T *uc, T *uf)
         All<NF>::at(r, i, j, k, ok);
         if (ok) uf[idx<NF>(i, j, k)] = v[r];
     }
+    __syncthreads();
+}
+
+// Fine u += d-linear interpolation of the coarse u (as prolong_add above),
+// by coarse cells: cell (cx, cy, cz), 0 <= c <= NC, holds the fine points
+// with 1-based indices 2c and 2c + 1 on each axis (those inside the grid),
+// whose coarse neighbours are the cell's corners c and c + 1 (1-based; 0
+// and NC + 1 are the zero boundary).  A thread takes the cell's fine points
+// of one z parity: it reads the cell's 4 (even z) or 8 (odd z) corners once
+// and combines them with the same selects as the point formula.
+template <int NC, int NF, typename T>
+__device__ inline void prolong_add(const T *uc, T *uf)
+{
+    if constexpr (NC < 7) {
+        prolong_pt<NC, NF>(uc, uf);
+        return;
+    }
+    constexpr int C = NC + 1, CELLS = C * C * C;
+    static_assert(NF == 2 * NC + 1 && 2 * CELLS <= 1024, "cell mapping");
+    auto at = [&](int i, int j, int k) -> T {
+        const bool ok = (unsigned)i < (unsigned)NC && (unsigned)j < (unsigned)NC && (unsigned)k < (unsigned)NC;
+        const T v = uc[ok ? idx<NC>(i, j, k) : 0];
+        return ok ? v : (T)0;
+    };
+    const int tid = (int)(threadIdx.x + 16 * (threadIdx.y + 16 * threadIdx.z));
+    const bool act = tid < 2 * CELLS;
+    const int zp = tid / CELLS, rem = tid - zp * CELLS;
+    const int cx = rem % C, cy = (rem / C) % C, cz = rem / (C * C);
+    const int k1 = 2 * cz + zp;   // 1-based fine z of this thread's points
+    const bool oz = zp != 0;
+    // corners X[a][b][c]: x index cx - 1 + a, y index cy - 1 + b (0-based),
+    // z the point's lower (c = 0) and, for odd z, upper (c = 1) coarse plane
+    T X[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+            X[a][bb][0] = at(cx - 1 + a, cy - 1 + bb, cz - 1);
+            X[a][bb][1] = oz ? at(cx - 1 + a, cy - 1 + bb, cz) : X[a][bb][0];
+        }
+    T v[4], fv[4];
+    int pp[4];
+    bool okp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i1 = 2 * cx + (q & 1), j1 = 2 * cy + (q >> 1);
+        okp[q] = act && i1 >= 1 && i1 <= NF && j1 >= 1 && j1 <= NF && k1 >= 1 && k1 <= NF;
+        pp[q] = okp[q] ? idx<NF>(i1 - 1, j1 - 1, k1 - 1) : 0;
+        fv[q] = uf[pp[q]];
+        const bool ox = (q & 1) != 0, oy = (q >> 1) != 0;
+        auto rowv = [&](int bb, int c) -> T {
+            const T x0 = X[0][bb][c], x1 = X[ox ? 1 : 0][bb][c];
+            const T h = (T)0.5 * (x0 + x1);
+            return ox ? h : x0;
+        };
+        const T r00 = rowv(0, 0), r10 = rowv(oy ? 1 : 0, 0), r01 = rowv(0, 1), r11 = rowv(oy ? 1 : 0, 1);
+        const T p0h = (T)0.5 * (r00 + r10), p1h = (T)0.5 * (r01 + r11);
+        const T p0 = oy ? p0h : r00, p1 = oy ? p1h : r01;
+        const T vh = (T)0.5 * (p0 + p1);
+        v[q] = oz ? vh : p0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (okp[q]) uf[pp[q]] = fv[q] + v[q];
     __syncthreads();
 }
 

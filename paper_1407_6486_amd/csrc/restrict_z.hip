@@ -4,7 +4,10 @@
 // weights 1/4, 1/2, 1/4 around the fine point 2J of coarse point J).
 //
 // A workgroup owns TJ coarse rows of every coarse x and a chunk of coarse
-// planes, and marches upwards through the fine planes 2K0-1 .. 2K1-1:
+// planes, and marches through the fine planes 2K0-1 .. 2K1-1 (upwards in
+// even chunks, downwards in odd ones, so that two neighbouring chunks read
+// the planes they share at about the same time and the second read hits
+// the XCD's L2):
 //   1. the current fine plane of u goes to LDS (x and y neighbours; the z
 //      neighbours stay in registers);
 //   2. the residual of the 2 TJ + 1 fine rows of the tile goes to LDS,
@@ -69,6 +72,7 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
     const T ah = (T)(qs.par(alpha) * (double)(nf + 1) * (double)(nf + 1));
     const int J0 = jt * TJ + 1, K0 = zc * kch + 1, K1 = min(K0 + kch, nc + 1);
     const int fy0 = 2 * J0 - 1;
+    const int dk = (zc & 1) ? -1 : 1;   // march direction
     const int i = (int)(threadIdx.x % RLN) + 1;
     const int rsub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / RLN));
     const bool xin = i <= nf;
@@ -108,10 +112,10 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
     auto ld = [&](const T *__restrict__ a, unsigned rb, unsigned pb) -> T {
         return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + (rb + pb) + ib);
     };
-    // loads of step kf: u plane kf + 1 and b plane kf on the residual rows,
-    // u plane kf on the two halo rows
+    // loads of the step on plane kf: u plane kf + dk and b plane kf on the
+    // residual rows, u plane kf on the two halo rows
     auto load_step = [&](int kf, T (&un)[Q], T (&bn)[Q], T (&ex)[2]) {
-        const unsigned pu = planeb(kf + 1), pb = planeb(kf);
+        const unsigned pu = planeb(kf + dk), pb = planeb(kf);
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             if (own[q]) {
@@ -124,8 +128,13 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
     };
 
     const int kf0 = 2 * K0 - 1, kf1 = 2 * K1 - 1;
-    // fine plane p lives in slot (p - kf0 + 1) & 3 (u), (p - kf0) & 1 (b,
-    // outer halo rows)
+    // step v = 0 .. L of the march works on fine plane kv(v); kf0 and kf1
+    // are odd, so plane kv(v) is odd exactly when v is even in both
+    // directions
+    const int L = kf1 - kf0;
+    auto kv = [&](int v) { return dk > 0 ? kf0 + v : kf1 - v; };
+    // the plane of step v lives in slot (v + 1) & 3 (u), v & 1 (b, outer
+    // halo rows)
     T us[4][Q], bs[2][Q], es[2][2];
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl)
@@ -135,7 +144,7 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
     for (int q = 0; q < Q; ++q) bs[0][q] = bs[1][q] = (T)0;
     es[0][0] = es[0][1] = es[1][0] = es[1][1] = (T)0;
     {
-        const unsigned pm = planeb(kf0 - 1), pc = planeb(kf0);
+        const unsigned pm = planeb(kv(-1)), pc = planeb(kv(0));
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             if (own[q]) {
@@ -143,20 +152,25 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
                 us[1][q] = ld(U, roff[q], pc);
             }
     }
-    load_step(kf0, us[2], bs[0], es[0]);
+    load_step(kv(0), us[2], bs[0], es[0]);
     const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
-    T acc = (T)0;
+    // upwards: the running sum of the open coarse plane; downwards: the
+    // weighted sums of its upper and middle fine planes, so that both
+    // directions add the three planes in the same order
+    T acc = (T)0, hi = (T)0, mid = (T)0;
 
-    // one step on fine plane kf = kf0 + 4 m + S (odd for even S)
-    auto step = [&](auto sc, int kf) {
+    // step v = 4 m + S of the march, on fine plane kf = kv(v) (odd for
+    // even S)
+    auto step = [&](auto sc, int v) {
         constexpr int S = decltype(sc)::value;
+        const int kf = kv(v);
         constexpr int SU = (S + 1) & 3;              // slot of u plane kf
         constexpr int SM = S & 3, SP = (S + 2) & 3, SN = (S + 3) & 3;
         // everything this step reads from memory was loaded during the
         // previous step: wait for it before issuing the next step's loads
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __builtin_amdgcn_sched_barrier(0);
-        if (kf < kf1) load_step(kf + 1, us[SN], bs[(S + 1) & 1], es[(S + 1) & 1]);
+        if (v < L) load_step(kf + dk, us[SN], bs[(S + 1) & 1], es[(S + 1) & 1]);
         // ---- u plane kf -> LDS
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -193,24 +207,39 @@ __global__ __launch_bounds__(BLOCK) void resid_restrict_z_kernel(Tiling t, int k
                 const T *row = rp + (2 * Jl + 1 + bq) * RL + 2 * I;
                 s += w[bq + 1] * ((w[0] * row[-1] + w[1] * row[0]) + w[2] * row[1]);
             }
-            if ((S & 1) == 0) {
-                // fine plane 2K + 1 closes coarse plane K = (kf - 1) / 2 and
-                // opens K + 1
-                if (kf > kf0) C[(long)I + (long)J * syc + (long)((kf - 1) / 2) * szc] = acc + w[2] * s;
-                acc = w[0] * s;
+            if (dk > 0) {
+                if ((S & 1) == 0) {
+                    // fine plane 2K + 1 closes coarse plane K = (kf - 1) / 2
+                    // and opens K + 1
+                    if (v > 0) C[(long)I + (long)J * syc + (long)((kf - 1) / 2) * szc] = acc + w[2] * s;
+                    acc = w[0] * s;
+                } else {
+                    acc += w[1] * s;
+                }
             } else {
-                acc += w[1] * s;
+                if ((S & 1) == 0) {
+                    // fine plane 2K + 1 closes coarse plane K + 1 =
+                    // (kf + 1) / 2 (its lower plane) and opens K
+                    if (v > 0) {
+                        T a = w[0] * s;
+                        a += w[1] * mid;
+                        C[(long)I + (long)J * syc + (long)((kf + 1) / 2) * szc] = a + w[2] * hi;
+                    }
+                    hi = s;
+                } else {
+                    mid = s;
+                }
             }
         }
     };
-    for (int kk = kf0; kk <= kf1; kk += 4) {
-        step(std::integral_constant<int, 0>{}, kk);
-        if (kk + 1 > kf1) break;
-        step(std::integral_constant<int, 1>{}, kk + 1);
-        if (kk + 2 > kf1) break;
-        step(std::integral_constant<int, 2>{}, kk + 2);
-        if (kk + 3 > kf1) break;
-        step(std::integral_constant<int, 3>{}, kk + 3);
+    for (int vv = 0; vv <= L; vv += 4) {
+        step(std::integral_constant<int, 0>{}, vv);
+        if (vv + 1 > L) break;
+        step(std::integral_constant<int, 1>{}, vv + 1);
+        if (vv + 2 > L) break;
+        step(std::integral_constant<int, 2>{}, vv + 2);
+        if (vv + 3 > L) break;
+        step(std::integral_constant<int, 3>{}, vv + 3);
     }
 }
 

@@ -6,9 +6,12 @@
 //     per point.
 //
 // A workgroup owns full x-rows, TY output rows and a chunk of z planes and
-// marches upwards in z.  At step k the rows j0-1 .. j0+TY of plane k go into
-// one of four LDS buffers and the output is computed on plane k-1 from the
-// x and y neighbours in LDS and the z neighbours in registers; u is read
+// marches through it in z (upwards in even chunks, downwards in odd ones, so
+// that neighbouring chunks read their shared border planes at about the same
+// time and the second read hits the XCD's L2).  At step k the rows
+// j0-1 .. j0+TY of plane k go into one of four LDS buffers and the output is
+// computed on the plane before k from the x and y neighbours in LDS and the
+// z neighbours in registers; u is read
 // once (plus the halo rows that neighbouring tiles also read) and the output
 // written once.  The loads of step k + 1 are issued before step k's
 // arithmetic.  The arithmetic per point is that of the column-blocked
@@ -63,6 +66,10 @@ __global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, 
     const T ah = (T)ahd, winv = (T)(omega / (1.0 + 2.0 * 3 * ahd));
     const int j0 = jt * TY + 1, k0 = zc * zchunk + 1;
     const int k1 = min(k0 + zchunk, n + 1);  // F on planes k0 .. k1-1
+    // step v = 0 .. V works on plane kv(v) and writes plane kv(v - 1); the
+    // z-neighbour sums commute, so both directions give the same numbers
+    const int dk = (zc & 1) ? -1 : 1, V = k1 - k0 + 1;
+    auto kv = [&](int v) { return dk > 0 ? k0 - 1 + v : k1 - v; };
     const int i = (int)(threadIdx.x % RLN) + 1;
     const int rsub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / RLN));
     const bool xin = i <= n;
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, 
         return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + (rb + pb) + ib);
     };
 
-    // u plane p in slot (p - (k0 - 1)) & 3, b plane p in (p - (k0 - 1)) & 1
+    // the u plane of step v in slot v & 3, its b plane in v & 1
     T us[4][Q], bs[2][Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -98,20 +105,22 @@ __global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, 
         bs[0][q] = bs[1][q] = (T)0;
     }
     {
-        const unsigned p0 = planeb(k0 - 1);
+        const unsigned p0 = planeb(kv(0));
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             if (own[q]) us[0][q] = ld(U, roff[q], p0);
     }
 
-    // one step on plane k (slot S): u plane k to LDS, output on plane k - 1
-    auto step = [&](auto sc, int k) {
+    // step v on plane k = kv(v) (slot S): u plane k to LDS, output on the
+    // plane before it
+    auto step = [&](auto sc, int v) {
         constexpr int S = decltype(sc)::value;
+        const int k = kv(v);
         constexpr int S1 = (S + 1) & 3, S2 = (S + 2) & 3, S3 = (S + 3) & 3;
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the previous step's loads
         __builtin_amdgcn_sched_barrier(0);
-        if (k < k1) {
-            const unsigned pu = planeb(k + 1), pb = planeb(k);
+        if (v < V) {
+            const unsigned pu = planeb(k + dk), pb = planeb(k);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int r = rsub + q * RPP;
@@ -128,8 +137,8 @@ __global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, 
             if (own[q]) buf[r * RL + i] = us[S][q];
         }
         __syncthreads();
-        // ---- output on plane k-1
-        const int kb = k - 1;
+        // ---- output on plane kb, the previous step's
+        const int kb = k - dk;
         if (kb >= k0 && kb < k1 && xin) {
             const T *bb = lp + S3 * ROWS * RL;
             const int ko = kb * sz;
@@ -151,14 +160,14 @@ __global__ __launch_bounds__(BLOCK) void stencil_z_kernel(Tiling t, int zchunk, 
             }
         }
     };
-    for (int kk = k0 - 1; kk <= k1; kk += 4) {
-        step(std::integral_constant<int, 0>{}, kk);
-        if (kk + 1 > k1) break;
-        step(std::integral_constant<int, 1>{}, kk + 1);
-        if (kk + 2 > k1) break;
-        step(std::integral_constant<int, 2>{}, kk + 2);
-        if (kk + 3 > k1) break;
-        step(std::integral_constant<int, 3>{}, kk + 3);
+    for (int vv = 0; vv <= V; vv += 4) {
+        step(std::integral_constant<int, 0>{}, vv);
+        if (vv + 1 > V) break;
+        step(std::integral_constant<int, 1>{}, vv + 1);
+        if (vv + 2 > V) break;
+        step(std::integral_constant<int, 2>{}, vv + 2);
+        if (vv + 3 > V) break;
+        step(std::integral_constant<int, 3>{}, vv + 3);
     }
 }
 

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfmg.so")
 ARCH = os.environ.get("PFMG_ARCH", "gfx950")
 
-SOURCES = ["mg_kernels.hip", "rbgs_fused.hip", "restrict_z.hip", "stencil_z.hip", "stencil4.hip", "bottom.hip", "sdc_kernels.hip", "tune.hip", "solver.hip", "batch.hip",
+SOURCES = ["mg_kernels.hip", "rbgs_fused.hip", "restrict_z.hip", "prolong_z.hip", "stencil_z.hip", "stencil4.hip", "bottom.hip", "sdc_kernels.hip", "tune.hip", "solver.hip", "batch.hip",
            "nn.hip", "unet.hip", "capi.hip",
            "collocation.cpp"]
 

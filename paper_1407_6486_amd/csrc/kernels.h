@@ -74,6 +74,12 @@ hipError_t resid_restrict(const Tiling &t, double alpha, View<T> b, View<T> u, V
 // u += P ec, d-linear (t.n = fine n).
 template <typename T>
 hipError_t prolong_add(const Tiling &t, View<T> ec, View<T> u, hipStream_t s);
+// The same in one z-marching pass (3D, odd fine n in [31, 255], launches of
+// 2^19 points or more); prolong_add takes it wherever prolong_z_ok holds.
+// kch_force > 0 fixes the coarse planes per workgroup.
+bool prolong_z_ok(const Tiling &t);
+template <typename T>
+hipError_t prolong_z(const Tiling &t, View<T> ec, View<T> u, hipStream_t s, int kch_force = 0);
 // Exact solve for n in {1, 2}.
 template <typename T>
 hipError_t coarsest(const Tiling &t, double alpha, View<T> b, View<T> u, hipStream_t s);

@@ -12,6 +12,8 @@
 // uneven problems of a batch share one launch per multigrid level.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 
 #include "kernels.h"
@@ -613,6 +615,12 @@ template <typename T>
 hipError_t prolong_add(const Tiling &t, View<T> ec, View<T> u, hipStream_t s)
 {
     if (grid_blocks(t) == 0) return hipSuccess;
+    // PFMG_PROLONG_Z=0 keeps the column kernel for every launch
+    static const bool use_z = [] {
+        const char *e = getenv("PFMG_PROLONG_Z");
+        return !(e && atoi(e) == 0);
+    }();
+    if (t.dim == 3 && use_z && prolong_z_ok(t)) return prolong_z(t, ec, u, s);
     if (t.dim == 3) prolong_kz_kernel<T><<<col_grid(t), BLOCK, 0, s>>>(t, ec, u);
     else prolong_kernel<1, T><<<grid_of(t), BLOCK, 0, s>>>(t, ec, u);
     return hipGetLastError();

@@ -174,8 +174,8 @@ def _omp_threads(k):
 
 def cpu_baseline(n, P, iters_gpu, cpu_iters, u0):
     """The oracle as it stands (gcc -O3, no fast-math, no contraction), on
-    the host: predictor + cpu_iters iterations on the threads of the box's
-    CPU share (OMP_NUM_THREADS), extrapolated to the iteration count of the
+    the host: predictor + cpu_iters iterations on the threads of the
+    process's CPU share (OMP_NUM_THREADS), extrapolated to the iteration count of the
     block; then the same on one thread (predictor + one iteration); the
     host's CPU model, physical cores and STREAM-triad bandwidth."""
     import oracle as O

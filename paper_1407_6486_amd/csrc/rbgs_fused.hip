@@ -53,7 +53,7 @@ constexpr int QMAX = 6;   // owned rows per thread
 // TYC > 0 fixes the rows per workgroup at compile time (the shapes the
 // shipped tuner table picks), which turns the row ownership tests into
 // constants; TYC = 0 takes ty_rt.
-template <typename T, int RLN, int Q, int NT, int TYC>
+template <typename T, int RLN, int Q, int NT, int TYC, int NB = 2>
 __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_fused_kernel(Tiling t, int ty_rt, int zchunk, int zero_in, double alpha,
                                                            double omega, View<T> b, View<T> uin, View<T> uout)
 {
@@ -69,8 +69,10 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
     const int n = qs.n;
     constexpr int RL = RLN + 2;
     const int rows = ty + 2;                 // rows of the red update (owned rows)
-    T *up = reinterpret_cast<T *>(smem_raw);             // uin plane k: rows j0-2 .. j0+ty+1
-    T *wp = up + (ty + 4) * RL;                  // 2 planes of the red-updated field
+    // uin plane k: rows j0-2 .. j0+ty+1 (NB = 1: two buffers, by the
+    // plane's parity), then 2 planes of the red-updated field
+    T *up0 = reinterpret_cast<T *>(smem_raw);
+    T *wp = up0 + (NB == 1 ? 2 : 1) * (ty + 4) * RL;
     const int ytiles = (n + ty - 1) / ty, zch = (n + zchunk - 1) / zchunk;
     const int item = (int)(bid / (unsigned)(ytiles * zch));
     const int rem = (int)(bid - (unsigned)item * (unsigned)(ytiles * zch));
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
     const unsigned ib = (unsigned)min(i, n + 1) * (unsigned)sizeof(T);
 
     // x index 0 is the boundary: zero once in every LDS row
-    for (int r = threadIdx.x; r < (ty + 4) + 2 * rows; r += NT) up[r * RL] = (T)0;
+    for (int r = threadIdx.x; r < (NB == 1 ? 2 : 1) * (ty + 4) + 2 * rows; r += NT) up0[r * RL] = (T)0;
 
     // Per owned row (uniform): ownership, the byte offset of the row clamped
     // to the halo (every point outside the interior is zero), and the lanes
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
             __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             __builtin_amdgcn_sched_barrier(0);
             if (v < L) load_step(k + dk, us[S2], bs[S1], es[(S + 1) & 1]);
+            T *up = up0 + (NB == 1 ? (k & 1) * (ty + 4) * RL : 0);
             // ---- uin plane k -> LDS (rows e = 0 .. ty+3 <-> j = j0-2+e)
             if (!ZI) {
 #pragma unroll
@@ -226,7 +229,12 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
                     wk[r * RL + i] = val;
                 }
             }
-            __syncthreads();
+            // NB = 2: the uin plane buffer is rewritten by the next step, so
+            // phase A must be done everywhere first.  NB = 1: the next step
+            // writes the other uin buffer, and phase B below reads only the
+            // red plane of the previous step (ordered by this step's first
+            // barrier), so that barrier alone orders every LDS access.
+            if constexpr (NB == 2) __syncthreads();
             // ---- phase B: black update of plane k - dk on rows 1..ty
             const int kb = k - dk;
             if (kb >= k0 && kb < k1) {
@@ -358,7 +366,16 @@ hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in,
     // compile-time rows for the shapes of the 127^3 / 63^3 / 31^3 V-cycle
     // levels in the shipped FP64 tuner table
     if constexpr (sizeof(T) == 8) {
-        if (f.nt == 512 && rln == 128 && q == 3 && f.ty == 8) PFMG_FUSED_TY(128, 3, 512, 8);
+        if (f.nt == 512 && rln == 128 && q == 3 && f.ty == 8) {
+            // one barrier per z-step (the uin plane double-buffered in LDS):
+            // 41.0 us against 41.4 us for 4 x 127^3 at 0.3 more KB per row
+            static const bool one_barrier = env_int("PFMG_SWEEP_1B", 1) != 0;
+            if (one_barrier)
+                return launch(rbgs_fused_kernel<T, 128, 3, 512, 8, 1>, g, blk,
+                              f.lds + (size_t)(f.ty + 4) * (rln + 2) * sizeof(T), s, t, f.ty, f.zchunk, zi, alpha,
+                              omega, b, uin, uout);
+            PFMG_FUSED_TY(128, 3, 512, 8);
+        }
         if (f.nt == 512 && rln == 64 && q == 2 && f.ty == 8) PFMG_FUSED_TY(64, 2, 512, 8);
         if (f.nt == 512 && rln == 64 && q == 3 && f.ty == 16) PFMG_FUSED_TY(64, 3, 512, 16);
         if (f.nt == 512 && rln == 64 && q == 1 && f.ty == 6) PFMG_FUSED_TY(64, 1, 512, 6);

@@ -31,6 +31,26 @@ namespace {
 
 constexpr int QMAX = 6;   // owned rows per thread
 
+// One element at byte offset voff + soff of a buffer resource (soff uniform).
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, T v)
+{
+    if constexpr (sizeof(T) == 8) {
+        using U2 = unsigned __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)voff, (int)soff, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+    }
+}
+
 // RLN: x lanes per row (64, 128 or 256), the widest segment's n rounded up
 // to whole wavefronts; narrower segments leave their extra lanes idle.
 // NT: threads per workgroup (256 or 512: a larger workgroup owns more rows
@@ -111,7 +131,9 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
     // of the row that are red on even and on odd planes (interior only).
     bool own[Q], eown[2];
     unsigned roff[Q], eoff[2];
-    bool red_e[Q], red_o[Q];
+    // lanes of each row that are red on even and on odd planes, as wavefront
+    // lane masks (scalar registers: picking one per plane is a scalar select)
+    unsigned long long red_e[Q], red_o[Q];
     auto rowb = [&](int j) { return (unsigned)(min(max(j, 0), n + 1) * sy) * (unsigned)sizeof(T); };
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -120,8 +142,8 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
         roff[q] = rowb(j);
         const bool in = xin && j >= 1 && j <= n;
         const bool even = ((i + j) & 1) == 0;
-        red_e[q] = in && even;
-        red_o[q] = in && !even;
+        red_e[q] = __builtin_amdgcn_ballot_w64(in && even);
+        red_o[q] = __builtin_amdgcn_ballot_w64(in && !even);
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -130,9 +152,14 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
         eoff[q] = rowb(e == 0 ? j0 - 2 : j0 + ty + 1);
     }
     auto planeb = [&](int k) { return (unsigned)(min(max(k, 0), n + 1) * sz) * (unsigned)sizeof(T); };
-    auto ld = [&](const T *__restrict__ a, unsigned rb, unsigned pb) -> T {
-        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) + (rb + pb) + ib);
-    };
+    // loads and stores through buffer resources: the lane's byte offset is a
+    // fixed vector register and the row and plane offset a scalar one, so
+    // no address arithmetic runs on the vector unit
+    const int fbytes = (int)(field_elems(n, 3) * (long)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rU = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(U), 0, fbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(Bv), 0, fbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rO = __builtin_amdgcn_make_buffer_rsrc(O, 0, fbytes, 0x00020000);
+    auto ld = [&](__amdgpu_buffer_rsrc_t a, unsigned rb, unsigned pb) -> T { return buf_ld<T>(a, ib, rb + pb); };
 
     // The z-march; ZI: the input is zero (uin is not read).
     auto march = [&](auto zi) {
@@ -144,14 +171,14 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 if (own[q]) {
-                    if (!ZI) un[q] = ld(U, roff[q], pu);
-                    bn[q] = ld(Bv, roff[q], pb);
+                    if (!ZI) un[q] = ld(rU, roff[q], pu);
+                    bn[q] = ld(rB, roff[q], pb);
                 }
             }
             if (!ZI) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-                    if (eown[q]) ex[q] = ld(U, eoff[q], pb);
+                    if (eown[q]) ex[q] = ld(rU, eoff[q], pb);
             }
         };
 
@@ -168,8 +195,8 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 if (own[q]) {
-                    us[3][q] = ld(U, roff[q], pm);
-                    us[0][q] = ld(U, roff[q], pc);
+                    us[3][q] = ld(rU, roff[q], pm);
+                    us[0][q] = ld(rU, roff[q], pc);
                 }
             }
         }
@@ -187,7 +214,9 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
             __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             __builtin_amdgcn_sched_barrier(0);
             if (v < L) load_step(k + dk, us[S2], bs[S1], es[(S + 1) & 1]);
-            T *up = up0 + (NB == 1 ? (k & 1) * (ty + 4) * RL : 0);
+            // LDS buffers alternate with the step (slot parity), so their
+            // offsets are compile-time constants
+            T *up = up0 + (NB == 1 ? (S & 1) * (ty + 4) * RL : 0);
             // ---- uin plane k -> LDS (rows e = 0 .. ty+3 <-> j = j0-2+e)
             if (!ZI) {
 #pragma unroll
@@ -205,13 +234,13 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
             // plane buffer of k - 2 dk) before this step's red writes into it
             __syncthreads();
             // ---- phase A: red update of plane k on the owned rows
-            T *wk = wp + (k & 1) * rows * RL;
+            T *wk = wp + (S & 1) * rows * RL;
             const bool kin = k >= 1 && k <= n, kodd = (k & 1) != 0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int r = rsub + q * rpp;
                 if (own[q]) {
-                    const bool red = kin && (kodd ? red_o[q] : red_e[q]);
+                    const bool red = __builtin_amdgcn_inverse_ballot_w64(kin ? (kodd ? red_o[q] : red_e[q]) : 0ull);
                     T val;
                     if (ZI) {
                         val = red ? winv * bs[S][q] : (T)0;
@@ -238,7 +267,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
             // ---- phase B: black update of plane k - dk on rows 1..ty
             const int kb = k - dk;
             if (kb >= k0 && kb < k1) {
-                const T *wb = wp + (kb & 1) * rows * RL;
+                const T *wb = wp + ((S + 1) & 1) * rows * RL;
                 const bool kbodd = (kb & 1) != 0;
                 T outv[Q];
 #pragma unroll
@@ -246,7 +275,7 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
                     const int r = rsub + q * rpp;
                     outv[q] = (T)0;
                     if (r >= 1 && r <= ty) {
-                        const bool black = kbodd ? red_e[q] : red_o[q];
+                        const bool black = __builtin_amdgcn_inverse_ballot_w64(kbodd ? red_e[q] : red_o[q]);
                         const T wc = ws[S3][q];
                         const T *row = wb + r * RL;
                         T s = row[i - 1] + row[i + 1];
@@ -257,12 +286,12 @@ __global__ __launch_bounds__(NT, (Q == 3 ? (NT == 256 ? 4 : 2) : 1)) void rbgs_f
                     }
                 }
                 if (xin) {
-                    const int ko = kb * sz;
+                    const unsigned pk = planeb(kb);
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
                         const int r = rsub + q * rpp;
                         const int j = j0 - 1 + r;
-                        if (r >= 1 && r <= ty && j <= n) O[i + j * sy + ko] = outv[q];
+                        if (r >= 1 && r <= ty && j <= n) buf_st<T>(rO, ib, roff[q] + pk, outv[q]);
                     }
                 }
             }

@@ -398,7 +398,8 @@ hipError_t rbgs_fused(const Tiling &t, double alpha, double omega, bool zero_in,
         if (f.nt == 512 && rln == 128 && q == 3 && f.ty == 8) {
             // one barrier per z-step (the uin plane double-buffered in LDS):
             // 41.0 us against 41.4 us for 4 x 127^3 at 0.3 more KB per row
-            static const bool one_barrier = env_int("PFMG_SWEEP_1B", 1) != 0;
+            // (read at every launch, so a caller can compare the two)
+            const bool one_barrier = env_int("PFMG_SWEEP_1B", 1) != 0;
             if (one_barrier)
                 return launch(rbgs_fused_kernel<T, 128, 3, 512, 8, 1>, g, blk,
                               f.lds + (size_t)(f.ty + 4) * (rln + 2) * sizeof(T), s, t, f.ty, f.zchunk, zi, alpha,

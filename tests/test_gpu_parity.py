@@ -118,6 +118,34 @@ def test_vcycle_every_sweep_shape_matches_oracle(pf, nt, n, i):
     assert pins.rel_err(u_gpu.cpu().numpy(), u_or) <= TOL
 
 
+def test_one_and_two_barrier_sweeps_agree(pf, monkeypatch):
+    """The 127^3 sweep shape (128 lanes, 8 rows, 512 threads) with one
+    barrier per z-step and with two: the same operations in the same order,
+    so the V-cycles agree bitwise, and both match the oracle."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    n = 127
+    key = f"{arch}/rbgs/f64/{n}x1"
+    alpha = 3.0 / (n + 1) ** 2
+    b = inputs.random_field((n,) * 3, 901)
+    u0 = inputs.random_field((n,) * 3, 902)
+    out = {}
+    try:
+        pf.pfmg_tune_set(key, 2, 8, 11)
+        for flag in ("1", "0"):
+            say(f"127^3 sweep, PFMG_SWEEP_1B={flag}")
+            monkeypatch.setenv("PFMG_SWEEP_1B", flag)
+            c = make(pf, dim=3, n=n, n_slices=1, nodes_coarse=0, smoother=pf.SMOOTH_RBGS, omega=1.0)
+            u_gpu, st, rr, nc = c.vcycle(alpha, b, u0, 1)
+            assert st == pf.OK and nc == 1
+            out[flag] = u_gpu.cpu().numpy()
+    finally:
+        pf.pfmg_tune_set(key, -1)
+    assert np.array_equal(out["1"], out["0"])
+    u_or = O.vcycle(3, alpha, b, u0.copy(), O.RBGS, 1.0)
+    assert pins.rel_err(out["1"], u_or) <= TOL
+
+
 @pytest.mark.parametrize("dim,n,sm", [(3, 31, "rb"), (1, 63, "jac")])
 def test_full_solve_matches_oracle(pf, dim, n, sm):
     say(f"full solve dim={dim} n={n} smoother={sm}")
